@@ -1,0 +1,101 @@
+"""Tensor-ring model (Def. 2, eq. (3)), TR-SVD, and Alg. 3 (rBKI-TK-TR).
+
+Alg. 3 cites TR-SVD (Zhao et al. 2016, "Tensor ring decomposition") for the
+decomposition of the small core but does not restate it.  Written here from
+that method's published description, with fixed ranks instead of an accuracy
+threshold:
+
+  with TR ranks (r_1, ..., r_N) and closing rank r_0 = r_N,
+  1. unfold the tensor as S_1 x (S_2 ... S_N) and take its SVD; keep
+     k = min(r_0 r_1, rank) triplets, zero-padded to r_0 r_1 columns;
+  2. core 1 is the left factor reshaped to (S_1, r_0, r_1) with column
+     c = a0 * r_1 + a1, permuted to (r_0, S_1, r_1);
+  3. the remainder Sigma V^T is reshaped to (r_0, r_1, S_2, ..., S_N) and its
+     r_0 axis moved last, giving (r_1, S_2, ..., S_N, r_0);
+  4. for k = 2 .. N-1, unfold the remainder as (r_{k-1} S_k) x rest, SVD,
+     keep r_k triplets (zero-padded), core k is the left factor reshaped to
+     (r_{k-1}, S_k, r_k), the remainder is Sigma V^T;
+  5. the last core is the remainder reshaped to (r_{N-1}, S_N, r_0).
+
+Readings: Alg. 3 wraps "TR-ALS(G, R_n)" in a loop over n, but a TR-SVD yields
+all cores at once, so it is run once; the contraction of step 4 attaches the
+Tucker factor to the middle (dimension) mode of each core,
+X_n = G_n x_2 U^(n) in R^{R_{n-1} x I_n x R_n}.
+
+Because each step's left factor has orthonormal columns, the squared error
+||G - TR(cores)||_F^2 equals the sum of the squared discarded singular values
+over all steps; and because the Tucker factors are orthonormal,
+||X - TR(X_1..X_N)||^2 = ||X - [[G; U]]||^2 + ||G - TR(G_1..G_N)||^2.
+"""
+import numpy as np
+
+from .rbki import rbki_tucker
+from .tensor import fro
+
+
+def _truncated_svd_padded(M, r):
+    """Leading min(r, rank) singular triplets of M, zero-padded to r."""
+    U, s, Vt = np.linalg.svd(M, full_matrices=False)
+    k = min(r, s.size)
+    Ul = np.zeros((M.shape[0], r))
+    Rl = np.zeros((r, M.shape[1]))
+    Ul[:, :k] = U[:, :k]
+    Rl[:k] = s[:k, None] * Vt[:k]
+    discarded = float(np.sum(s[k:] ** 2))
+    return Ul, Rl, discarded
+
+
+def tr_svd(G, tr_ranks):
+    """TR-SVD of G (S_1 x ... x S_N) with TR ranks (r_1, ..., r_N), r_0 = r_N.
+    Returns the cores [(r_{k-1}, S_k, r_k)] and the sum of the squared
+    discarded singular values."""
+    G = np.asarray(G, np.float64)
+    N = G.ndim
+    S = G.shape
+    r = [int(tr_ranks[-1])] + [int(v) for v in tr_ranks]     # r[0] = r_N
+    discarded = 0.0
+    Ul, C, d = _truncated_svd_padded(G.reshape(S[0], -1), r[0] * r[1])
+    discarded += d
+    cores = [Ul.reshape(S[0], r[0], r[1]).transpose(1, 0, 2).copy()]
+    C = C.reshape((r[0], r[1]) + S[1:])
+    C = np.moveaxis(C, 0, -1)                                  # (r1, S2..SN, r0)
+    for k in range(1, N - 1):
+        M = C.reshape(r[k] * S[k], -1)
+        Ul, C, d = _truncated_svd_padded(M, r[k + 1])
+        discarded += d
+        cores.append(Ul.reshape(r[k], S[k], r[k + 1]))
+        C = C.reshape((r[k + 1],) + S[k + 1:] + (r[0],))
+    cores.append(C.reshape(r[N - 1], S[N - 1], r[0]).copy())
+    return cores, discarded
+
+
+def tr_to_full(cores):
+    """X(i_1..i_N) = trace(X_1(:, i_1, :) X_2(:, i_2, :) ... X_N(:, i_N, :))
+    (eq. (3))."""
+    T = cores[0]                                     # (r0, S1, r1)
+    for Ck in cores[1:]:
+        T = np.tensordot(T, Ck, axes=([T.ndim - 1], [0]))
+    # T has shape (r0, S1, ..., SN, r0): close the ring
+    return np.trace(T, axis1=0, axis2=T.ndim - 1)
+
+
+def attach_factors(cores, factors):
+    """Alg. 3, step 4: X_n = G_n x_2 U^(n)."""
+    return [np.einsum("asb,is->aib", Gn, U) for Gn, U in zip(cores, factors)]
+
+
+def rbki_htr(X, tucker_ranks, p, q, seed, tr_ranks, explicit_error=True):
+    """Alg. 3 (rBKI-TK-TR) with the TR-SVD branch.  Returns the TR cores of
+    X, the relative error and a dict of intermediate results."""
+    X = np.asarray(X, np.float64)
+    G, factors, e_tk = rbki_tucker(X, tucker_ranks, p, q, seed)
+    core_cores, discarded = tr_svd(G, tr_ranks)
+    cores = attach_factors(core_cores, factors)
+    nx = fro(X)
+    if explicit_error:
+        err = fro(X - tr_to_full(cores)) / nx
+    else:
+        err = float(np.sqrt((e_tk * nx) ** 2 + discarded)) / nx
+    info = {"G": G, "factors": factors, "core_cores": core_cores,
+            "tucker_error": e_tk, "discarded": discarded}
+    return cores, err, info

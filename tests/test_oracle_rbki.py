@@ -1,0 +1,191 @@
+"""Pins for the oracle's Alg. 1 / Alg. 2 against what mathematics fixes:
+exact recovery, reduction to a truncated SVD, Eckart-Young, Rayleigh-Ritz
+nesting, the HOSVD error bound, the EVD/SVD equivalence of Remark 1 and the
+orthogonality identities of the core."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import philox
+from oracle.rbki import (rbki_basis, literal_krylov_basis, power_basis, ritz_factor,
+                         mode_factor, rbki_tucker, per_mode_error, sketch_size, orth)
+from oracle.thosvd import thosvd, leading_left_singular
+from oracle.tensor import unfold, project_core, tucker_to_full, fro, view_dims
+from oracle.metrics import projector_distance, orthonormality_defect
+
+
+def noisy_tucker(dims, ranks, snr, seed):
+    Xc, rng = synth.orthonormal_tucker(dims, ranks, seed)
+    return synth.add_noise(Xc, snr, rng), Xc
+
+
+def test_sketch_size_rule():
+    assert sketch_size(10, 5, 200, 40000) == 15
+    assert sketch_size(10, 5, 12, 40000) == 12
+    assert sketch_size(10, 5, 200, 8) == 8
+
+
+def test_exact_rank_tucker_is_recovered():
+    Xc, _ = synth.orthonormal_tucker((20, 24, 18), (3, 4, 2), seed=5)
+    G, Us, err = rbki_tucker(Xc, (3, 4, 2), p=5, q=2, seed=11)
+    assert err <= 1e-12
+    for U in Us:
+        assert orthonormality_defect(U) < 1e-13
+
+
+def test_exact_rank_with_rank_deficient_krylov_blocks():
+    # S > true rank: W has rank 3 < S = 8, later blocks deflate completely
+    Xc, _ = synth.orthonormal_tucker((16, 16, 16), (3, 3, 3), seed=6)
+    G, Us, err, infos = rbki_tucker(Xc, (3, 3, 3), p=5, q=2, seed=12, return_info=True)
+    assert err <= 1e-12
+    for info in infos:
+        assert info["widths"][0] == 3 and sum(info["widths"][1:]) == 0
+
+
+def test_full_krylov_reduces_to_truncated_svd():
+    # S (q+1) >= I: the basis spans R^I and U is the LAPACK truncated SVD
+    X, _ = noisy_tucker((12, 30, 25), (4, 4, 4), 10.0, seed=7)
+    for n in range(3):
+        U, info = mode_factor(X, n, 4, p=3, q=2, seed=13, return_info=True)
+        I = X.shape[n]
+        assert info["Q"].shape[1] == min(I, 7 * 3)
+        Xn = unfold(X, n)
+        Ut, s = leading_left_singular(Xn, 4)
+        if I <= 21:
+            assert (s[3] - s[4]) / s[0] > 1e-6
+            assert projector_distance(U, Ut) <= 1e-10
+
+
+def test_strong_gap_converges_to_svd():
+    # sigma_{R+1}/sigma_R <= 1e-3 with q >= 2: (1e-3)^(2q+1) is far below 1e-10
+    rng = np.random.default_rng(8)
+    I, J, R = 60, 500, 5
+    Uq = np.linalg.qr(rng.standard_normal((I, I)))[0]
+    Vq = np.linalg.qr(rng.standard_normal((J, I)))[0]
+    s = np.concatenate([np.linspace(10, 5, R), 5e-3 * np.linspace(1, 0.5, I - R)])
+    Xn = (Uq * s) @ Vq.T
+    Om = philox.omega(3, 0, J, R + 2)
+    Q, _ = rbki_basis(Xn, Om, q=2)
+    U, _ = ritz_factor(Xn, Q, R)
+    assert projector_distance(U, Uq[:, :R]) <= 1e-10
+
+
+def test_eckart_young_per_mode_and_orthonormal():
+    X, _ = noisy_tucker((30, 26, 34), (5, 5, 5), 0.0, seed=9)
+    for n in range(3):
+        U = mode_factor(X, n, 5, p=2, q=1, seed=14)
+        assert orthonormality_defect(U) < 1e-13
+        Ut, _ = leading_left_singular(unfold(X, n), 5)
+        assert per_mode_error(X, n, U) >= per_mode_error(X, n, Ut) * (1 - 1e-12)
+
+
+def test_rayleigh_ritz_nesting_in_q_and_p_and_vs_power_iteration():
+    X, _ = noisy_tucker((40, 36, 30), (6, 6, 6), -5.0, seed=10)
+    n, R = 0, 6
+    Xn = unfold(X, n)
+    J = Xn.shape[1]
+    errs_q = []
+    for q in range(4):
+        Q, _ = rbki_basis(Xn, philox.omega(21, n, J, R + 2), q)
+        U, _ = ritz_factor(Xn, Q, R)
+        errs_q.append(fro(Xn - U @ (U.T @ Xn)))
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(errs_q, errs_q[1:]))
+    errs_p = []
+    for p in range(0, 6):
+        Q, _ = rbki_basis(Xn, philox.omega(21, n, J, R + p), 1)
+        U, _ = ritz_factor(Xn, Q, R)
+        errs_p.append(fro(Xn - U @ (U.T @ Xn)))
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(errs_p, errs_p[1:]))
+    # the power-iteration space (XX^T)^q W lies inside the Krylov space
+    for q in (1, 2, 3):
+        Om = philox.omega(21, n, J, R + 2)
+        Qk, _ = rbki_basis(Xn, Om, q)
+        Qp = power_basis(Xn, Om, q)
+        Uk, _ = ritz_factor(Xn, Qk, R)
+        Up, _ = ritz_factor(Xn, Qp, R)
+        assert fro(Xn - Uk @ (Uk.T @ Xn)) <= fro(Xn - Up @ (Up.T @ Xn)) * (1 + 1e-12)
+
+
+def test_q0_is_single_sketch_range_finder():
+    # q = 0: U comes from the range of W = X Omega alone (Sec. 2.2)
+    X, _ = noisy_tucker((25, 20, 22), (4, 4, 4), 5.0, seed=15)
+    Xn = unfold(X, 1)
+    Om = philox.omega(5, 1, Xn.shape[1], 7)
+    Q, _ = rbki_basis(Xn, Om, 0)
+    Qw, _ = np.linalg.qr(Xn @ Om)
+    assert projector_distance(Q, Qw) < 1e-12
+
+
+def test_hosvd_error_bound():
+    # ||X - Xhat||^2 <= sum_n ||X - X x_n U U^T||^2 (eq. (10))
+    X, _ = noisy_tucker((28, 30, 26), (5, 4, 6), 0.0, seed=16)
+    G, Us, err = rbki_tucker(X, (5, 4, 6), p=5, q=2, seed=17)
+    lhs = (err * fro(X)) ** 2
+    rhs = sum(per_mode_error(X, n, Us[n]) ** 2 for n in range(3))
+    assert lhs <= rhs * (1 + 1e-12)
+
+
+def test_literal_and_orthonormalised_krylov_span_agree_when_well_conditioned():
+    rng = np.random.default_rng(18)
+    I, J = 30, 200
+    s = np.linspace(1.0, 0.6, I)
+    Xn = (np.linalg.qr(rng.standard_normal((I, I)))[0] * s) @ np.linalg.qr(rng.standard_normal((J, I)))[0].T
+    Om = philox.omega(4, 0, J, 4)
+    Ql, K = literal_krylov_basis(Xn, Om, 2)
+    assert np.linalg.cond(K) <= 1e6
+    Qo, _ = rbki_basis(Xn, Om, 2)
+    assert Qo.shape[1] == Ql.shape[1]
+    assert projector_distance(Qo, Ql) <= 1e-9
+
+
+def test_evd_route_equals_svd_route():
+    # Remark 1: eigenvectors of Q^T X X^T Q = left singular vectors of Q^T X
+    X, _ = noisy_tucker((26, 24, 28), (5, 5, 5), 5.0, seed=19)
+    Xn = unfold(X, 2)
+    Q, _ = rbki_basis(Xn, philox.omega(6, 2, Xn.shape[1], 8), 2)
+    Ue, _ = ritz_factor(Xn, Q, 5)
+    Us, _, _ = np.linalg.svd(Q.T @ Xn, full_matrices=False)
+    assert projector_distance(Ue, Q @ Us[:, :5]) <= 1e-10
+
+
+def test_core_orthogonality_identities():
+    X, _ = noisy_tucker((24, 26, 22), (4, 5, 3), 10.0, seed=20)
+    G, Us, err = rbki_tucker(X, (4, 5, 3), p=5, q=2, seed=22)
+    nx = fro(X)
+    # ||X - [[G;U]]||^2 = ||X||^2 - ||G||^2 for orthonormal U and G = X x U^T
+    assert abs((err * nx) ** 2 - (nx ** 2 - fro(G) ** 2)) <= 1e-12 * nx ** 2
+    # perturbing the core adds exactly its squared norm to the squared error
+    dG = np.random.default_rng(0).standard_normal(G.shape) * 1e-3
+    e2 = fro(X - tucker_to_full(G + dG, Us)) ** 2
+    assert abs(e2 - ((err * nx) ** 2 + fro(dG) ** 2)) <= 1e-10 * nx ** 2
+
+
+def test_rbki_is_no_better_than_tsvd_on_noise_free_low_rank_plus_tail():
+    X, _ = noisy_tucker((30, 30, 30), (5, 5, 5), 15.0, seed=23)
+    _, _, e_r = rbki_tucker(X, (5, 5, 5), p=5, q=2, seed=24)
+    _, _, e_t = thosvd(X, (5, 5, 5))
+    assert e_r >= e_t * (1 - 1e-6)
+    assert e_r <= e_t * 1.01
+
+
+def test_plausible_mistakes_are_caught():
+    """Mutations of the method (dropping the Krylov blocks, using X^T X,
+    using the wrong eigen-order) each violate one of the pins above."""
+    X, _ = noisy_tucker((30, 24, 20), (4, 4, 4), -5.0, seed=25)
+    Xn = unfold(X, 0)
+    J = Xn.shape[1]
+    Om = philox.omega(7, 0, J, 9)
+    Q, _ = rbki_basis(Xn, Om, 2)
+    U, lam = ritz_factor(Xn, Q, 4)
+    Ut, _ = leading_left_singular(Xn, 4)
+    good = fro(Xn - U @ (U.T @ Xn))
+    # ascending instead of descending eigen-order gives a far worse factor
+    Bm = Q.T @ Xn
+    w, V = np.linalg.eigh(Bm @ Bm.T)
+    Ubad = Q @ V[:, :4]
+    assert fro(Xn - Ubad @ (Ubad.T @ Xn)) > 1.1 * good
+    # q = 0 (no Krylov blocks) is measurably worse at -5 dB
+    Q0, _ = rbki_basis(Xn, Om, 0)
+    U0, _ = ritz_factor(Xn, Q0, 4)
+    assert fro(Xn - U0 @ (U0.T @ Xn)) > good * (1 + 1e-3)
+    assert abs(good - fro(Xn - Ut @ (Ut.T @ Xn))) < 1e-3 * good

@@ -1,0 +1,72 @@
+"""Pins for the oracle's TR-SVD and Alg. 3: exact recovery of a TT tensor
+(the r_0 = 1 special case of a ring), the orthogonality identity of the
+truncation error, and the Tucker + ring error split."""
+import itertools
+
+import numpy as np
+
+import synth
+from oracle.trsvd import tr_svd, tr_to_full, attach_factors, rbki_htr
+from oracle.rbki import rbki_tucker
+from oracle.tensor import fro, tucker_to_full
+
+
+def test_ring_elementwise_definition():
+    rng = np.random.default_rng(1)
+    cores = [rng.standard_normal((2, 3, 3)), rng.standard_normal((3, 2, 4)), rng.standard_normal((4, 4, 2))]
+    X = tr_to_full(cores)
+    for i, j, k in itertools.product(range(3), range(2), range(4)):
+        v = np.trace(cores[0][:, i, :] @ cores[1][:, j, :] @ cores[2][:, k, :])
+        assert abs(X[i, j, k] - v) < 1e-12
+
+
+def test_exact_tt_tensor_is_recovered():
+    rng = np.random.default_rng(2)
+    ranks = (2, 3, 2, 1)       # r_4 = r_0 = 1: a tensor train
+    dims = (5, 6, 4, 7)
+    r = [1, 2, 3, 2, 1]
+    cores = [rng.standard_normal((r[k], dims[k], r[k + 1])) for k in range(4)]
+    X = tr_to_full(cores)
+    out, discarded = tr_svd(X, ranks)
+    assert fro(X - tr_to_full(out)) <= 1e-12 * fro(X)
+    assert discarded <= 1e-24 * fro(X) ** 2
+    assert [c.shape for c in out] == [(1, 5, 2), (2, 6, 3), (3, 4, 2), (2, 7, 1)]
+
+
+def test_truncation_error_equals_discarded_energy():
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((6, 5, 7, 4))
+    for ranks in [(2, 2, 2, 2), (3, 2, 4, 1), (1, 3, 3, 3)]:
+        cores, discarded = tr_svd(G, ranks)
+        assert abs(fro(G - tr_to_full(cores)) ** 2 - discarded) <= 1e-10 * fro(G) ** 2
+        shapes = [c.shape for c in cores]
+        r = [ranks[-1]] + list(ranks)
+        assert shapes == [(r[k], G.shape[k], r[k + 1]) for k in range(4)]
+
+
+def test_zero_padding_when_ring_ranks_exceed_the_unfolding():
+    # r_0 r_1 = 64 > S_1 = 6: only 6 triplets exist; ranks stay literally 8
+    rng = np.random.default_rng(4)
+    G = rng.standard_normal((6, 6, 6))
+    cores, discarded = tr_svd(G, (8, 8, 8))
+    assert [c.shape for c in cores] == [(8, 6, 8)] * 3
+    assert fro(G - tr_to_full(cores)) <= 1e-12 * fro(G)
+
+
+def test_htr_error_split_and_contraction():
+    X, _ = synth.tensor_ring_data((14, 12, 13, 11), 3, seed=5, var=1.0 / 3)
+    X = synth.add_noise(X, 15.0, np.random.default_rng(6))
+    cores, err, info = rbki_htr(X, (6, 6, 6, 6), p=3, q=2, seed=7, tr_ranks=(3, 3, 3, 3))
+    nx = fro(X)
+    e_tk = info["tucker_error"]
+    # ||X - TR||^2 = ||X - [[G;U]]||^2 + ||G - TR(G_n)||^2  (orthonormal U)
+    gap = fro(info["G"] - tr_to_full(info["core_cores"])) ** 2
+    assert abs((err * nx) ** 2 - ((e_tk * nx) ** 2 + gap)) <= 1e-10 * nx ** 2
+    assert abs(gap - info["discarded"]) <= 1e-10 * nx ** 2
+    _, err2, _ = rbki_htr(X, (6, 6, 6, 6), p=3, q=2, seed=7, tr_ranks=(3, 3, 3, 3), explicit_error=False)
+    assert abs(err2 - err) <= 1e-10
+    # X_n = G_n x_2 U^(n): the TR of the contracted cores equals [[TR(G_n); U]]
+    lifted = tucker_to_full(tr_to_full(info["core_cores"]), info["factors"])
+    assert fro(lifted - tr_to_full(cores)) <= 1e-12 * nx
+    for c, U in zip(cores, info["factors"]):
+        assert c.shape[1] == U.shape[0]
