@@ -1,0 +1,226 @@
+"""Throughput of one rBKI-TK decomposition step on one MI355X.
+
+A step is one full pass of the hot path over the resident input tensor: for
+every mode the sketch and Gram products, the block Krylov basis, the
+projected eigenproblem and the factor; then the core by a chain of mode
+products and the explicit reconstruction error (Alg. 2).
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--precision P]
+
+Prints one JSON line.  `value` is the executed (algorithmic) TFLOP/s of the
+whole step; `roofline` reports the Gram/sketch kernel (the dominant launch)
+against the MFMA peak of its arithmetic type, timed with HIP events on the
+stream it runs on; `cpu_baseline` times the FP64 oracle on a bounded slab of
+the same input.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"bf16": 2500.0, "fp8": 5000.0, "f32": 157.3, "f64": 78.6}
+HBM_GBPS = 8000.0
+
+
+def mode_views(dims):
+    out = []
+    for n in range(len(dims)):
+        A = 1
+        for k in range(n):
+            A *= dims[k]
+        B = 1
+        for k in range(n + 1, len(dims)):
+            B *= dims[k]
+        out.append((A, dims[n], B))
+    return out
+
+
+def step_flops(dims, ranks, p, q):
+    """Executed flops of the Gram route (see DESIGN: flop accounting)."""
+    T = 1
+    for d in dims:
+        T *= d
+    total = 0.0
+    gram = []
+    for (A, I, B), R in zip(mode_views(dims), ranks):
+        J = A * B
+        S = min(R + p, I, J)
+        Sp = S * (q + 1)
+        g = I * (I + 1) * J + 2.0 * I * J * S           # symmetric Gram + sketch
+        gram.append(g)
+        kry = 0.0
+        for j in range(1, q + 1):
+            m = S * j
+            kry += 2.0 * I * I * S + 2 * (2.0 * S * m * I * 2) + 4.0 * S * S * I
+        kry += 2.0 * I * I * S + 2.0 * Sp * Sp * I + 2.0 * R * Sp * I
+        total += g + kry
+    # core chain: first product on the mode with the largest I/R, then ascending
+    first = max(range(len(dims)), key=lambda n: (dims[n] / ranks[n], -n))
+    cur = list(dims)
+    order = [first] + [n for n in range(len(dims)) if n != first]
+    for n in order:
+        size = 1
+        for d in cur:
+            size *= d
+        total += 2.0 * ranks[n] * size
+        cur[n] = ranks[n]
+    # reconstruction chain (modes 1..N-1) and the residual with U^(1)
+    for n in range(1, len(dims)):
+        size = 1
+        for k, d in enumerate(cur):
+            size *= d
+        total += 2.0 * dims[n] * size
+        cur[n] = dims[n]
+    total += 2.0 * ranks[0] * T
+    return total, gram
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("gram.hip", "rbki_mma.h"):
+        with open(os.path.join(ROOT, "paper_2211_14828_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, precision):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(f"gram/{workload}/{precision}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(X, w, slab):
+    """FP64 oracle on a bounded slab X[:, :, :slab] of the same tensor: the
+    mode-0 factor (sketch, q Krylov steps in the streamed product form, Z and
+    its eigenvectors).  Returns TFLOP/s of the oracle's own executed flops."""
+    import numpy as np
+    from oracle.rbki import mode_factor
+    Xs = X[:, :, :slab].double().cpu().numpy()
+    Xs = np.ascontiguousarray(Xs)
+    I = Xs.shape[0]
+    J = Xs.size // I
+    R, p, q = w["ranks"][0], w["p"], w["q"]
+    S = min(R + p, I, J)
+    Sp = min(S * (q + 1), I)
+    t0 = time.perf_counter()
+    mode_factor(Xs, 0, R, p, q, w["seeds"][1])
+    dt = time.perf_counter() - t0
+    # W = X Omega, q streamed steps X (X^T Q), B = Q^T X, Z = B B^T, U = Q V
+    flops = 2.0 * I * J * S + q * 4.0 * I * J * S + 2.0 * Sp * I * J + 2.0 * Sp * Sp * J + 2.0 * I * Sp * R
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"FP64 oracle, mode-0 factor of Alg. 2 (sketch, {q} Krylov steps in the streamed "
+                      f"form, Z, eigenvectors) on the slab X[:, :, :{slab}] ({I}x{Xs.shape[1]}x{slab}) of the "
+                      f"same input; {dt:.2f} s; host cpu_count={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tucker1000_f32")
+    ap.add_argument("--precision", default="mixed_bf16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-slab", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the per-GPU slab of a sharded "
+              "run is the same kernel at a smaller shape); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2211_14828_amd as rb
+    import synth
+
+    rb.load_library(build_if_missing=True)
+    w = synth.WORKLOADS[args.workload]
+    dims, ranks, p, q = tuple(w["dims"]), tuple(w["ranks"]), w["p"], w["q"]
+    print(f"[bench] generating {args.workload} {dims} on the device", file=sys.stderr, flush=True)
+    X = synth.make_device(w)
+    torch.cuda.synchronize()
+    seed = w["seeds"][1]
+
+    def step():
+        return rb.tucker(X, ranks, p=p, q=q, seed=seed, precision=args.precision, out_dtype=torch.float32)
+
+    for i in range(args.warmup):
+        _, _, e = step()
+        print(f"[bench] warmup {i} rel_err {e:.8f}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    rb.profile_reset()
+    rb.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, _, e = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rb.profile_enable(False)
+    ms = dt / args.steps * 1e3
+    flops, gram_flops = step_flops(dims, ranks, p, q)
+    tflops = flops / (dt / args.steps) / 1e12
+    nlaunch, gram_ms = rb.profile_read("gram")
+    avg_gram_ms = gram_ms / max(nlaunch, 1)
+    alg_gram = sum(gram_flops) / len(gram_flops)       # per launch (one launch per mode)
+    achieved = alg_gram / (avg_gram_ms * 1e-3) / 1e12
+    gram_dtype = {"plain": "f32" if w["dtype"] == "float32" else ("f64" if w["dtype"] == "float64" else "bf16"),
+                  "mixed_bf16": "bf16", "mixed_fp8": "fp8"}[args.precision]
+    peak = PEAK_TFLOPS[gram_dtype]
+    stages = {}
+    for k in ("omega", "gram", "jacobi", "ttm", "error", "convert"):
+        n, t = rb.profile_read(k)
+        if n:
+            stages[k] = round(t / args.steps, 4)
+    print(f"[bench] {args.steps} steps, {ms:.3f} ms/step, rel_err {e:.8f}, stage ms/step {stages}",
+          file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a slab", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(X, w, args.cpu_slab)
+    dtype = {"plain": {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}[w["dtype"]],
+             "mixed_bf16": "bf16", "mixed_fp8": "fp8"}[args.precision]
+    rec = {
+        "metric": "rBKI-TK TFLOP/s (executed flops of the Gram route per step)",
+        "value": round(tflops, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dims": list(dims), "ranks": list(ranks), "p": p, "q": q,
+                   "precision": args.precision, "input_dtype": w["dtype"], "rel_err": e,
+                   "stage_ms_per_step": stages},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 5), "traffic": load_traffic(args.workload, args.precision),
+                     "kernel": "gram_sketch_kernel", "avg_launch_ms": round(avg_gram_ms, 5),
+                     "launches": nlaunch, "alg_flops_per_launch": alg_gram},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

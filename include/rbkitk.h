@@ -1,0 +1,161 @@
+/*
+ * rbkitk.h - C ABI of the MI355X (gfx950) implementation of randomized block
+ * Krylov iteration for Tucker decomposition (rBKI-TK) and of the hierarchical
+ * tensor-ring variant (rBKI-TK-TR), after Qiu, Sun, Zhou and Zhao,
+ * "Towards Efficient and Accurate Approximation: Tensor Decomposition Based on
+ * Randomized Block Krylov Iteration", arXiv 2211.14828.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Tensor, factor, core and workspace pointers are DEVICE pointers unless a
+ *   parameter says "host".  Tensors are row-major (last index fastest).
+ *   The caller owns every buffer; the library never allocates or frees caller
+ *   memory, and never allocates device memory in these calls (all scratch
+ *   space comes from the caller's workspace).
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Work is enqueued asynchronously on it; an entry point that returns a host
+ *   value (rel_err, widths) synchronises that stream before returning.
+ * - All arguments are validated before anything is enqueued: on a status
+ *   other than RBKI_OK nothing was launched, except RBKI_E_HIP (a launch or
+ *   runtime error, outputs undefined) and RBKI_E_NOCONV (results written,
+ *   but an eigen-solver hit its sweep limit).  rbki_last_error() returns a
+ *   thread-local message for the last failing call of the calling thread.
+ * - Mode indices are 0-based; the Philox "mode" word of the sketch stream is
+ *   the 0-based mode index.
+ * - Thread safety: calls on different streams with disjoint buffers may run
+ *   concurrently.
+ */
+#ifndef RBKITK_H
+#define RBKITK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RBKI_OK = 0,
+  RBKI_E_INVALID = 1,     /* bad argument or workspace too small; nothing launched */
+  RBKI_E_NOMEM = 2,       /* reserved */
+  RBKI_E_HIP = 3,         /* HIP runtime / launch error */
+  RBKI_E_NOCONV = 4,      /* Jacobi eigen-solver reached its sweep limit */
+  RBKI_E_UNSUPPORTED = 5  /* valid request this build does not support */
+} rbki_status;
+
+typedef enum { RBKI_F64 = 0, RBKI_F32 = 1, RBKI_BF16 = 2 } rbki_dtype;
+
+/* Arithmetic of the products that read the tensor (sketch, Gram/Krylov
+ * products, mode products, error).  Orthonormalisation, the projected
+ * eigenproblem and all norms are float64 in every form.
+ *   PLAIN      : the tensor's own type (fp64 MFMA for F64, fp32 MFMA for F32,
+ *                bf16 MFMA for BF16), fp32 or fp64 accumulation.
+ *   MIXED_BF16 : a bf16 copy of X feeds bf16 MFMA with fp32 accumulation.
+ *   MIXED_FP8  : an e4m3 copy of X with power-of-two scales per 32^N block
+ *                feeds the Gram and sketch products (block-scaled fp8 MFMA,
+ *                fp32 accumulation); the mode products and the error use a
+ *                bf16 copy. */
+typedef enum { RBKI_PLAIN = 0, RBKI_MIXED_BF16 = 1, RBKI_MIXED_FP8 = 2 } rbki_precision;
+
+/* Problem statement of Alg. 2: tensor order N, sizes I_n, multilinear rank
+ * R_n, sketch sizes S_n = min(R_n + oversample, I_n, J_n) (Sec. 4.1 uses
+ * oversample = 5), and the number of Krylov steps q ("power"; Alg. 1 gives it
+ * only as Theta(log d / sqrt(eps)), Sec. 3.1 uses 2).  The Krylov basis of
+ * mode n has width S'_n = min(S_n (q+1), I_n). */
+typedef struct {
+  int order;              /* N >= 2 (N = 2 is the matrix rBKI-SVD case) */
+  const int64_t *dims;    /* host[N], I_n >= 1 */
+  const int64_t *ranks;   /* host[N], 1 <= R_n <= min(I_n, J_n) */
+  int oversample;         /* p >= 0 */
+  int power;              /* q >= 0 */
+  uint64_t seed;          /* key of the Philox sketch stream */
+  int precision;          /* rbki_precision */
+} rbki_params;
+
+/* Library version string (static storage). */
+const char *rbki_version(void);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char *rbki_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Sketch stream (Alg. 1, step 1: the Gaussian sketching matrix Omega^(n)).
+ * Writes Omega^(n)T, i.e. S rows of J values, row s holding Omega^(n)[0..J-1, s]
+ * = the stream values at linear indices s*J .. s*J+J-1 of (seed, mode, tag 0),
+ * as `dtype` (F64: Box-Muller in double; F32 and BF16: in float, rounded).
+ * out: device, S*J elements.
+ */
+rbki_status rbki_omega(uint64_t seed, int mode, int64_t J, int64_t S, int dtype, void *out,
+                       void *stream);
+
+/* Raw Philox4x32-10 blocks (Salmon et al., SC'11) for `count` counters:
+ * ctr (device, count x 4 uint32) -> out (device, count x 4 uint32) under key
+ * (seed mod 2^32, seed >> 32).  For verifying the generator bit for bit. */
+rbki_status rbki_philox(const uint32_t *ctr, int64_t count, uint64_t seed, uint32_t *out, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Alg. 1 (tensor sketching via rBKI) for one mode: the orthonormal basis Q of
+ * the block Krylov space span[W, (X_(n)X_(n)^T) W, ..., (X_(n)X_(n)^T)^q W],
+ * W = X_(n) Omega^(n), built with orthonormalisation between steps.
+ *   X      : device tensor, row-major, dims prm->dims, type xtype.
+ *   mode   : n in [0, N).
+ *   Qt     : device float64, S'_n x I_n row-major (row k = basis column k).
+ *            Rows beyond the numerical rank of the Krylov space are zero.
+ *   width  : host, receives the number of nonzero basis vectors (synchronises).
+ * The unfolding is never formed: X is read through the [A_n, I_n, B_n] view,
+ * X_(n)[i, a*B_n + b] = X[a, i, b] (Table 1).
+ */
+size_t rbki_basis_workspace(const rbki_params *prm, int xtype, int mode);
+rbki_status rbki_basis(const void *X, int xtype, const rbki_params *prm, int mode, double *Qt,
+                       int64_t *width, void *workspace, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Alg. 2 (rBKI-TK).  For every mode independently: Q^(n) by Alg. 1,
+ * Z = Q^T X_(n) X_(n)^T Q, its eigenvectors in descending order (Remark 1),
+ * U^(n) = Q Utilde(:, 1:R_n); then G = X x_1 U^(1)T ... x_N U^(N)T.
+ *   core     : device, R_1 x ... x R_N row-major, out_type (F64 or F32).
+ *   factors  : host array of N device pointers, factor n is I_n x R_n
+ *              row-major, out_type.  Columns beyond the numerical rank of the
+ *              Krylov space are zero.
+ *   rel_err  : host, nullable.  ||X - [[G; U]]||_F / ||X||_F from the explicit
+ *              residual, float64 accumulation (synchronises).
+ */
+size_t rbki_tucker_workspace(const rbki_params *prm, int xtype);
+rbki_status rbki_tucker(const void *X, int xtype, const rbki_params *prm, void *core,
+                        void *const *factors, int out_type, void *workspace, size_t ws_bytes,
+                        double *rel_err, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Alg. 3 (rBKI-TK-TR) with the TR-SVD branch: rBKI-TK with the Tucker ranks
+ * of prm (the compress sizes), TR-SVD of the core with TR ranks
+ * (r_1, ..., r_N) and closing rank r_0 = r_N (Def. 2), then X_n = G_n x_2 U^(n).
+ *   tr_ranks : host[N].
+ *   tr_cores : host array of N device pointers, core n is r_{n-1} x I_n x r_n
+ *              row-major, out_type.  When r_0 r_1 exceeds the rank of the
+ *              first unfolding the missing directions are zero.
+ *   rel_err  : host, nullable: ||X - TR(X_1..X_N)||_F / ||X||_F, from
+ *              ||X - [[G;U]]||^2 + ||G - TR(G_1..G_N)||^2 (orthonormal U),
+ *              both terms computed explicitly in float64 (synchronises).
+ */
+size_t rbki_htr_workspace(const rbki_params *prm, int xtype, const int64_t *tr_ranks);
+rbki_status rbki_htr(const void *X, int xtype, const rbki_params *prm, const int64_t *tr_ranks,
+                     void *const *tr_cores, int out_type, void *workspace, size_t ws_bytes,
+                     double *rel_err, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing.  When enabled, the library records HIP events around every
+ * launch of the named kernels on the stream the kernel is launched on, and
+ * accumulates their durations at the next synchronising call or at
+ * rbki_profile_read.  Names: "gram" (Gram + sketch products), "ttm" (first
+ * mode product of the core), "error" (residual reduction), "jacobi",
+ * "convert", "omega".
+ */
+void rbki_profile_enable(int on);
+void rbki_profile_reset(void);
+rbki_status rbki_profile_read(const char *kernel, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBKITK_H */

@@ -30,6 +30,10 @@ design notes of the repository):
   in descending order (svd of a symmetric PSD matrix; Remark 1); the factor
   is U^(n) = Q Utilde(:, 1:R_n) (Alg. 2, steps 4-5).  If the basis has fewer
   than R_n columns, the missing factor columns are zero.
+* Singular vectors have no sign in the paper.  Each factor column is given
+  the sign that makes its largest-magnitude entry positive (lowest index on
+  ties), so the core, and the TR-SVD of Alg. 3 that depends on its slice
+  signs, are fixed by the data.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -116,6 +120,18 @@ def power_basis(Xn, Omega, q, tau=TAU):
     return Q
 
 
+def canonical_signs(U):
+    """Flip each column so that its largest-magnitude entry (lowest index on
+    ties) is positive; zero columns are left alone."""
+    U = np.array(U, dtype=np.float64, copy=True)
+    if U.size == 0:
+        return U
+    idx = np.argmax(np.abs(U), axis=0)
+    sgn = np.sign(U[idx, np.arange(U.shape[1])])
+    sgn[sgn == 0] = 1.0
+    return U * sgn
+
+
 def ritz_factor(Xn, Q, R):
     """Alg. 2, steps 3-5: Z = Q^T Xn Xn^T Q, descending eigendecomposition,
     U = Q Utilde(:, 1:R).  Returns U (I x R) and the eigenvalues of Z."""
@@ -130,7 +146,7 @@ def ritz_factor(Xn, Q, R):
     lam, V = lam[order], V[:, order]
     k = min(R, Q.shape[1])
     U[:, :k] = Q @ V[:, :k]                           # step 5
-    return U, lam
+    return canonical_signs(U), lam
 
 
 def mode_factor(X, n, R, p, q, seed, tau=TAU, return_info=False):

@@ -24,18 +24,31 @@ X_n = G_n x_2 U^(n) in R^{R_{n-1} x I_n x R_n}.
 
 Because each step's left factor has orthonormal columns, the squared error
 ||G - TR(cores)||_F^2 equals the sum of the squared discarded singular values
-over all steps; and because the Tucker factors are orthonormal,
-||X - TR(X_1..X_N)||^2 = ||X - [[G; U]]||^2 + ||G - TR(G_1..G_N)||^2.
+over all steps when r_0 r_1 does not exceed the rank of the first unfolding
+(with zero padding it is at most that sum); and because the Tucker factors
+are orthonormal, ||X - TR(X_1..X_N)||^2 = ||X - [[G; U]]||^2 +
+||G - TR(G_1..G_N)||^2.
+
+Sign reading.  With r_0 > 1 the first step files singular vector c under the
+index pair (a0, a1); negating one singular vector negates one (a1, a0) block
+of the next unfolding, which is not an orthogonal change of that matrix and
+alters the truncation.  TR-SVD is therefore fixed here by giving every left
+singular vector the sign that makes its largest-magnitude entry positive
+(the same rule as the Tucker factors).
 """
 import numpy as np
 
-from .rbki import rbki_tucker
+from .rbki import rbki_tucker, canonical_signs
 from .tensor import fro
 
 
 def _truncated_svd_padded(M, r):
-    """Leading min(r, rank) singular triplets of M, zero-padded to r."""
+    """Leading min(r, rank) singular triplets of M, zero-padded to r, with
+    canonical signs (largest-magnitude entry of each left vector positive)."""
     U, s, Vt = np.linalg.svd(M, full_matrices=False)
+    Uc = canonical_signs(U)
+    flip = np.where(np.sum(Uc * U, axis=0) < 0, -1.0, 1.0)
+    U, Vt = Uc, Vt * flip[:, None]
     k = min(r, s.size)
     Ul = np.zeros((M.shape[0], r))
     Rl = np.zeros((r, M.shape[1]))

@@ -1,0 +1,282 @@
+"""rBKI-TK / rBKI-TK-TR on MI355X: Python binding of the C-ABI library.
+
+Argument marshalling only: every step of the decomposition runs in the HIP
+kernels of ``librbkitk.so``.  PyTorch provides device memory (inputs, outputs
+and the workspace) and the current HIP stream.  There is no CPU fallback: if
+the library is missing or no GPU is visible, the calls raise.
+
+    core, factors, rel_err = tucker(X, ranks, p=5, q=2, seed=0)
+    cores, rel_err = htr(X, tucker_ranks, tr_ranks, p=6, q=2, seed=0)
+    Qt, width = basis(X, mode, ranks, p, q, seed)          # Alg. 1, one mode
+"""
+import ctypes
+import os
+import threading
+
+__all__ = ["tucker", "htr", "basis", "omega", "philox", "workspace_bytes", "profile_enable",
+           "profile_reset", "profile_read", "library_path", "load_library", "RbkiError",
+           "PLAIN", "MIXED_BF16", "MIXED_FP8", "SYMBOLS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "librbkitk.so")
+
+PLAIN, MIXED_BF16, MIXED_FP8 = 0, 1, 2
+_PRECISIONS = {"plain": PLAIN, "mixed_bf16": MIXED_BF16, "bf16": MIXED_BF16, "mixed_fp8": MIXED_FP8,
+               "fp8": MIXED_FP8}
+_F64, _F32, _BF16 = 0, 1, 2
+_STATUS = {0: "RBKI_OK", 1: "RBKI_E_INVALID", 2: "RBKI_E_NOMEM", 3: "RBKI_E_HIP", 4: "RBKI_E_NOCONV",
+           5: "RBKI_E_UNSUPPORTED"}
+
+# Every symbol the header declares.
+SYMBOLS = ("rbki_version", "rbki_last_error", "rbki_omega", "rbki_philox", "rbki_basis_workspace",
+           "rbki_basis", "rbki_tucker_workspace", "rbki_tucker", "rbki_htr_workspace", "rbki_htr",
+           "rbki_profile_enable", "rbki_profile_reset", "rbki_profile_read")
+
+
+class RbkiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("dims", ctypes.POINTER(ctypes.c_int64)),
+                ("ranks", ctypes.POINTER(ctypes.c_int64)), ("oversample", ctypes.c_int),
+                ("power", ctypes.c_int), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def load_library(build_if_missing=True):
+    """Load librbkitk.so (building it first only if it does not exist)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB_PATH):
+            if not build_if_missing:
+                raise ImportError(f"{_LIB_PATH} is not built")
+            from . import build as _build
+            _build.build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER
+        vp, i64, u64, ci, sz, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
+        sig = {
+            "rbki_version": (ctypes.c_char_p, []),
+            "rbki_last_error": (ctypes.c_char_p, []),
+            "rbki_omega": (ci, [u64, ci, i64, i64, ci, vp, vp]),
+            "rbki_philox": (ci, [vp, i64, u64, vp, vp]),
+            "rbki_basis_workspace": (sz, [P(_Params), ci, ci]),
+            "rbki_basis": (ci, [vp, ci, P(_Params), ci, vp, P(i64), vp, sz, vp]),
+            "rbki_tucker_workspace": (sz, [P(_Params), ci]),
+            "rbki_tucker": (ci, [vp, ci, P(_Params), vp, P(vp), ci, vp, sz, P(dbl), vp]),
+            "rbki_htr_workspace": (sz, [P(_Params), ci, P(i64)]),
+            "rbki_htr": (ci, [vp, ci, P(_Params), P(i64), P(vp), ci, vp, sz, P(dbl), vp]),
+            "rbki_profile_enable": (None, [ci]),
+            "rbki_profile_reset": (None, []),
+            "rbki_profile_read": (ci, [ctypes.c_char_p, P(i64), P(dbl)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+        return lib
+
+
+def _check(status):
+    if status != 0:
+        raise RbkiError(status, load_library().rbki_last_error().decode())
+
+
+# ------------------------------------------------------------------ helpers
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("rbkitk needs a GPU (HIP device); none is visible")
+    return torch
+
+
+def _dtype_code(torch, dt):
+    if dt == torch.float64:
+        return _F64
+    if dt == torch.float32:
+        return _F32
+    if dt == torch.bfloat16:
+        return _BF16
+    raise TypeError(f"unsupported tensor dtype {dt}")
+
+
+def _params(dims, ranks, p, q, seed, precision):
+    n = len(dims)
+    if len(ranks) != n:
+        raise ValueError("ranks must have one entry per mode")
+    d = (ctypes.c_int64 * n)(*[int(v) for v in dims])
+    r = (ctypes.c_int64 * n)(*[int(v) for v in ranks])
+    prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    prm = _Params(n, ctypes.cast(d, ctypes.POINTER(ctypes.c_int64)), ctypes.cast(r, ctypes.POINTER(ctypes.c_int64)),
+                  int(p), int(q), int(seed) & 0xFFFFFFFFFFFFFFFF, prec)
+    prm._keep = (d, r)
+    return prm
+
+
+def _stream(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+_ws_cache = {}
+
+
+def _workspace(torch, device, nbytes):
+    """A device buffer of at least nbytes, reused across calls on the device."""
+    key = str(device)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        _ws_cache.pop(key, None)
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def _as_input(torch, X):
+    if not X.is_cuda:
+        raise ValueError("X must be a GPU tensor")
+    return X.contiguous()
+
+
+# ------------------------------------------------------------------ public API
+
+def workspace_bytes(dims, ranks, p, q, dtype, precision="plain", tr_ranks=None):
+    lib = load_library()
+    import torch
+    prm = _params(dims, ranks, p, q, 0, precision)
+    code = _dtype_code(torch, dtype)
+    if tr_ranks is not None:
+        tr = (ctypes.c_int64 * len(tr_ranks))(*tr_ranks)
+        return lib.rbki_htr_workspace(ctypes.byref(prm), code, tr)
+    return lib.rbki_tucker_workspace(ctypes.byref(prm), code)
+
+
+def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_err=True, stream=None,
+           workspace=None):
+    """rBKI-TK (Alg. 2).  Returns (core, [U^(1), ..., U^(N)], rel_err or None)."""
+    torch = _torch()
+    lib = load_library()
+    X = _as_input(torch, X)
+    code = _dtype_code(torch, X.dtype)
+    if out_dtype is None:
+        out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
+    ocode = _dtype_code(torch, out_dtype)
+    prm = _params(X.shape, ranks, p, q, seed, precision)
+    need = lib.rbki_tucker_workspace(ctypes.byref(prm), code)
+    if need == 0:
+        _check(lib.rbki_tucker(None, code, ctypes.byref(prm), None, None, ocode, None, 0, None, None))
+    ws = workspace if workspace is not None else _workspace(torch, X.device, need)
+    core = torch.empty(tuple(int(r) for r in ranks), dtype=out_dtype, device=X.device)
+    factors = [torch.empty((int(I), int(R)), dtype=out_dtype, device=X.device) for I, R in zip(X.shape, ranks)]
+    fptr = (ctypes.c_void_p * len(factors))(*[f.data_ptr() for f in factors])
+    err = ctypes.c_double(0.0)
+    _check(lib.rbki_tucker(ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm), ctypes.c_void_p(core.data_ptr()),
+                           fptr, ocode, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                           ctypes.byref(err) if rel_err else None, _stream(torch, stream)))
+    return core, factors, (err.value if rel_err else None)
+
+
+def htr(X, tucker_ranks, tr_ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_err=True,
+        stream=None):
+    """rBKI-TK-TR (Alg. 3, TR-SVD branch).  Returns ([X_1, ..., X_N], rel_err or None)."""
+    torch = _torch()
+    lib = load_library()
+    X = _as_input(torch, X)
+    code = _dtype_code(torch, X.dtype)
+    if out_dtype is None:
+        out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
+    ocode = _dtype_code(torch, out_dtype)
+    N = X.dim()
+    prm = _params(X.shape, tucker_ranks, p, q, seed, precision)
+    tr = (ctypes.c_int64 * N)(*[int(v) for v in tr_ranks])
+    need = lib.rbki_htr_workspace(ctypes.byref(prm), code, tr)
+    if need == 0:
+        _check(lib.rbki_htr(None, code, ctypes.byref(prm), tr, None, ocode, None, 0, None, None))
+    ws = _workspace(torch, X.device, need)
+    r = [int(tr_ranks[-1])] + [int(v) for v in tr_ranks]
+    cores = [torch.empty((r[n], int(X.shape[n]), r[n + 1]), dtype=out_dtype, device=X.device) for n in range(N)]
+    cptr = (ctypes.c_void_p * N)(*[c.data_ptr() for c in cores])
+    err = ctypes.c_double(0.0)
+    _check(lib.rbki_htr(ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm), tr, cptr, ocode,
+                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(err) if rel_err else None,
+                        _stream(torch, stream)))
+    return cores, (err.value if rel_err else None)
+
+
+def basis(X, mode, ranks, p=5, q=2, seed=0, precision="plain", stream=None):
+    """Alg. 1 for one mode.  Returns (Qt as a float64 (S' x I_n) tensor whose
+    first `width` rows are the orthonormal basis, width)."""
+    torch = _torch()
+    lib = load_library()
+    X = _as_input(torch, X)
+    code = _dtype_code(torch, X.dtype)
+    prm = _params(X.shape, ranks, p, q, seed, precision)
+    need = lib.rbki_basis_workspace(ctypes.byref(prm), code, int(mode))
+    if need == 0:
+        _check(lib.rbki_basis(None, code, ctypes.byref(prm), int(mode), None, None, None, 0, None))
+    ws = _workspace(torch, X.device, need)
+    I = int(X.shape[mode])
+    J = X.numel() // I
+    S = min(int(ranks[mode]) + int(p), I, J)
+    Sp = min(S * (int(q) + 1), I)
+    Qt = torch.empty((Sp, I), dtype=torch.float64, device=X.device)
+    width = ctypes.c_int64(0)
+    _check(lib.rbki_basis(ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm), int(mode),
+                          ctypes.c_void_p(Qt.data_ptr()), ctypes.byref(width), ctypes.c_void_p(ws.data_ptr()),
+                          ws.numel(), _stream(torch, stream)))
+    return Qt, width.value
+
+
+def omega(seed, mode, J, S, dtype=None, device="cuda", stream=None):
+    """Omega^(n)T (S x J) of the sketch stream, on the device."""
+    torch = _torch()
+    lib = load_library()
+    dtype = dtype or torch.float64
+    out = torch.empty((int(S), int(J)), dtype=dtype, device=device)
+    _check(lib.rbki_omega(int(seed), int(mode), int(J), int(S), _dtype_code(torch, dtype),
+                          ctypes.c_void_p(out.data_ptr()), _stream(torch, stream)))
+    return out
+
+
+def philox(counters, seed, stream=None):
+    """Raw Philox4x32-10 blocks for counters (count x 4, int32 or uint32 bit
+    patterns on the device); returns count x 4 int32 bit patterns."""
+    torch = _torch()
+    lib = load_library()
+    c = counters.contiguous()
+    if c.dtype not in (torch.int32, torch.uint32) or c.dim() != 2 or c.shape[1] != 4:
+        raise ValueError("counters must be a (count, 4) 32-bit integer tensor")
+    out = torch.empty_like(c)
+    _check(lib.rbki_philox(ctypes.c_void_p(c.data_ptr()), int(c.shape[0]), int(seed), ctypes.c_void_p(out.data_ptr()),
+                           _stream(torch, stream)))
+    return out
+
+
+def profile_enable(on=True):
+    load_library().rbki_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    load_library().rbki_profile_reset()
+
+
+def profile_read(kernel):
+    lib = load_library()
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(lib.rbki_profile_read(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value

@@ -1,0 +1,638 @@
+// C-ABI entry points (include/rbkitk.h) and the host-side driver of the
+// hot path: per-mode rBKI (Alg. 1 and Alg. 2, steps 2-5), the core by a
+// chain of mode products (Alg. 2, step 6), the explicit reconstruction error,
+// and the TR-SVD branch of Alg. 3.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rbki_kernels.h"
+
+namespace rbki {
+hipError_t tr_svd_device(const void* Gcore, int core_elem, int N, const int64_t* S, const int64_t* r,
+                         double* const* cores, double* work, size_t work_bytes, int* info, double* discarded,
+                         hipStream_t st);
+size_t tr_svd_work_bytes(int N, const int64_t* S, const int64_t* r);
+hipError_t tr_attach(const double* core, const double* Ut, int64_t ra, int64_t Sn, int64_t rb, int64_t I,
+                     void* out, int out_elem, hipStream_t st);
+hipError_t tr_gap2(const void* Gcore, int core_elem, int N, const int64_t* S, const int64_t* r,
+                   double* const* cores, double* work, double* out, hipStream_t st);
+size_t tr_gap2_work_bytes(int N, const int64_t* S, const int64_t* r);
+}  // namespace rbki
+
+using namespace rbki;
+
+namespace {
+
+thread_local std::string g_err;
+
+rbki_status fail(rbki_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                            \
+  do {                                                                                          \
+    hipError_t e__ = (expr);                                                                    \
+    if (e__ != hipSuccess) return fail(RBKI_E_HIP, "%s: %s", #expr, hipGetErrorString(e__));    \
+  } while (0)
+
+// ------------------------------------------------------------------ timing
+struct ProfRec {
+  int64_t launches = 0;
+  double ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::map<std::string, ProfRec> g_prof;
+
+struct ProfScope {
+  hipEvent_t a = nullptr, b = nullptr;
+  const char* name;
+  hipStream_t s;
+  ProfScope(const char* n, hipStream_t st) : name(n), s(st) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+    (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof[name].pending.push_back({a, b});
+  }
+};
+
+void prof_drain() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto& kv : g_prof) {
+    for (auto& ev : kv.second.pending) {
+      (void)hipEventSynchronize(ev.second);
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) {
+        kv.second.ms += ms;
+        kv.second.launches += 1;
+      }
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+    kv.second.pending.clear();
+  }
+}
+
+int cu_count() {
+  static int cached = 0;
+  if (cached) return cached;
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+    cached = n;
+  else
+    cached = 256;
+  return cached;
+}
+
+// ------------------------------------------------------------------ planning
+struct ModeGeom {
+  int64_t A, I, B, J, R, S, Sp;   // Sp = S * (q + 1): rows of the Krylov basis buffer
+};
+
+struct Plan {
+  int N = 0;
+  int64_t dims[8], ranks[8];
+  int p = 0, q = 0;
+  uint64_t seed = 0;
+  int prec = 0;
+  int xelem = 0;     // storage of X
+  int gelem = 0;     // Gram / sketch product
+  int telem = 0;     // first mode product (reads X)
+  int celem = 0;     // later mode products, reconstruction and error
+  bool need_xconv = false;
+  int64_t T = 1;
+  ModeGeom m[8];
+  int first_mode = 0;
+  int64_t maxI = 0, maxS = 0, maxSp = 0, maxRI = 0, maxSJ = 0;
+  size_t partial_bytes = 0;
+  int64_t chain_elems = 0;   // largest intermediate of the core / reconstruction chains
+};
+
+int dtype_elem(int dt) { return dt == RBKI_F64 ? E_F64 : dt == RBKI_F32 ? E_F32 : E_BF16; }
+
+rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
+  if (!prm) return fail(RBKI_E_INVALID, "params is NULL");
+  if (prm->order < 2 || prm->order > 8) return fail(RBKI_E_INVALID, "order %d outside [2, 8]", prm->order);
+  if (!prm->dims || !prm->ranks) return fail(RBKI_E_INVALID, "dims/ranks is NULL");
+  if (xtype != RBKI_F64 && xtype != RBKI_F32 && xtype != RBKI_BF16)
+    return fail(RBKI_E_INVALID, "unknown tensor dtype %d", xtype);
+  if (prm->oversample < 0 || prm->power < 0 || prm->power > 64)
+    return fail(RBKI_E_INVALID, "oversample %d / power %d out of range", prm->oversample, prm->power);
+  if (prm->precision != RBKI_PLAIN && prm->precision != RBKI_MIXED_BF16 && prm->precision != RBKI_MIXED_FP8)
+    return fail(RBKI_E_INVALID, "unknown precision %d", prm->precision);
+  if (prm->precision == RBKI_MIXED_FP8) return fail(RBKI_E_UNSUPPORTED, "fp8 form not built yet");
+  P.N = prm->order;
+  P.p = prm->oversample;
+  P.q = prm->power;
+  P.seed = prm->seed;
+  P.prec = prm->precision;
+  P.T = 1;
+  for (int n = 0; n < P.N; ++n) {
+    P.dims[n] = prm->dims[n];
+    P.ranks[n] = prm->ranks[n];
+    if (P.dims[n] < 1) return fail(RBKI_E_INVALID, "dims[%d] = %lld < 1", n, (long long)P.dims[n]);
+    P.T *= P.dims[n];
+  }
+  P.xelem = dtype_elem(xtype);
+  if (P.xelem == E_F64 && P.prec == RBKI_PLAIN) {
+    P.gelem = P.telem = P.celem = E_F64;
+  } else if (P.prec == RBKI_PLAIN) {
+    P.gelem = P.telem = P.xelem;      // F32 or BF16
+    P.celem = E_F32;
+  } else {
+    P.gelem = P.telem = E_BF16;
+    P.celem = E_F32;
+    P.need_xconv = P.xelem != E_BF16;
+  }
+  double best = -1.0;
+  for (int n = 0; n < P.N; ++n) {
+    ModeGeom& g = P.m[n];
+    g.A = 1;
+    for (int k = 0; k < n; ++k) g.A *= P.dims[k];
+    g.I = P.dims[n];
+    g.B = 1;
+    for (int k = n + 1; k < P.N; ++k) g.B *= P.dims[k];
+    g.J = g.A * g.B;
+    g.R = P.ranks[n];
+    if (g.R < 1 || g.R > g.I || g.R > g.J)
+      return fail(RBKI_E_INVALID, "ranks[%d] = %lld outside [1, min(I_n, J_n)]", n, (long long)g.R);
+    g.S = std::min<int64_t>(std::min<int64_t>(g.R + P.p, g.I), g.J);   // Sec. 2.3, Sec. 4.1
+    g.Sp = g.S * (P.q + 1);
+    if (g.Sp > 1200) return fail(RBKI_E_UNSUPPORTED, "Krylov width %lld > 1200 (mode %d)", (long long)g.Sp, n);
+    const double ratio = (double)g.I / (double)g.R;
+    if (ratio > best) { best = ratio; P.first_mode = n; }
+    P.maxI = std::max(P.maxI, g.I);
+    P.maxS = std::max(P.maxS, g.S);
+    P.maxSp = std::max(P.maxSp, g.Sp);
+    P.maxRI = std::max(P.maxRI, g.R * g.I);
+    P.maxSJ = std::max(P.maxSJ, g.S * g.J);
+    GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)g.S, cu_count());
+    P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(ga, P.gelem));
+  }
+  // chain sizes: core chain starting with first_mode, then ascending; the
+  // reconstruction chain expands modes 1..N-1 from the core.
+  int64_t cur[8];
+  for (int n = 0; n < P.N; ++n) cur[n] = P.dims[n];
+  int64_t mx = 0;
+  auto prod = [&](const int64_t* d) { int64_t t = 1; for (int k = 0; k < P.N; ++k) t *= d[k]; return t; };
+  cur[P.first_mode] = P.ranks[P.first_mode];
+  mx = std::max(mx, prod(cur));
+  for (int n = 0; n < P.N; ++n)
+    if (n != P.first_mode) { cur[n] = P.ranks[n]; mx = std::max(mx, prod(cur)); }
+  for (int n = 1; n < P.N; ++n) { cur[n] = P.dims[n]; mx = std::max(mx, prod(cur)); }
+  P.chain_elems = mx;
+  return RBKI_OK;
+}
+
+struct Arena {
+  char* base;
+  size_t off = 0, cap;
+  bool sizing;
+  Arena(void* b, size_t c) : base((char*)b), cap(c), sizing(b == nullptr) {}
+  void* take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void* p = sizing ? nullptr : base + off;
+    off += bytes;
+    return p;
+  }
+};
+
+struct Buffers {
+  void* xconv = nullptr;
+  void* omegaT = nullptr;
+  void* partial = nullptr;
+  double* C = nullptr;
+  double* Qt = nullptr;
+  double* CQt = nullptr;
+  double* Yt = nullptr;
+  double* Pm = nullptr;
+  double* G = nullptr;
+  double* L = nullptr;
+  int* flags = nullptr;
+  double* ref2 = nullptr;
+  double* Z = nullptr;
+  double* lam = nullptr;
+  double* Vt = nullptr;
+  void* jwork = nullptr;
+  int* info = nullptr;
+  double* Ut64[8] = {};
+  void* Uop = nullptr;     // one factor in a product element type
+  void* chainA = nullptr;
+  void* chainB = nullptr;
+  void* gkeep = nullptr;   // the core, kept apart from the reconstruction chain
+  void* rpartial = nullptr;
+  double* sums = nullptr;
+};
+
+void carve(const Plan& P, Arena& ar, Buffers& b) {
+  const int es_g = elem_size(P.gelem);
+  if (P.need_xconv) b.xconv = ar.take((size_t)P.T * elem_size(P.telem));
+  b.omegaT = ar.take((size_t)P.maxSJ * es_g);
+  b.partial = ar.take(P.partial_bytes);
+  b.C = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
+  b.Qt = (double*)ar.take((size_t)P.maxSp * P.maxI * 8);
+  b.CQt = (double*)ar.take((size_t)P.maxSp * P.maxI * 8);
+  b.Yt = (double*)ar.take((size_t)P.maxS * P.maxI * 8);
+  b.Pm = (double*)ar.take((size_t)P.maxS * P.maxSp * 8);
+  b.G = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
+  b.L = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
+  b.flags = (int*)ar.take((size_t)P.maxSp * 4);
+  b.ref2 = (double*)ar.take((size_t)P.maxS * 8);
+  b.Z = (double*)ar.take((size_t)P.maxSp * P.maxSp * 8);
+  b.lam = (double*)ar.take((size_t)P.maxSp * 8);
+  b.Vt = (double*)ar.take((size_t)P.maxSp * P.maxSp * 8);
+  b.jwork = ar.take(jacobi_work_bytes(P.maxSp));
+  b.info = (int*)ar.take(64);
+  for (int n = 0; n < P.N; ++n) b.Ut64[n] = (double*)ar.take((size_t)P.m[n].R * P.m[n].I * 8);
+  b.Uop = ar.take((size_t)P.maxRI * 8);
+  const size_t ce = P.celem == E_F64 ? 8 : 4;
+  b.chainA = ar.take((size_t)P.chain_elems * ce);
+  b.chainB = ar.take((size_t)P.chain_elems * ce);
+  int64_t ncore = 1;
+  for (int n = 0; n < P.N; ++n) ncore *= P.ranks[n];
+  b.gkeep = ar.take((size_t)ncore * ce);
+  b.rpartial = ar.take(residual_work_bytes(P.dims[0], P.T / P.dims[0]));
+  b.sums = (double*)ar.take(64);
+}
+
+size_t plan_bytes(const Plan& P) {
+  Arena ar(nullptr, 0);
+  Buffers b;
+  carve(P, ar, b);
+  return ar.off + 256;
+}
+
+// ------------------------------------------------------------------ one mode
+// Alg. 1 + Alg. 2 steps 3-5 for mode n.  Leaves the basis in b.Qt (Sp rows),
+// C Q in b.CQt, and (if with_factor) U^(n)T in b.Ut64[n].
+constexpr double TAU_REL = 1e-12;   // pivot vs its own column: direction already spanned
+constexpr double TAU_ABS = 1e-10;   // pivot vs the block before projection (matches the oracle)
+
+rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, bool with_factor,
+                     hipStream_t st) {
+  const ModeGeom& g = P.m[n];
+  const int64_t I = g.I, S = g.S, Sp = g.Sp;
+  {
+    ProfScope ps("omega", st);
+    HIPCHK(launch_omega(P.gelem, P.seed, n, S * g.J, b.omegaT, st));
+  }
+  GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)S, cu_count());
+  ga.X = xsrc;
+  ga.omegaT = b.omegaT;
+  ga.partial = b.partial;
+  {
+    ProfScope ps("gram", st);
+    HIPCHK(launch_gram_main(P.gelem, ga, st));
+  }
+  // C -> b.C (I x I), W^T -> b.Yt (S x I)
+  HIPCHK(launch_gram_reduce(P.gelem, ga, b.C, b.Yt, st));
+
+  // block 0: Q_0 = orth(W)
+  HIPCHK(row_norms2(b.Yt, S, I, b.ref2, st));
+  HIPCHK(chol_orth(b.Yt, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st));
+  HIPCHK(chol_orth(b.Yt, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
+  HIPCHK(copy_rows_f64(b.Qt, I, b.Yt, I, S, I, st));
+  for (int j = 1; j <= P.q; ++j) {
+    const int64_t m = S * j;                     // rows of the basis so far
+    const double* Qlast = b.Qt + (m - S) * I;
+    // Y_j^T = Q_{j-1}^T C  (C symmetric)
+    HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qlast, I, b.C, I, 0.0, b.Yt, I, st));
+    HIPCHK(copy_rows_f64(b.CQt + (m - S) * I, I, b.Yt, I, S, I, st));
+    HIPCHK(row_norms2(b.Yt, S, I, b.ref2, st));
+    for (int pass = 0; pass < 2; ++pass) {       // remove earlier blocks, twice
+      HIPCHK(dgemm(0, 1, S, m, I, 1.0, b.Yt, I, b.Qt, I, 0.0, b.Pm, m, st));
+      HIPCHK(dgemm(0, 0, S, I, m, -1.0, b.Pm, m, b.Qt, I, 1.0, b.Yt, I, st));
+    }
+    HIPCHK(chol_orth(b.Yt, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st));
+    HIPCHK(chol_orth(b.Yt, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
+    HIPCHK(copy_rows_f64(b.Qt + m * I, I, b.Yt, I, S, I, st));
+  }
+  if (!with_factor) return RBKI_OK;
+  // C Q_q, then Z = Q^T (C Q) (Alg. 2, step 3)
+  HIPCHK(dgemm(0, 0, S, I, I, 1.0, b.Qt + (Sp - S) * I, I, b.C, I, 0.0, b.CQt + (Sp - S) * I, I, st));
+  HIPCHK(dgemm(0, 1, Sp, Sp, I, 1.0, b.Qt, I, b.CQt, I, 0.0, b.Z, Sp, st));
+  {
+    ProfScope ps("jacobi", st);
+    HIPCHK(jacobi_eig(b.Z, Sp, b.lam, b.Vt, b.jwork, b.info, 40, st));   // steps 4: eigenvectors, descending
+  }
+  // U^T = Vt(1:R, :) Q^T  (step 5)
+  HIPCHK(dgemm(0, 0, g.R, I, Sp, 1.0, b.Vt, Sp, b.Qt, I, 0.0, b.Ut64[n], I, st));
+  // sign rule: largest-magnitude entry of each factor column positive
+  HIPCHK(canonical_sign_rows(b.Ut64[n], g.R, I, st));
+  return RBKI_OK;
+}
+
+// Core chain and error.  Returns the core (chain element type) in *core_out.
+rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, const void* xsrc, void* core,
+                               int out_elem, double* rel_err, void** core_out, hipStream_t st) {
+  const size_t ce = P.celem == E_F64 ? 8 : 4;
+  int64_t cur[8];
+  for (int n = 0; n < P.N; ++n) cur[n] = P.dims[n];
+  auto view = [&](int n, int64_t& A, int64_t& I, int64_t& B) {
+    A = 1;
+    for (int k = 0; k < n; ++k) A *= cur[k];
+    I = cur[n];
+    B = 1;
+    for (int k = n + 1; k < P.N; ++k) B *= cur[k];
+  };
+  void* bufs[2] = {b.chainA, b.chainB};
+  int which = 0;
+  // first product reads X
+  {
+    const int n = P.first_mode;
+    int64_t A, I, B;
+    view(n, A, I, B);
+    HIPCHK(convert_tensor(E_F64, b.Ut64[n], P.telem, b.Uop, P.m[n].R * I, st));
+    ProfScope ps("ttm", st);
+    HIPCHK(launch_ttm(P.telem, xsrc, A, I, B, b.Uop, P.m[n].R, bufs[which], nullptr, 0, st));
+    cur[n] = P.m[n].R;
+  }
+  for (int n = 0; n < P.N; ++n) {
+    if (n == P.first_mode) continue;
+    int64_t A, I, B;
+    view(n, A, I, B);
+    HIPCHK(convert_tensor(E_F64, b.Ut64[n], P.celem, b.Uop, P.m[n].R * I, st));
+    HIPCHK(launch_ttm(P.celem, bufs[which], A, I, B, b.Uop, P.m[n].R, bufs[which ^ 1], nullptr, 0, st));
+    which ^= 1;
+    cur[n] = P.m[n].R;
+  }
+  void* G = bufs[which];
+  int64_t nc = 1;
+  for (int n = 0; n < P.N; ++n) nc *= P.ranks[n];
+  if (core) HIPCHK(convert_tensor(P.celem, G, out_elem, core, nc, st));
+  if (core_out) {
+    // the reconstruction chain below reuses both chain buffers
+    HIPCHK(convert_tensor(P.celem, G, P.celem, b.gkeep, nc, st));
+    *core_out = b.gkeep;
+  }
+  if (!rel_err) return RBKI_OK;
+  // reconstruction chain H = G x_2 U2 ... x_N UN into the other buffer(s)
+  void* src = G;
+  int wsrc = which;
+  for (int n = 1; n < P.N; ++n) {
+    // expanding mode n: Y[a, i, b] = sum_r U[i, r] G[a, r, b] -> product with U^T^T: use Ut = U (I x R)
+    int64_t A = 1, B = 1;
+    for (int k = 0; k < n; ++k) A *= cur[k];
+    for (int k = n + 1; k < P.N; ++k) B *= cur[k];
+    const int64_t R = P.m[n].R, I = P.m[n].I;
+    // launch_ttm contracts the middle index of length "I" against Ut rows: here
+    // the middle index is R and the output length I, so pass U as an I x R
+    // "Ut" (rows = output index, k = r).
+    HIPCHK(store_factor(b.Ut64[n], R, I, b.Uop, P.celem == E_F64 ? E_F64 : E_F32, st));
+    void* dst = bufs[wsrc ^ 1];
+    HIPCHK(launch_ttm(P.celem, src, A, R, B, b.Uop, I, dst, nullptr, 0, st));
+    src = dst;
+    wsrc ^= 1;
+    cur[n] = I;
+  }
+  // residual over X_(0) with U^(1)
+  {
+    const int64_t I0 = P.dims[0], J0 = P.T / P.dims[0], R0 = P.m[0].R;
+    HIPCHK(convert_tensor(E_F64, b.Ut64[0], P.celem, b.Uop, R0 * I0, st));
+    ProfScope ps("error", st);
+    HIPCHK(launch_residual(P.xelem, X, P.celem, b.Uop, src, I0, J0, R0, b.sums, b.rpartial, 0, st));
+  }
+  double h[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(h, b.sums, 16, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *rel_err = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+  (void)ce;
+  return RBKI_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* rbki_version(void) { return "rbkitk 0.1 (gfx950)"; }
+
+const char* rbki_last_error(void) { return g_err.c_str(); }
+
+void rbki_profile_enable(int on) { g_prof_on = on != 0; }
+
+void rbki_profile_reset(void) {
+  prof_drain();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof.clear();
+}
+
+rbki_status rbki_profile_read(const char* kernel, int64_t* launches, double* total_ms) {
+  if (!kernel) return fail(RBKI_E_INVALID, "kernel name is NULL");
+  prof_drain();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  auto it = g_prof.find(kernel);
+  if (launches) *launches = it == g_prof.end() ? 0 : it->second.launches;
+  if (total_ms) *total_ms = it == g_prof.end() ? 0.0 : it->second.ms;
+  return RBKI_OK;
+}
+
+rbki_status rbki_omega(uint64_t seed, int mode, int64_t J, int64_t S, int dtype, void* out, void* stream) {
+  if (J < 0 || S < 0 || mode < 0) return fail(RBKI_E_INVALID, "negative size or mode");
+  if (dtype != RBKI_F64 && dtype != RBKI_F32 && dtype != RBKI_BF16) return fail(RBKI_E_INVALID, "bad dtype");
+  if (J * S > 0 && !out) return fail(RBKI_E_INVALID, "out is NULL");
+  HIPCHK(launch_omega(dtype_elem(dtype), seed, mode, J * S, out, (hipStream_t)stream));
+  return RBKI_OK;
+}
+
+rbki_status rbki_philox(const uint32_t* ctr, int64_t count, uint64_t seed, uint32_t* out, void* stream) {
+  if (count < 0) return fail(RBKI_E_INVALID, "negative count");
+  if (count > 0 && (!ctr || !out)) return fail(RBKI_E_INVALID, "NULL buffer");
+  HIPCHK(launch_philox(ctr, count, seed, out, (hipStream_t)stream));
+  return RBKI_OK;
+}
+
+size_t rbki_basis_workspace(const rbki_params* prm, int xtype, int mode) {
+  Plan P;
+  if (make_plan(prm, xtype, P) != RBKI_OK) return 0;
+  (void)mode;
+  return plan_bytes(P);
+}
+
+rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mode, double* Qt, int64_t* width,
+                       void* workspace, size_t ws_bytes, void* stream) {
+  Plan P;
+  rbki_status s = make_plan(prm, xtype, P);
+  if (s != RBKI_OK) return s;
+  if (mode < 0 || mode >= P.N) return fail(RBKI_E_INVALID, "mode %d outside [0, %d)", mode, P.N);
+  if (!X || !Qt) return fail(RBKI_E_INVALID, "NULL tensor or output");
+  const size_t need = plan_bytes(P);
+  if (!workspace || ws_bytes < need)
+    return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  Arena ar(workspace, ws_bytes);
+  Buffers b;
+  carve(P, ar, b);
+  const void* xsrc = X;
+  if (P.need_xconv) {
+    ProfScope ps("convert", st);
+    HIPCHK(convert_tensor(P.xelem, X, P.telem, b.xconv, P.T, st));
+    xsrc = b.xconv;
+  }
+  s = run_mode(P, b, xsrc, mode, false, st);
+  if (s != RBKI_OK) return s;
+  const ModeGeom& g = P.m[mode];
+  // compact the kept basis vectors (rows whose norm is nonzero) into Qt
+  const int64_t Sout = std::min<int64_t>(g.Sp, g.I);
+  HIPCHK(row_norms2(b.Qt, g.Sp, g.I, b.lam, st));
+  std::vector<double> nrm(g.Sp);
+  HIPCHK(hipMemcpyAsync(nrm.data(), b.lam, g.Sp * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int64_t w = 0;
+  for (int64_t k = 0; k < g.Sp && w < Sout; ++k) {
+    if (nrm[k] > 0.0) {
+      HIPCHK(hipMemcpyAsync(Qt + w * g.I, b.Qt + k * g.I, g.I * 8, hipMemcpyDeviceToDevice, st));
+      ++w;
+    }
+  }
+  if (w < Sout) HIPCHK(fill_zero(Qt + w * g.I, (size_t)(Sout - w) * g.I * 8, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (width) *width = w;
+  return RBKI_OK;
+}
+
+size_t rbki_tucker_workspace(const rbki_params* prm, int xtype) {
+  Plan P;
+  if (make_plan(prm, xtype, P) != RBKI_OK) return 0;
+  return plan_bytes(P);
+}
+
+static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
+                               int out_type, void* workspace, size_t ws_bytes, double* rel_err, hipStream_t st,
+                               Plan& P, Buffers& b, void** core_chain) {
+  rbki_status s = make_plan(prm, xtype, P);
+  if (s != RBKI_OK) return s;
+  if (!X) return fail(RBKI_E_INVALID, "X is NULL");
+  if (out_type != RBKI_F64 && out_type != RBKI_F32) return fail(RBKI_E_INVALID, "out_type must be F64 or F32");
+  const size_t need = plan_bytes(P);
+  if (!workspace || ws_bytes < need)
+    return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
+  Arena ar(workspace, ws_bytes);
+  carve(P, ar, b);
+  const void* xsrc = X;
+  if (P.need_xconv) {
+    ProfScope ps("convert", st);
+    HIPCHK(convert_tensor(P.xelem, X, P.telem, b.xconv, P.T, st));
+    xsrc = b.xconv;
+  }
+  HIPCHK(fill_zero(b.info, 64, st));
+  for (int n = 0; n < P.N; ++n) {
+    s = run_mode(P, b, xsrc, n, true, st);
+    if (s != RBKI_OK) return s;
+    if (factors && factors[n])
+      HIPCHK(store_factor(b.Ut64[n], P.m[n].R, P.m[n].I, factors[n], dtype_elem(out_type), st));
+  }
+  s = run_core_and_error(P, b, X, xsrc, core, dtype_elem(out_type), rel_err, core_chain, st);
+  if (s != RBKI_OK) return s;
+  if (rel_err) {
+    int info = 0;
+    HIPCHK(hipMemcpyAsync(&info, b.info, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (info) return fail(RBKI_E_NOCONV, "Jacobi reached its sweep limit (%d)", info);
+  }
+  return RBKI_OK;
+}
+
+rbki_status rbki_tucker(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
+                        int out_type, void* workspace, size_t ws_bytes, double* rel_err, void* stream) {
+  Plan P;
+  Buffers b;
+  return tucker_impl(X, xtype, prm, core, factors, out_type, workspace, ws_bytes, rel_err, (hipStream_t)stream, P,
+                     b, nullptr);
+}
+
+// ---------------------------------------------------------------- Alg. 3
+static bool htr_sizes(const Plan& P, const int64_t* tr, int64_t* r) {
+  // r[0..N]: r[0] = r_N closing rank, r[k] = tr[k-1]
+  r[0] = tr[P.N - 1];
+  for (int k = 0; k < P.N; ++k) r[k + 1] = tr[k];
+  for (int k = 0; k <= P.N; ++k)
+    if (r[k] < 1) return false;
+  return true;
+}
+
+size_t rbki_htr_workspace(const rbki_params* prm, int xtype, const int64_t* tr_ranks) {
+  Plan P;
+  if (make_plan(prm, xtype, P) != RBKI_OK || !tr_ranks) return 0;
+  int64_t r[9];
+  if (!htr_sizes(P, tr_ranks, r)) return 0;
+  int64_t S[8];
+  for (int n = 0; n < P.N; ++n) S[n] = P.ranks[n];
+  size_t extra = 0;
+  for (int n = 0; n < P.N; ++n) extra += ((size_t)r[n] * S[n] * r[n + 1] * 8 + 255) & ~(size_t)255;
+  extra += tr_svd_work_bytes(P.N, S, r) + tr_gap2_work_bytes(P.N, S, r) + 1024;
+  return plan_bytes(P) + extra;
+}
+
+rbki_status rbki_htr(const void* X, int xtype, const rbki_params* prm, const int64_t* tr_ranks,
+                     void* const* tr_cores, int out_type, void* workspace, size_t ws_bytes, double* rel_err,
+                     void* stream) {
+  Plan P;
+  rbki_status s = make_plan(prm, xtype, P);
+  if (s != RBKI_OK) return s;
+  if (!tr_ranks || !tr_cores) return fail(RBKI_E_INVALID, "NULL tr_ranks or tr_cores");
+  int64_t r[9];
+  if (!htr_sizes(P, tr_ranks, r)) return fail(RBKI_E_INVALID, "TR ranks must be >= 1");
+  for (int n = 0; n < P.N; ++n)
+    if (!tr_cores[n]) return fail(RBKI_E_INVALID, "tr_cores[%d] is NULL", n);
+  const size_t need = rbki_htr_workspace(prm, xtype, tr_ranks);
+  if (!workspace || ws_bytes < need) return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  Buffers b;
+  void* Gchain = nullptr;
+  double e_tk = 0.0;
+  s = tucker_impl(X, xtype, prm, nullptr, nullptr, RBKI_F64, workspace, ws_bytes, rel_err ? &e_tk : nullptr, st, P, b,
+                  &Gchain);
+  if (s != RBKI_OK && s != RBKI_E_NOCONV) return s;
+  // the remaining workspace after the Tucker plan
+  size_t off = (plan_bytes(P) + 255) & ~(size_t)255;
+  char* base = (char*)workspace + off;
+  int64_t S[8];
+  for (int n = 0; n < P.N; ++n) S[n] = P.ranks[n];
+  double* cores[8];
+  for (int n = 0; n < P.N; ++n) {
+    cores[n] = (double*)base;
+    base += ((size_t)r[n] * S[n] * r[n + 1] * 8 + 255) & ~(size_t)255;
+  }
+  const size_t tw = tr_svd_work_bytes(P.N, S, r);
+  double* twork = (double*)base;
+  base += (tw + 255) & ~(size_t)255;
+  double* gwork = (double*)base;
+  base += (tr_gap2_work_bytes(P.N, S, r) + 255) & ~(size_t)255;
+  double* small = (double*)base;   // [0..1]: gap2, discarded; int info at +64
+  HIPCHK(tr_svd_device(Gchain, P.celem, P.N, S, r, cores, twork, tw, (int*)(small + 8), small + 1, st));
+  for (int n = 0; n < P.N; ++n)
+    HIPCHK(tr_attach(cores[n], b.Ut64[n], r[n], S[n], r[n + 1], P.dims[n], tr_cores[n], dtype_elem(out_type), st));
+  if (rel_err) {
+    // ||X - TR||^2 = ||X - [[G;U]]||^2 + ||G - TR(G_n)||^2 (orthonormal U)
+    HIPCHK(tr_gap2(Gchain, P.celem, P.N, S, r, cores, gwork, small, st));
+    double gap2 = 0.0, sums[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&gap2, small, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(sums, b.sums, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *rel_err = sums[1] > 0 ? std::sqrt((sums[0] + gap2) / sums[1]) : 0.0;
+  }
+  return s;
+}
+
+}  // extern "C"

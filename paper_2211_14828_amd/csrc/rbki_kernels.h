@@ -1,0 +1,91 @@
+// Host-side launchers of the device kernels (internal to the library).
+#pragma once
+#include <algorithm>
+#include "rbki_common.h"
+
+namespace rbki {
+
+// ------------------------------------------------------------ gram.hip
+struct GramArgs {
+  const void* X;            // mode view source (element type of the product)
+  const void* omegaT;       // S x J sketch rows (same element type), may be null if S == 0
+  const unsigned char* xexp;  // fp8 only: per-block E8M0 exponents of X
+  int64_t A, I, B, J;
+  int S;
+  int nt, ntri, nw, ntiles;
+  int64_t nkt, nbt;
+  int splits, xcd_map, vec_ok;
+  void* partial;            // [splits][ntiles][128*128] float (double for fp64)
+  // fp8 block-exponent geometry (blocks of 32 per dimension)
+  int order, mode;
+  int64_t pdims[8];         // (padded) tensor dims
+  int64_t nblk[8];          // blocks per dim
+};
+
+int elem_size(int elem);
+int gram_bk(int elem);
+GramArgs gram_plan(int elem, int64_t A, int64_t I, int64_t B, int S, int cu_count);
+size_t gram_partial_bytes(const GramArgs& g, int elem);
+hipError_t launch_gram_main(int elem, const GramArgs& g, hipStream_t s);
+hipError_t launch_gram_reduce(int elem, const GramArgs& g, double* C, double* Wt, hipStream_t s);
+hipError_t launch_omega(int elem, uint64_t seed, int mode, int64_t total, void* out, hipStream_t s);
+hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint64_t seed, uint32_t* out, hipStream_t s);
+
+// ------------------------------------------------------------ linalg.hip (float64)
+// C[m x n] = alpha * op(A) op(B) + beta * C, all row-major with leading dims.
+// opA: 0 -> A is m x k (lda), 1 -> A is k x m (A^T used).
+// opB: 0 -> B is k x n (ldb), 1 -> B is n x k (B^T used).
+hipError_t dgemm(int opA, int opB, int64_t m, int64_t n, int64_t k, double alpha, const double* A,
+                 int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                 hipStream_t s);
+
+// Orthonormalise the rows of Y (s x n, row-major: s vectors of length n) in
+// place by CholeskyQR with column dropping (directions whose pivot falls
+// below tau_rel * (pivot scale) or below the absolute floor abs2[k] are set to
+// zero).  G is s x s scratch, L is s x s scratch, flags (int[s]) receives 1
+// for kept vectors.  ref2 (device, s doubles, nullable) gives per-vector
+// squared reference norms for the absolute floor.
+hipError_t chol_orth(double* Y, int64_t s, int64_t n, double* G, double* Lm, int* flags,
+                     const double* ref2, double tau_rel, double tau_abs, hipStream_t st);
+
+// Row norms squared of Y (s x n) -> out[s].
+hipError_t row_norms2(const double* Y, int64_t s, int64_t n, double* out, hipStream_t st);
+
+// One-sided Jacobi on the columns of symmetric PSD Z (n x n, row-major
+// input); writes the eigenvalues (descending) to lam[n] and the matching unit
+// eigenvectors as the rows of Vt (n x n row-major).  work: scratch of
+// jacobi_work_bytes(n).  info (device int): 0 ok, >0 sweep limit reached.
+size_t jacobi_work_bytes(int64_t n);
+hipError_t jacobi_eig(const double* Z, int64_t n, double* lam, double* Vt, void* work, int* info,
+                      int max_sweeps, hipStream_t st);
+
+// Copy / convert helpers.
+hipError_t copy_rows_f64(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows,
+                         int64_t cols, hipStream_t st);
+hipError_t store_factor(const double* Ut /* R x I */, int64_t R, int64_t I, void* out /* I x R */,
+                        int out_elem, hipStream_t st);
+hipError_t fill_zero(void* p, size_t bytes, hipStream_t st);
+// Flip each row of V (rows x n) so its largest-magnitude entry is positive.
+hipError_t canonical_sign_rows(double* V, int64_t rows, int64_t n, hipStream_t st);
+
+// ------------------------------------------------------------ ttm.hip
+// Y[a, r, b] = sum_i U[i, r] X[a, i, b] for the view [A, I, B] of X;
+// U given as Ut (R x I row-major, element type of the product).
+// X element type elem; Y written as float (F32/BF16 products) or double (F64).
+hipError_t launch_ttm(int elem, const void* X, int64_t A, int64_t I, int64_t B, const void* Ut,
+                      int64_t R, void* Y, void* work, size_t work_bytes, hipStream_t s);
+size_t ttm_work_bytes(int elem, int64_t A, int64_t I, int64_t B, int64_t R);
+
+// Sum over all entries of (X - Uh)^2 and X^2 where Uh[i, j] = sum_r U[i, r] H[r, j]
+// (X viewed as I x J row-major, the mode-0 unfolding); partial sums in
+// float64, returned in out[0] (residual) and out[1] (norm), reduced in a fixed order.
+hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* Ut, const void* H,
+                           int64_t I, int64_t J, int64_t R, double* out, void* work,
+                           size_t work_bytes, hipStream_t s);
+size_t residual_work_bytes(int64_t I, int64_t J);
+
+// Element conversions of the whole tensor.
+hipError_t convert_tensor(int src_elem, const void* src, int dst_elem, void* dst, int64_t n,
+                          hipStream_t s);
+
+}  // namespace rbki

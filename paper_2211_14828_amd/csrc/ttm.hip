@@ -1,0 +1,366 @@
+// Mode-n products (Alg. 2, step 6: G <- G x_n U^(n)T, and the reconstruction
+// G x_n U^(n)) and the fused reconstruction-error reduction, on MFMA.
+//
+// Both are products out[row, col] = sum_k Aop[row, k] * Bop[col, k] in which
+// each operand is strided: either k is its contiguous index ("k-contiguous")
+// or the row is ("row-contiguous", transposed while staged into LDS).  A
+// mode-n product with U on the view [A, I, B] is, for every a, the product
+// Y[a] (R x B) = U^T (R x I) X[a] (I x B); for the last mode (B = 1) it is
+// Y (A x R) = X (A x I) U (I x R).  The error pass computes the mode-0
+// reconstruction Xhat_(0) = U^(1) H tile by tile and folds (x - xhat)^2 and
+// x^2 into float64 partial sums without writing Xhat.
+#include "rbki_kernels.h"
+#include "rbki_mma.h"
+
+namespace rbki {
+
+namespace {
+
+struct Operand {
+  const void* base;
+  int64_t row_stride, k_stride;   // one of them is 1
+  int64_t batch_stride;
+  int64_t rows;                   // valid rows
+};
+
+struct ProdArgs {
+  Operand a, b;
+  int64_t K;                      // contraction length
+  int64_t row_tiles, col_tiles;
+  // store epilogue
+  void* out;
+  int64_t out_rs, out_cs, out_bs;
+  // residual epilogue: X (row-major rows x J) of element x_elem
+  const void* X;
+  int x_elem;
+  int64_t xJ;
+  double* partial;                // [grid] x 2
+  int vec_a, vec_b;
+};
+
+template <int E>
+__device__ inline void load_op(uint4* chunk, const Operand& op, int64_t batch, int64_t row0, int64_t k0,
+                               int64_t K, bool vec) {
+  typedef typename Mma<E>::T T;
+  constexpr int EPC = 16 / (int)sizeof(T);
+  constexpr int BK = Mma<E>::BK;
+  const T* base = (const T*)op.base + batch * op.batch_stride;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = tid + 256 * j;
+    union { uint4 v; T e[EPC]; } u;
+    u.v = make_uint4(0, 0, 0, 0);
+    if (op.k_stride == 1) {
+      const int row = c / (BK / EPC);
+      const int kk = (c % (BK / EPC)) * EPC;
+      const int64_t r = row0 + row, k = k0 + kk;
+      if (r < op.rows) {
+        const T* p = base + r * op.row_stride + k;
+        if (vec && k + EPC <= K) u.v = *(const uint4*)p;
+        else
+#pragma unroll
+          for (int e = 0; e < EPC; ++e)
+            if (k + e < K) u.e[e] = p[e];
+      }
+    } else {
+      const int per_k = TILE / EPC;
+      const int kk = c / per_k;
+      const int row = (c % per_k) * EPC;
+      const int64_t r = row0 + row, k = k0 + kk;
+      if (k < K) {
+        const T* p = base + k * op.k_stride + r;
+        if (vec && r + EPC <= op.rows) u.v = *(const uint4*)p;
+        else
+#pragma unroll
+          for (int e = 0; e < EPC; ++e)
+            if (r + e < op.rows) u.e[e] = p[e];
+      }
+    }
+    chunk[j] = u.v;
+  }
+}
+
+template <int E>
+__device__ inline void store_op(const uint4* chunk, const Operand& op, char* lds) {
+  typedef typename Mma<E>::T T;
+  constexpr int EPC = 16 / (int)sizeof(T);
+  constexpr int BK = Mma<E>::BK;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = tid + 256 * j;
+    if (op.k_stride == 1) {
+      const int row = c / (BK / EPC);
+      const int kk = (c % (BK / EPC)) * EPC;
+      *(uint4*)(lds + row * LDS_ROW + kk * (int)sizeof(T)) = chunk[j];
+    } else {
+      const int per_k = TILE / EPC;
+      const int kk = c / per_k;
+      const int row = (c % per_k) * EPC;
+      union { uint4 v; T e[EPC]; } u;
+      u.v = chunk[j];
+#pragma unroll
+      for (int e = 0; e < EPC; ++e) *(T*)(lds + (row + e) * LDS_ROW + kk * (int)sizeof(T)) = u.e[e];
+    }
+  }
+}
+
+template <class T> __device__ inline double load_x(const void* X, int64_t i);
+template <> __device__ inline double load_x<double>(const void* X, int64_t i) { return ((const double*)X)[i]; }
+template <> __device__ inline double load_x<float>(const void* X, int64_t i) { return (double)((const float*)X)[i]; }
+template <> __device__ inline double load_x<bf16_t>(const void* X, int64_t i) {
+  return (double)bf16_to_f32(((const bf16_t*)X)[i]);
+}
+
+// EPI = 0: store; EPI = 1: residual with X of type XT
+template <int E, int EPI, class XT>
+__global__ void __launch_bounds__(256, E == E_F64 ? 1 : 2) prod_kernel(ProdArgs p) {
+  typedef Mma<E> M;
+  typedef typename M::Out Out;
+  constexpr int BK = M::BK;
+  __shared__ __attribute__((aligned(16))) char lds[2][2][TILE * LDS_ROW];
+  __shared__ double red[2][4];
+
+  const int64_t tile = blockIdx.x;
+  const int64_t batch = blockIdx.y;
+  const int64_t rt = tile % p.row_tiles, ct = tile / p.row_tiles;
+  const int64_t r0 = rt * TILE, c0 = ct * TILE;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+
+  typename M::Frag f;
+  M::zero(f);
+  uint4 ca[4], cb[4];
+  const int64_t nk = ceil_div(p.K, BK);
+  load_op<E>(ca, p.a, batch, r0, 0, p.K, p.vec_a);
+  load_op<E>(cb, p.b, batch, c0, 0, p.K, p.vec_b);
+  store_op<E>(ca, p.a, lds[0][0]);
+  store_op<E>(cb, p.b, lds[0][1]);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) {
+      load_op<E>(ca, p.a, batch, r0, (kt + 1) * BK, p.K, p.vec_a);
+      load_op<E>(cb, p.b, batch, c0, (kt + 1) * BK, p.K, p.vec_b);
+    }
+    M::step(f, lds[buf][0], lds[buf][1], lane, wr, wc);
+    if (more) {
+      store_op<E>(ca, p.a, lds[buf ^ 1][0]);
+      store_op<E>(cb, p.b, lds[buf ^ 1][1]);
+    }
+    __syncthreads();
+  }
+
+  if (EPI == 0) {
+    Out* out = (Out*)p.out + batch * p.out_bs;
+#pragma unroll
+    for (int j = 0; j < M::NACC; ++j) {
+      int row, col;
+      M::coord(j, lane, row, col);
+      const int64_t r = r0 + wr + row, c = c0 + wc + col;
+      if (r < p.a.rows && c < p.b.rows) out[r * p.out_rs + c * p.out_cs] = M::get(f, j);
+    }
+  } else {
+    double res = 0.0, nrm = 0.0;
+#pragma unroll
+    for (int j = 0; j < M::NACC; ++j) {
+      int row, col;
+      M::coord(j, lane, row, col);
+      const int64_t r = r0 + wr + row, c = c0 + wc + col;
+      if (r < p.a.rows && c < p.b.rows) {
+        const double x = load_x<XT>(p.X, r * p.xJ + c);
+        const double d = x - (double)M::get(f, j);
+        res = fma(d, d, res);
+        nrm = fma(x, x, nrm);
+      }
+    }
+    res = warp_sum(res);
+    nrm = warp_sum(nrm);
+    if (lane == 0) {
+      red[0][wave] = res;
+      red[1][wave] = nrm;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int64_t g = blockIdx.y * (int64_t)gridDim.x + blockIdx.x;
+      p.partial[2 * g] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+      p.partial[2 * g + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+  }
+}
+
+// Fixed-order sum of the per-workgroup partials.
+__global__ void sum_pairs_kernel(const double* partial, int64_t n, double* out) {
+  __shared__ double sr[16], sn[16];
+  double r = 0.0, q = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    r += partial[2 * i];
+    q += partial[2 * i + 1];
+  }
+  r = warp_sum(r);
+  q = warp_sum(q);
+  if ((threadIdx.x & 63) == 0) {
+    sr[threadIdx.x >> 6] = r;
+    sn[threadIdx.x >> 6] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a += sr[w];
+      b += sn[w];
+    }
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+template <class S, class D> __device__ inline D conv(S v);
+template <> __device__ inline float conv<double, float>(double v) { return (float)v; }
+template <> __device__ inline double conv<float, double>(float v) { return (double)v; }
+template <> __device__ inline float conv<float, float>(float v) { return v; }
+template <> __device__ inline double conv<double, double>(double v) { return v; }
+template <> __device__ inline bf16_t conv<float, bf16_t>(float v) { return f32_to_bf16(v); }
+template <> __device__ inline bf16_t conv<double, bf16_t>(double v) { return f32_to_bf16((float)v); }
+template <> __device__ inline float conv<bf16_t, float>(bf16_t v) { return bf16_to_f32(v); }
+template <> __device__ inline double conv<bf16_t, double>(bf16_t v) { return (double)bf16_to_f32(v); }
+template <> __device__ inline bf16_t conv<bf16_t, bf16_t>(bf16_t v) { return v; }
+
+template <class S, class D>
+__global__ void convert_kernel(const S* src, D* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = conv<S, D>(src[i]);
+}
+
+template <int E, int EPI, class XT>
+hipError_t launch_prod(const ProdArgs& p, int64_t batches, hipStream_t s) {
+  // the batch index runs on grid.y (at most 65535 per launch)
+  typedef typename Mma<E>::T T;
+  typedef typename Mma<E>::Out Out;
+  for (int64_t b0 = 0; b0 < batches; b0 += 65535) {
+    const int64_t nb = std::min<int64_t>(65535, batches - b0);
+    ProdArgs q = p;
+    q.a.base = (const T*)p.a.base + b0 * p.a.batch_stride;
+    q.b.base = (const T*)p.b.base + b0 * p.b.batch_stride;
+    if (EPI == 0) q.out = (Out*)p.out + b0 * p.out_bs;
+    dim3 grid((unsigned)(p.row_tiles * p.col_tiles), (unsigned)nb);
+    hipLaunchKernelGGL((prod_kernel<E, EPI, XT>), grid, dim3(256), 0, s, q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+size_t ttm_work_bytes(int, int64_t, int64_t, int64_t, int64_t) { return 0; }
+
+hipError_t launch_ttm(int elem, const void* X, int64_t A, int64_t I, int64_t B, const void* Ut, int64_t R,
+                      void* Y, void*, size_t, hipStream_t s) {
+  const int es = elem_size(elem);
+  ProdArgs p = {};
+  p.K = I;
+  int64_t batches;
+  if (B > 1) {
+    // Y[a] (R x B) = Ut (R x I) . X[a] (I x B): rows r, cols b
+    p.a = {Ut, I, 1, 0, R};
+    p.b = {X, 1, B, I * B, B};
+    p.out = Y;
+    p.out_rs = B;
+    p.out_cs = 1;
+    p.out_bs = R * B;
+    p.row_tiles = ceil_div(R, TILE);
+    p.col_tiles = ceil_div(B, TILE);
+    p.vec_a = (I * es) % 16 == 0 && aligned16(Ut);
+    p.vec_b = (B * es) % 16 == 0 && aligned16(X);
+    batches = A;
+  } else {
+    // Y (A x R) = X (A x I) . U (I x R): rows a, cols r
+    p.a = {X, I, 1, 0, A};
+    p.b = {Ut, I, 1, 0, R};
+    p.out = Y;
+    p.out_rs = R;
+    p.out_cs = 1;
+    p.out_bs = 0;
+    p.row_tiles = ceil_div(A, TILE);
+    p.col_tiles = ceil_div(R, TILE);
+    p.vec_a = (I * es) % 16 == 0 && aligned16(X);
+    p.vec_b = (I * es) % 16 == 0 && aligned16(Ut);
+    batches = 1;
+  }
+  switch (elem) {
+    case E_F64: return launch_prod<E_F64, 0, double>(p, batches, s);
+    case E_F32: return launch_prod<E_F32, 0, float>(p, batches, s);
+    case E_BF16: return launch_prod<E_BF16, 0, float>(p, batches, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t residual_work_bytes(int64_t I, int64_t J) {
+  return (size_t)(ceil_div(I, TILE) * ceil_div(J, TILE)) * 16 + 64;
+}
+
+hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* Ut, const void* H, int64_t I,
+                           int64_t J, int64_t R, double* out, void* work, size_t, hipStream_t s) {
+  const int es = elem_size(op_elem);
+  ProdArgs p = {};
+  p.K = R;
+  // Xhat[i, j] = sum_r U[i, r] H[r, j]: rows i from Ut (R x I, row-contiguous),
+  // cols j from H (R x J, row-contiguous)
+  p.a = {Ut, 1, I, 0, I};
+  p.b = {H, 1, J, 0, J};
+  p.row_tiles = ceil_div(I, TILE);
+  p.col_tiles = ceil_div(J, TILE);
+  p.vec_a = (I * es) % 16 == 0 && aligned16(Ut);
+  p.vec_b = (J * es) % 16 == 0 && aligned16(H);
+  p.X = X;
+  p.x_elem = x_elem;
+  p.xJ = J;
+  p.partial = (double*)work;
+  hipError_t e;
+  if (op_elem == E_F64) {
+    if (x_elem != E_F64) return hipErrorInvalidValue;
+    e = launch_prod<E_F64, 1, double>(p, 1, s);
+  } else if (op_elem == E_F32) {
+    if (x_elem == E_F32) e = launch_prod<E_F32, 1, float>(p, 1, s);
+    else if (x_elem == E_BF16) e = launch_prod<E_F32, 1, bf16_t>(p, 1, s);
+    else e = launch_prod<E_F32, 1, double>(p, 1, s);
+  } else if (op_elem == E_BF16) {
+    if (x_elem == E_F32) e = launch_prod<E_BF16, 1, float>(p, 1, s);
+    else if (x_elem == E_BF16) e = launch_prod<E_BF16, 1, bf16_t>(p, 1, s);
+    else e = launch_prod<E_BF16, 1, double>(p, 1, s);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  const int64_t n = p.row_tiles * p.col_tiles;
+  hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(1024), 0, s, (const double*)work, n, out);
+  return hipGetLastError();
+}
+
+hipError_t convert_tensor(int src_elem, const void* src, int dst_elem, void* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n, 256), 65536);
+#define CV(SE, ST, DE, DT)                                                                                    \
+  if (src_elem == SE && dst_elem == DE) {                                                                     \
+    hipLaunchKernelGGL((convert_kernel<ST, DT>), dim3(grid), dim3(256), 0, s, (const ST*)src, (DT*)dst, n); \
+    return hipGetLastError();                                                                                 \
+  }
+  CV(E_F64, double, E_F32, float)
+  CV(E_F32, float, E_F64, double)
+  CV(E_F32, float, E_F32, float)
+  CV(E_F64, double, E_F64, double)
+  CV(E_F32, float, E_BF16, bf16_t)
+  CV(E_F64, double, E_BF16, bf16_t)
+  CV(E_BF16, bf16_t, E_F32, float)
+  CV(E_BF16, bf16_t, E_F64, double)
+  CV(E_BF16, bf16_t, E_BF16, bf16_t)
+#undef CV
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rbki

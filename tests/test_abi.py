@@ -1,0 +1,95 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it is built for
+gfx950, it loads, and it exports every entry point the header declares with
+C linkage."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2211_14828_amd as rb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rbkitk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rbki_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_symbols():
+    assert declared_functions() == sorted(rb.SYMBOLS)
+
+
+def test_library_loads_and_exports_every_symbol():
+    lib = rb.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", rb.library_path()], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (rbki_\w+)", out))
+    assert set(declared_functions()) <= exported
+    assert lib.rbki_version().decode().startswith("rbkitk")
+
+
+def test_library_holds_gfx950_code_objects():
+    data = open(rb.library_path(), "rb").read()
+    assert b"gfx950" in data
+
+
+def test_oracle_is_not_linked_into_the_product():
+    # the product package never imports the oracle
+    pkg = os.path.join(ROOT, "paper_2211_14828_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
+
+
+def _params(dims, ranks, p=5, q=2, precision=0):
+    n = len(dims)
+    d = (ctypes.c_int64 * n)(*dims)
+    r = (ctypes.c_int64 * n)(*ranks)
+    prm = rb._Params(n, ctypes.cast(d, ctypes.POINTER(ctypes.c_int64)), ctypes.cast(r, ctypes.POINTER(ctypes.c_int64)),
+                     p, q, 0, precision)
+    prm._keep = (d, r)
+    return prm
+
+
+@pytest.mark.parametrize("dims,ranks,p,q,prec,why", [
+    ((10, 10, 10), (11, 3, 3), 5, 2, 0, "rank above dim"),
+    ((10, 10, 10), (0, 3, 3), 5, 2, 0, "zero rank"),
+    ((10,), (3,), 5, 2, 0, "order 1"),
+    ((10, 10, 10), (3, 3, 3), -1, 2, 0, "negative oversampling"),
+    ((10, 10, 10), (3, 3, 3), 5, -2, 0, "negative q"),
+    ((10, 10, 10), (3, 3, 3), 5, 2, 7, "unknown precision"),
+    ((10, 0, 10), (3, 1, 3), 5, 2, 0, "empty mode"),
+])
+def test_invalid_arguments_are_rejected_before_any_launch(dims, ranks, p, q, prec, why):
+    lib = rb.load_library()
+    prm = _params(dims, ranks, p, q, prec)
+    st = lib.rbki_tucker(ctypes.c_void_p(16), 1, ctypes.byref(prm), None, None, 1, None, 0, None, None)
+    assert st == 1, why
+    assert lib.rbki_last_error().decode()
+    assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) == 0
+
+
+def test_workspace_too_small_is_rejected():
+    lib = rb.load_library()
+    prm = _params((20, 20, 20), (3, 3, 3))
+    need = lib.rbki_tucker_workspace(ctypes.byref(prm), 1)
+    assert need > 0
+    st = lib.rbki_tucker(ctypes.c_void_p(256), 1, ctypes.byref(prm), None, None, 1, ctypes.c_void_p(256), need - 1,
+                         None, None)
+    assert st == 1 and "workspace" in lib.rbki_last_error().decode()
+
+
+def test_unknown_dtype_and_null_tensor_are_rejected():
+    lib = rb.load_library()
+    prm = _params((20, 20, 20), (3, 3, 3))
+    assert lib.rbki_tucker(ctypes.c_void_p(256), 9, ctypes.byref(prm), None, None, 1, None, 0, None, None) == 1
+    assert lib.rbki_tucker(None, 1, ctypes.byref(prm), None, None, 1, None, 0, None, None) == 1
+    assert lib.rbki_tucker(ctypes.c_void_p(256), 1, ctypes.byref(prm), None, None, 2, None, 0, None, None) == 1

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path through the C-ABI against the FP64 oracle on the
+same seeded inputs (same bytes, same Philox sketch stream).
+
+Tolerances (relative, on the reconstruction error e = ||X - Xhat|| / ||X||):
+  float64 form                1e-10
+  float32 form                1e-5
+  bf16 mixed / bf16 inputs    1e-3
+Factors are compared through their projectors (signs and rotations inside
+degenerate clusters are free), only where the oracle's relative eigen-gap
+at R_n is at least 1e-2."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import philox as oph
+from oracle.rbki import rbki_tucker, mode_factor
+from oracle.thosvd import leading_left_singular
+from oracle.tensor import unfold, project_core, fro, tucker_to_full
+from oracle.metrics import projector_distance, orthonormality_defect
+from oracle.trsvd import rbki_htr, tr_to_full
+
+pytestmark = pytest.mark.gpu
+
+TOL = {("float64", "plain"): 1e-10, ("float32", "plain"): 1e-5, ("float32", "mixed_bf16"): 1e-3,
+       ("float64", "mixed_bf16"): 1e-3, ("bfloat16", "plain"): 1e-3, ("bfloat16", "mixed_bf16"): 1e-3}
+PROJ_TOL = {"float64": 1e-8, "float32": 1e-3, "bfloat16": 3e-2}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    import paper_2211_14828_amd as rb
+    rb.load_library(build_if_missing=False)
+    return torch, rb
+
+
+def to_device(torch, X, dtype):
+    t = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32 if dtype == "bfloat16" else X.dtype))
+    if dtype == "bfloat16":
+        t = t.to(torch.bfloat16)
+    return t.to("cuda")
+
+
+def host_values(torch, Xg):
+    return Xg.to(torch.float64).cpu().numpy()
+
+
+def gap_ok(lam, R):
+    if lam.size <= R:
+        return True
+    return (lam[R - 1] - lam[R]) / lam[0] >= 1e-2
+
+
+# ------------------------------------------------------------------ sketch stream
+
+def test_philox_bit_exact(env):
+    torch, rb = env
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, size=(8192, 4), dtype=np.uint64)
+    ctr[0] = 0
+    ctr[1] = 2 ** 32 - 1
+    ctr[2] = [2 ** 32 - 1, 0, 2 ** 32 - 1, 0]
+    for seed in (0, 1, 0x1122334455667788, 2 ** 64 - 1):
+        out = rb.philox(torch.tensor(ctr.astype(np.uint32).view(np.int32), device="cuda"), seed)
+        got = out.cpu().numpy().view(np.uint32)
+        k0, k1 = oph.seed_key(seed)
+        ref = np.stack([w.astype(np.uint32) for w in oph.philox4x32(ctr[:, 0], ctr[:, 1], ctr[:, 2], ctr[:, 3], k0, k1)], 1)
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("J,S,mode,seed", [(1001, 7, 2, 77), (4096, 13, 0, 2 ** 40 + 3), (3, 1, 5, 0)])
+def test_omega_matches_oracle(env, J, S, mode, seed):
+    torch, rb = env
+    ref = oph.omega(seed, mode, J, S).T                  # S x J
+    g64 = rb.omega(seed, mode, J, S, torch.float64).cpu().numpy()
+    assert np.max(np.abs(g64 - ref) / (1.0 + np.abs(ref))) <= 1e-14
+    g32 = rb.omega(seed, mode, J, S, torch.float32).cpu().double().numpy()
+    assert np.max(np.abs(g32 - ref) / (1.0 + np.abs(ref))) <= 1e-6
+    gbf = rb.omega(seed, mode, J, S, torch.bfloat16).float().cpu().double().numpy()
+    assert np.max(np.abs(gbf - ref) / (1.0 + np.abs(ref))) <= 2.0 ** -8
+
+
+# ------------------------------------------------------------------ Alg. 1
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_krylov_basis_spans_the_oracle_space(env, mode):
+    torch, rb = env
+    w = synth.WORKLOADS["tucker64_f64"]
+    X, _ = synth.make_host(w)
+    Xg = torch.from_numpy(X).cuda()
+    Qt, width = rb.basis(Xg, mode, w["ranks"], p=w["p"], q=w["q"], seed=w["seeds"][1])
+    _, info = mode_factor(X, mode, w["ranks"][mode], w["p"], w["q"], w["seeds"][1], return_info=True)
+    Q = Qt[:width].cpu().numpy().T
+    assert width == info["Q"].shape[1]
+    assert orthonormality_defect(Q) <= 1e-12
+    assert projector_distance(Q, info["Q"]) <= 1e-10
+
+
+def test_krylov_basis_fills_the_space_when_wide(env):
+    # S (q+1) >= I: the basis spans R^I and its width is I
+    torch, rb = env
+    X, _ = synth.orthonormal_tucker((12, 30, 25), (4, 4, 4), seed=7)
+    X = synth.add_noise(X, 10.0, np.random.default_rng(1))
+    Qt, width = rb.basis(torch.from_numpy(X).cuda(), 0, (4, 4, 4), p=3, q=2, seed=13)
+    assert width == 12
+    Q = Qt[:width].cpu().numpy()
+    assert orthonormality_defect(Q.T) <= 1e-12
+
+
+# ------------------------------------------------------------------ Alg. 2
+
+CASES = [
+    # dims, ranks, p, q, dtype, precision, kind
+    ((64, 64, 64), (8, 8, 8), 5, 2, "float64", "plain", "c1"),
+    ((37, 45, 29), (4, 5, 3), 5, 2, "float64", "plain", "ragged"),
+    ((12, 10, 14, 9), (3, 4, 2, 3), 4, 2, "float64", "plain", "order4"),
+    ((200, 300), (10, 10), 5, 2, "float64", "plain", "matrix"),
+    ((130, 70, 150), (10, 8, 12), 5, 2, "float32", "plain", "tiles"),
+    ((130, 70, 150), (10, 8, 12), 5, 2, "float32", "mixed_bf16", "tiles"),
+    ((160, 160, 160), (20, 20, 20), 10, 3, "float32", "plain", "c2small"),
+    ((160, 160, 160), (20, 20, 20), 10, 3, "float32", "mixed_bf16", "c2small"),
+    ((64, 50, 40), (6, 6, 6), 5, 1, "bfloat16", "plain", "bf16in"),
+    ((8, 20, 20), (8, 5, 5), 2, 1, "float64", "plain", "full_rank_mode"),
+    ((5, 300, 7), (2, 3, 2), 5, 2, "float64", "plain", "thin"),
+]
+
+
+def make_case(dims, ranks, dtype, kind, seed):
+    if kind == "c1":
+        X, _ = synth.make_host(synth.WORKLOADS["tucker64_f64"])
+        return X
+    Xc, rng = synth.orthonormal_tucker(dims, ranks, seed, factor_decay="inverse" if kind == "c2small" else None)
+    X = synth.add_noise(Xc, 10.0, rng)
+    return X.astype(np.float64 if dtype == "float64" else np.float32)
+
+
+@pytest.mark.parametrize("dims,ranks,p,q,dtype,prec,kind", CASES)
+def test_tucker_matches_oracle(env, dims, ranks, p, q, dtype, prec, kind):
+    torch, rb = env
+    seed = 1000 + len(dims) * 7 + sum(dims)
+    X = make_case(dims, ranks, dtype, kind, seed)
+    Xg = to_device(torch, X, dtype)
+    Xh = host_values(torch, Xg)                   # exactly the bytes the GPU reads
+    core, facs, e_g = rb.tucker(Xg, ranks, p=p, q=q, seed=seed + 1, precision=prec, out_dtype=torch.float64)
+    G, Us, e_o, infos = rbki_tucker(Xh, ranks, p, q, seed + 1, return_info=True)
+    tol = TOL[(dtype, prec)]
+    assert abs(e_g - e_o) / e_o <= tol, (e_g, e_o)
+    Ug = [f.cpu().numpy() for f in facs]
+    for n in range(len(dims)):
+        assert orthonormality_defect(Ug[n]) <= 1e-12
+        if gap_ok(infos[n]["eigenvalues"], ranks[n]):
+            assert projector_distance(Ug[n], Us[n]) <= PROJ_TOL[dtype if prec == "plain" else "bfloat16"]
+    # the core is X x_n U^(n)T for the GPU's own factors
+    Gref = project_core(Xh, Ug)
+    ctol = 1e-12 if dtype == "float64" else (2e-6 if prec == "plain" and dtype == "float32" else 5e-3)
+    assert fro(core.cpu().numpy() - Gref) <= ctol * fro(Gref)
+    # the reported error is the explicit residual of the returned decomposition
+    e_explicit = fro(Xh - tucker_to_full(core.cpu().numpy(), Ug)) / fro(Xh)
+    assert abs(e_explicit - e_g) <= (1e-12 if dtype == "float64" else 1e-5) * e_explicit + 1e-14
+
+
+def test_exact_rank_tensor_is_recovered(env):
+    torch, rb = env
+    Xc, _ = synth.orthonormal_tucker((20, 24, 18), (3, 4, 2), seed=5)
+    core, facs, e = rb.tucker(torch.from_numpy(Xc).cuda(), (3, 4, 2), p=5, q=2, seed=11)
+    assert e <= 1e-12
+
+
+def test_full_krylov_factor_is_the_truncated_svd(env):
+    torch, rb = env
+    X, _ = synth.orthonormal_tucker((12, 30, 25), (4, 4, 4), seed=7)
+    X = synth.add_noise(X, 10.0, np.random.default_rng(2))
+    _, facs, _ = rb.tucker(torch.from_numpy(X).cuda(), (4, 4, 4), p=3, q=2, seed=13)
+    Ut, s = leading_left_singular(unfold(X, 0), 4)
+    assert (s[3] - s[4]) / s[0] > 1e-6
+    assert projector_distance(facs[0].cpu().numpy(), Ut) <= 1e-10
+
+
+def test_deterministic(env):
+    torch, rb = env
+    X = make_case((130, 70, 150), (10, 8, 12), "float32", "tiles", 3)
+    Xg = torch.from_numpy(X).cuda()
+    a = rb.tucker(Xg, (10, 8, 12), p=5, q=2, seed=4)
+    b = rb.tucker(Xg, (10, 8, 12), p=5, q=2, seed=4)
+    assert a[2] == b[2]
+    assert torch.equal(a[0], b[0])
+    for u, v in zip(a[1], b[1]):
+        assert torch.equal(u, v)
+
+
+# ------------------------------------------------------------------ Alg. 3
+
+@pytest.mark.parametrize("dims,tk,tr,dtype", [((20, 18, 22, 16), (6, 6, 6, 6), (3, 3, 3, 3), "float64"),
+                                              ((24, 20, 26), (10, 9, 12), (4, 3, 5), "float64"),
+                                              ((30, 28, 26, 24), (8, 8, 8, 8), (3, 3, 3, 3), "float32")])
+def test_htr_matches_oracle(env, dims, tk, tr, dtype):
+    torch, rb = env
+    X, _ = synth.tensor_ring_data(dims, 3, seed=5, var=1.0 / 3)
+    X = synth.add_noise(X, 15.0, np.random.default_rng(6)).astype(dtype)
+    Xg = torch.from_numpy(X).cuda()
+    Xh = host_values(torch, Xg)
+    cores_g, e_g = rb.htr(Xg, tk, tr, p=3, q=2, seed=7, out_dtype=torch.float64)
+    cores_o, e_o, info = rbki_htr(Xh, tk, 3, 2, 7, tr)
+    tol = 1e-10 if dtype == "float64" else 1e-5
+    assert abs(e_g - e_o) / e_o <= tol
+    r = [tr[-1]] + list(tr)
+    assert [tuple(c.shape) for c in cores_g] == [(r[n], dims[n], r[n + 1]) for n in range(len(dims))]
+    Xr = tr_to_full([c.cpu().numpy() for c in cores_g])
+    e_explicit = fro(Xh - Xr) / fro(Xh)
+    assert abs(e_explicit - e_g) <= tol * e_explicit
+    assert fro(Xr - tr_to_full(cores_o)) <= (1e-8 if dtype == "float64" else 1e-3) * fro(Xh)
+
+
+def test_htr_zero_pads_ring_ranks_beyond_the_core(env):
+    # r_0 r_1 = 64 exceeds S_1 = 6: missing directions are zero, ranks stay literal
+    torch, rb = env
+    X, _ = synth.tensor_ring_data((14, 12, 13), 2, seed=8, var=0.5)
+    Xg = torch.from_numpy(X).cuda()
+    cores_g, e_g = rb.htr(Xg, (6, 6, 6), (8, 8, 8), p=3, q=2, seed=9, out_dtype=torch.float64)
+    assert [tuple(c.shape) for c in cores_g] == [(8, 14, 8), (8, 12, 8), (8, 13, 8)]
+    cores_o, e_o, _ = rbki_htr(X, (6, 6, 6), 3, 2, 9, (8, 8, 8))
+    assert abs(e_g - e_o) <= 1e-10 * max(e_o, 1e-12) + 1e-13

@@ -70,3 +70,49 @@ def test_htr_error_split_and_contraction():
     assert fro(lifted - tr_to_full(cores)) <= 1e-12 * nx
     for c, U in zip(cores, info["factors"]):
         assert c.shape[1] == U.shape[0]
+
+
+def test_canonical_signs_fix_singular_vector_signs():
+    from oracle.rbki import canonical_signs
+    rng = np.random.default_rng(9)
+    U = np.linalg.qr(rng.standard_normal((7, 4)))[0]
+    D = np.diag([1.0, -1.0, -1.0, 1.0])
+    assert np.array_equal(canonical_signs(U @ D), canonical_signs(U))
+    C = canonical_signs(U)
+    assert np.all(C[np.argmax(np.abs(C), axis=0), np.arange(4)] > 0)
+
+
+def test_ring_sweep_depends_on_first_step_signs_and_the_rule_fixes_them():
+    """With r_0 > 1 negating one first-step singular vector changes the TR-SVD
+    truncation (the (a0, a1) split mixes rows and columns of the next
+    unfolding), so the sign rule is needed for TR-SVD to be a function of G;
+    with it, negating the input gives the negated ring and the same error."""
+    rng = np.random.default_rng(10)
+    G = rng.standard_normal((6, 5, 7, 4))
+    ranks = (2, 3, 2, 3)
+    cores, d = tr_svd(G, ranks)
+    e0 = fro(G - tr_to_full(cores))
+    cores_neg, _ = tr_svd(-G, ranks)
+    assert abs(fro(-G - tr_to_full(cores_neg)) - e0) <= 1e-10 * fro(G)
+    # flip one first-step left vector by hand and redo the sweep without the rule
+    S = G.shape
+    r = [ranks[-1]] + list(ranks)
+    U, s, Vt = np.linalg.svd(G.reshape(S[0], -1), full_matrices=False)
+    errs = []
+    for flip in (1.0, -1.0):
+        Uf, Vf = U.copy(), Vt.copy()
+        Uf[:, 1] *= flip
+        Vf[1] *= flip
+        k = r[0] * r[1]
+        C = (s[:k, None] * Vf[:k]).reshape((r[0], r[1]) + S[1:])
+        C = np.moveaxis(C, 0, -1)
+        c1 = Uf[:, :k].reshape(S[0], r[0], r[1]).transpose(1, 0, 2)
+        out = [c1]
+        for kk in range(1, 3):
+            M = C.reshape(r[kk] * S[kk], -1)
+            U2, s2, V2 = np.linalg.svd(M, full_matrices=False)
+            out.append(U2[:, :r[kk + 1]].reshape(r[kk], S[kk], r[kk + 1]))
+            C = (s2[:r[kk + 1], None] * V2[:r[kk + 1]]).reshape((r[kk + 1],) + S[kk + 1:] + (r[0],))
+        out.append(C.reshape(r[3], S[3], r[0]))
+        errs.append(fro(G - tr_to_full(out)))
+    assert abs(errs[0] - errs[1]) > 1e-6 * fro(G)
