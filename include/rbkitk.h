@@ -144,6 +144,22 @@ rbki_status rbki_htr(const void *X, int xtype, const rbki_params *prm, const int
                      double *rel_err, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * The small symmetric eigenproblem of Alg. 2, steps 3-4 (Z = Q^T X X^T Q,
+ * "svd(Z)"; Remark 1): eigenvalues in descending order and unit eigenvectors
+ * of a symmetric positive semidefinite float64 matrix, by one-sided Jacobi on
+ * the device.
+ *   Z        : device, n x n row-major (read only; must be symmetric PSD).
+ *   lam      : device, n doubles, descending.
+ *   Vt       : device, n x n row-major; row k is the eigenvector of lam[k],
+ *              signed so that its largest-magnitude entry is positive.
+ *   sweeps   : host, nullable: sweeps used (synchronises).
+ * n <= 1200.  Returns RBKI_E_NOCONV if the sweep limit was reached.
+ */
+size_t rbki_sym_eig_workspace(int64_t n);
+rbki_status rbki_sym_eig(const double *Z, int64_t n, double *lam, double *Vt, void *workspace,
+                         size_t ws_bytes, int *sweeps, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing.  When enabled, the library records HIP events around every
  * launch of the named kernels on the stream the kernel is launched on, and
  * accumulates their durations at the next synchronising call or at

@@ -13,7 +13,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["tucker", "htr", "basis", "omega", "philox", "workspace_bytes", "profile_enable",
+__all__ = ["tucker", "htr", "basis", "sym_eig", "omega", "philox", "workspace_bytes", "profile_enable",
            "profile_reset", "profile_read", "library_path", "load_library", "RbkiError",
            "PLAIN", "MIXED_BF16", "MIXED_FP8", "SYMBOLS"]
 
@@ -30,7 +30,8 @@ _STATUS = {0: "RBKI_OK", 1: "RBKI_E_INVALID", 2: "RBKI_E_NOMEM", 3: "RBKI_E_HIP"
 # Every symbol the header declares.
 SYMBOLS = ("rbki_version", "rbki_last_error", "rbki_omega", "rbki_philox", "rbki_basis_workspace",
            "rbki_basis", "rbki_tucker_workspace", "rbki_tucker", "rbki_htr_workspace", "rbki_htr",
-           "rbki_profile_enable", "rbki_profile_reset", "rbki_profile_read")
+           "rbki_sym_eig_workspace", "rbki_sym_eig", "rbki_profile_enable", "rbki_profile_reset",
+           "rbki_profile_read")
 
 
 class RbkiError(RuntimeError):
@@ -78,6 +79,8 @@ def load_library(build_if_missing=True):
             "rbki_tucker": (ci, [vp, ci, P(_Params), vp, P(vp), ci, vp, sz, P(dbl), vp]),
             "rbki_htr_workspace": (sz, [P(_Params), ci, P(i64)]),
             "rbki_htr": (ci, [vp, ci, P(_Params), P(i64), P(vp), ci, vp, sz, P(dbl), vp]),
+            "rbki_sym_eig_workspace": (sz, [i64]),
+            "rbki_sym_eig": (ci, [vp, i64, vp, vp, vp, sz, P(ci), vp]),
             "rbki_profile_enable": (None, [ci]),
             "rbki_profile_reset": (None, []),
             "rbki_profile_read": (ci, [ctypes.c_char_p, P(i64), P(dbl)]),
@@ -239,6 +242,25 @@ def basis(X, mode, ranks, p=5, q=2, seed=0, precision="plain", stream=None):
                           ctypes.c_void_p(Qt.data_ptr()), ctypes.byref(width), ctypes.c_void_p(ws.data_ptr()),
                           ws.numel(), _stream(torch, stream)))
     return Qt, width.value
+
+
+def sym_eig(Z, stream=None):
+    """Eigenvalues (descending) and eigenvectors (rows) of a symmetric PSD
+    float64 device matrix by the device Jacobi solver.  Returns (lam, Vt, sweeps)."""
+    torch = _torch()
+    lib = load_library()
+    Z = Z.contiguous()
+    if Z.dtype != torch.float64 or Z.dim() != 2 or Z.shape[0] != Z.shape[1]:
+        raise ValueError("Z must be a square float64 tensor")
+    n = int(Z.shape[0])
+    ws = _workspace(torch, Z.device, lib.rbki_sym_eig_workspace(n))
+    lam = torch.empty(n, dtype=torch.float64, device=Z.device)
+    Vt = torch.empty((n, n), dtype=torch.float64, device=Z.device)
+    sweeps = ctypes.c_int(0)
+    _check(lib.rbki_sym_eig(ctypes.c_void_p(Z.data_ptr()), n, ctypes.c_void_p(lam.data_ptr()),
+                            ctypes.c_void_p(Vt.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                            ctypes.byref(sweeps), _stream(torch, stream)))
+    return lam, Vt, sweeps.value
 
 
 def omega(seed, mode, J, S, dtype=None, device="cuda", stream=None):

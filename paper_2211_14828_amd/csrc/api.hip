@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -203,6 +204,8 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
   return RBKI_OK;
 }
 
+constexpr size_t kDgemmScratch = (size_t)32 << 20;
+
 struct Arena {
   char* base;
   size_t off = 0, cap;
@@ -221,18 +224,20 @@ struct Buffers {
   void* omegaT = nullptr;
   void* partial = nullptr;
   double* C = nullptr;
-  double* Qt = nullptr;
+  double* Qt[8] = {};      // per mode: S'_n x I_n basis rows
   double* CQt = nullptr;
   double* Yt = nullptr;
+  double* Ytmp = nullptr;
   double* Pm = nullptr;
+  double* dscratch = nullptr;   // split-K partials of the float64 GEMMs
   double* G = nullptr;
   double* L = nullptr;
   int* flags = nullptr;
   double* ref2 = nullptr;
-  double* Z = nullptr;
-  double* lam = nullptr;
-  double* Vt = nullptr;
-  void* jwork = nullptr;
+  double* Z[8] = {};       // per mode: S'_n x S'_n
+  double* lam[8] = {};
+  double* Vt[8] = {};
+  void* jwork[8] = {};
   int* info = nullptr;
   double* Ut64[8] = {};
   void* Uop = nullptr;     // one factor in a product element type
@@ -249,19 +254,24 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
   b.omegaT = ar.take((size_t)P.maxSJ * es_g);
   b.partial = ar.take(P.partial_bytes);
   b.C = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
-  b.Qt = (double*)ar.take((size_t)P.maxSp * P.maxI * 8);
+  for (int n = 0; n < P.N; ++n) b.Qt[n] = (double*)ar.take((size_t)P.m[n].Sp * P.m[n].I * 8);
   b.CQt = (double*)ar.take((size_t)P.maxSp * P.maxI * 8);
   b.Yt = (double*)ar.take((size_t)P.maxS * P.maxI * 8);
+  b.Ytmp = (double*)ar.take((size_t)P.maxS * P.maxI * 8);
   b.Pm = (double*)ar.take((size_t)P.maxS * P.maxSp * 8);
+  b.dscratch = (double*)ar.take(kDgemmScratch);
   b.G = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
   b.L = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
   b.flags = (int*)ar.take((size_t)P.maxSp * 4);
   b.ref2 = (double*)ar.take((size_t)P.maxS * 8);
-  b.Z = (double*)ar.take((size_t)P.maxSp * P.maxSp * 8);
-  b.lam = (double*)ar.take((size_t)P.maxSp * 8);
-  b.Vt = (double*)ar.take((size_t)P.maxSp * P.maxSp * 8);
-  b.jwork = ar.take(jacobi_work_bytes(P.maxSp));
-  b.info = (int*)ar.take(64);
+  for (int n = 0; n < P.N; ++n) {
+    const int64_t Sp = P.m[n].Sp;
+    b.Z[n] = (double*)ar.take((size_t)Sp * Sp * 8);
+    b.lam[n] = (double*)ar.take((size_t)Sp * 8);
+    b.Vt[n] = (double*)ar.take((size_t)Sp * Sp * 8);
+    b.jwork[n] = ar.take(jacobi_work_bytes(Sp));
+  }
+  b.info = (int*)ar.take(256);
   for (int n = 0; n < P.N; ++n) b.Ut64[n] = (double*)ar.take((size_t)P.m[n].R * P.m[n].I * 8);
   b.Uop = ar.take((size_t)P.maxRI * 8);
   const size_t ce = P.celem == E_F64 ? 8 : 4;
@@ -291,6 +301,7 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
                      hipStream_t st) {
   const ModeGeom& g = P.m[n];
   const int64_t I = g.I, S = g.S, Sp = g.Sp;
+  double* Qt = b.Qt[n];
   {
     ProfScope ps("omega", st);
     HIPCHK(launch_omega(P.gelem, P.seed, n, S * g.J, b.omegaT, st));
@@ -308,36 +319,56 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
 
   // block 0: Q_0 = orth(W)
   HIPCHK(row_norms2(b.Yt, S, I, b.ref2, st));
-  HIPCHK(chol_orth(b.Yt, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st));
-  HIPCHK(chol_orth(b.Yt, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
-  HIPCHK(copy_rows_f64(b.Qt, I, b.Yt, I, S, I, st));
+  HIPCHK(chol_orth(b.Yt, b.Ytmp, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st));
+  HIPCHK(chol_orth(b.Ytmp, Qt, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
   for (int j = 1; j <= P.q; ++j) {
     const int64_t m = S * j;                     // rows of the basis so far
-    const double* Qlast = b.Qt + (m - S) * I;
+    const double* Qlast = Qt + (m - S) * I;
     // Y_j^T = Q_{j-1}^T C  (C symmetric)
     HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qlast, I, b.C, I, 0.0, b.Yt, I, st));
     HIPCHK(copy_rows_f64(b.CQt + (m - S) * I, I, b.Yt, I, S, I, st));
     HIPCHK(row_norms2(b.Yt, S, I, b.ref2, st));
     for (int pass = 0; pass < 2; ++pass) {       // remove earlier blocks, twice
-      HIPCHK(dgemm(0, 1, S, m, I, 1.0, b.Yt, I, b.Qt, I, 0.0, b.Pm, m, st));
-      HIPCHK(dgemm(0, 0, S, I, m, -1.0, b.Pm, m, b.Qt, I, 1.0, b.Yt, I, st));
+      HIPCHK(dgemm(0, 1, S, m, I, 1.0, b.Yt, I, Qt, I, 0.0, b.Pm, m, st));
+      HIPCHK(dgemm(0, 0, S, I, m, -1.0, b.Pm, m, Qt, I, 1.0, b.Yt, I, st));
     }
-    HIPCHK(chol_orth(b.Yt, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st));
-    HIPCHK(chol_orth(b.Yt, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
-    HIPCHK(copy_rows_f64(b.Qt + m * I, I, b.Yt, I, S, I, st));
+    HIPCHK(chol_orth(b.Yt, b.Ytmp, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st));
+    HIPCHK(chol_orth(b.Ytmp, Qt + m * I, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
   }
   if (!with_factor) return RBKI_OK;
   // C Q_q, then Z = Q^T (C Q) (Alg. 2, step 3)
-  HIPCHK(dgemm(0, 0, S, I, I, 1.0, b.Qt + (Sp - S) * I, I, b.C, I, 0.0, b.CQt + (Sp - S) * I, I, st));
-  HIPCHK(dgemm(0, 1, Sp, Sp, I, 1.0, b.Qt, I, b.CQt, I, 0.0, b.Z, Sp, st));
+  HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt + (Sp - S) * I, I, b.C, I, 0.0, b.CQt + (Sp - S) * I, I, st));
+  HIPCHK(dgemm(0, 1, Sp, Sp, I, 1.0, Qt, I, b.CQt, I, 0.0, b.Z[n], Sp, st));
+  return RBKI_OK;
+}
+
+// Alg. 2, steps 4-5 for all modes: the eigenvectors of every Z in one batched
+// Jacobi launch, then U^T = Vt(1:R, :) Q^T with the sign rule.
+rbki_status run_factors(const Plan& P, const Buffers& b, hipStream_t st) {
+  const double* Zs[8];
+  int64_t ns[8];
+  double* ls[8];
+  double* vs[8];
+  void* ws[8];
+  int* is[8];
+  for (int n = 0; n < P.N; ++n) {
+    Zs[n] = b.Z[n];
+    ns[n] = P.m[n].Sp;
+    ls[n] = b.lam[n];
+    vs[n] = b.Vt[n];
+    ws[n] = b.jwork[n];
+    is[n] = b.info + 2 * n;
+  }
   {
     ProfScope ps("jacobi", st);
-    HIPCHK(jacobi_eig(b.Z, Sp, b.lam, b.Vt, b.jwork, b.info, 40, st));   // steps 4: eigenvectors, descending
+    HIPCHK(jacobi_eig_batched(P.N, Zs, ns, ls, vs, ws, is, 40, st));
   }
-  // U^T = Vt(1:R, :) Q^T  (step 5)
-  HIPCHK(dgemm(0, 0, g.R, I, Sp, 1.0, b.Vt, Sp, b.Qt, I, 0.0, b.Ut64[n], I, st));
-  // sign rule: largest-magnitude entry of each factor column positive
-  HIPCHK(canonical_sign_rows(b.Ut64[n], g.R, I, st));
+  for (int n = 0; n < P.N; ++n) {
+    const ModeGeom& g = P.m[n];
+    HIPCHK(dgemm(0, 0, g.R, g.I, g.Sp, 1.0, b.Vt[n], g.Sp, b.Qt[n], g.I, 0.0, b.Ut64[n], g.I, st));
+    // sign rule: largest-magnitude entry of each factor column positive
+    HIPCHK(canonical_sign_rows(b.Ut64[n], g.R, g.I, st));
+  }
   return RBKI_OK;
 }
 
@@ -462,6 +493,43 @@ rbki_status rbki_philox(const uint32_t* ctr, int64_t count, uint64_t seed, uint3
   return RBKI_OK;
 }
 
+size_t rbki_sym_eig_workspace(int64_t n) {
+  if (n < 1 || n > 1200) return 0;
+  return jacobi_work_bytes(n) + 512;
+}
+
+rbki_status rbki_sym_eig(const double* Z, int64_t n, double* lam, double* Vt, void* workspace, size_t ws_bytes,
+                         int* sweeps, void* stream) {
+  if (n < 1 || n > 1200) return fail(RBKI_E_INVALID, "n = %lld outside [1, 1200]", (long long)n);
+  if (!Z || !lam || !Vt) return fail(RBKI_E_INVALID, "NULL matrix or output");
+  const size_t need = rbki_sym_eig_workspace(n);
+  if (!workspace || ws_bytes < need) return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  int* info = (int*)((char*)workspace + ((jacobi_work_bytes(n) + 255) & ~(size_t)255));
+  {
+    ProfScope ps("jacobi", st);
+    HIPCHK(jacobi_eig(Z, n, lam, Vt, workspace, info, 40, st));
+  }
+  HIPCHK(canonical_sign_rows(Vt, n, n, st));
+  if (getenv("RBKI_JACOBI_PROF")) {
+    unsigned long long pr[6];
+    HIPCHK(hipMemcpyAsync(pr, (char*)workspace + jacobi_work_bytes(n) - 256 + 3 * 8 * 8, sizeof(pr),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    fprintf(stderr, "[jacobi n=%lld] rounds %llu  us/round: stage %.2f gram %.2f inner %.2f apply %.2f gridsync %.2f\n",
+            (long long)n, pr[5], pr[0] / 100.0 / pr[5], pr[1] / 100.0 / pr[5], pr[2] / 100.0 / pr[5],
+            pr[3] / 100.0 / pr[5], pr[4] / 100.0 / pr[5]);
+  }
+  if (sweeps) {
+    int h[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(h, info, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *sweeps = h[1];
+    if (h[0]) return fail(RBKI_E_NOCONV, "Jacobi reached its sweep limit (%d sweeps)", h[1]);
+  }
+  return RBKI_OK;
+}
+
 size_t rbki_basis_workspace(const rbki_params* prm, int xtype, int mode) {
   Plan P;
   if (make_plan(prm, xtype, P) != RBKI_OK) return 0;
@@ -483,6 +551,7 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
   Arena ar(workspace, ws_bytes);
   Buffers b;
   carve(P, ar, b);
+  dgemm_set_scratch(b.dscratch, kDgemmScratch);
   const void* xsrc = X;
   if (P.need_xconv) {
     ProfScope ps("convert", st);
@@ -494,14 +563,14 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
   const ModeGeom& g = P.m[mode];
   // compact the kept basis vectors (rows whose norm is nonzero) into Qt
   const int64_t Sout = std::min<int64_t>(g.Sp, g.I);
-  HIPCHK(row_norms2(b.Qt, g.Sp, g.I, b.lam, st));
+  HIPCHK(row_norms2(b.Qt[mode], g.Sp, g.I, b.lam[mode], st));
   std::vector<double> nrm(g.Sp);
-  HIPCHK(hipMemcpyAsync(nrm.data(), b.lam, g.Sp * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(nrm.data(), b.lam[mode], g.Sp * 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   int64_t w = 0;
   for (int64_t k = 0; k < g.Sp && w < Sout; ++k) {
     if (nrm[k] > 0.0) {
-      HIPCHK(hipMemcpyAsync(Qt + w * g.I, b.Qt + k * g.I, g.I * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(Qt + w * g.I, b.Qt[mode] + k * g.I, g.I * 8, hipMemcpyDeviceToDevice, st));
       ++w;
     }
   }
@@ -529,6 +598,7 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
     return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
   Arena ar(workspace, ws_bytes);
   carve(P, ar, b);
+  dgemm_set_scratch(b.dscratch, kDgemmScratch);
   const void* xsrc = X;
   if (P.need_xconv) {
     ProfScope ps("convert", st);
@@ -539,16 +609,25 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   for (int n = 0; n < P.N; ++n) {
     s = run_mode(P, b, xsrc, n, true, st);
     if (s != RBKI_OK) return s;
+  }
+  s = run_factors(P, b, st);
+  if (s != RBKI_OK) return s;
+  for (int n = 0; n < P.N; ++n)
     if (factors && factors[n])
       HIPCHK(store_factor(b.Ut64[n], P.m[n].R, P.m[n].I, factors[n], dtype_elem(out_type), st));
-  }
   s = run_core_and_error(P, b, X, xsrc, core, dtype_elem(out_type), rel_err, core_chain, st);
   if (s != RBKI_OK) return s;
   if (rel_err) {
-    int info = 0;
-    HIPCHK(hipMemcpyAsync(&info, b.info, 4, hipMemcpyDeviceToHost, st));
+    int info[16] = {0};
+    HIPCHK(hipMemcpyAsync(info, b.info, 2 * P.N * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (info) return fail(RBKI_E_NOCONV, "Jacobi reached its sweep limit (%d)", info);
+    for (int n = 0; n < P.N; ++n) {
+      if (g_prof_on) {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof["jacobi_sweeps"].launches += info[2 * n + 1];
+      }
+      if (info[2 * n]) return fail(RBKI_E_NOCONV, "Jacobi reached its sweep limit in mode %d", n);
+    }
   }
   return RBKI_OK;
 }

@@ -3,6 +3,7 @@
 // matrices of at most a few thousand rows/columns and runs entirely on the
 // device.
 #include <hip/hip_cooperative_groups.h>
+#include <cstdlib>
 
 #include "rbki_kernels.h"
 
@@ -20,20 +21,23 @@ constexpr int GT = 64, GK = 16;
 __global__ void __launch_bounds__(256) dgemm_kernel(int opA, int opB, int64_t m, int64_t n, int64_t k,
                                                     double alpha, const double* __restrict__ A, int64_t lda,
                                                     const double* __restrict__ B, int64_t ldb, double beta,
-                                                    double* __restrict__ C, int64_t ldc) {
+                                                    double* __restrict__ C, int64_t ldc, double* __restrict__ part,
+                                                    int64_t kchunk) {
   __shared__ double As[GK][GT + 1];
   __shared__ double Bs[GK][GT + 1];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t row0 = (int64_t)blockIdx.y * GT, col0 = (int64_t)blockIdx.x * GT;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = kb + kchunk < k ? kb + kchunk : k;
   double acc[4][4] = {};
-  for (int64_t k0 = 0; k0 < k; k0 += GK) {
+  for (int64_t k0 = kb; k0 < ke; k0 += GK) {
     // stage A tile: As[kk][i] = op(A)[row0 + i, k0 + kk]
     for (int e = threadIdx.x; e < GK * GT; e += 256) {
       int kk, i;
       if (opA == 0) { i = e / GK; kk = e % GK; } else { kk = e / GT; i = e % GT; }
       const int64_t r = row0 + i, c = k0 + kk;
       double v = 0.0;
-      if (r < m && c < k) v = opA == 0 ? A[r * lda + c] : A[c * lda + r];
+      if (r < m && c < ke) v = opA == 0 ? A[r * lda + c] : A[c * lda + r];
       As[kk][i] = v;
     }
     for (int e = threadIdx.x; e < GK * GT; e += 256) {
@@ -41,7 +45,7 @@ __global__ void __launch_bounds__(256) dgemm_kernel(int opA, int opB, int64_t m,
       if (opB == 0) { kk = e / GT; j = e % GT; } else { j = e / GK; kk = e % GK; }
       const int64_t r = k0 + kk, c = col0 + j;
       double v = 0.0;
-      if (r < k && c < n) v = opB == 0 ? B[r * ldb + c] : B[c * ldb + r];
+      if (r < ke && c < n) v = opB == 0 ? B[r * ldb + c] : B[c * ldb + r];
       Bs[kk][j] = v;
     }
     __syncthreads();
@@ -66,18 +70,105 @@ __global__ void __launch_bounds__(256) dgemm_kernel(int opA, int opB, int64_t m,
     for (int v = 0; v < 4; ++v) {
       const int64_t r = row0 + ty + 16 * u, c = col0 + tx + 16 * v;
       if (r < m && c < n) {
-        double* p = C + r * ldc + c;
-        *p = beta == 0.0 ? alpha * acc[u][v] : alpha * acc[u][v] + beta * *p;
+        if (part) {
+          part[(int64_t)blockIdx.z * m * n + r * n + c] = acc[u][v];
+        } else {
+          double* p = C + r * ldc + c;
+          *p = beta == 0.0 ? alpha * acc[u][v] : alpha * acc[u][v] + beta * *p;
+        }
       }
     }
 }
 
+// C = alpha * sum_z part[z] + beta * C, summed in a fixed order.
+__global__ void dgemm_reduce_kernel(int64_t m, int64_t n, int splits, const double* part, double alpha, double beta,
+                                    double* C, int64_t ldc) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m * n; e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int z = 0; z < splits; ++z) acc += part[(int64_t)z * m * n + e];
+    const int64_t r = e / n, c = e - r * n;
+    double* p = C + r * ldc + c;
+    *p = beta == 0.0 ? alpha * acc : alpha * acc + beta * *p;
+  }
+}
+
 // ------------------------------------------------------------ Cholesky QR
+// Right-looking Cholesky of the s x s Gram matrix G in LDS with column
+// dropping, then the inverse of the (reduced) factor, one workgroup.  A pivot
+// d_k (the Schur-complement diagonal) is dropped, with its row and column of
+// the factor set to zero, when d_k <= tau_rel * G_kk (the vector lies within
+// the span of the earlier kept ones to working accuracy) or
+// d_k <= tau_abs^2 * max_k ref2[k] (it is at round-off level relative to the
+// block before projection).  Writes Linv (s x s, zero rows/columns for dropped
+// vectors) and flags[k] = 1 for kept vectors.
+constexpr int CHOL_MAX = 96;
+
+__global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t s, double* Linv, int* flags,
+                                                        const double* ref2, double tau_rel, double tau_abs) {
+  __shared__ double Ls[CHOL_MAX][CHOL_MAX + 1];
+  __shared__ double Xs[CHOL_MAX][CHOL_MAX + 1];
+  __shared__ double d0[CHOL_MAX];
+  __shared__ int keep[CHOL_MAX];
+  __shared__ double red[16];
+  __shared__ double sh_ref;
+  const int tid = threadIdx.x;
+  double mx = 0.0;
+  if (ref2)
+    for (int64_t i = tid; i < s; i += blockDim.x) mx = fmax(mx, ref2[i]);
+  mx = warp_max(mx);
+  if ((tid & 63) == 0) red[tid >> 6] = mx;
+  for (int64_t e = tid; e < s * s; e += blockDim.x) {
+    const int64_t i = e / s, j = e - i * s;
+    Ls[i][j] = G[e];
+    if (i == j) d0[i] = G[e];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double v = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
+    sh_ref = v;
+  }
+  __syncthreads();
+  const double abs_floor = tau_abs * tau_abs * sh_ref;
+  for (int k = 0; k < s; ++k) {
+    const double d = Ls[k][k];
+    const int kp = (d0[k] > 0.0) && (d > tau_rel * d0[k]) && (d > abs_floor);
+    const double piv = kp ? sqrt(d) : 0.0;
+    __syncthreads();
+    for (int i = k + tid; i < s; i += blockDim.x) Ls[i][k] = kp ? (i == k ? piv : Ls[i][k] / piv) : 0.0;
+    if (tid == 0) keep[k] = kp;
+    __syncthreads();
+    if (kp) {
+      const int t = s - k - 1;
+      for (int e = tid; e < t * t; e += blockDim.x) {
+        const int i = k + 1 + e / t, j = k + 1 + e % t;
+        if (j <= i) Ls[i][j] -= Ls[i][k] * Ls[j][k];
+      }
+    }
+    __syncthreads();
+  }
+  // X = L^{-1} restricted to kept rows/columns: column c by forward substitution
+  for (int c = tid; c < s; c += blockDim.x) {
+    for (int i = 0; i < s; ++i) {
+      double v = 0.0;
+      if (keep[i] && keep[c] && i >= c) {
+        v = (i == c) ? 1.0 : 0.0;
+        for (int j = c; j < i; ++j) v -= Ls[i][j] * Xs[j][c];
+        v /= Ls[i][i];
+      }
+      Xs[i][c] = v;
+    }
+  }
+  __syncthreads();
+  for (int64_t e = tid; e < s * s; e += blockDim.x) {
+    const int64_t i = e / s, j = e - i * s;
+    Linv[e] = Xs[i][j];
+  }
+  for (int64_t i = tid; i < s; i += blockDim.x) flags[i] = keep[i];
+}
+
 // Left-looking Cholesky of the s x s Gram matrix G with column dropping, one
-// workgroup.  A pivot d_k = G_kk - sum_j L_kj^2 is dropped (column of L set
-// to zero) when d_k <= tau_rel * G_kk (the vector lies within the span of the
-// earlier kept ones to working accuracy) or d_k <= tau_abs^2 * max_k ref2[k]
-// (it is at round-off level relative to the block before projection).
+// workgroup, for s beyond the LDS variant (same drop rule).
 __global__ void __launch_bounds__(1024) chol_drop_kernel(const double* G, int64_t s, double* L, int* flags,
                                                          const double* ref2, double tau_rel, double tau_abs) {
   __shared__ double red[16];
@@ -85,7 +176,6 @@ __global__ void __launch_bounds__(1024) chol_drop_kernel(const double* G, int64_
   __shared__ int sh_keep;
   __shared__ double sh_piv;
   const int tid = threadIdx.x;
-  // max reference norm
   double mx = 0.0;
   if (ref2)
     for (int64_t i = tid; i < s; i += blockDim.x) mx = fmax(mx, ref2[i]);
@@ -155,24 +245,31 @@ __global__ void row_norms2_kernel(const double* Y, int64_t s, int64_t n, double*
 }
 
 // ------------------------------------------------------------ Jacobi
-// Block one-sided (Hestenes) Jacobi on the columns of a symmetric PSD matrix.
-// The n columns are split into nblk blocks of nb columns (zero-padded).
-// Rounds follow the circle method over blocks: in each round every
-// workgroup takes one pair of blocks, stages their 2*nb columns in LDS, and
-// orthogonalises every pair of those columns once (an inner cyclic sweep).
-// nblk - 1 rounds make one sweep; all workgroups meet at a grid barrier
-// between rounds.  The sweep ends the iteration when no pair needed a
-// rotation above tol (largest |cos| between two columns).  At convergence
-// A = Z V has orthogonal columns a_j = lambda_j v_j, so the eigenvalues are
-// the column norms and the eigenvectors the normalised columns.
+// Block one-sided (Hestenes) Jacobi on the columns of symmetric PSD matrices,
+// several matrices per launch.  The columns of each matrix are split into
+// nblk blocks of nb columns (zero-padded).  Rounds follow the circle method
+// over blocks: in each round a workgroup takes one pair of blocks and stages
+// their 2 nb columns P in LDS.  It forms the small Gram matrix G = P^T P once,
+// diagonalises it by cyclic two-sided Jacobi sweeps on G itself while
+// accumulating the rotation V (the rotation angles come from three entries of
+// G instead of three length-n dot products), and applies P <- P V once.  The
+// nblk - 1 rounds of a sweep are separated by grid barriers.  A matrix is done
+// when a whole sweep met no pair of its columns with |cos| above tol.  At
+// convergence A = Z V has orthogonal columns a_j = lambda_j v_j: eigenvalues
+// are the column norms and eigenvectors the normalised columns.
+constexpr int JAC_MAXB = 8;    // matrices per launch
+
 struct JacobiArgs {
-  double* A;        // npad x n column-major working copy (column j at A + j*n)
-  int64_t n, npad;
-  int nb, nblk;
-  int max_sweeps;
+  double* A[JAC_MAXB];         // npad x n column-major working copies
+  int64_t n[JAC_MAXB];
+  int nblk[JAC_MAXB];
+  int* info[JAC_MAXB];         // info[0]: 0 or sweeps at the limit, info[1]: sweeps used
+  int nmat, nb, npos, max_nblk;
+  int64_t ld;
+  int max_sweeps, inner_sweeps;
   double tol;
-  unsigned long long* offmax;   // [3] per-sweep max |cos| bit patterns (rotating slots)
-  int* info;
+  unsigned long long* offmax;  // [3][JAC_MAXB] per-sweep max |cos| bit patterns
+  unsigned long long* prof;    // nullable: phase clocks of workgroup 0 (diagnostics)
 };
 
 __device__ inline int circle_block(int pos, int round, int nblk) {
@@ -180,100 +277,237 @@ __device__ inline int circle_block(int pos, int round, int nblk) {
   return 1 + (pos - 1 + round) % (nblk - 1);
 }
 
+// Rotation (c, s) zeroing the (p, q) entry of a 2x2 Gram block
+// [al ga; ga be]: new_p = c p - s q, new_q = s p + c q.  Returns false when
+// |ga| <= tol sqrt(al be) (the pair is already orthogonal to tolerance).
+__device__ inline bool jacobi_rotation(double al, double be, double ga, double tol, double& c, double& s,
+                                       double& cosang) {
+  c = 1.0;
+  s = 0.0;
+  const double nrm = sqrt(fmax(al, 0.0) * fmax(be, 0.0));
+  if (!(nrm > 1e-300)) { cosang = 0.0; return false; }
+  cosang = fabs(ga) / nrm;
+  if (cosang <= tol) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = rsqrt(1.0 + t * t);
+  s = c * t;
+  return true;
+}
+
 __global__ void __launch_bounds__(1024) jacobi_kernel(JacobiArgs J) {
-  extern __shared__ double cols[];               // 2*nb columns of length n
+  extern __shared__ double sm[];
   __shared__ double sh_off[16];
-  __shared__ int sh_stop;
+  __shared__ int sh_done[JAC_MAXB];
   cg::grid_group grid = cg::this_grid();
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  const int64_t n = J.n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = blockIdx.x / J.npos, pos = blockIdx.x % J.npos;
   const int nb = J.nb, two = 2 * nb;
+  const int nbk = (two + 15) / 16;                 // 16-wide MFMA blocks across the pair
+  const int64_t n = J.n[m];
+  const int64_t ld = J.ld;                         // odd stride >= n: conflict-free column reads
+  double* P = sm;                                  // columns-major [two][ld]
+  double* G = P + (int64_t)two * ld;               // [two][two + 1]
+  double* V = G + two * (two + 1);
+  double* S = V + two * (two + 1);                 // Gram partials [16][256]
+  const int gs = two + 1;
+  if (tid < JAC_MAXB) sh_done[tid] = 0;
+  __syncthreads();
   int sweep;
   for (sweep = 0; sweep < J.max_sweeps; ++sweep) {
-    // slot sweep%3 collects this sweep; slot (sweep+1)%3 was last read two
-    // grid barriers ago and is cleared for the next sweep
-    if (blockIdx.x == 0 && tid == 0) J.offmax[(sweep + 1) % 3] = 0ull;
+    if (blockIdx.x == 0 && tid < J.nmat) J.offmax[((sweep + 1) % 3) * JAC_MAXB + tid] = 0ull;
     double local_off = 0.0;
-    for (int round = 0; round < J.nblk - 1; ++round) {
-      const int pos = blockIdx.x;
-      const int bp = circle_block(pos, round, J.nblk);
-      const int bq = circle_block(J.nblk - 1 - pos, round, J.nblk);
-      // stage: local column c < nb from block bp, else from bq
-      for (int64_t e = tid; e < (int64_t)two * n; e += blockDim.x) {
-        const int c = (int)(e / n);
-        const int64_t r = e - (int64_t)c * n;
-        const int gc = (c < nb ? bp * nb + c : bq * nb + (c - nb));
-        cols[e] = J.A[(int64_t)gc * n + r];
-      }
-      __syncthreads();
-      // inner cyclic sweep over the 2nb local columns (circle method again)
-      for (int ir = 0; ir < two - 1; ++ir) {
-        for (int pr = wave; pr < nb; pr += nwaves) {
-          const int p = circle_block(pr, ir, two);
-          const int q = circle_block(two - 1 - pr, ir, two);
-          double* cp = cols + (int64_t)p * n;
-          double* cq = cols + (int64_t)q * n;
-          double al = 0.0, be = 0.0, ga = 0.0;
-          for (int64_t r = lane; r < n; r += 64) {
-            const double x = cp[r], y = cq[r];
-            al = fma(x, x, al);
-            be = fma(y, y, be);
-            ga = fma(x, y, ga);
+    const bool mine = !sh_done[m] && pos < J.nblk[m] / 2;
+    for (int round = 0; round < J.max_nblk - 1; ++round) {
+      unsigned long long t0 = wall_clock64();
+      if (mine && round < J.nblk[m] - 1) {
+        const int bp = circle_block(pos, round, J.nblk[m]);
+        const int bq = circle_block(J.nblk[m] - 1 - pos, round, J.nblk[m]);
+        double* A = J.A[m];
+        for (int c = wave; c < two; c += 16) {
+          const int gc = c < nb ? bp * nb + c : bq * nb + (c - nb);
+          const double* src = A + (int64_t)gc * n;
+          for (int64_t r = lane; r < n; r += 64) P[c * ld + r] = src[r];
+        }
+        __syncthreads();
+        unsigned long long t1 = wall_clock64();
+        // G = P^T P on fp64 MFMA 16x16x4: wave w takes output block (w % nbk^2)
+        // and K slice (w / nbk^2); slices are summed through LDS.
+        {
+          const int nblk2 = nbk * nbk;
+          const int nslice = 16 / nblk2;
+          const int blk = wave % nblk2, sl = wave / nblk2;
+          const int bi = blk / nbk, bj = blk % nbk;
+          const int i = bi * 16 + (lane & 15), j = bj * 16 + (lane & 15);
+          const int64_t ksteps = (n + 3) / 4;
+          const int64_t k0 = ksteps * sl / nslice, k1 = ksteps * (sl + 1) / nslice;
+          f64x4_t d = {0.0, 0.0, 0.0, 0.0};
+          for (int64_t kt = k0; kt < k1; ++kt) {
+            const int64_t r = kt * 4 + (lane >> 4);
+            const double a = (i < two && r < n) ? P[i * ld + r] : 0.0;
+            const double b = (j < two && r < n) ? P[j * ld + r] : 0.0;
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
           }
-          al = warp_sum(al);
-          be = warp_sum(be);
-          ga = warp_sum(ga);
-          const double nrm = sqrt(al) * sqrt(be);
-          if (nrm > 1e-300) {
-            const double cosang = fabs(ga) / nrm;
-            local_off = fmax(local_off, cosang);
-            if (cosang > J.tol) {
-              const double zeta = (be - al) / (2.0 * ga);
-              const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-              const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-              for (int64_t r = lane; r < n; r += 64) {
-                const double x = cp[r], y = cq[r];
-                cp[r] = c * x - s * y;
-                cq[r] = s * x + c * y;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) S[(sl * nblk2 + blk) * 256 + (4 * v + (lane >> 4)) * 16 + (lane & 15)] = d[v];
+          __syncthreads();
+          for (int e = tid; e < two * two; e += blockDim.x) {
+            const int ii = e / two, jj = e % two;
+            const int b2 = (ii >> 4) * nbk + (jj >> 4);
+            double acc = 0.0;
+            for (int q = 0; q < nslice; ++q) acc += S[(q * nblk2 + b2) * 256 + (ii & 15) * 16 + (jj & 15)];
+            G[ii * gs + jj] = acc;
+            V[ii * gs + jj] = ii == jj ? 1.0 : 0.0;
+          }
+          __syncthreads();
+        }
+        unsigned long long t2 = wall_clock64();
+        // inner cyclic sweep on G (two-sided), accumulating V.  Waves 0..3 do
+        // the work: lane (l & 3) of wave w computes the rotation of pair
+        // 4w + (l & 3); the 16 lanes of quarter l >> 4 then update that pair's
+        // rows, and after a barrier its columns of G and V.
+        const int pwaves = (nb + 3) / 4;
+        for (int isw = 0; isw < J.inner_sweeps; ++isw) {
+          double inner_off = 0.0;
+          for (int ir = 0; ir < two - 1; ++ir) {
+            double c = 1.0, s = 0.0;
+            int p = 0, q = 0;
+            if (wave < pwaves) {
+              const int k = wave * 4 + (lane & 3);
+              if (k < nb) {
+                p = circle_block(k, ir, two);
+                q = circle_block(two - 1 - k, ir, two);
+                double ca;
+                jacobi_rotation(G[p * gs + p], G[q * gs + q], G[p * gs + q], J.tol, c, s, ca);
+                inner_off = fmax(inner_off, ca);
+              }
+              const int src = lane >> 4;           // pair of this quarter-wave
+              c = __shfl(c, src, 64);
+              s = __shfl(s, src, 64);
+              p = __shfl(p, src, 64);
+              q = __shfl(q, src, 64);
+              const int k2 = wave * 4 + src;
+              if (k2 < nb && s != 0.0) {
+                for (int jj = (lane & 15); jj < two; jj += 16) {
+                  const double gp = G[p * gs + jj], gq = G[q * gs + jj];
+                  G[p * gs + jj] = c * gp - s * gq;
+                  G[q * gs + jj] = s * gp + c * gq;
+                }
+              }
+            }
+            __syncthreads();
+            if (wave < pwaves) {
+              const int k2 = wave * 4 + (lane >> 4);
+              if (k2 < nb && s != 0.0) {
+                for (int ii = (lane & 15); ii < two; ii += 16) {
+                  const double gp = G[ii * gs + p], gq = G[ii * gs + q];
+                  G[ii * gs + p] = c * gp - s * gq;
+                  G[ii * gs + q] = s * gp + c * gq;
+                  const double vp = V[ii * gs + p], vq = V[ii * gs + q];
+                  V[ii * gs + p] = c * vp - s * vq;
+                  V[ii * gs + q] = s * vp + c * vq;
+                }
+              }
+            }
+            __syncthreads();
+          }
+          double w = warp_max(inner_off);
+          if (lane == 0) sh_off[wave] = w;
+          __syncthreads();
+          double mx = 0.0;
+          for (int k = 0; k < (int)(blockDim.x >> 6); ++k) mx = fmax(mx, sh_off[k]);
+          __syncthreads();
+          if (isw == 0) local_off = fmax(local_off, mx);
+          if (mx <= J.tol) break;
+        }
+        unsigned long long t3 = wall_clock64();
+        // A(:, pair) <- P V on fp64 MFMA: 16 x 16 output blocks over
+        // (row block, column block), K = two.
+        {
+          const int64_t rblocks = (n + 15) / 16;
+          const int64_t nblocks = rblocks * nbk;
+          for (int64_t ob = wave; ob < nblocks; ob += 16) {
+            const int64_t rb = ob / nbk;
+            const int cb = (int)(ob % nbk);
+            const int64_t r = rb * 16 + (lane & 15);
+            const int j = cb * 16 + (lane & 15);
+            f64x4_t d = {0.0, 0.0, 0.0, 0.0};
+            for (int kt = 0; kt < (two + 3) / 4; ++kt) {
+              const int k = kt * 4 + (lane >> 4);
+              const double a = (r < n && k < two) ? P[k * ld + r] : 0.0;
+              const double b = (j < two && k < two) ? V[k * gs + j] : 0.0;
+              d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+            }
+            const int jo = cb * 16 + (lane & 15);
+            if (jo < two) {
+              const int gc = jo < nb ? bp * nb + jo : bq * nb + (jo - nb);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int64_t ro = rb * 16 + 4 * v + (lane >> 4);
+                if (ro < n) A[(int64_t)gc * n + ro] = d[v];
               }
             }
           }
         }
-        __syncthreads();
+        __threadfence();
+        if (J.prof && blockIdx.x == 0 && tid == 0) {
+          unsigned long long t4 = wall_clock64();
+          J.prof[0] += t1 - t0;
+          J.prof[1] += t2 - t1;
+          J.prof[2] += t3 - t2;
+          J.prof[3] += t4 - t3;
+          J.prof[5] += 1;
+        }
       }
-      for (int64_t e = tid; e < (int64_t)two * n; e += blockDim.x) {
-        const int c = (int)(e / n);
-        const int64_t r = e - (int64_t)c * n;
-        const int gc = (c < nb ? bp * nb + c : bq * nb + (c - nb));
-        J.A[(int64_t)gc * n + r] = cols[e];
-      }
-      __threadfence();
+      unsigned long long tg = wall_clock64();
       grid.sync();
+      if (J.prof && blockIdx.x == 0 && tid == 0) J.prof[4] += wall_clock64() - tg;
     }
-    // publish this workgroup's largest |cos| of the sweep
-    local_off = warp_max(local_off);
-    if (lane == 0) sh_off[wave] = local_off;
-    __syncthreads();
-    if (tid == 0) {
-      double v = 0.0;
-      for (int w = 0; w < nwaves; ++w) v = fmax(v, sh_off[w]);
-      atomicMax(&J.offmax[sweep % 3], (unsigned long long)__double_as_longlong(v));
-    }
+    // publish this workgroup's largest |cos| of the sweep (first inner sweep of
+    // each round: the state before any rotation of that round)
+    if (tid == 0 && mine)
+      atomicMax(&J.offmax[(sweep % 3) * JAC_MAXB + m], (unsigned long long)__double_as_longlong(local_off));
     __threadfence();
     grid.sync();
-    if (tid == 0) {
-      const double v = __longlong_as_double((long long)__atomic_load_n(&J.offmax[sweep % 3], __ATOMIC_RELAXED));
-      sh_stop = v <= J.tol;
+    if (tid < J.nmat && !sh_done[tid]) {
+      const double v = __longlong_as_double(
+          (long long)__atomic_load_n(&J.offmax[(sweep % 3) * JAC_MAXB + tid], __ATOMIC_RELAXED));
+      if (v <= J.tol) {
+        sh_done[tid] = 1;
+        if (blockIdx.x == 0) {
+          J.info[tid][0] = 0;
+          J.info[tid][1] = sweep + 1;
+        }
+      }
     }
     __syncthreads();
-    if (sh_stop) break;
+    bool all = true;
+    for (int k = 0; k < J.nmat; ++k) all = all && sh_done[k];
+    if (all) break;
   }
-  if (blockIdx.x == 0 && tid == 0) *J.info = (sweep >= J.max_sweeps) ? sweep : 0;
+  if (blockIdx.x == 0 && tid < J.nmat && !sh_done[tid]) {
+    J.info[tid][0] = sweep;
+    J.info[tid][1] = sweep;
+  }
 }
 
 // Column norms of the converged A, then a rank sort (descending, ties by
-// index) and normalised columns as rows of Vt.
-__global__ void jacobi_finish_kernel(const double* A, int64_t n, double* lam, double* Vt, double* norms) {
+// index) and normalised columns as rows of Vt.  One workgroup per matrix.
+struct FinishArgs {
+  const double* A[JAC_MAXB];
+  int64_t n[JAC_MAXB];
+  double* lam[JAC_MAXB];
+  double* Vt[JAC_MAXB];
+  double* norms[JAC_MAXB];
+};
+
+__global__ void jacobi_finish_kernel(FinishArgs F) {
+  const int m = blockIdx.x;
+  const double* A = F.A[m];
+  const int64_t n = F.n[m];
+  double* lam = F.lam[m];
+  double* Vt = F.Vt[m];
+  double* norms = F.norms[m];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
   for (int64_t j = wave; j < n; j += nwaves) {
     double acc = 0.0;
@@ -290,7 +524,6 @@ __global__ void jacobi_finish_kernel(const double* A, int64_t n, double* lam, do
       rank += (w > v) || (w == v && i < j);
     }
     lam[rank] = v;
-    // stash the destination row in the sign-free slot: handled below
     norms[n + j] = (double)rank;
   }
   __syncthreads();
@@ -366,11 +599,34 @@ inline unsigned grid_for(int64_t work, int64_t per = 256, int64_t cap = 8192) {
 
 }  // namespace
 
+// per host thread: the scratch of the call being enqueued by that thread
+static thread_local double* g_dgemm_scratch = nullptr;
+static thread_local size_t g_dgemm_scratch_bytes = 0;
+
+void dgemm_set_scratch(double* p, size_t bytes) {
+  g_dgemm_scratch = p;
+  g_dgemm_scratch_bytes = bytes;
+}
+
 hipError_t dgemm(int opA, int opB, int64_t m, int64_t n, int64_t k, double alpha, const double* A, int64_t lda,
                  const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  dim3 grid((unsigned)ceil_div(n, GT), (unsigned)ceil_div(m, GT));
-  hipLaunchKernelGGL(dgemm_kernel, grid, dim3(256), 0, s, opA, opB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+  const int64_t tiles = ceil_div(m, GT) * ceil_div(n, GT);
+  int64_t splits = ceil_div(256, tiles);
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, k / 64));
+  splits = std::min<int64_t>(splits, 64);
+  if (g_dgemm_scratch == nullptr) splits = 1;
+  while (splits > 1 && (size_t)splits * m * n * 8 > g_dgemm_scratch_bytes) --splits;
+  const int64_t kchunk = splits > 1 ? ceil_div(ceil_div(k, splits), GK) * GK : std::max<int64_t>(k, 1);
+  splits = splits > 1 ? ceil_div(k, kchunk) : 1;
+  dim3 grid((unsigned)ceil_div(n, GT), (unsigned)ceil_div(m, GT), (unsigned)splits);
+  double* part = splits > 1 ? g_dgemm_scratch : nullptr;
+  hipLaunchKernelGGL(dgemm_kernel, grid, dim3(256), 0, s, opA, opB, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                     part, kchunk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits == 1) return e;
+  hipLaunchKernelGGL(dgemm_reduce_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(m * n, 256), 4096)), dim3(256), 0, s,
+                     m, n, (int)splits, part, alpha, beta, C, ldc);
   return hipGetLastError();
 }
 
@@ -380,20 +636,35 @@ hipError_t row_norms2(const double* Y, int64_t s, int64_t n, double* out, hipStr
   return hipGetLastError();
 }
 
-hipError_t chol_orth(double* Y, int64_t s, int64_t n, double* G, double* Lm, int* flags, const double* ref2,
-                     double tau_rel, double tau_abs, hipStream_t st) {
+hipError_t chol_orth(double* Y, double* Yout, int64_t s, int64_t n, double* G, double* Lm, int* flags,
+                     const double* ref2, double tau_rel, double tau_abs, hipStream_t st) {
   if (s <= 0) return hipSuccess;
   hipError_t e = dgemm(0, 1, s, s, n, 1.0, Y, n, Y, n, 0.0, G, s, st);
   if (e != hipSuccess) return e;
+  if (s <= CHOL_MAX) {
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, G, s, Lm, flags, ref2, tau_rel, tau_abs);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return dgemm(0, 0, s, n, s, 1.0, Lm, s, Y, n, 0.0, Yout, n, st);
+  }
   hipLaunchKernelGGL(chol_drop_kernel, dim3(1), dim3(1024), 0, st, G, s, Lm, flags, ref2, tau_rel, tau_abs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(trsm_rows_kernel, dim3(grid_for(n)), dim3(256), 0, st, Y, s, n, Lm, flags);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return copy_rows_f64(Yout, n, Y, n, s, n, st);
+}
+
+// Block width: the staged pair (2 nb columns of length n), G, V and the
+// Gram partials (16 x 256 doubles) must fit in 160 KB of LDS.
+static size_t jacobi_lds_bytes(int64_t n, int nb) {
+  const int two = 2 * nb;
+  const int64_t ld = (n & 1) ? n : n + 1;
+  return (size_t)(two * ld + 2 * two * (two + 1) + 16 * 256) * 8;
 }
 
 static void jacobi_geometry(int64_t n, int& nb, int& nblk) {
-  nb = n <= 512 ? 16 : 8;
-  if (n <= 32) nb = (int)std::max<int64_t>(1, (n + 1) / 2);
+  nb = 16;
+  while (nb > 2 && jacobi_lds_bytes(n, nb) > 160 * 1024 - 1024) nb /= 2;
+  if (n <= 2 * nb) nb = (int)std::max<int64_t>(1, (n + 1) / 2);
   nblk = (int)ceil_div(n, nb);
   if (nblk < 2) nblk = 2;
   if (nblk & 1) ++nblk;
@@ -402,42 +673,79 @@ static void jacobi_geometry(int64_t n, int& nb, int& nblk) {
 size_t jacobi_work_bytes(int64_t n) {
   // npad <= n + 2 * nb <= n + 32, so this bound grows with n and covers every
   // smaller matrix that reuses the same scratch
-  return (size_t)((n + 32) * n * 8 + 2 * n * 8 + 64);  // A, norms/ranks, offmax[3]
+  return (size_t)((n + 32) * n * 8 + 2 * n * 8 + 256);  // A, norms/ranks, offmax
+}
+
+hipError_t jacobi_eig_batched(int nmat, const double* const* Z, const int64_t* ns, double* const* lam,
+                              double* const* Vt, void* const* work, int* const* info, int max_sweeps, hipStream_t st) {
+  if (nmat <= 0) return hipSuccess;
+  if (nmat > JAC_MAXB) return hipErrorInvalidValue;
+  int64_t nmax = 0;
+  for (int k = 0; k < nmat; ++k) nmax = std::max(nmax, ns[k]);
+  int nb, nblk_dummy;
+  jacobi_geometry(nmax, nb, nblk_dummy);
+  JacobiArgs ja = {};
+  FinishArgs fa = {};
+  ja.nmat = nmat;
+  ja.nb = nb;
+  ja.max_sweeps = max_sweeps;
+  ja.inner_sweeps = 1;
+  if (const char* e = getenv("RBKI_JACOBI_INNER")) ja.inner_sweeps = std::max(1, atoi(e));
+  ja.tol = 1e-12;
+  ja.max_nblk = 2;
+  hipError_t e;
+  for (int k = 0; k < nmat; ++k) {
+    const int64_t n = ns[k];
+    int nbk = (int)ceil_div(n, nb);
+    if (nbk < 2) nbk = 2;
+    if (nbk & 1) ++nbk;
+    const int64_t npad = (int64_t)nb * nbk;
+    char* w = (char*)work[k];
+    ja.A[k] = (double*)w;
+    ja.n[k] = n;
+    ja.nblk[k] = nbk;
+    ja.info[k] = info[k];
+    ja.max_nblk = std::max(ja.max_nblk, nbk);
+    fa.A[k] = ja.A[k];
+    fa.n[k] = n;
+    fa.lam[k] = lam[k];
+    fa.Vt[k] = Vt[k];
+    fa.norms[k] = (double*)(w + npad * n * 8);
+    hipLaunchKernelGGL(pad_copy_kernel, dim3(grid_for(npad * n)), dim3(256), 0, st, Z[k], n, npad, ja.A[k]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // the convergence slots live after matrix 0's scratch
+  {
+    int nb0 = (int)ceil_div(ns[0], nb);
+    if (nb0 < 2) nb0 = 2;
+    if (nb0 & 1) ++nb0;
+    (void)nb0;
+  }
+  ja.offmax = (unsigned long long*)((char*)work[0] + jacobi_work_bytes(ns[0]) - 256);
+  ja.prof = getenv("RBKI_JACOBI_PROF") ? ja.offmax + 3 * JAC_MAXB : nullptr;   // 6 slots after offmax
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(64), 0, st, (unsigned*)ja.offmax, (size_t)(3 * JAC_MAXB * 2 + 12));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  ja.npos = ja.max_nblk / 2;
+  ja.ld = (nmax & 1) ? nmax : nmax + 1;
+  const size_t shmem = jacobi_lds_bytes(nmax, nb);
+  e = hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+  if (e != hipSuccess) return e;
+  void* args[] = {&ja};
+  e = hipLaunchCooperativeKernel((const void*)jacobi_kernel, dim3(ja.npos * nmat), dim3(1024), args, shmem, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(nmat), dim3(1024), 0, st, fa);
+  return hipGetLastError();
 }
 
 hipError_t jacobi_eig(const double* Z, int64_t n, double* lam, double* Vt, void* work, int* info, int max_sweeps,
                       hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int nb, nblk;
-  jacobi_geometry(n, nb, nblk);
-  const int64_t npad = (int64_t)nb * nblk;
-  char* w = (char*)work;
-  double* A = (double*)w;
-  double* norms = (double*)(w + npad * n * 8);
-  unsigned long long* offmax = (unsigned long long*)(w + npad * n * 8 + 2 * n * 8);
-  hipLaunchKernelGGL(pad_copy_kernel, dim3(grid_for(npad * n)), dim3(256), 0, st, Z, n, npad, A);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3(1), dim3(64), 0, st, (unsigned*)offmax, (size_t)6);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  JacobiArgs ja;
-  ja.A = A;
-  ja.n = n;
-  ja.npad = npad;
-  ja.nb = nb;
-  ja.nblk = nblk;
-  ja.max_sweeps = max_sweeps;
-  ja.tol = 1e-13;
-  ja.offmax = offmax;
-  ja.info = info;
-  void* args[] = {&ja};
-  const size_t shmem = (size_t)2 * nb * n * 8;
-  e = hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  if (e != hipSuccess) return e;
-  e = hipLaunchCooperativeKernel((const void*)jacobi_kernel, dim3(nblk / 2), dim3(1024), args, shmem, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(jacobi_finish_kernel, dim3(1), dim3(1024), 0, st, A, n, lam, Vt, norms);
-  return hipGetLastError();
+  const double* Zs[1] = {Z};
+  int64_t ns[1] = {n};
+  double* ls[1] = {lam};
+  double* vs[1] = {Vt};
+  void* ws[1] = {work};
+  int* is[1] = {info};
+  return jacobi_eig_batched(1, Zs, ns, ls, vs, ws, is, max_sweeps, st);
 }
 
 hipError_t copy_rows_f64(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows, int64_t cols,

@@ -39,14 +39,18 @@ hipError_t dgemm(int opA, int opB, int64_t m, int64_t n, int64_t k, double alpha
                  int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                  hipStream_t s);
 
-// Orthonormalise the rows of Y (s x n, row-major: s vectors of length n) in
-// place by CholeskyQR with column dropping (directions whose pivot falls
-// below tau_rel * (pivot scale) or below the absolute floor abs2[k] are set to
-// zero).  G is s x s scratch, L is s x s scratch, flags (int[s]) receives 1
-// for kept vectors.  ref2 (device, s doubles, nullable) gives per-vector
-// squared reference norms for the absolute floor.
-hipError_t chol_orth(double* Y, int64_t s, int64_t n, double* G, double* Lm, int* flags,
+// Orthonormalise the rows of Y (s x n, row-major: s vectors of length n) by
+// CholeskyQR with column dropping, writing the result to Yout (which must not
+// alias Y; Y is clobbered when s exceeds the in-LDS variant).  A pivot is
+// dropped (its vector set to zero) when it falls below tau_rel times its own
+// Gram diagonal or below tau_abs^2 times the largest ref2 entry.  G and Lm
+// are s x s scratch; flags (int[s]) receives 1 for kept vectors; ref2
+// (device, s doubles, nullable) holds squared reference norms.
+hipError_t chol_orth(double* Y, double* Yout, int64_t s, int64_t n, double* G, double* Lm, int* flags,
                      const double* ref2, double tau_rel, double tau_abs, hipStream_t st);
+
+// Scratch for split-K float64 GEMMs (nullptr disables split-K).
+void dgemm_set_scratch(double* p, size_t bytes);
 
 // Row norms squared of Y (s x n) -> out[s].
 hipError_t row_norms2(const double* Y, int64_t s, int64_t n, double* out, hipStream_t st);
@@ -58,6 +62,11 @@ hipError_t row_norms2(const double* Y, int64_t s, int64_t n, double* out, hipStr
 size_t jacobi_work_bytes(int64_t n);
 hipError_t jacobi_eig(const double* Z, int64_t n, double* lam, double* Vt, void* work, int* info,
                       int max_sweeps, hipStream_t st);
+// The same for up to 8 matrices in one launch (each with its own scratch;
+// info[k] points at two ints per matrix).
+hipError_t jacobi_eig_batched(int nmat, const double* const* Z, const int64_t* n, double* const* lam,
+                              double* const* Vt, void* const* work, int* const* info, int max_sweeps,
+                              hipStream_t st);
 
 // Copy / convert helpers.
 hipError_t copy_rows_f64(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows,
