@@ -120,6 +120,7 @@ struct Plan {
   int telem = 0;     // first mode product (reads X)
   int celem = 0;     // later mode products, reconstruction and error
   bool need_xconv = false;
+  bool need_xt = false;      // transposed bf16 copy for the last mode (large-tile Gram)
   int64_t T = 1;
   ModeGeom m[8];
   int first_mode = 0;
@@ -164,6 +165,7 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     P.celem = E_F32;
     P.need_xconv = P.xelem != E_BF16;
   }
+  P.need_xt = P.gelem == E_BF16;
   double best = -1.0;
   for (int n = 0; n < P.N; ++n) {
     ModeGeom& g = P.m[n];
@@ -186,8 +188,14 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     P.maxSp = std::max(P.maxSp, g.Sp);
     P.maxRI = std::max(P.maxRI, g.R * g.I);
     P.maxSJ = std::max(P.maxSJ, g.S * g.J);
-    GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)g.S, cu_count());
-    P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(ga, P.gelem));
+    if (P.gelem == E_BF16) {
+      GramArgs ga = g.B > 1 ? gram_plan_big(g.A, g.I, g.B, (int)g.S, cu_count())
+                            : gram_plan_big(1, g.I, g.A, (int)g.S, cu_count());
+      P.partial_bytes = std::max(P.partial_bytes, gram_big_partial_bytes(ga));
+    } else {
+      GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)g.S, cu_count());
+      P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(ga, P.gelem));
+    }
   }
   // chain sizes: core chain starting with first_mode, then ascending; the
   // reconstruction chain expands modes 1..N-1 from the core.
@@ -221,6 +229,7 @@ struct Arena {
 
 struct Buffers {
   void* xconv = nullptr;
+  void* xt = nullptr;      // last mode, transposed bf16 copy (I_N x prod_{k<N} I_k)
   void* omegaT = nullptr;
   void* partial = nullptr;
   double* C = nullptr;
@@ -251,6 +260,7 @@ struct Buffers {
 void carve(const Plan& P, Arena& ar, Buffers& b) {
   const int es_g = elem_size(P.gelem);
   if (P.need_xconv) b.xconv = ar.take((size_t)P.T * elem_size(P.telem));
+  if (P.need_xt) b.xt = ar.take((size_t)P.T * 2);
   b.omegaT = ar.take((size_t)P.maxSJ * es_g);
   b.partial = ar.take(P.partial_bytes);
   b.C = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
@@ -306,16 +316,30 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
     ProfScope ps("omega", st);
     HIPCHK(launch_omega(P.gelem, P.seed, n, S * g.J, b.omegaT, st));
   }
-  GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)S, cu_count());
-  ga.X = xsrc;
-  ga.omegaT = b.omegaT;
-  ga.partial = b.partial;
-  {
-    ProfScope ps("gram", st);
-    HIPCHK(launch_gram_main(P.gelem, ga, st));
-  }
   // C -> b.C (I x I), W^T -> b.Yt (S x I)
-  HIPCHK(launch_gram_reduce(P.gelem, ga, b.C, b.Yt, st));
+  if (P.gelem == E_BF16) {
+    // k-contiguous view of every mode: the last one reads the transposed copy
+    GramArgs ga = g.B > 1 ? gram_plan_big(g.A, g.I, g.B, (int)S, cu_count())
+                          : gram_plan_big(1, g.I, g.A, (int)S, cu_count());
+    ga.X = g.B > 1 ? xsrc : b.xt;
+    ga.omegaT = b.omegaT;
+    ga.partial = b.partial;
+    {
+      ProfScope ps("gram", st);
+      HIPCHK(launch_gram_big(ga, st));
+    }
+    HIPCHK(launch_gram_big_reduce(ga, b.C, b.Yt, st));
+  } else {
+    GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)S, cu_count());
+    ga.X = xsrc;
+    ga.omegaT = b.omegaT;
+    ga.partial = b.partial;
+    {
+      ProfScope ps("gram", st);
+      HIPCHK(launch_gram_main(P.gelem, ga, st));
+    }
+    HIPCHK(launch_gram_reduce(P.gelem, ga, b.C, b.Yt, st));
+  }
 
   // block 0: Q_0 = orth(W)
   HIPCHK(row_norms2(b.Yt, S, I, b.ref2, st));
@@ -558,6 +582,11 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
     HIPCHK(convert_tensor(P.xelem, X, P.telem, b.xconv, P.T, st));
     xsrc = b.xconv;
   }
+  if (P.need_xt) {
+    ProfScope ps("convert", st);
+    const ModeGeom& gl = P.m[P.N - 1];
+    HIPCHK(launch_transpose_bf16(P.xelem, X, gl.A, gl.I, b.xt, st));
+  }
   s = run_mode(P, b, xsrc, mode, false, st);
   if (s != RBKI_OK) return s;
   const ModeGeom& g = P.m[mode];
@@ -604,6 +633,11 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
     ProfScope ps("convert", st);
     HIPCHK(convert_tensor(P.xelem, X, P.telem, b.xconv, P.T, st));
     xsrc = b.xconv;
+  }
+  if (P.need_xt) {
+    ProfScope ps("convert", st);
+    const ModeGeom& gl = P.m[P.N - 1];
+    HIPCHK(launch_transpose_bf16(P.xelem, X, gl.A, gl.I, b.xt, st));
   }
   HIPCHK(fill_zero(b.info, 64, st));
   for (int n = 0; n < P.N; ++n) {
