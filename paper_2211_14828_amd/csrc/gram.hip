@@ -32,11 +32,20 @@ struct Stage {
   static constexpr int BK = Mma<E>::BK;
   static constexpr int EPC = 16 / (int)sizeof(T);     // elements per 16-byte chunk
   uint4 chunk[4];
+  unsigned valid;                                     // VEC form: bit j = chunk j in range
 };
 
 // Load one operand tile (128 rows x BK k) of the mode view into registers.
-// rows_from_omega: rows are sketch columns s (rows of Omega^T, length J).
-template <int E>
+// omega_rows: rows are sketch columns s (rows of Omega^T, length J).
+//
+// VEC (rows and row strides a multiple of 16 bytes, so a 16-byte chunk is
+// either wholly inside the tile or wholly outside): every lane issues its
+// loads unconditionally from a clamped, always valid address and records
+// which chunks are real; the mask is applied when the chunks are written to
+// LDS.  No load sits under divergent control flow, so all of them stay in
+// flight together while the previous K tile is multiplied.  The other form
+// reads element by element with per-element bounds.
+template <int E, bool VEC>
 __device__ inline void load_operand(Stage<E>& st, const GramArgs& g, const void* base, bool omega_rows,
                                     int64_t row0, int64_t nrows, int64_t a, int64_t b0, int64_t kvalid) {
   typedef typename Mma<E>::T T;
@@ -44,27 +53,34 @@ __device__ inline void load_operand(Stage<E>& st, const GramArgs& g, const void*
   constexpr int BK = Stage<E>::BK;
   const T* X = (const T*)base;
   const int tid = threadIdx.x;
+  if (VEC) st.valid = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = tid + 256 * j;
-    union { uint4 v; T e[EPC]; } u;
-    u.v = make_uint4(0, 0, 0, 0);
     if (g.B > 1 || omega_rows) {
       // chunk c: row c / (BK/EPC), k offset (c % (BK/EPC)) * EPC
       const int row = c / (BK / EPC);
       const int kk = (c % (BK / EPC)) * EPC;
       const int64_t r = row0 + row;
-      if (r < nrows) {
-        int64_t off;
-        if (omega_rows) off = r * g.J + (g.B > 1 ? a * g.B + b0 : b0) + kk;
-        else off = (a * g.I + r) * g.B + b0 + kk;
-        if (kk + EPC <= kvalid && g.vec_ok) {
-          u.v = *(const uint4*)(X + off);
-        } else {
+      if (VEC) {
+        const bool ok = r < nrows && kk < kvalid;
+        const int64_t rc = r < nrows ? r : nrows - 1;
+        const int kc = kk < kvalid ? kk : 0;
+        const int64_t off = omega_rows ? rc * g.J + (g.B > 1 ? a * g.B + b0 : b0) + kc
+                                       : (a * g.I + rc) * g.B + b0 + kc;
+        st.chunk[j] = *(const uint4*)(X + off);
+        st.valid |= ok ? 1u << j : 0u;
+      } else {
+        union { uint4 v; T e[EPC]; } u;
+        u.v = make_uint4(0, 0, 0, 0);
+        if (r < nrows) {
+          const int64_t off = omega_rows ? r * g.J + (g.B > 1 ? a * g.B + b0 : b0) + kk
+                                         : (a * g.I + r) * g.B + b0 + kk;
 #pragma unroll
           for (int e = 0; e < EPC; ++e)
             if (kk + e < kvalid) u.e[e] = X[off + e];
         }
+        st.chunk[j] = u.v;
       }
     } else {
       // B == 1, rows of X_(n) are the contiguous index: chunk c covers EPC
@@ -73,22 +89,28 @@ __device__ inline void load_operand(Stage<E>& st, const GramArgs& g, const void*
       const int kk = c / per_k;
       const int row = (c % per_k) * EPC;
       const int64_t r = row0 + row;
-      if (kk < kvalid) {
-        const int64_t off = (b0 + kk) * g.I + r;       // b0 is a0 here
-        if (r + EPC <= nrows && g.vec_ok) {
-          u.v = *(const uint4*)(X + off);
-        } else {
+      if (VEC) {
+        const bool ok = kk < kvalid && r < nrows;
+        const int64_t rc = r < nrows ? r : nrows - EPC;
+        const int kc = kk < kvalid ? kk : 0;
+        st.chunk[j] = *(const uint4*)(X + (b0 + kc) * g.I + rc);   // b0 is a0 here
+        st.valid |= ok ? 1u << j : 0u;
+      } else {
+        union { uint4 v; T e[EPC]; } u;
+        u.v = make_uint4(0, 0, 0, 0);
+        if (kk < kvalid) {
+          const int64_t off = (b0 + kk) * g.I + r;
 #pragma unroll
           for (int e = 0; e < EPC; ++e)
             if (r + e < nrows) u.e[e] = X[off + e];
         }
+        st.chunk[j] = u.v;
       }
     }
-    st.chunk[j] = u.v;
   }
 }
 
-template <int E>
+template <int E, bool VEC>
 __device__ inline void store_operand(const Stage<E>& st, const GramArgs& g, bool omega_rows, char* lds) {
   typedef typename Mma<E>::T T;
   constexpr int EPC = Stage<E>::EPC;
@@ -97,16 +119,18 @@ __device__ inline void store_operand(const Stage<E>& st, const GramArgs& g, bool
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = tid + 256 * j;
+    uint4 v = st.chunk[j];
+    if (VEC && !((st.valid >> j) & 1u)) v = make_uint4(0, 0, 0, 0);
     if (g.B > 1 || omega_rows) {
       const int row = c / (BK / EPC);
       const int kk = (c % (BK / EPC)) * EPC;
-      *(uint4*)(lds + row * LDS_ROW + kk * (int)sizeof(T)) = st.chunk[j];
+      *(uint4*)(lds + row * LDS_ROW + kk * (int)sizeof(T)) = v;
     } else {
       const int per_k = TILE / EPC;
       const int kk = c / per_k;
       const int row = (c % per_k) * EPC;
       union { uint4 v; T e[EPC]; } u;
-      u.v = st.chunk[j];
+      u.v = v;
 #pragma unroll
       for (int e = 0; e < EPC; ++e) *(T*)(lds + (row + e) * LDS_ROW + kk * (int)sizeof(T)) = u.e[e];
     }
@@ -130,7 +154,7 @@ __device__ inline void decode_tile(const GramArgs& g, int tile, int& ti, int& tj
   }
 }
 
-template <int E>
+template <int E, bool VEC>
 __global__ void __launch_bounds__(256, E == E_F64 ? 1 : 2) gram_sketch_kernel(GramArgs g) {
   typedef Mma<E> M;
   typedef typename M::Out Out;
@@ -178,14 +202,14 @@ __global__ void __launch_bounds__(256, E == E_F64 ? 1 : 2) gram_sketch_kernel(Gr
   auto load = [&](int64_t kt) {
     int64_t a, b0, kv;
     kt_coords(kt, a, b0, kv);
-    load_operand<E>(sa, g, g.X, false, r0, g.I, a, b0, kv);
-    if (is_w) load_operand<E>(sb, g, g.omegaT, true, c0, g.S, a, b0, kv);
-    else if (!diag) load_operand<E>(sb, g, g.X, false, c0, g.I, a, b0, kv);
+    load_operand<E, VEC>(sa, g, g.X, false, r0, g.I, a, b0, kv);
+    if (is_w) load_operand<E, VEC>(sb, g, g.omegaT, true, c0, g.S, a, b0, kv);
+    else if (!diag) load_operand<E, VEC>(sb, g, g.X, false, c0, g.I, a, b0, kv);
   };
   auto store = [&](int buf) {
-    store_operand<E>(sa, g, false, lds[buf][0]);
-    if (is_w) store_operand<E>(sb, g, true, lds[buf][1]);
-    else if (!diag) store_operand<E>(sb, g, false, lds[buf][1]);
+    store_operand<E, VEC>(sa, g, false, lds[buf][0]);
+    if (is_w) store_operand<E, VEC>(sb, g, true, lds[buf][1]);
+    else if (!diag) store_operand<E, VEC>(sb, g, false, lds[buf][1]);
   };
 
   if (kt0 < kt1) {
@@ -240,41 +264,49 @@ __device__ inline void decode_big_tile(const GramArgs& g, int tile, int& ti, int
 
 // Load `nrows_tile` rows x 64 bf16 (k contiguous) into registers: chunk c of
 // 16 bytes = row c / 8, k offset (c % 8) * 8.
-template <int NCH>
-__device__ inline void load_rows_bf16(uint4* ch, const bf16_t* base, int64_t row_stride, int64_t row0,
-                                      int64_t nrows, int64_t kvalid, bool vec) {
+template <int NCH, bool VEC>
+__device__ inline void load_rows_bf16(uint4* ch, unsigned& valid, const bf16_t* base, int64_t row_stride,
+                                      int64_t row0, int64_t nrows, int64_t kvalid) {
   const int tid = threadIdx.x;
+  valid = 0;
 #pragma unroll
   for (int j = 0; j < NCH; ++j) {
     const int c = tid + 256 * j;
     const int row = c >> 3, kk = (c & 7) * 8;
     const int64_t r = row0 + row;
-    union { uint4 v; bf16_t e[8]; } u;
-    u.v = make_uint4(0, 0, 0, 0);
-    if (r < nrows) {
-      const bf16_t* p = base + r * row_stride + kk;
-      if (vec && kk + 8 <= kvalid) {
-        u.v = *(const uint4*)p;
-      } else {
+    if (VEC) {
+      // clamped address, always in bounds; out-of-range chunks are zeroed at the LDS store
+      const int64_t rc = r < nrows ? r : nrows - 1;
+      const int kc = kk < kvalid ? kk : 0;
+      ch[j] = *(const uint4*)(base + rc * row_stride + kc);
+      valid |= (r < nrows && kk < kvalid) ? 1u << j : 0u;
+    } else {
+      union { uint4 v; bf16_t e[8]; } u;
+      u.v = make_uint4(0, 0, 0, 0);
+      if (r < nrows) {
+        const bf16_t* p = base + r * row_stride + kk;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
           if (kk + e < kvalid) u.e[e] = p[e];
       }
+      ch[j] = u.v;
+      valid |= 1u << j;
     }
-    ch[j] = u.v;
   }
 }
 
 template <int NCH>
-__device__ inline void store_rows_lds(const uint4* ch, char* lds) {
+__device__ inline void store_rows_lds(const uint4* ch, unsigned valid, char* lds) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < NCH; ++j) {
     const int c = tid + 256 * j;
-    *(uint4*)(lds + (c >> 3) * LDS_ROW + (c & 7) * 16) = ch[j];
+    const uint4 v = ((valid >> j) & 1u) ? ch[j] : make_uint4(0, 0, 0, 0);
+    *(uint4*)(lds + (c >> 3) * LDS_ROW + (c & 7) * 16) = v;
   }
 }
 
+template <bool VEC>
 __global__ void __launch_bounds__(256, 1) gram_bf16_big_kernel(GramArgs g) {
   __shared__ __attribute__((aligned(16))) char lds[2][2][BT * LDS_ROW];
   const int w = blockIdx.x;
@@ -312,6 +344,7 @@ __global__ void __launch_bounds__(256, 1) gram_bf16_big_kernel(GramArgs g) {
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
 
   uint4 ca[8], cb[8];
+  unsigned va = 0, vb = 0;
   auto kt_coords = [&](int64_t kt, int64_t& a, int64_t& b0, int64_t& kvalid) {
     a = kt / g.nbt;
     b0 = (kt - a * g.nbt) * 64;
@@ -323,15 +356,15 @@ __global__ void __launch_bounds__(256, 1) gram_bf16_big_kernel(GramArgs g) {
     int64_t a, b0, kv;
     kt_coords(kt, a, b0, kv);
     const bf16_t* xa = X + a * g.I * g.B + b0;
-    load_rows_bf16<8>(ca, xa, g.B, r0, g.I, kv, g.vec_ok);
+    load_rows_bf16<8, VEC>(ca, va, xa, g.B, r0, g.I, kv);
     if (!diag) {
-      if (is_w) load_rows_bf16<8>(cb, Om + a * g.B + b0, g.J, c0, brows, kv, g.vec_ok);
-      else load_rows_bf16<8>(cb, xa, g.B, c0, g.I, kv, g.vec_ok);
+      if (is_w) load_rows_bf16<8, VEC>(cb, vb, Om + a * g.B + b0, g.J, c0, brows, kv);
+      else load_rows_bf16<8, VEC>(cb, vb, xa, g.B, c0, g.I, kv);
     }
   };
   auto store = [&](int buf) {
-    store_rows_lds<8>(ca, lds[buf][0]);
-    if (!diag) store_rows_lds<8>(cb, lds[buf][1]);
+    store_rows_lds<8>(ca, va, lds[buf][0]);
+    if (!diag) store_rows_lds<8>(cb, vb, lds[buf][1]);
   };
   const int lim = is_w ? 2 : 4;     // 32 x 32 blocks per wave along each side
 
@@ -575,29 +608,23 @@ size_t gram_partial_bytes(const GramArgs& g, int elem) {
   return (size_t)g.splits * g.ntiles * TILE * TILE * (elem == E_F64 ? 8 : 4);
 }
 
-hipError_t launch_gram(int elem, const GramArgs& g, double* C, double* Wt, hipStream_t s) {
-  const unsigned grid = (unsigned)(g.ntiles * g.splits);
-  switch (elem) {
-    case E_F64: hipLaunchKernelGGL(gram_sketch_kernel<E_F64>, dim3(grid), dim3(256), 0, s, g); break;
-    case E_F32: hipLaunchKernelGGL(gram_sketch_kernel<E_F32>, dim3(grid), dim3(256), 0, s, g); break;
-    case E_BF16: hipLaunchKernelGGL(gram_sketch_kernel<E_BF16>, dim3(grid), dim3(256), 0, s, g); break;
-    default: return hipErrorInvalidValue;
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t total = g.I * g.I + (int64_t)g.S * g.I;
-  unsigned rgrid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 4096);
-  if (elem == E_F64) hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3(rgrid), dim3(256), 0, s, g, C, Wt);
-  else hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3(rgrid), dim3(256), 0, s, g, C, Wt);
-  return hipGetLastError();
+// Vector loads need every row start 16-byte aligned: sizes (vec_ok) and base pointers.
+static bool gram_vec(const GramArgs& g) {
+  return g.vec_ok && ((uintptr_t)g.X % 16) == 0 && ((uintptr_t)g.omegaT % 16) == 0;
+}
+
+template <int E>
+static void launch_sketch(const GramArgs& g, unsigned grid, hipStream_t s) {
+  if (gram_vec(g)) hipLaunchKernelGGL((gram_sketch_kernel<E, true>), dim3(grid), dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((gram_sketch_kernel<E, false>), dim3(grid), dim3(256), 0, s, g);
 }
 
 hipError_t launch_gram_main(int elem, const GramArgs& g, hipStream_t s) {
   const unsigned grid = (unsigned)(g.ntiles * g.splits);
   switch (elem) {
-    case E_F64: hipLaunchKernelGGL(gram_sketch_kernel<E_F64>, dim3(grid), dim3(256), 0, s, g); break;
-    case E_F32: hipLaunchKernelGGL(gram_sketch_kernel<E_F32>, dim3(grid), dim3(256), 0, s, g); break;
-    case E_BF16: hipLaunchKernelGGL(gram_sketch_kernel<E_BF16>, dim3(grid), dim3(256), 0, s, g); break;
+    case E_F64: launch_sketch<E_F64>(g, grid, s); break;
+    case E_F32: launch_sketch<E_F32>(g, grid, s); break;
+    case E_BF16: launch_sketch<E_BF16>(g, grid, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -640,7 +667,9 @@ GramArgs gram_plan_big(int64_t A, int64_t I, int64_t B, int S, int cu_count) {
 size_t gram_big_partial_bytes(const GramArgs& g) { return (size_t)g.splits * g.part_stride * 4; }
 
 hipError_t launch_gram_big(const GramArgs& g, hipStream_t s) {
-  hipLaunchKernelGGL(gram_bf16_big_kernel, dim3((unsigned)(g.ntiles * g.splits)), dim3(256), 0, s, g);
+  const dim3 grid((unsigned)(g.ntiles * g.splits));
+  if (gram_vec(g)) hipLaunchKernelGGL(gram_bf16_big_kernel<true>, grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL(gram_bf16_big_kernel<false>, grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
