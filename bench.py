@@ -101,33 +101,100 @@ def load_traffic(workload, precision):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(X, w, slab):
-    """FP64 oracle on a bounded slab X[:, :, :slab] of the same tensor: the
-    mode-0 factor (sketch, q Krylov steps in the streamed product form, Z and
-    its eigenvectors).  Returns TFLOP/s of the oracle's own executed flops."""
-    import numpy as np
-    from oracle.rbki import mode_factor
-    Xs = X[:, :, :slab].double().cpu().numpy()
-    Xs = np.ascontiguousarray(Xs)
-    I = Xs.shape[0]
-    J = Xs.size // I
-    R, p, q = w["ranks"][0], w["p"], w["q"]
+# torch.mul(src, 1.0, out=dst) on float32: reads and writes n*4 bytes
+COPY_KERNEL = "AUnaryFunctor<float, float, float, at::native::binary_internal::MulFunctor<float> >"
+
+
+def _pmc_rows(path, counter):
+    import csv
+    out = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") != counter:
+                continue
+            d = int(r["Dispatch_Id"])
+            out[d] = (r["Kernel_Name"], out.get(d, (None, 0.0))[1] + float(r["Counter_Value"]))
+    return out
+
+
+def traffic_from(fetch_csv, write_csv, workload, precision, copy_mib, command):
+    """HBM bytes per Gram launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
+    for the calibration copy of known size in the same program."""
+    kernel = "gram_bf16_big_kernel" if precision == "mixed_bf16" else "gram_sketch_kernel"
+    known = copy_mib * 1024 * 1024
+    res = {}
+    for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _pmc_rows(path, counter)
+        copies = [v * 1024 for k, v in rows.values() if COPY_KERNEL in k]
+        grams = [v * 1024 for k, v in rows.values() if kernel in k]
+        if not copies or not grams:
+            raise SystemExit(f"{path}: no {COPY_KERNEL} or {kernel} dispatches with {counter}")
+        scale = known / (sum(copies) / len(copies))
+        res[name] = {"raw_bytes_per_launch": sum(grams) / len(grams), "copy_scale": scale,
+                     "bytes_per_launch": sum(grams) / len(grams) * scale, "launches": len(grams)}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    db = json.load(open(path)) if os.path.exists(path) else {}
+    db[f"gram/{workload}/{precision}"] = {
+        "kernel": kernel, "bytes_per_launch": res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"],
+        "fetch": res["fetch"], "write": res["write"], "copy_bytes": known,
+        "source_hash": source_hash(), "command": command}
+    with open(path, "w") as fh:
+        json.dump(db, fh, indent=1, sort_keys=True)
+        fh.write("\n")
+    print(json.dumps(db[f"gram/{workload}/{precision}"]))
+
+
+def mode0_gram_flops(I, J, R, p, q):
+    """Gram-route flops of the mode-0 factor (sketch + Gram, Krylov steps on
+    C, Z and U) for an I x J unfolding: the same accounting as step_flops."""
     S = min(R + p, I, J)
     Sp = min(S * (q + 1), I)
-    t0 = time.perf_counter()
-    mode_factor(Xs, 0, R, p, q, w["seeds"][1])
-    dt = time.perf_counter() - t0
-    # W = X Omega, q streamed steps X (X^T Q), B = Q^T X, Z = B B^T, U = Q V
-    flops = 2.0 * I * J * S + q * 4.0 * I * J * S + 2.0 * Sp * I * J + 2.0 * Sp * Sp * J + 2.0 * I * Sp * R
+    f = I * (I + 1) * J + 2.0 * I * J * S
+    for j in range(1, q + 1):
+        m = S * j
+        f += 2.0 * I * I * S + 2 * (2.0 * S * m * I * 2) + 4.0 * S * S * I
+    f += 2.0 * I * I * S + 2.0 * Sp * Sp * I + 2.0 * R * Sp * I
+    return f
+
+
+def cpu_baseline(X, w, target_s=15.0):
+    """The FP64 oracle, as it stands, on a bounded slab X[:, :, :slab] of the
+    same tensor: the mode-0 factor (sketch, q Krylov steps in the streamed
+    form, Z and its eigenvectors).  A short probe on a thin slab sizes the
+    timed slab to about target_s seconds.  The value is reported in the unit of
+    the GPU figure: Gram-route flops of the same work (the accounting of
+    step_flops) per second, so that value_gpu / value_cpu is the speed ratio
+    for equal work."""
+    import numpy as np
+    from oracle.rbki import mode_factor
+    R, p, q = w["ranks"][0], w["p"], w["q"]
+    I, d1, d2 = X.shape[0], X.shape[1], X.shape[2]
+
+    def run(slab):
+        Xs = np.ascontiguousarray(X[:, :, :slab].double().cpu().numpy())
+        t0 = time.perf_counter()
+        mode_factor(Xs, 0, R, p, q, w["seeds"][1])
+        return time.perf_counter() - t0, Xs.size // I
+
+    probe = max(1, min(d2, 20))
+    dt, J = run(probe)
+    slab = int(min(d2, max(probe, probe * target_s / max(dt, 1e-3))))
+    dt, J = run(slab)
+    flops = mode0_gram_flops(I, J, R, p, q)
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
     except Exception:
         threads = os.cpu_count()
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"FP64 oracle, mode-0 factor of Alg. 2 (sketch, {q} Krylov steps in the streamed "
-                      f"form, Z, eigenvectors) on the slab X[:, :, :{slab}] ({I}x{Xs.shape[1]}x{slab}) of the "
-                      f"same input; {dt:.2f} s; host cpu_count={os.cpu_count()}"}
+            "sample": f"FP64 oracle (numpy/LAPACK, {threads} BLAS threads, host cpu_count={os.cpu_count()}): "
+                      f"mode-0 factor of Alg. 2 (sketch, {q} Krylov steps in the streamed form, Z, eigenvectors) "
+                      f"on the slab X[:, :, :{slab}] ({I}x{d1}x{slab}) of the same input, {dt:.2f} s; value = "
+                      f"Gram-route flops of that work ({flops:.3e}) / time"}
+
+
+METRIC = "rBKI-TK TFLOP/s + rel err vs FP64 oracle; served solves/s, p50/p99 latency"
 
 
 def main():
@@ -138,8 +205,19 @@ def main():
     ap.add_argument("--workload", default="tucker1000_f32")
     ap.add_argument("--precision", default="mixed_bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slab", type=int, default=200)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP64 and plain-form runs that follow the timed region")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="run a plain copy of MIB MiB first (the reference for PMC byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs and exit")
+    ap.add_argument("--traffic-command", default="")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(args.traffic_from[0], args.traffic_from[1], args.workload, args.precision,
+                     args.calibrate_copy, args.traffic_command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the per-GPU slab of a sharded "
               "run is the same kernel at a smaller shape); run with --gpus 1", file=sys.stderr)
@@ -157,8 +235,17 @@ def main():
     torch.cuda.synchronize()
     seed = w["seeds"][1]
 
-    def step():
-        return rb.tucker(X, ranks, p=p, q=q, seed=seed, precision=args.precision, out_dtype=torch.float32)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * 1024 * 1024 // 4
+        src = torch.ones(n, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def step(Xin=X, precision=args.precision):
+        return rb.tucker(Xin, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float32)
 
     for i in range(args.warmup):
         _, _, e = step()
@@ -180,8 +267,9 @@ def main():
     avg_gram_ms = gram_ms / max(nlaunch, 1)
     alg_gram = sum(gram_flops) / len(gram_flops)       # per launch (one launch per mode)
     achieved = alg_gram / (avg_gram_ms * 1e-3) / 1e12
-    gram_dtype = {"plain": "f32" if w["dtype"] == "float32" else ("f64" if w["dtype"] == "float64" else "bf16"),
-                  "mixed_bf16": "bf16", "mixed_fp8": "fp8"}[args.precision]
+    in_dt = {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}[w["dtype"]]
+    gram_dtype = {"plain": in_dt, "mixed_bf16": "bf16", "mixed_fp8": "fp8"}[args.precision]
+    kernel = "gram_bf16_big_kernel" if gram_dtype == "bf16" else "gram_sketch_kernel"
     peak = PEAK_TFLOPS[gram_dtype]
     stages = {}
     for k in ("omega", "gram", "jacobi", "ttm", "error", "convert"):
@@ -191,14 +279,34 @@ def main():
     print(f"[bench] {args.steps} steps, {ms:.3f} ms/step, rel_err {e:.8f}, stage ms/step {stages}",
           file=sys.stderr, flush=True)
 
+    compare = {}
+    if not args.no_compare:
+        # outside the timed region: the FP64 form on the same values (parity-pinned
+        # to the oracle) gives the reference error; the plain form gives the wall
+        # time the mixed form is compared with
+        X64 = X.double()
+        _, _, e64 = step(X64, "plain")
+        del X64
+        torch.cuda.empty_cache()
+        compare["rel_err_f64"] = e64
+        compare["excess_vs_f64"] = (e - e64) / e64 if e64 > 0 else None
+        if args.precision != "plain":
+            step(X, "plain")
+            torch.cuda.synchronize()
+            n_plain = max(1, min(3, args.steps))
+            t1 = time.perf_counter()
+            for _ in range(n_plain):
+                step(X, "plain")
+            torch.cuda.synchronize()
+            compare["plain_ms_per_step"] = round((time.perf_counter() - t1) / n_plain * 1e3, 4)
+        print(f"[bench] compare {compare}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a slab", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(X, w, args.cpu_slab)
-    dtype = {"plain": {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}[w["dtype"]],
-             "mixed_bf16": "bf16", "mixed_fp8": "fp8"}[args.precision]
+        cpu = cpu_baseline(X, w, args.cpu_seconds)
     rec = {
-        "metric": "rBKI-TK TFLOP/s (executed flops of the Gram route per step)",
+        "metric": METRIC,
         "value": round(tflops, 4),
         "unit": "TFLOP/s",
         "n_gpus": 1,
@@ -208,14 +316,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": dtype,
+        "dtype": gram_dtype,
         "data": "synthetic",
         "config": {"workload": args.workload, "dims": list(dims), "ranks": list(ranks), "p": p, "q": q,
                    "precision": args.precision, "input_dtype": w["dtype"], "rel_err": e,
-                   "stage_ms_per_step": stages},
+                   **compare, "stage_ms_per_step": stages,
+                   "flops_per_step": flops},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 5), "traffic": load_traffic(args.workload, args.precision),
-                     "kernel": "gram_sketch_kernel", "avg_launch_ms": round(avg_gram_ms, 5),
+                     "kernel": kernel, "avg_launch_ms": round(avg_gram_ms, 5),
                      "launches": nlaunch, "alg_flops_per_launch": alg_gram},
         "cpu_baseline": cpu,
     }
