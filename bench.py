@@ -145,43 +145,31 @@ def traffic_from(fetch_csv, write_csv, workload, precision, copy_mib, command):
     print(json.dumps(db[f"gram/{workload}/{precision}"]))
 
 
-def mode0_gram_flops(I, J, R, p, q):
-    """Gram-route flops of the mode-0 factor (sketch + Gram, Krylov steps on
-    C, Z and U) for an I x J unfolding: the same accounting as step_flops."""
-    S = min(R + p, I, J)
-    Sp = min(S * (q + 1), I)
-    f = I * (I + 1) * J + 2.0 * I * J * S
-    for j in range(1, q + 1):
-        m = S * j
-        f += 2.0 * I * I * S + 2 * (2.0 * S * m * I * 2) + 4.0 * S * S * I
-    f += 2.0 * I * I * S + 2.0 * Sp * Sp * I + 2.0 * R * Sp * I
-    return f
-
-
-def cpu_baseline(X, w, target_s=15.0):
-    """The FP64 oracle, as it stands, on a bounded slab X[:, :, :slab] of the
-    same tensor: the mode-0 factor (sketch, q Krylov steps in the streamed
-    form, Z and its eigenvectors).  A short probe on a thin slab sizes the
-    timed slab to about target_s seconds.  The value is reported in the unit of
-    the GPU figure: Gram-route flops of the same work (the accounting of
-    step_flops) per second, so that value_gpu / value_cpu is the speed ratio
-    for equal work."""
+def cpu_baseline(X, w, target_s=20.0):
+    """The FP64 oracle, as it stands, on a bounded slab X[..., :slab] of the
+    same tensor: the whole decomposition (every mode's sketch, q Krylov steps
+    in the streamed form, Z and its eigenvectors, the core and the explicit
+    error).  A probe on a thin slab sizes the timed slab to about target_s
+    seconds.  The value is in the unit of the GPU figure: the flops that the
+    GPU route executes for the slab's shape (step_flops) per second of the
+    oracle, so value_gpu / value_cpu is the speed ratio for equal work."""
     import numpy as np
-    from oracle.rbki import mode_factor
-    R, p, q = w["ranks"][0], w["p"], w["q"]
-    I, d1, d2 = X.shape[0], X.shape[1], X.shape[2]
+    from oracle.rbki import rbki_tucker
+    p, q, seed = w["p"], w["q"], w["seeds"][1]
+    last = X.shape[-1]
 
     def run(slab):
-        Xs = np.ascontiguousarray(X[:, :, :slab].double().cpu().numpy())
+        Xs = np.ascontiguousarray(X[..., :slab].double().cpu().numpy())
+        ranks = tuple(min(R, d) for R, d in zip(w["ranks"], Xs.shape))
         t0 = time.perf_counter()
-        mode_factor(Xs, 0, R, p, q, w["seeds"][1])
-        return time.perf_counter() - t0, Xs.size // I
+        rbki_tucker(Xs, ranks, p, q, seed)
+        return time.perf_counter() - t0, Xs.shape, ranks
 
-    probe = max(1, min(d2, 20))
-    dt, J = run(probe)
-    slab = int(min(d2, max(probe, probe * target_s / max(dt, 1e-3))))
-    dt, J = run(slab)
-    flops = mode0_gram_flops(I, J, R, p, q)
+    probe = max(1, min(last, 60))
+    dt, _, _ = run(probe)
+    slab = int(min(last, max(probe, probe * target_s / max(dt, 1e-3))))
+    dt, shape, ranks = run(slab)
+    flops, _ = step_flops(shape, ranks, p, q)
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
@@ -189,9 +177,10 @@ def cpu_baseline(X, w, target_s=15.0):
         threads = os.cpu_count()
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"FP64 oracle (numpy/LAPACK, {threads} BLAS threads, host cpu_count={os.cpu_count()}): "
-                      f"mode-0 factor of Alg. 2 (sketch, {q} Krylov steps in the streamed form, Z, eigenvectors) "
-                      f"on the slab X[:, :, :{slab}] ({I}x{d1}x{slab}) of the same input, {dt:.2f} s; value = "
-                      f"Gram-route flops of that work ({flops:.3e}) / time"}
+                      f"whole rBKI-TK decomposition (Alg. 2: every mode's sketch, {q} Krylov steps in the "
+                      f"streamed form, Z, eigenvectors, core, explicit error) of the slab X[..., :{slab}] "
+                      f"({'x'.join(str(d) for d in shape)}, ranks {ranks}) of the same input, {dt:.2f} s; value = "
+                      f"GPU-route flops of that shape ({flops:.3e}) / time"}
 
 
 METRIC = "rBKI-TK TFLOP/s + rel err vs FP64 oracle; served solves/s, p50/p99 latency"
@@ -207,7 +196,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 and plain-form runs that follow the timed region")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="run a plain copy of MIB MiB first (the reference for PMC byte counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
