@@ -117,8 +117,8 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
     for (int64_t i = tid; i < s; i += blockDim.x) mx = fmax(mx, ref2[i]);
   mx = warp_max(mx);
   if ((tid & 63) == 0) red[tid >> 6] = mx;
-  for (int64_t e = tid; e < s * s; e += blockDim.x) {
-    const int64_t i = e / s, j = e - i * s;
+  for (int e = tid; e < (int)(s * s); e += blockDim.x) {
+    const int i = e / (int)s, j = e - i * (int)s;
     Ls[i][j] = G[e];
     if (i == j) d0[i] = G[e];
   }
@@ -147,22 +147,36 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
     }
     __syncthreads();
   }
-  // X = L^{-1} restricted to kept rows/columns: column c by forward substitution
-  for (int c = tid; c < s; c += blockDim.x) {
-    for (int i = 0; i < s; ++i) {
-      double v = 0.0;
-      if (keep[i] && keep[c] && i >= c) {
-        v = (i == c) ? 1.0 : 0.0;
-        for (int j = c; j < i; ++j) v -= Ls[i][j] * Xs[j][c];
-        v /= Ls[i][i];
-      }
-      Xs[i][c] = v;
-    }
+  // X = L^{-1} restricted to kept rows/columns, right-looking: starting from
+  // the identity, row k is scaled by 1 / L_kk and then removed from the rows
+  // below it.  Only columns c <= k of a row are nonzero at step k.  A dropped
+  // k has a zero factor column, so its row and column of X stay zero.
+  const int sn = (int)s;
+  for (int e = tid; e < sn * sn; e += blockDim.x) {
+    const int i = e / sn, j = e - i * sn;
+    Xs[i][j] = (i == j && keep[i]) ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int64_t e = tid; e < s * s; e += blockDim.x) {
-    const int64_t i = e / s, j = e - i * s;
-    Linv[e] = Xs[i][j];
+  for (int k = 0; k < sn; ++k) {
+    if (keep[k]) {
+      const double inv = 1.0 / Ls[k][k];
+      for (int c = tid; c <= k; c += blockDim.x) Xs[k][c] *= inv;
+    }
+    __syncthreads();
+    if (keep[k]) {
+      const int w = k + 1, t = sn - k - 1;
+      for (int e = tid; e < t * w; e += blockDim.x) {
+        const int i = k + 1 + e / w, c = e - (e / w) * w;
+        Xs[i][c] -= Ls[i][k] * Xs[k][c];
+      }
+    }
+    __syncthreads();
+  }
+  // a dropped row k of L still holds its entries left of the diagonal, which
+  // reached row k of X above: dropped vectors get a zero row
+  for (int e = tid; e < sn * sn; e += blockDim.x) {
+    const int i = e / sn, j = e - i * sn;
+    Linv[e] = keep[i] ? Xs[i][j] : 0.0;
   }
   for (int64_t i = tid; i < s; i += blockDim.x) flags[i] = keep[i];
 }

@@ -217,6 +217,131 @@ __global__ void sum_pairs_kernel(const double* partial, int64_t n, double* out) 
   }
 }
 
+// ------------------------------------------------------------------------
+// Streaming reconstruction-error pass for float32 operands and R <= 64.
+// Workgroup w owns columns j0 .. j0+127 of X_(0) (I x J) and walks every
+// 128-row tile of it: H(:, j0..j0+127) is staged once in LDS as [j][k], the
+// rows of U (I x 64, zero-padded) are read straight from L2 into MFMA
+// fragments, and the tile of X is requested before the MFMAs so that its HBM
+// reads are in flight while Xhat = U H is formed.  (x - xhat)^2 and x^2 are
+// accumulated in float64; Xhat is never written.
+struct ResArgs {
+  const float* Up;      // I x 64 row-major, columns >= R zero
+  const float* H;       // R x J row-major
+  const void* X;        // I x J row-major
+  int64_t I, J;
+  int R, nkt;           // nkt = ceil(R / 32) K tiles of 32
+  double* partial;      // [gridDim.x] x 2
+};
+
+template <class XT>
+__device__ inline float x_to_f(XT v);
+template <> __device__ inline float x_to_f<float>(float v) { return v; }
+template <> __device__ inline float x_to_f<bf16_t>(bf16_t v) { return bf16_to_f32(v); }
+
+template <class XT>
+__global__ void __launch_bounds__(256, 2) residual_kernel(ResArgs a) {
+  __shared__ __attribute__((aligned(16))) char ldsB[2][TILE * LDS_ROW];
+  __shared__ double red[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, lr = lane & 31;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  const int64_t j0 = (int64_t)blockIdx.x * TILE;
+
+  // H block -> LDS, transposed: chunk c holds 4 consecutive j at one k
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int c = tid + 256 * q;
+    const int kk = c >> 5, jj = (c & 31) * 4;
+    const bool ok = kk < a.R && j0 + jj < a.J;
+    const int kc = kk < a.R ? kk : 0;
+    const int64_t jc = j0 + jj < a.J ? j0 + jj : 0;
+    float4 v = *(const float4*)(a.H + (int64_t)kc * a.J + jc);
+    if (!ok) v = make_float4(0.f, 0.f, 0.f, 0.f);
+    char* base = ldsB[kk >> 5] + (kk & 31) * 4;
+    *(float*)(base + (jj + 0) * LDS_ROW) = v.x;
+    *(float*)(base + (jj + 1) * LDS_ROW) = v.y;
+    *(float*)(base + (jj + 2) * LDS_ROW) = v.z;
+    *(float*)(base + (jj + 3) * LDS_ROW) = v.w;
+  }
+  __syncthreads();
+
+  const XT* X = (const XT*)a.X;
+  double res = 0.0, nrm = 0.0;
+  const int64_t nit = ceil_div(a.I, TILE);
+  for (int64_t it = 0; it < nit; ++it) {
+    const int64_t i0 = it * TILE;
+    // 1. this tile of X, in the accumulator layout (clamped, masked later)
+    XT xv[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+      int row, col;
+      Mma<E_F32>::coord(j, lane, row, col);
+      int64_t i = i0 + wr + row, jj = j0 + wc + col;
+      i = i < a.I ? i : a.I - 1;
+      jj = jj < a.J ? jj : a.J - 1;
+      xv[j] = X[i * a.J + jj];
+    }
+    // 2. Xhat tile = U(i0.., :) H(:, j0..)
+    Mma<E_F32>::Frag f;
+    Mma<E_F32>::zero(f);
+    for (int kt = 0; kt < a.nkt; ++kt) {
+      float av[2][16], bv[2][16];
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        int64_t i = i0 + wr + m * 32 + lr;
+        i = i < a.I ? i : a.I - 1;          // rows past I are never accumulated
+        const float4* pa = (const float4*)(a.Up + i * 64 + kt * 32 + half * 16);
+        const float4* pb = (const float4*)(ldsB[kt] + (wc + m * 32 + lr) * LDS_ROW + half * 64);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 va = pa[q], vb = pb[q];
+          av[m][4 * q] = va.x; av[m][4 * q + 1] = va.y; av[m][4 * q + 2] = va.z; av[m][4 * q + 3] = va.w;
+          bv[m][4 * q] = vb.x; bv[m][4 * q + 1] = vb.y; bv[m][4 * q + 2] = vb.z; bv[m][4 * q + 3] = vb.w;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int n = 0; n < 2; ++n)
+            f.c[m * 2 + n] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[m][t], bv[n][t], f.c[m * 2 + n], 0, 0, 0);
+    }
+    // 3. fold the tile into the sums
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+      int row, col;
+      Mma<E_F32>::coord(j, lane, row, col);
+      const bool ok = i0 + wr + row < a.I && j0 + wc + col < a.J;
+      const double x = ok ? (double)x_to_f<XT>(xv[j]) : 0.0;
+      const double d = ok ? x - (double)Mma<E_F32>::get(f, j) : 0.0;
+      res = fma(d, d, res);
+      nrm = fma(x, x, nrm);
+    }
+  }
+  res = warp_sum(res);
+  nrm = warp_sum(nrm);
+  if (lane == 0) {
+    red[0][wave] = res;
+    red[1][wave] = nrm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.partial[2 * blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    a.partial[2 * blockIdx.x + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// U (given as Ut, R x I float32) -> Up (I x 64 float32, zero-padded columns)
+__global__ void pad_u_kernel(const float* Ut, int64_t R, int64_t I, float* Up) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < I * 64;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e >> 6, k = e & 63;
+    Up[e] = k < R ? Ut[k * I + i] : 0.f;
+  }
+}
+
 template <class S, class D> __device__ inline D conv(S v);
 template <> __device__ inline float conv<double, float>(double v) { return (float)v; }
 template <> __device__ inline double conv<float, double>(float v) { return (double)v; }
@@ -301,11 +426,37 @@ hipError_t launch_ttm(int elem, const void* X, int64_t A, int64_t I, int64_t B, 
 }
 
 size_t residual_work_bytes(int64_t I, int64_t J) {
-  return (size_t)(ceil_div(I, TILE) * ceil_div(J, TILE)) * 16 + 64;
+  const int64_t tiles = std::max<int64_t>(ceil_div(I, TILE) * ceil_div(J, TILE), ceil_div(J, TILE));
+  return (size_t)tiles * 16 + 256 + (size_t)I * 64 * 4 + 64;
 }
 
 hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* Ut, const void* H, int64_t I,
                            int64_t J, int64_t R, double* out, void* work, size_t, hipStream_t s) {
+  const int64_t tiles = std::max<int64_t>(ceil_div(I, TILE) * ceil_div(J, TILE), ceil_div(J, TILE));
+  double* partial = (double*)work;
+  if (op_elem == E_F32 && R <= 64 && (x_elem == E_F32 || x_elem == E_BF16) && J % 4 == 0 && aligned16(H) &&
+      ceil_div(J, TILE) <= 0x7fffffff) {
+    // streaming form
+    float* Up = (float*)((char*)work + ((tiles * 16 + 255) / 256) * 256);
+    hipLaunchKernelGGL(pad_u_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(I * 64, 256), 4096)), dim3(256), 0,
+                       s, (const float*)Ut, R, I, Up);
+    ResArgs ra;
+    ra.Up = Up;
+    ra.H = (const float*)H;
+    ra.X = X;
+    ra.I = I;
+    ra.J = J;
+    ra.R = (int)R;
+    ra.nkt = (int)ceil_div(R, 32);
+    ra.partial = partial;
+    const dim3 grid((unsigned)ceil_div(J, TILE));
+    if (x_elem == E_F32) hipLaunchKernelGGL(residual_kernel<float>, grid, dim3(256), 0, s, ra);
+    else hipLaunchKernelGGL(residual_kernel<bf16_t>, grid, dim3(256), 0, s, ra);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(1024), 0, s, (const double*)partial, (int64_t)grid.x, out);
+    return hipGetLastError();
+  }
   const int es = elem_size(op_elem);
   ProdArgs p = {};
   p.K = R;
@@ -320,7 +471,7 @@ hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* U
   p.X = X;
   p.x_elem = x_elem;
   p.xJ = J;
-  p.partial = (double*)work;
+  p.partial = partial;
   hipError_t e;
   if (op_elem == E_F64) {
     if (x_elem != E_F64) return hipErrorInvalidValue;
@@ -338,7 +489,7 @@ hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* U
   }
   if (e != hipSuccess) return e;
   const int64_t n = p.row_tiles * p.col_tiles;
-  hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(1024), 0, s, (const double*)work, n, out);
+  hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(1024), 0, s, (const double*)partial, n, out);
   return hipGetLastError();
 }
 
