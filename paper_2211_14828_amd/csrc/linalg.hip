@@ -272,6 +272,7 @@ __global__ void row_norms2_kernel(const double* Y, int64_t s, int64_t n, double*
 // convergence A = Z V has orthogonal columns a_j = lambda_j v_j: eigenvalues
 // are the column norms and eigenvectors the normalised columns.
 constexpr int JAC_MAXB = 8;    // matrices per launch
+constexpr int JAC_APPLY_MAX = 5;   // 16 x 16 output blocks per wave in the apply phase
 
 struct JacobiArgs {
   double* A[JAC_MAXB];         // npad x n column-major working copies
@@ -286,9 +287,13 @@ struct JacobiArgs {
   unsigned long long* prof;    // nullable: phase clocks of workgroup 0 (diagnostics)
 };
 
+// Circle ordering: position pos (0 <= pos < nblk) holds this element in round
+// `round` (0 <= round < nblk - 1); position 0 is fixed, the others rotate.
 __device__ inline int circle_block(int pos, int round, int nblk) {
   if (pos == 0) return 0;
-  return 1 + (pos - 1 + round) % (nblk - 1);
+  int v = pos - 1 + round;              // < 2 (nblk - 1)
+  if (v >= nblk - 1) v -= nblk - 1;
+  return 1 + v;
 }
 
 // Rotation (c, s) zeroing the (p, q) entry of a 2x2 Gram block
@@ -313,6 +318,8 @@ __global__ void __launch_bounds__(1024) jacobi_kernel(JacobiArgs J) {
   extern __shared__ double sm[];
   __shared__ double sh_off[16];
   __shared__ int sh_done[JAC_MAXB];
+  __shared__ double rot_c[16], rot_s[16];
+  __shared__ int rot_p[16], rot_q[16];
   cg::grid_group grid = cg::this_grid();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = blockIdx.x / J.npos, pos = blockIdx.x % J.npos;
@@ -376,91 +383,117 @@ __global__ void __launch_bounds__(1024) jacobi_kernel(JacobiArgs J) {
           __syncthreads();
         }
         unsigned long long t2 = wall_clock64();
-        // inner cyclic sweep on G (two-sided), accumulating V.  Waves 0..3 do
-        // the work: lane (l & 3) of wave w computes the rotation of pair
-        // 4w + (l & 3); the 16 lanes of quarter l >> 4 then update that pair's
-        // rows, and after a barrier its columns of G and V.
-        const int pwaves = (nb + 3) / 4;
-        for (int isw = 0; isw < J.inner_sweeps; ++isw) {
-          double inner_off = 0.0;
-          for (int ir = 0; ir < two - 1; ++ir) {
-            double c = 1.0, s = 0.0;
-            int p = 0, q = 0;
-            if (wave < pwaves) {
-              const int k = wave * 4 + (lane & 3);
-              if (k < nb) {
-                p = circle_block(k, ir, two);
-                q = circle_block(two - 1 - k, ir, two);
-                double ca;
+        // inner cyclic sweep on G (two-sided), accumulating V.  In each step
+        // lanes k < nb of wave 0 form the rotation of pair k once and publish
+        // it in LDS; then, in one phase, thread t < nb^2 applies both
+        // rotations of its 2 x 2 block of G (rows of pair t / nb, columns of
+        // pair t % nb: G' = J^T G J restricted to that block), and the next
+        // 2 nb^2 threads apply the column rotations to V.  The pairs partition
+        // the indices, so every entry has exactly one writer.
+        {
+          for (int isw = 0; isw < J.inner_sweeps; ++isw) {
+            double inner_off = 0.0;
+            for (int ir = 0; ir < two - 1; ++ir) {
+              if (tid < nb) {
+                const int p = circle_block(tid, ir, two);
+                const int q = circle_block(two - 1 - tid, ir, two);
+                double c, s, ca;
                 jacobi_rotation(G[p * gs + p], G[q * gs + q], G[p * gs + q], J.tol, c, s, ca);
                 inner_off = fmax(inner_off, ca);
+                rot_c[tid] = c;
+                rot_s[tid] = s;
+                rot_p[tid] = p;
+                rot_q[tid] = q;
               }
-              const int src = lane >> 4;           // pair of this quarter-wave
-              c = __shfl(c, src, 64);
-              s = __shfl(s, src, 64);
-              p = __shfl(p, src, 64);
-              q = __shfl(q, src, 64);
-              const int k2 = wave * 4 + src;
-              if (k2 < nb && s != 0.0) {
-                for (int jj = (lane & 15); jj < two; jj += 16) {
-                  const double gp = G[p * gs + jj], gq = G[q * gs + jj];
-                  G[p * gs + jj] = c * gp - s * gq;
-                  G[q * gs + jj] = s * gp + c * gq;
+              __syncthreads();
+              if (tid < nb * nb) {
+                const int k1 = tid / nb, k2 = tid - k1 * nb;
+                const double c1 = rot_c[k1], s1 = rot_s[k1], c2 = rot_c[k2], s2 = rot_s[k2];
+                if (s1 != 0.0 || s2 != 0.0) {
+                  const int a0 = rot_p[k1], a1 = rot_q[k1], b0 = rot_p[k2], b1 = rot_q[k2];
+                  const double g00 = G[a0 * gs + b0], g01 = G[a0 * gs + b1];
+                  const double g10 = G[a1 * gs + b0], g11 = G[a1 * gs + b1];
+                  // rows: p' = c1 p - s1 q, q' = s1 p + c1 q
+                  const double h00 = c1 * g00 - s1 * g10, h01 = c1 * g01 - s1 * g11;
+                  const double h10 = s1 * g00 + c1 * g10, h11 = s1 * g01 + c1 * g11;
+                  // columns: p' = c2 p - s2 q, q' = s2 p + c2 q
+                  G[a0 * gs + b0] = c2 * h00 - s2 * h01;
+                  G[a0 * gs + b1] = s2 * h00 + c2 * h01;
+                  G[a1 * gs + b0] = c2 * h10 - s2 * h11;
+                  G[a1 * gs + b1] = s2 * h10 + c2 * h11;
+                }
+              } else if (tid < nb * nb + two * nb) {
+                const int e = tid - nb * nb;
+                const int i = e / nb, k = e - i * nb;
+                const double c = rot_c[k], sn = rot_s[k];
+                if (sn != 0.0) {
+                  const int p = rot_p[k], q = rot_q[k];
+                  const double vp = V[i * gs + p], vq = V[i * gs + q];
+                  V[i * gs + p] = c * vp - sn * vq;
+                  V[i * gs + q] = sn * vp + c * vq;
                 }
               }
+              __syncthreads();
+            }
+            if (wave == 0) {
+              const double w = warp_max(inner_off);
+              if (lane == 0) sh_off[0] = w;
             }
             __syncthreads();
-            if (wave < pwaves) {
-              const int k2 = wave * 4 + (lane >> 4);
-              if (k2 < nb && s != 0.0) {
-                for (int ii = (lane & 15); ii < two; ii += 16) {
-                  const double gp = G[ii * gs + p], gq = G[ii * gs + q];
-                  G[ii * gs + p] = c * gp - s * gq;
-                  G[ii * gs + q] = s * gp + c * gq;
-                  const double vp = V[ii * gs + p], vq = V[ii * gs + q];
-                  V[ii * gs + p] = c * vp - s * vq;
-                  V[ii * gs + q] = s * vp + c * vq;
-                }
-              }
-            }
+            const double mx = sh_off[0];
             __syncthreads();
+            if (isw == 0) local_off = fmax(local_off, mx);
+            if (mx <= J.tol) break;
           }
-          double w = warp_max(inner_off);
-          if (lane == 0) sh_off[wave] = w;
-          __syncthreads();
-          double mx = 0.0;
-          for (int k = 0; k < (int)(blockDim.x >> 6); ++k) mx = fmax(mx, sh_off[k]);
-          __syncthreads();
-          if (isw == 0) local_off = fmax(local_off, mx);
-          if (mx <= J.tol) break;
         }
         unsigned long long t3 = wall_clock64();
         // A(:, pair) <- P V on fp64 MFMA: 16 x 16 output blocks over
-        // (row block, column block), K = two.
+        // (row block, column block), K = two.  The blocks are held in
+        // registers until every wave has finished reading P, written back
+        // into P, and then copied out column by column (coalesced).
         {
           const int64_t rblocks = (n + 15) / 16;
-          const int64_t nblocks = rblocks * nbk;
-          for (int64_t ob = wave; ob < nblocks; ob += 16) {
-            const int64_t rb = ob / nbk;
-            const int cb = (int)(ob % nbk);
-            const int64_t r = rb * 16 + (lane & 15);
-            const int j = cb * 16 + (lane & 15);
-            f64x4_t d = {0.0, 0.0, 0.0, 0.0};
-            for (int kt = 0; kt < (two + 3) / 4; ++kt) {
-              const int k = kt * 4 + (lane >> 4);
-              const double a = (r < n && k < two) ? P[k * ld + r] : 0.0;
-              const double b = (j < two && k < two) ? V[k * gs + j] : 0.0;
-              d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
-            }
-            const int jo = cb * 16 + (lane & 15);
-            if (jo < two) {
-              const int gc = jo < nb ? bp * nb + jo : bq * nb + (jo - nb);
+          const int64_t nblocks = rblocks * nbk;   // <= 16 * JAC_APPLY_MAX (host check)
+          f64x4_t d[JAC_APPLY_MAX];
 #pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int64_t ro = rb * 16 + 4 * v + (lane >> 4);
-                if (ro < n) A[(int64_t)gc * n + ro] = d[v];
+          for (int it = 0; it < JAC_APPLY_MAX; ++it) {
+            d[it] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+            const int64_t ob = wave + 16 * it;
+            if (ob < nblocks) {
+              const int64_t rb = ob / nbk;
+              const int cb = (int)(ob % nbk);
+              const int64_t r = rb * 16 + (lane & 15);
+              const int j = cb * 16 + (lane & 15);
+              for (int kt = 0; kt < (two + 3) / 4; ++kt) {
+                const int k = kt * 4 + (lane >> 4);
+                const double a = (r < n && k < two) ? P[k * ld + r] : 0.0;
+                const double b = (j < two && k < two) ? V[k * gs + j] : 0.0;
+                d[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d[it], 0, 0, 0);
               }
             }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int it = 0; it < JAC_APPLY_MAX; ++it) {
+            const int64_t ob = wave + 16 * it;
+            if (ob < nblocks) {
+              const int64_t rb = ob / nbk;
+              const int cb = (int)(ob % nbk);
+              const int jo = cb * 16 + (lane & 15);
+              if (jo < two) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  const int64_t ro = rb * 16 + 4 * v + (lane >> 4);
+                  if (ro < n) P[jo * ld + ro] = d[it][v];
+                }
+              }
+            }
+          }
+          __syncthreads();
+          for (int c = wave; c < two; c += 16) {
+            const int gc = c < nb ? bp * nb + c : bq * nb + (c - nb);
+            double* dst = A + (int64_t)gc * n;
+            for (int64_t r = lane; r < n; r += 64) dst[r] = P[c * ld + r];
           }
         }
         __threadfence();
@@ -698,6 +731,7 @@ hipError_t jacobi_eig_batched(int nmat, const double* const* Z, const int64_t* n
   for (int k = 0; k < nmat; ++k) nmax = std::max(nmax, ns[k]);
   int nb, nblk_dummy;
   jacobi_geometry(nmax, nb, nblk_dummy);
+  if (ceil_div(nmax, 16) * ceil_div(2 * nb, 16) > 16 * JAC_APPLY_MAX) return hipErrorInvalidValue;
   JacobiArgs ja = {};
   FinishArgs fa = {};
   ja.nmat = nmat;
