@@ -119,8 +119,9 @@ struct Plan {
   int gelem = 0;     // Gram / sketch product
   int telem = 0;     // first mode product (reads X)
   int celem = 0;     // later mode products, reconstruction and error
-  bool need_xconv = false;
-  bool need_xt = false;      // transposed bf16 copy for the last mode (large-tile Gram)
+  bool need_pad = false;     // zero-padded bf16 copies (Xpad, Xt) for the bf16 Gram products
+  int64_t in_pad = 0;        // last dimension padded to a multiple of 64
+  int64_t rows_pad = 0;      // T / I_N padded to a multiple of 64 (row length of Xt)
   int64_t T = 1;
   ModeGeom m[8];
   int first_mode = 0;
@@ -130,6 +131,20 @@ struct Plan {
 };
 
 int dtype_elem(int dt) { return dt == RBKI_F64 ? E_F64 : dt == RBKI_F32 ? E_F32 : E_BF16; }
+
+// Mode n of the zero-padded bf16 operands: modes before the last read Xpad as
+// [A_n, I_n, Bp_n] with Bp_n = (B_n / I_N) I_Npad; the last mode reads Xt as
+// [1, I_N, rows_pad].
+void padded_view(const Plan& P, int n, int64_t& A, int64_t& Bp) {
+  const ModeGeom& g = P.m[n];
+  if (n == P.N - 1) {
+    A = 1;
+    Bp = P.rows_pad;
+  } else {
+    A = g.A;
+    Bp = (g.B / P.dims[P.N - 1]) * P.in_pad;
+  }
+}
 
 rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
   if (!prm) return fail(RBKI_E_INVALID, "params is NULL");
@@ -155,17 +170,13 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     P.T *= P.dims[n];
   }
   P.xelem = dtype_elem(xtype);
-  if (P.xelem == E_F64 && P.prec == RBKI_PLAIN) {
-    P.gelem = P.telem = P.celem = E_F64;
-  } else if (P.prec == RBKI_PLAIN) {
-    P.gelem = P.telem = P.xelem;      // F32 or BF16
-    P.celem = E_F32;
-  } else {
-    P.gelem = P.telem = E_BF16;
-    P.celem = E_F32;
-    P.need_xconv = P.xelem != E_BF16;
-  }
-  P.need_xt = P.gelem == E_BF16;
+  // the first mode product always reads X itself, in its own type
+  P.telem = P.xelem;
+  P.celem = P.xelem == E_F64 ? E_F64 : E_F32;
+  P.gelem = P.prec == RBKI_PLAIN ? P.xelem : E_BF16;
+  P.need_pad = P.gelem == E_BF16;
+  P.in_pad = pad64(P.dims[P.N - 1]);
+  P.rows_pad = pad64(P.T / P.dims[P.N - 1]);
   double best = -1.0;
   for (int n = 0; n < P.N; ++n) {
     ModeGeom& g = P.m[n];
@@ -187,12 +198,18 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     P.maxS = std::max(P.maxS, g.S);
     P.maxSp = std::max(P.maxSp, g.Sp);
     P.maxRI = std::max(P.maxRI, g.R * g.I);
-    P.maxSJ = std::max(P.maxSJ, g.S * g.J);
     if (P.gelem == E_BF16) {
-      GramArgs ga = g.B > 1 ? gram_plan_big(g.A, g.I, g.B, (int)g.S, cu_count())
-                            : gram_plan_big(1, g.I, g.A, (int)g.S, cu_count());
-      P.partial_bytes = std::max(P.partial_bytes, gram_big_partial_bytes(ga));
+      int64_t A, Bp;
+      padded_view(P, n, A, Bp);
+      P.maxSJ = std::max(P.maxSJ, g.S * A * Bp);
+      if (gram_pipe_ok(g.I, (int)g.S)) {
+        P.partial_bytes = std::max(P.partial_bytes, gram_pipe_partial_bytes(gram_plan_pipe(A, g.I, Bp, (int)g.S, cu_count())));
+      } else {
+        GramArgs ga = gram_plan(E_BF16, A, g.I, Bp, (int)g.S, cu_count());
+        P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(ga, E_BF16));
+      }
     } else {
+      P.maxSJ = std::max(P.maxSJ, g.S * g.J);
       GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)g.S, cu_count());
       P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(ga, P.gelem));
     }
@@ -228,8 +245,8 @@ struct Arena {
 };
 
 struct Buffers {
-  void* xconv = nullptr;
-  void* xt = nullptr;      // last mode, transposed bf16 copy (I_N x prod_{k<N} I_k)
+  void* xpad = nullptr;    // bf16, (T / I_N) x I_Npad, zero-padded
+  void* xt = nullptr;      // bf16, I_N x rows_pad: the last mode, transposed and zero-padded
   void* omegaT = nullptr;
   void* partial = nullptr;
   double* C = nullptr;
@@ -259,8 +276,10 @@ struct Buffers {
 
 void carve(const Plan& P, Arena& ar, Buffers& b) {
   const int es_g = elem_size(P.gelem);
-  if (P.need_xconv) b.xconv = ar.take((size_t)P.T * elem_size(P.telem));
-  if (P.need_xt) b.xt = ar.take((size_t)P.T * 2);
+  if (P.need_pad) {
+    b.xpad = ar.take((size_t)(P.T / P.dims[P.N - 1]) * P.in_pad * 2);
+    b.xt = ar.take((size_t)P.dims[P.N - 1] * P.rows_pad * 2);
+  }
   b.omegaT = ar.take((size_t)P.maxSJ * es_g);
   b.partial = ar.take(P.partial_bytes);
   b.C = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
@@ -312,24 +331,42 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
   const ModeGeom& g = P.m[n];
   const int64_t I = g.I, S = g.S, Sp = g.Sp;
   double* Qt = b.Qt[n];
-  {
-    ProfScope ps("omega", st);
-    HIPCHK(launch_omega(P.gelem, P.seed, n, S * g.J, b.omegaT, st));
-  }
   // C -> b.C (I x I), W^T -> b.Yt (S x I)
   if (P.gelem == E_BF16) {
-    // k-contiguous view of every mode: the last one reads the transposed copy
-    GramArgs ga = g.B > 1 ? gram_plan_big(g.A, g.I, g.B, (int)S, cu_count())
-                          : gram_plan_big(1, g.I, g.A, (int)S, cu_count());
-    ga.X = g.B > 1 ? xsrc : b.xt;
-    ga.omegaT = b.omegaT;
-    ga.partial = b.partial;
+    // zero-padded bf16 operands: Xpad for the leading modes, Xt for the last
+    int64_t A, Bp;
+    padded_view(P, n, A, Bp);
     {
-      ProfScope ps("gram", st);
-      HIPCHK(launch_gram_big(ga, st));
+      ProfScope ps("omega", st);
+      HIPCHK(launch_omega_pad(P.seed, n, S, g.J, g.B, P.dims[P.N - 1], A * Bp, b.omegaT, st));
     }
-    HIPCHK(launch_gram_big_reduce(ga, b.C, b.Yt, st));
+    const void* xop = n == P.N - 1 ? b.xt : b.xpad;
+    if (gram_pipe_ok(I, (int)S)) {
+      GramArgs ga = gram_plan_pipe(A, I, Bp, (int)S, cu_count());
+      ga.X = xop;
+      ga.omegaT = b.omegaT;
+      ga.partial = b.partial;
+      {
+        ProfScope ps("gram", st);
+        HIPCHK(launch_gram_pipe(ga, st));
+      }
+      HIPCHK(launch_gram_pipe_reduce(ga, b.C, b.Yt, st));
+    } else {
+      GramArgs ga = gram_plan(E_BF16, A, I, Bp, (int)S, cu_count());
+      ga.X = xop;
+      ga.omegaT = b.omegaT;
+      ga.partial = b.partial;
+      {
+        ProfScope ps("gram", st);
+        HIPCHK(launch_gram_main(E_BF16, ga, st));
+      }
+      HIPCHK(launch_gram_reduce(E_BF16, ga, b.C, b.Yt, st));
+    }
   } else {
+    {
+      ProfScope ps("omega", st);
+      HIPCHK(launch_omega(P.gelem, P.seed, n, S * g.J, b.omegaT, st));
+    }
     GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)S, cu_count());
     ga.X = xsrc;
     ga.omegaT = b.omegaT;
@@ -577,15 +614,9 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
   carve(P, ar, b);
   dgemm_set_scratch(b.dscratch, kDgemmScratch);
   const void* xsrc = X;
-  if (P.need_xconv) {
+  if (P.need_pad) {
     ProfScope ps("convert", st);
-    HIPCHK(convert_tensor(P.xelem, X, P.telem, b.xconv, P.T, st));
-    xsrc = b.xconv;
-  }
-  if (P.need_xt) {
-    ProfScope ps("convert", st);
-    const ModeGeom& gl = P.m[P.N - 1];
-    HIPCHK(launch_transpose_bf16(P.xelem, X, gl.A, gl.I, b.xt, st));
+    HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
   }
   s = run_mode(P, b, xsrc, mode, false, st);
   if (s != RBKI_OK) return s;
@@ -629,15 +660,9 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   carve(P, ar, b);
   dgemm_set_scratch(b.dscratch, kDgemmScratch);
   const void* xsrc = X;
-  if (P.need_xconv) {
+  if (P.need_pad) {
     ProfScope ps("convert", st);
-    HIPCHK(convert_tensor(P.xelem, X, P.telem, b.xconv, P.T, st));
-    xsrc = b.xconv;
-  }
-  if (P.need_xt) {
-    ProfScope ps("convert", st);
-    const ModeGeom& gl = P.m[P.N - 1];
-    HIPCHK(launch_transpose_bf16(P.xelem, X, gl.A, gl.I, b.xt, st));
+    HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
   }
   HIPCHK(fill_zero(b.info, 64, st));
   for (int n = 0; n < P.N; ++n) {

@@ -235,242 +235,6 @@ __global__ void __launch_bounds__(256, E == E_F64 ? 1 : 2) gram_sketch_kernel(Gr
   }
 }
 
-// ------------------------------------------------------------------------
-// bf16 Gram + sketch with large tiles.  Lower-triangle tiles of C are
-// 256 x 256 (four waves of 128 x 128, 4 x 4 MFMA 32x32x16 blocks each); the
-// sketch tiles are 256 x 64 (four waves of 64 x 64).  Both operands are read
-// k-contiguous (the last mode reads a transposed copy), staged through LDS in
-// double-buffered K tiles of 64, and every workgroup writes one split-K
-// partial tile.  At 128 x 128 per wave the LDS traffic per flop is half that
-// of 64 x 64 wave tiles, which is what bf16 MFMA rate on gfx950 needs.
-constexpr int BT = 256;            // big tile rows
-constexpr int BTW = 64;            // sketch tile columns
-
-__device__ inline void decode_big_tile(const GramArgs& g, int tile, int& ti, int& tj, bool& is_w) {
-  if (tile < g.ntri) {
-    int t = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
-    while ((t + 1) * (t + 2) / 2 <= tile) ++t;
-    while (t * (t + 1) / 2 > tile) --t;
-    ti = t;
-    tj = tile - t * (t + 1) / 2;
-    is_w = false;
-  } else {
-    const int w = tile - g.ntri;
-    ti = w / g.nw;
-    tj = w % g.nw;
-    is_w = true;
-  }
-}
-
-// Load `nrows_tile` rows x 64 bf16 (k contiguous) into registers: chunk c of
-// 16 bytes = row c / 8, k offset (c % 8) * 8.
-template <int NCH, bool VEC>
-__device__ inline void load_rows_bf16(uint4* ch, unsigned& valid, const bf16_t* base, int64_t row_stride,
-                                      int64_t row0, int64_t nrows, int64_t kvalid) {
-  const int tid = threadIdx.x;
-  valid = 0;
-#pragma unroll
-  for (int j = 0; j < NCH; ++j) {
-    const int c = tid + 256 * j;
-    const int row = c >> 3, kk = (c & 7) * 8;
-    const int64_t r = row0 + row;
-    if (VEC) {
-      // clamped address, always in bounds; out-of-range chunks are zeroed at the LDS store
-      const int64_t rc = r < nrows ? r : nrows - 1;
-      const int kc = kk < kvalid ? kk : 0;
-      ch[j] = *(const uint4*)(base + rc * row_stride + kc);
-      valid |= (r < nrows && kk < kvalid) ? 1u << j : 0u;
-    } else {
-      union { uint4 v; bf16_t e[8]; } u;
-      u.v = make_uint4(0, 0, 0, 0);
-      if (r < nrows) {
-        const bf16_t* p = base + r * row_stride + kk;
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (kk + e < kvalid) u.e[e] = p[e];
-      }
-      ch[j] = u.v;
-      valid |= 1u << j;
-    }
-  }
-}
-
-template <int NCH>
-__device__ inline void store_rows_lds(const uint4* ch, unsigned valid, char* lds) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int j = 0; j < NCH; ++j) {
-    const int c = tid + 256 * j;
-    const uint4 v = ((valid >> j) & 1u) ? ch[j] : make_uint4(0, 0, 0, 0);
-    *(uint4*)(lds + (c >> 3) * LDS_ROW + (c & 7) * 16) = v;
-  }
-}
-
-template <bool VEC>
-__global__ void __launch_bounds__(256, 1) gram_bf16_big_kernel(GramArgs g) {
-  __shared__ __attribute__((aligned(16))) char lds[2][2][BT * LDS_ROW];
-  const int w = blockIdx.x;
-  int split, tile;
-  if (g.xcd_map) {
-    const int xcd = w & 7, slot = w >> 3;
-    split = xcd + 8 * (slot / g.ntiles);
-    tile = slot % g.ntiles;
-  } else {
-    split = w / g.ntiles;
-    tile = w % g.ntiles;
-  }
-  int ti, tj;
-  bool is_w;
-  decode_big_tile(g, tile, ti, tj, is_w);
-  const bool diag = !is_w && ti == tj;
-  const int64_t r0 = (int64_t)ti * BT;
-  const int64_t c0 = is_w ? (int64_t)tj * BTW : (int64_t)tj * BT;
-  const int64_t kt0 = (int64_t)split * g.nkt / g.splits;
-  const int64_t kt1 = (int64_t)(split + 1) * g.nkt / g.splits;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int half = lane >> 5, lr = lane & 31;
-  // wave tile: C tiles 128 x 128 at (wr, wc); sketch tiles 64 x 64 at (64 * wave, 0)
-  const int wr = is_w ? 64 * wave : (wave >> 1) * 128;
-  const int wc = is_w ? 0 : (wave & 1) * 128;
-  const bf16_t* X = (const bf16_t*)g.X;
-  const bf16_t* Om = (const bf16_t*)g.omegaT;
-
-  f32x16_t acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.f;
-
-  uint4 ca[8], cb[8];
-  unsigned va = 0, vb = 0;
-  auto kt_coords = [&](int64_t kt, int64_t& a, int64_t& b0, int64_t& kvalid) {
-    a = kt / g.nbt;
-    b0 = (kt - a * g.nbt) * 64;
-    kvalid = g.B - b0 < 64 ? g.B - b0 : 64;
-  };
-  // sketch rows beyond this tile's 64 columns are not needed
-  const int64_t brows = is_w ? (g.S < c0 + BTW ? g.S : c0 + BTW) : g.I;
-  auto load = [&](int64_t kt) {
-    int64_t a, b0, kv;
-    kt_coords(kt, a, b0, kv);
-    const bf16_t* xa = X + a * g.I * g.B + b0;
-    load_rows_bf16<8, VEC>(ca, va, xa, g.B, r0, g.I, kv);
-    if (!diag) {
-      if (is_w) load_rows_bf16<8, VEC>(cb, vb, Om + a * g.B + b0, g.J, c0, brows, kv);
-      else load_rows_bf16<8, VEC>(cb, vb, xa, g.B, c0, g.I, kv);
-    }
-  };
-  auto store = [&](int buf) {
-    store_rows_lds<8>(ca, va, lds[buf][0]);
-    if (!diag) store_rows_lds<8>(cb, vb, lds[buf][1]);
-  };
-  const int lim = is_w ? 2 : 4;     // 32 x 32 blocks per wave along each side
-
-  if (kt0 < kt1) {
-    load(kt0);
-    store(0);
-    __syncthreads();
-    for (int64_t kt = kt0; kt < kt1; ++kt) {
-      const int buf = (int)((kt - kt0) & 1);
-      const bool more = kt + 1 < kt1;
-      if (more) load(kt + 1);
-      const char* la = lds[buf][0];
-      const char* lb = diag ? lds[buf][0] : lds[buf][1];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {          // four K steps of 16
-        const int koff = half * 64 + t * 16;  // lane half takes k [32 half + 8 t, +8)
-        bf16x8_t av[4], bv[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          if (m < lim) {
-            av[m] = *(const bf16x8_t*)(la + (wr + m * 32 + lr) * LDS_ROW + koff);
-            bv[m] = *(const bf16x8_t*)(lb + (wc + m * 32 + lr) * LDS_ROW + koff);
-          }
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int n = 0; n < 4; ++n)
-            if (m < lim && n < lim)
-              acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
-      }
-      if (more) store(buf ^ 1);
-      __syncthreads();
-    }
-  }
-
-  // partial tile: C tiles are BT x BT, sketch tiles BT x BTW (row-major)
-  const int width = is_w ? BTW : BT;
-  float* out = (float*)g.partial + (int64_t)split * g.part_stride + (is_w ? g.ntri * (int64_t)BT * BT +
-                                                                          (int64_t)(tile - g.ntri) * BT * BTW
-                                                                        : (int64_t)tile * BT * BT);
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      if (m < lim && n < lim) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int row = wr + m * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-          const int col = wc + n * 32 + lr;
-          out[row * width + col] = acc[m][n][v];
-        }
-      }
-    }
-}
-
-// Reduce the big-tile partials: C (I x I) and W^T (S x I), float64, fixed order.
-__global__ void gram_big_reduce_kernel(GramArgs g, double* C, double* Wt) {
-  const int64_t nC = g.I * g.I;
-  const int64_t total = nC + (int64_t)g.S * g.I;
-  const float* P = (const float*)g.partial;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t off;
-    if (e < nC) {
-      int64_t i = e / g.I, j = e - i * g.I;
-      if (j > i) { const int64_t t = i; i = j; j = t; }
-      const int64_t ti = i / BT, tj = j / BT;
-      const int64_t tile = ti * (ti + 1) / 2 + tj;
-      off = tile * BT * BT + (i - ti * BT) * BT + (j - tj * BT);
-    } else {
-      const int64_t f = e - nC;
-      const int64_t s = f / g.I, i = f - s * g.I;
-      const int64_t ti = i / BT, sj = s / BTW;
-      off = g.ntri * (int64_t)BT * BT + (ti * g.nw + sj) * BT * BTW + (i - ti * BT) * BTW + (s - sj * BTW);
-    }
-    double acc = 0.0;
-    for (int sp = 0; sp < g.splits; ++sp) acc += (double)P[sp * g.part_stride + off];
-    if (e < nC) C[e] = acc;
-    else Wt[e - nC] = acc;
-  }
-}
-
-// Transposed bf16 copy for the last mode: X viewed as rows (A x I) of any
-// element type -> Xt (I x A) bf16, 64 x 64 tiles through LDS.
-template <class T>
-__global__ void transpose_to_bf16_kernel(const T* X, int64_t A, int64_t I, bf16_t* Xt) {
-  __shared__ float tile[64][65];
-  const int64_t a0 = (int64_t)blockIdx.y * 64, i0 = (int64_t)blockIdx.x * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 256 threads: 4 rows at a time
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t a = a0 + r, i = i0 + tx;
-    float v = 0.f;
-    if (a < A && i < I) {
-      if constexpr (sizeof(T) == 2) v = bf16_to_f32(((const bf16_t*)X)[a * I + i]);
-      else v = (float)X[a * I + i];
-    }
-    tile[r][tx] = v;
-  }
-  __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t i = i0 + r, a = a0 + tx;
-    if (a < A && i < I) Xt[i * A + a] = f32_to_bf16(tile[tx][r]);
-  }
-}
-
 // Sum the split-K partials in a fixed order: C (I x I, both triangles) and
 // W^T (S x I), float64.
 template <class Out>
@@ -635,59 +399,6 @@ hipError_t launch_gram_reduce(int elem, const GramArgs& g, double* C, double* Wt
   unsigned rgrid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 4096);
   if (elem == E_F64) hipLaunchKernelGGL(gram_reduce_kernel<double>, dim3(rgrid), dim3(256), 0, s, g, C, Wt);
   else hipLaunchKernelGGL(gram_reduce_kernel<float>, dim3(rgrid), dim3(256), 0, s, g, C, Wt);
-  return hipGetLastError();
-}
-
-GramArgs gram_plan_big(int64_t A, int64_t I, int64_t B, int S, int cu_count) {
-  GramArgs g = {};
-  g.A = A;
-  g.I = I;
-  g.B = B;
-  g.J = A * B;
-  g.S = S;
-  g.nt = (int)ceil_div(I, BT);
-  g.ntri = g.nt * (g.nt + 1) / 2;
-  g.nw = S > 0 ? (int)ceil_div(S, BTW) : 0;
-  g.ntiles = g.ntri + g.nt * g.nw;
-  g.nbt = ceil_div(B, 64);
-  g.nkt = A * g.nbt;
-  const int64_t want = ceil_div(2 * (int64_t)cu_count, g.ntiles);
-  int64_t splits = want < 1 ? 1 : want;
-  const int64_t max_by_k = g.nkt / 8 > 0 ? g.nkt / 8 : 1;
-  if (splits > max_by_k) splits = max_by_k;
-  if (splits >= 8) splits = (splits + 7) / 8 * 8;
-  if (splits > g.nkt) splits = g.nkt > 0 ? g.nkt : 1;
-  g.splits = (int)splits;
-  g.xcd_map = (g.splits % 8 == 0) ? 1 : 0;
-  g.vec_ok = ((B * 2) % 16 == 0 && (g.J * 2) % 16 == 0) ? 1 : 0;
-  g.part_stride = (int64_t)g.ntri * BT * BT + (int64_t)g.nt * g.nw * BT * BTW;
-  return g;
-}
-
-size_t gram_big_partial_bytes(const GramArgs& g) { return (size_t)g.splits * g.part_stride * 4; }
-
-hipError_t launch_gram_big(const GramArgs& g, hipStream_t s) {
-  const dim3 grid((unsigned)(g.ntiles * g.splits));
-  if (gram_vec(g)) hipLaunchKernelGGL(gram_bf16_big_kernel<true>, grid, dim3(256), 0, s, g);
-  else hipLaunchKernelGGL(gram_bf16_big_kernel<false>, grid, dim3(256), 0, s, g);
-  return hipGetLastError();
-}
-
-hipError_t launch_gram_big_reduce(const GramArgs& g, double* C, double* Wt, hipStream_t s) {
-  const int64_t total = g.I * g.I + (int64_t)g.S * g.I;
-  unsigned rgrid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 4096);
-  hipLaunchKernelGGL(gram_big_reduce_kernel, dim3(rgrid), dim3(256), 0, s, g, C, Wt);
-  return hipGetLastError();
-}
-
-hipError_t launch_transpose_bf16(int src_elem, const void* X, int64_t A, int64_t I, void* Xt, hipStream_t s) {
-  dim3 grid((unsigned)ceil_div(I, 64), (unsigned)ceil_div(A, 64));
-  if (grid.y > 65535) return hipErrorInvalidValue;
-  switch (src_elem) {
-    case E_F64: hipLaunchKernelGGL(transpose_to_bf16_kernel<double>, grid, dim3(256), 0, s, (const double*)X, A, I, (bf16_t*)Xt); break;
-    case E_F32: hipLaunchKernelGGL(transpose_to_bf16_kernel<float>, grid, dim3(256), 0, s, (const float*)X, A, I, (bf16_t*)Xt); break;
-    default: hipLaunchKernelGGL(transpose_to_bf16_kernel<bf16_t>, grid, dim3(256), 0, s, (const bf16_t*)X, A, I, (bf16_t*)Xt); break;
-  }
   return hipGetLastError();
 }
 

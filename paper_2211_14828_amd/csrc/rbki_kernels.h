@@ -16,7 +16,8 @@ struct GramArgs {
   int64_t nkt, nbt;
   int splits, xcd_map, vec_ok;
   void* partial;            // [splits][ntiles][128*128] float (double for fp64)
-  int64_t part_stride;      // elements per split (large-tile bf16 form)
+  int64_t part_stride;      // elements per split (pipelined bf16 form)
+  int64_t wpart_off;        // pipelined form: offset of the sketch partials within a split
   // fp8 block-exponent geometry (blocks of 32 per dimension)
   int order, mode;
   int64_t pdims[8];         // (padded) tensor dims
@@ -30,14 +31,22 @@ size_t gram_partial_bytes(const GramArgs& g, int elem);
 hipError_t launch_gram_main(int elem, const GramArgs& g, hipStream_t s);
 hipError_t launch_gram_reduce(int elem, const GramArgs& g, double* C, double* Wt, hipStream_t s);
 hipError_t launch_omega(int elem, uint64_t seed, int mode, int64_t total, void* out, hipStream_t s);
-// bf16 large-tile form (256 x 256 Gram tiles, 256 x 64 sketch tiles); both
-// operands k-contiguous (B > 1 views; the last mode uses a transposed copy).
-GramArgs gram_plan_big(int64_t A, int64_t I, int64_t B, int S, int cu_count);
-size_t gram_big_partial_bytes(const GramArgs& g);
-hipError_t launch_gram_big(const GramArgs& g, hipStream_t s);
-hipError_t launch_gram_big_reduce(const GramArgs& g, double* C, double* Wt, hipStream_t s);
-// X viewed as (A x I) rows -> Xt (I x A) in bf16.
-hipError_t launch_transpose_bf16(int src_elem, const void* X, int64_t A, int64_t I, void* Xt, hipStream_t s);
+// bf16 pipelined form (gram_pipe.hip): 256 x 256 lower-triangle tiles, the
+// sketch (S <= 64) computed by the spare wave of each diagonal tile; operands
+// are the zero-padded bf16 views described there (row pitch Bp, a multiple of 64).
+int64_t pad64(int64_t v);
+bool gram_pipe_ok(int64_t I, int S);
+GramArgs gram_plan_pipe(int64_t A, int64_t I, int64_t Bp, int S, int cu_count);
+size_t gram_pipe_partial_bytes(const GramArgs& g);
+hipError_t launch_gram_pipe(const GramArgs& g, hipStream_t s);
+hipError_t launch_gram_pipe_reduce(const GramArgs& g, double* C, double* Wt, hipStream_t s);
+// X viewed as R rows of length L -> Xpad (R x pad64(L)) and Xt (L x pad64(R)),
+// bf16 with zero padding (either output may be null).
+hipError_t launch_pad_copies(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, hipStream_t s);
+// Omega^T (S x J) of one mode as bf16 in the padded column layout S x Jp
+// (B: the mode's trailing size, IN: the last dimension; B = 1 for the last mode).
+hipError_t launch_omega_pad(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t Jp,
+                            void* out, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint64_t seed, uint32_t* out, hipStream_t s);
 
 // ------------------------------------------------------------ linalg.hip (float64)

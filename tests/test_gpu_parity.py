@@ -122,6 +122,12 @@ CASES = [
     ((160, 160, 160), (20, 20, 20), 10, 3, "float32", "plain", "c2small"),
     ((160, 160, 160), (20, 20, 20), 10, 3, "float32", "mixed_bf16", "c2small"),
     ((64, 50, 40), (6, 6, 6), 5, 1, "bfloat16", "plain", "bf16in"),
+    # several 256-row Gram tiles (off-diagonal tiles, ragged last tile and
+    # padding of the last dimension), order 4, and a sketch wider than 64
+    ((600, 40, 530), (20, 6, 15), 10, 2, "float32", "mixed_bf16", "bigtiles"),
+    ((300, 8, 7, 260), (12, 3, 3, 10), 6, 2, "float32", "mixed_bf16", "order4big"),
+    ((300, 200, 90), (60, 50, 20), 10, 1, "float32", "mixed_bf16", "widesketch"),
+    ((300, 40, 270), (12, 6, 10), 5, 2, "bfloat16", "mixed_bf16", "bf16big"),
     ((8, 20, 20), (8, 5, 5), 2, 1, "float64", "plain", "full_rank_mode"),
     ((5, 300, 7), (2, 3, 2), 5, 2, "float64", "plain", "thin"),
 ]
