@@ -38,51 +38,72 @@ struct ProdArgs {
   int vec_a, vec_b;
 };
 
-template <int E>
-__device__ inline void load_op(uint4* chunk, const Operand& op, int64_t batch, int64_t row0, int64_t k0,
-                               int64_t K, bool vec) {
+// Stage 4 chunks (16 bytes each) of one operand tile in registers.
+// VEC (row starts 16-byte aligned, and the sizes make every chunk wholly in
+// or wholly out of range): each lane loads unconditionally from a clamped,
+// valid address and keeps a validity bit per chunk; the mask is applied when
+// the chunks are written to LDS, so no load sits under divergent control flow.
+template <int E, bool VEC>
+__device__ inline void load_op(uint4* chunk, unsigned& valid, const Operand& op, int64_t batch, int64_t row0,
+                               int64_t k0, int64_t K) {
   typedef typename Mma<E>::T T;
   constexpr int EPC = 16 / (int)sizeof(T);
   constexpr int BK = Mma<E>::BK;
   const T* base = (const T*)op.base + batch * op.batch_stride;
   const int tid = threadIdx.x;
+  valid = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = tid + 256 * j;
-    union { uint4 v; T e[EPC]; } u;
-    u.v = make_uint4(0, 0, 0, 0);
     if (op.k_stride == 1) {
       const int row = c / (BK / EPC);
       const int kk = (c % (BK / EPC)) * EPC;
       const int64_t r = row0 + row, k = k0 + kk;
-      if (r < op.rows) {
-        const T* p = base + r * op.row_stride + k;
-        if (vec && k + EPC <= K) u.v = *(const uint4*)p;
-        else
+      if (VEC) {
+        const int64_t rc = r < op.rows ? r : op.rows - 1;
+        const int64_t kc = k < K ? k : 0;
+        chunk[j] = *(const uint4*)(base + rc * op.row_stride + kc);
+        valid |= (r < op.rows && k < K) ? 1u << j : 0u;
+      } else {
+        union { uint4 v; T e[EPC]; } u;
+        u.v = make_uint4(0, 0, 0, 0);
+        if (r < op.rows) {
+          const T* p = base + r * op.row_stride + k;
 #pragma unroll
           for (int e = 0; e < EPC; ++e)
             if (k + e < K) u.e[e] = p[e];
+        }
+        chunk[j] = u.v;
+        valid |= 1u << j;
       }
     } else {
       const int per_k = TILE / EPC;
       const int kk = c / per_k;
       const int row = (c % per_k) * EPC;
       const int64_t r = row0 + row, k = k0 + kk;
-      if (k < K) {
-        const T* p = base + k * op.k_stride + r;
-        if (vec && r + EPC <= op.rows) u.v = *(const uint4*)p;
-        else
+      if (VEC) {
+        const int64_t rc = r < op.rows ? r : op.rows - EPC;
+        const int64_t kc = k < K ? k : 0;
+        chunk[j] = *(const uint4*)(base + kc * op.k_stride + rc);
+        valid |= (r < op.rows && k < K) ? 1u << j : 0u;
+      } else {
+        union { uint4 v; T e[EPC]; } u;
+        u.v = make_uint4(0, 0, 0, 0);
+        if (k < K) {
+          const T* p = base + k * op.k_stride + r;
 #pragma unroll
           for (int e = 0; e < EPC; ++e)
             if (r + e < op.rows) u.e[e] = p[e];
+        }
+        chunk[j] = u.v;
+        valid |= 1u << j;
       }
     }
-    chunk[j] = u.v;
   }
 }
 
 template <int E>
-__device__ inline void store_op(const uint4* chunk, const Operand& op, char* lds) {
+__device__ inline void store_op(const uint4* chunk, unsigned valid, const Operand& op, char* lds) {
   typedef typename Mma<E>::T T;
   constexpr int EPC = 16 / (int)sizeof(T);
   constexpr int BK = Mma<E>::BK;
@@ -90,16 +111,17 @@ __device__ inline void store_op(const uint4* chunk, const Operand& op, char* lds
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int c = tid + 256 * j;
+    const uint4 v = ((valid >> j) & 1u) ? chunk[j] : make_uint4(0, 0, 0, 0);
     if (op.k_stride == 1) {
       const int row = c / (BK / EPC);
       const int kk = (c % (BK / EPC)) * EPC;
-      *(uint4*)(lds + row * LDS_ROW + kk * (int)sizeof(T)) = chunk[j];
+      *(uint4*)(lds + row * LDS_ROW + kk * (int)sizeof(T)) = v;
     } else {
       const int per_k = TILE / EPC;
       const int kk = c / per_k;
       const int row = (c % per_k) * EPC;
       union { uint4 v; T e[EPC]; } u;
-      u.v = chunk[j];
+      u.v = v;
 #pragma unroll
       for (int e = 0; e < EPC; ++e) *(T*)(lds + (row + e) * LDS_ROW + kk * (int)sizeof(T)) = u.e[e];
     }
@@ -114,7 +136,7 @@ template <> __device__ inline double load_x<bf16_t>(const void* X, int64_t i) {
 }
 
 // EPI = 0: store; EPI = 1: residual with X of type XT
-template <int E, int EPI, class XT>
+template <int E, int EPI, class XT, bool VEC>
 __global__ void __launch_bounds__(256, E == E_F64 ? 1 : 2) prod_kernel(ProdArgs p) {
   typedef Mma<E> M;
   typedef typename M::Out Out;
@@ -132,23 +154,24 @@ __global__ void __launch_bounds__(256, E == E_F64 ? 1 : 2) prod_kernel(ProdArgs 
   typename M::Frag f;
   M::zero(f);
   uint4 ca[4], cb[4];
+  unsigned va, vb;
   const int64_t nk = ceil_div(p.K, BK);
-  load_op<E>(ca, p.a, batch, r0, 0, p.K, p.vec_a);
-  load_op<E>(cb, p.b, batch, c0, 0, p.K, p.vec_b);
-  store_op<E>(ca, p.a, lds[0][0]);
-  store_op<E>(cb, p.b, lds[0][1]);
+  load_op<E, VEC>(ca, va, p.a, batch, r0, 0, p.K);
+  load_op<E, VEC>(cb, vb, p.b, batch, c0, 0, p.K);
+  store_op<E>(ca, va, p.a, lds[0][0]);
+  store_op<E>(cb, vb, p.b, lds[0][1]);
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = (int)(kt & 1);
     const bool more = kt + 1 < nk;
     if (more) {
-      load_op<E>(ca, p.a, batch, r0, (kt + 1) * BK, p.K, p.vec_a);
-      load_op<E>(cb, p.b, batch, c0, (kt + 1) * BK, p.K, p.vec_b);
+      load_op<E, VEC>(ca, va, p.a, batch, r0, (kt + 1) * BK, p.K);
+      load_op<E, VEC>(cb, vb, p.b, batch, c0, (kt + 1) * BK, p.K);
     }
     M::step(f, lds[buf][0], lds[buf][1], lane, wr, wc);
     if (more) {
-      store_op<E>(ca, p.a, lds[buf ^ 1][0]);
-      store_op<E>(cb, p.b, lds[buf ^ 1][1]);
+      store_op<E>(ca, va, p.a, lds[buf ^ 1][0]);
+      store_op<E>(cb, vb, p.b, lds[buf ^ 1][1]);
     }
     __syncthreads();
   }
@@ -371,7 +394,8 @@ hipError_t launch_prod(const ProdArgs& p, int64_t batches, hipStream_t s) {
     q.b.base = (const T*)p.b.base + b0 * p.b.batch_stride;
     if (EPI == 0) q.out = (Out*)p.out + b0 * p.out_bs;
     dim3 grid((unsigned)(p.row_tiles * p.col_tiles), (unsigned)nb);
-    hipLaunchKernelGGL((prod_kernel<E, EPI, XT>), grid, dim3(256), 0, s, q);
+    if (p.vec_a && p.vec_b) hipLaunchKernelGGL((prod_kernel<E, EPI, XT, true>), grid, dim3(256), 0, s, q);
+    else hipLaunchKernelGGL((prod_kernel<E, EPI, XT, false>), grid, dim3(256), 0, s, q);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
