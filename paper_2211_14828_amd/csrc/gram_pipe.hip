@@ -303,29 +303,43 @@ __global__ void __launch_bounds__(256, 1) gram_pipe_kernel(GramArgs g) {
   else run_tile<false>(g, split, ti, tj);
 }
 
-// C (I x I, both triangles) and W^T (S x I) from the partials, float64, fixed order.
+// C (I x I, both triangles) and W^T (S x I) from the partials, float64,
+// summed over the splits in a fixed order.  Threads walk the partial layout
+// (tile by tile, row-major inside a tile), so every split's reads are
+// coalesced; each lower-triangle value is written to C(i, j) and C(j, i).
 __global__ void gram_pipe_reduce_kernel(GramArgs g, double* C, double* Wt) {
-  const int64_t nC = g.I * g.I;
-  const int64_t total = nC + (int64_t)g.S * g.I;
+  const int64_t nCp = (int64_t)g.ntri * PT * PT;
+  const int64_t nWp = (int64_t)g.nt * PT * PW;
   const float* P = (const float*)g.partial;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nCp + nWp;
        e += (int64_t)gridDim.x * blockDim.x) {
-    int64_t off;
-    if (e < nC) {
-      int64_t i = e / g.I, j = e - i * g.I;
-      if (j > i) { const int64_t t = i; i = j; j = t; }
-      const int64_t ti = i / PT, tj = j / PT;
-      off = (ti * (ti + 1) / 2 + tj) * PT * PT + (i - ti * PT) * PT + (j - tj * PT);
+    int64_t i, j, s = -1;
+    if (e < nCp) {
+      const int tile = (int)(e / (PT * PT));
+      const int w = (int)(e - (int64_t)tile * PT * PT);
+      int ti, tj;
+      decode_tri(tile, ti, tj);
+      i = (int64_t)ti * PT + (w >> 8);
+      j = (int64_t)tj * PT + (w & (PT - 1));
+      if (i >= g.I || j >= g.I || j > i) continue;   // padding rows, or the unused block of a diagonal tile
     } else {
-      const int64_t f = e - nC;
-      const int64_t s = f / g.I, i = f - s * g.I;
-      const int64_t ti = i / PT;
-      off = g.wpart_off + ti * PT * PW + (i - ti * PT) * PW + s;
+      const int64_t f = e - nCp;
+      const int64_t ti = f / (PT * PW);
+      const int w = (int)(f - ti * PT * PW);
+      i = ti * PT + w / PW;
+      s = w % PW;
+      if (i >= g.I || s >= g.S) continue;
+      j = 0;
     }
     double acc = 0.0;
+    const int64_t off = e < nCp ? e : g.wpart_off + (e - nCp);
     for (int sp = 0; sp < g.splits; ++sp) acc += (double)P[sp * g.part_stride + off];
-    if (e < nC) C[e] = acc;
-    else Wt[e - nC] = acc;
+    if (s < 0) {
+      C[i * g.I + j] = acc;
+      C[j * g.I + i] = acc;
+    } else {
+      Wt[s * g.I + i] = acc;
+    }
   }
 }
 
@@ -403,14 +417,16 @@ GramArgs gram_plan_pipe(int64_t A, int64_t I, int64_t Bp, int S, int cu_count) {
   g.nbt = Bp / PK;
   g.nkt = A * g.nbt;
   // splits: minimise rounds(tiles x splits over the CUs) x (K tiles per split
-  // + a fixed cost of 8 tiles); multiples of 8 keep the XCD mapping
+  // + a fixed cost of 8 tiles) + the partials each split adds to the
+  // reduction (a 256 x 256 float tile costs about 0.12 K-tile times);
+  // multiples of 8 keep the XCD mapping
   const int64_t cu = cu_count > 0 ? cu_count : 256;
   int64_t best = 1;
   double best_cost = 1e300;
-  for (int64_t s = 1; s <= 512 && s <= g.nkt; s = (s < 8 ? s + 1 : s + 8)) {
-    if (s >= 8 && s % 8) continue;
+  for (int64_t s = 1; s <= 512 && s <= g.nkt; ++s) {
+    if (s > 8 && s % 8) continue;
     const int64_t rounds = ceil_div(g.ntiles * s, cu);
-    const double cost = (double)rounds * ((double)g.nkt / (double)s + 8.0);
+    const double cost = (double)rounds * ((double)g.nkt / (double)s + 8.0) + 0.12 * (double)(g.ntiles * s);
     if (cost < best_cost * 0.999) { best_cost = cost; best = s; }
   }
   g.splits = (int)best;
@@ -431,7 +447,7 @@ hipError_t launch_gram_pipe(const GramArgs& g, hipStream_t s) {
 }
 
 hipError_t launch_gram_pipe_reduce(const GramArgs& g, double* C, double* Wt, hipStream_t s) {
-  const int64_t total = g.I * g.I + (int64_t)g.S * g.I;
+  const int64_t total = (int64_t)g.ntri * PT * PT + (int64_t)g.nt * PT * PW;
   unsigned rgrid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 4096);
   hipLaunchKernelGGL(gram_pipe_reduce_kernel, dim3(rgrid), dim3(256), 0, s, g, C, Wt);
   return hipGetLastError();

@@ -181,6 +181,70 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
   for (int64_t i = tid; i < s; i += blockDim.x) flags[i] = keep[i];
 }
 
+// CholeskyQR step for s <= 64 in one launch: Yout = L^{-1} Y where G = L L^T
+// (same drop rule as above: a dropped vector gets a zero row of Yout).
+// Every workgroup factors G itself: wave 0, lane i owning row i, runs a
+// left-looking Cholesky in LDS (within one wave LDS accesses complete in
+// order, so no barriers are needed).  Then each thread solves L y = Y(:, c)
+// for one column c by forward substitution, with y in registers and L read
+// by LDS broadcast.  flags is written by workgroup 0.
+constexpr int CS_MAX = 64;
+
+__global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s, const double* Y, int64_t n,
+                                                         double* Yout, int* flags, const double* ref2,
+                                                         double tau_rel, double tau_abs) {
+  __shared__ double Ls[CS_MAX][CS_MAX + 1];
+  __shared__ double dinv[CS_MAX];
+  __shared__ int keep[CS_MAX];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < s * s; e += blockDim.x) {
+    const int i = e / s, j = e - i * s;
+    Ls[i][j] = G[e];
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int i = tid;
+    double mx = (ref2 && i < s) ? ref2[i] : 0.0;
+    mx = warp_max(mx);
+    const double abs_floor = tau_abs * tau_abs * mx;
+    const double d0 = i < s ? Ls[i][i] : 0.0;
+    for (int k = 0; k < s; ++k) {
+      double v = 0.0;
+      if (i >= k && i < s) {
+        v = Ls[i][k];
+        for (int j = 0; j < k; ++j) v -= Ls[i][j] * Ls[k][j];
+      }
+      const double d = __shfl(v, k, 64);
+      const double dk0 = __shfl(d0, k, 64);
+      const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor);
+      const double piv = kp ? sqrt(d) : 0.0;
+      if (i >= k && i < s) Ls[i][k] = kp ? (i == k ? piv : v / piv) : 0.0;
+      if (i == k) {
+        keep[k] = kp;
+        dinv[k] = kp ? 1.0 / piv : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int i = tid; i < s; i += blockDim.x) flags[i] = keep[i];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + tid;
+  if (c >= n) return;
+  double y[CS_MAX];
+#pragma unroll
+  for (int k = 0; k < CS_MAX; ++k) {
+    if (k < s) {
+      double acc = Y[(int64_t)k * n + c];
+#pragma unroll
+      for (int j = 0; j < k; ++j) acc -= Ls[k][j] * y[j];
+      y[k] = acc * dinv[k];                      // zero for a dropped vector
+      Yout[(int64_t)k * n + c] = y[k];
+    } else {
+      y[k] = 0.0;
+    }
+  }
+}
+
 // Left-looking Cholesky of the s x s Gram matrix G with column dropping, one
 // workgroup, for s beyond the LDS variant (same drop rule).
 __global__ void __launch_bounds__(1024) chol_drop_kernel(const double* G, int64_t s, double* L, int* flags,
@@ -688,6 +752,11 @@ hipError_t chol_orth(double* Y, double* Yout, int64_t s, int64_t n, double* G, d
   if (s <= 0) return hipSuccess;
   hipError_t e = dgemm(0, 1, s, s, n, 1.0, Y, n, Y, n, 0.0, G, s, st);
   if (e != hipSuccess) return e;
+  if (s <= CS_MAX) {
+    hipLaunchKernelGGL(chol_solve_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, G, (int)s, Y, n, Yout,
+                       flags, ref2, tau_rel, tau_abs);
+    return hipGetLastError();
+  }
   if (s <= CHOL_MAX) {
     hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, G, s, Lm, flags, ref2, tau_rel, tau_abs);
     if ((e = hipGetLastError()) != hipSuccess) return e;
