@@ -172,9 +172,11 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
   P.xelem = dtype_elem(xtype);
   // the first mode product always reads X itself, in its own type
   P.telem = P.xelem;
-  P.celem = P.xelem == E_F64 ? E_F64 : E_F32;
   P.gelem = P.prec == RBKI_PLAIN ? P.xelem : E_BF16;
   P.need_pad = P.gelem == E_BF16;
+  // chain and error in float64 only for the plain float64 form (the bf16
+  // forms' first product writes float)
+  P.celem = (P.xelem == E_F64 && !P.need_pad) ? E_F64 : E_F32;
   P.in_pad = pad64(P.dims[P.N - 1]);
   P.rows_pad = pad64(P.T / P.dims[P.N - 1]);
   double best = -1.0;
@@ -453,9 +455,16 @@ rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, c
     const int n = P.first_mode;
     int64_t A, I, B;
     view(n, A, I, B);
-    HIPCHK(convert_tensor(E_F64, b.Ut64[n], P.telem, b.Uop, P.m[n].R * I, st));
-    ProfScope ps("ttm", st);
-    HIPCHK(launch_ttm(P.telem, xsrc, A, I, B, b.Uop, P.m[n].R, bufs[which], nullptr, 0, st));
+    if (P.need_pad) {
+      // precision form: the product reads the padded bf16 copy on bf16 MFMA
+      HIPCHK(convert_tensor(E_F64, b.Ut64[n], E_BF16, b.Uop, P.m[n].R * I, st));
+      ProfScope ps("ttm", st);
+      HIPCHK(launch_ttm_padded(b.xpad, A, I, B, P.dims[P.N - 1], b.Uop, P.m[n].R, bufs[which], st));
+    } else {
+      HIPCHK(convert_tensor(E_F64, b.Ut64[n], P.telem, b.Uop, P.m[n].R * I, st));
+      ProfScope ps("ttm", st);
+      HIPCHK(launch_ttm(P.telem, xsrc, A, I, B, b.Uop, P.m[n].R, bufs[which], nullptr, 0, st));
+    }
     cur[n] = P.m[n].R;
   }
   for (int n = 0; n < P.N; ++n) {

@@ -102,6 +102,10 @@ hipError_t canonical_sign_rows(double* V, int64_t rows, int64_t n, hipStream_t s
 hipError_t launch_ttm(int elem, const void* X, int64_t A, int64_t I, int64_t B, const void* Ut,
                       int64_t R, void* Y, void* work, size_t work_bytes, hipStream_t s);
 size_t ttm_work_bytes(int elem, int64_t A, int64_t I, int64_t B, int64_t R);
+// The same product in bf16 on the zero-padded copy Xpad (rows of the last
+// dimension IN padded to pad64(IN)); Y is written in the unpadded layout.
+hipError_t launch_ttm_padded(const void* Xpad, int64_t A, int64_t I, int64_t B, int64_t IN, const void* Ut,
+                             int64_t R, void* Y, hipStream_t s);
 
 // Sum over all entries of (X - Uh)^2 and X^2 where Uh[i, j] = sum_r U[i, r] H[r, j]
 // (X viewed as I x J row-major, the mode-0 unfolding); partial sums in

@@ -30,6 +30,7 @@ struct ProdArgs {
   // store epilogue
   void* out;
   int64_t out_rs, out_cs, out_bs;
+  int64_t out_in, out_inp;        // out_inp > 0: output columns are padded (groups of out_inp, out_in valid)
   // residual epilogue: X (row-major rows x J) of element x_elem
   const void* X;
   int x_elem;
@@ -182,8 +183,16 @@ __global__ void __launch_bounds__(256, E == E_F64 ? 1 : 2) prod_kernel(ProdArgs 
     for (int j = 0; j < M::NACC; ++j) {
       int row, col;
       M::coord(j, lane, row, col);
-      const int64_t r = r0 + wr + row, c = c0 + wc + col;
-      if (r < p.a.rows && c < p.b.rows) out[r * p.out_rs + c * p.out_cs] = M::get(f, j);
+      const int64_t r = r0 + wr + row;
+      int64_t c = c0 + wc + col;
+      if (r < p.a.rows && c < p.b.rows) {
+        if (p.out_inp > 0) {                       // padded column -> true column
+          const int64_t hi = c / p.out_inp, lo = c - hi * p.out_inp;
+          if (lo >= p.out_in) continue;
+          c = hi * p.out_in + lo;
+        }
+        out[r * p.out_rs + c * p.out_cs] = M::get(f, j);
+      }
     }
   } else {
     double res = 0.0, nrm = 0.0;
@@ -447,6 +456,45 @@ hipError_t launch_ttm(int elem, const void* X, int64_t A, int64_t I, int64_t B, 
     case E_BF16: return launch_prod<E_BF16, 0, float>(p, batches, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_ttm_padded(const void* Xpad, int64_t A, int64_t I, int64_t B, int64_t IN, const void* Ut,
+                             int64_t R, void* Y, hipStream_t s) {
+  const int64_t INp = pad64(IN);
+  ProdArgs p = {};
+  p.K = I;
+  int64_t batches;
+  if (B > 1) {
+    // Y[a] (R x B) = Ut (R x I) . Xpad[a] (I x Bp): rows r, padded columns mapped back
+    const int64_t Bp = (B / IN) * INp;
+    p.a = {Ut, I, 1, 0, R};
+    p.b = {Xpad, 1, Bp, I * Bp, Bp};
+    p.out = Y;
+    p.out_rs = B;
+    p.out_cs = 1;
+    p.out_bs = R * B;
+    p.out_in = IN;
+    p.out_inp = INp;
+    p.row_tiles = ceil_div(R, TILE);
+    p.col_tiles = ceil_div(Bp, TILE);
+    p.vec_a = (I * 2) % 16 == 0 && aligned16(Ut);
+    p.vec_b = aligned16(Xpad);
+    batches = A;
+  } else {
+    // last mode: Y (A x R) = Xpad (A x I, row pitch I_Npad) . U (I x R)
+    p.a = {Xpad, INp, 1, 0, A};
+    p.b = {Ut, I, 1, 0, R};
+    p.out = Y;
+    p.out_rs = R;
+    p.out_cs = 1;
+    p.out_bs = 0;
+    p.row_tiles = ceil_div(A, TILE);
+    p.col_tiles = ceil_div(R, TILE);
+    p.vec_a = (I * 2) % 16 == 0 && aligned16(Xpad);
+    p.vec_b = (I * 2) % 16 == 0 && aligned16(Ut);
+    batches = 1;
+  }
+  return launch_prod<E_BF16, 0, float>(p, batches, s);
 }
 
 size_t residual_work_bytes(int64_t I, int64_t J) {
