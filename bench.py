@@ -121,7 +121,7 @@ def traffic_from(fetch_csv, write_csv, workload, precision, copy_mib, command):
     """HBM bytes per Gram launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
     WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads
     for the calibration copy of known size in the same program."""
-    kernel = "gram_pipe_kernel" if precision == "mixed_bf16" else "gram_sketch_kernel"
+    kernel = "gram_pipe_kernel" if precision in ("mixed_bf16", "mixed_fp8") else "gram_sketch_kernel"
     known = copy_mib * 1024 * 1024
     res = {}
     for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
@@ -258,7 +258,7 @@ def main():
     achieved = alg_gram / (avg_gram_ms * 1e-3) / 1e12
     in_dt = {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}[w["dtype"]]
     gram_dtype = {"plain": in_dt, "mixed_bf16": "bf16", "mixed_fp8": "fp8"}[args.precision]
-    kernel = "gram_pipe_kernel" if gram_dtype == "bf16" else "gram_sketch_kernel"
+    kernel = "gram_pipe_kernel" if gram_dtype in ("bf16", "fp8") else "gram_sketch_kernel"
     peak = PEAK_TFLOPS[gram_dtype]
     stages = {}
     for k in ("omega", "gram", "jacobi", "ttm", "error", "convert"):

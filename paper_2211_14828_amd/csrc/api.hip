@@ -119,7 +119,10 @@ struct Plan {
   int gelem = 0;     // Gram / sketch product
   int telem = 0;     // first mode product (reads X)
   int celem = 0;     // later mode products, reconstruction and error
-  bool need_pad = false;     // zero-padded bf16 copies (Xpad, Xt) for the bf16 Gram products
+  bool need_pad = false;     // zero-padded bf16 copy Xpad (bf16 Gram products, first mode product)
+  bool need_xt16 = false;    // zero-padded bf16 transposed copy Xt (last mode on the bf16 Gram path)
+  bool need_fp8 = false;     // e4m3 copies with per-32 scales (fp8 Gram products)
+  int64_t xscl_bytes = 0, oscl_bytes = 0;   // gathered scales of one mode
   int64_t in_pad = 0;        // last dimension padded to a multiple of 64
   int64_t rows_pad = 0;      // T / I_N padded to a multiple of 64 (row length of Xt)
   int64_t T = 1;
@@ -156,7 +159,6 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     return fail(RBKI_E_INVALID, "oversample %d / power %d out of range", prm->oversample, prm->power);
   if (prm->precision != RBKI_PLAIN && prm->precision != RBKI_MIXED_BF16 && prm->precision != RBKI_MIXED_FP8)
     return fail(RBKI_E_INVALID, "unknown precision %d", prm->precision);
-  if (prm->precision == RBKI_MIXED_FP8) return fail(RBKI_E_UNSUPPORTED, "fp8 form not built yet");
   P.N = prm->order;
   P.p = prm->oversample;
   P.q = prm->power;
@@ -172,8 +174,9 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
   P.xelem = dtype_elem(xtype);
   // the first mode product always reads X itself, in its own type
   P.telem = P.xelem;
-  P.gelem = P.prec == RBKI_PLAIN ? P.xelem : E_BF16;
-  P.need_pad = P.gelem == E_BF16;
+  P.gelem = P.prec == RBKI_PLAIN ? P.xelem : (P.prec == RBKI_MIXED_FP8 ? E_FP8 : E_BF16);
+  P.need_pad = P.gelem == E_BF16 || P.gelem == E_FP8;
+  P.need_fp8 = P.gelem == E_FP8;
   // chain and error in float64 only for the plain float64 form (the bf16
   // forms' first product writes float)
   P.celem = (P.xelem == E_F64 && !P.need_pad) ? E_F64 : E_F32;
@@ -200,12 +203,20 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     P.maxS = std::max(P.maxS, g.S);
     P.maxSp = std::max(P.maxSp, g.Sp);
     P.maxRI = std::max(P.maxRI, g.R * g.I);
-    if (P.gelem == E_BF16) {
+    if (P.need_pad) {
       int64_t A, Bp;
       padded_view(P, n, A, Bp);
       P.maxSJ = std::max(P.maxSJ, g.S * A * Bp);
+      const bool fp8 = P.need_fp8 && gram_pipe_ok(g.I, (int)g.S);
+      if (n == P.N - 1 && !fp8) P.need_xt16 = true;
+      if (fp8) {
+        const int64_t ipad = pad64(g.I) + (256 - pad64(g.I) % 256) % 256;   // rows of whole 256-row tiles
+        P.xscl_bytes = std::max(P.xscl_bytes, A * (Bp / 64) * ipad * 2);
+        P.oscl_bytes = std::max(P.oscl_bytes, A * (Bp / 64) * 64 * 2);
+      }
       if (gram_pipe_ok(g.I, (int)g.S)) {
-        P.partial_bytes = std::max(P.partial_bytes, gram_pipe_partial_bytes(gram_plan_pipe(A, g.I, Bp, (int)g.S, cu_count())));
+        const int e = fp8 ? E_FP8 : E_BF16;
+        P.partial_bytes = std::max(P.partial_bytes, gram_pipe_partial_bytes(gram_plan_pipe(e, A, g.I, Bp, (int)g.S, cu_count())));
       } else {
         GramArgs ga = gram_plan(E_BF16, A, g.I, Bp, (int)g.S, cu_count());
         P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(ga, E_BF16));
@@ -248,6 +259,14 @@ struct Arena {
 
 struct Buffers {
   void* xpad = nullptr;    // bf16, (T / I_N) x I_Npad, zero-padded
+  void* xp8 = nullptr;     // e4m3 copies and their per-32 scale planes
+  void* sp8 = nullptr;
+  void* xt8 = nullptr;
+  void* st8 = nullptr;
+  void* om8 = nullptr;     // e4m3 Omega^T, its scale plane and the gathered scales
+  void* osc = nullptr;
+  void* oscl = nullptr;
+  void* xscl = nullptr;    // gathered scales of X for the current mode
   void* xt = nullptr;      // bf16, I_N x rows_pad: the last mode, transposed and zero-padded
   void* omegaT = nullptr;
   void* partial = nullptr;
@@ -279,10 +298,21 @@ struct Buffers {
 void carve(const Plan& P, Arena& ar, Buffers& b) {
   const int es_g = elem_size(P.gelem);
   if (P.need_pad) {
-    b.xpad = ar.take((size_t)(P.T / P.dims[P.N - 1]) * P.in_pad * 2);
-    b.xt = ar.take((size_t)P.dims[P.N - 1] * P.rows_pad * 2);
+    const size_t rows = (size_t)(P.T / P.dims[P.N - 1]);
+    b.xpad = ar.take(rows * P.in_pad * 2);
+    if (P.need_xt16) b.xt = ar.take((size_t)P.dims[P.N - 1] * P.rows_pad * 2);
+    if (P.need_fp8) {
+      b.xp8 = ar.take(rows * P.in_pad);
+      b.sp8 = ar.take(rows * P.in_pad / 32);
+      b.xt8 = ar.take((size_t)P.dims[P.N - 1] * P.rows_pad);
+      b.st8 = ar.take((size_t)P.dims[P.N - 1] * P.rows_pad / 32);
+      b.om8 = ar.take((size_t)P.maxSJ);
+      b.osc = ar.take((size_t)P.maxSJ / 32 + 64);
+      b.oscl = ar.take((size_t)P.oscl_bytes);
+      b.xscl = ar.take((size_t)P.xscl_bytes);
+    }
   }
-  b.omegaT = ar.take((size_t)P.maxSJ * es_g);
+  b.omegaT = ar.take((size_t)P.maxSJ * (P.need_pad ? 2 : es_g));   // the padded forms stage Omega in bf16
   b.partial = ar.take(P.partial_bytes);
   b.C = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
   for (int n = 0; n < P.N; ++n) b.Qt[n] = (double*)ar.take((size_t)P.m[n].Sp * P.m[n].I * 8);
@@ -334,26 +364,51 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
   const int64_t I = g.I, S = g.S, Sp = g.Sp;
   double* Qt = b.Qt[n];
   // C -> b.C (I x I), W^T -> b.Yt (S x I)
-  if (P.gelem == E_BF16) {
-    // zero-padded bf16 operands: Xpad for the leading modes, Xt for the last
+  if (P.need_pad) {
+    // zero-padded operands: Xpad / Xp8 for the leading modes, Xt / Xt8 for the last
     int64_t A, Bp;
     padded_view(P, n, A, Bp);
+    const int64_t Jp = A * Bp;
+    const bool last = n == P.N - 1;
+    const bool fp8 = P.need_fp8 && gram_pipe_ok(I, (int)S);
     {
       ProfScope ps("omega", st);
-      HIPCHK(launch_omega_pad(P.seed, n, S, g.J, g.B, P.dims[P.N - 1], A * Bp, b.omegaT, st));
+      HIPCHK(launch_omega_pad(P.seed, n, S, g.J, g.B, P.dims[P.N - 1], Jp, b.omegaT, st));
+      if (fp8) {
+        HIPCHK(launch_quantize_rows_fp8(b.omegaT, S, Jp, b.om8, b.osc, st));
+        HIPCHK(launch_gather_scales(b.osc, 1, S, Jp, 64, b.oscl, st));
+      }
     }
-    const void* xop = n == P.N - 1 ? b.xt : b.xpad;
-    if (gram_pipe_ok(I, (int)S)) {
-      GramArgs ga = gram_plan_pipe(A, I, Bp, (int)S, cu_count());
+    if (fp8) {
+      GramArgs ga = gram_plan_pipe(E_FP8, A, I, Bp, (int)S, cu_count());
+      const int64_t ipad = (int64_t)ga.nt * 256;
+      {
+        ProfScope ps("omega", st);
+        HIPCHK(launch_gather_scales(last ? b.st8 : b.sp8, A, I, Bp, ipad, b.xscl, st));
+      }
+      ga.X = last ? b.xt8 : b.xp8;
+      ga.omegaT = b.om8;
+      ga.xexp = (const unsigned char*)b.xscl;
+      ga.xexp_om = (const unsigned char*)b.oscl;
+      ga.partial = b.partial;
+      {
+        ProfScope ps("gram", st);
+        HIPCHK(launch_gram_pipe(E_FP8, ga, st));
+      }
+      HIPCHK(launch_gram_pipe_reduce(ga, b.C, b.Yt, st));
+    } else if (gram_pipe_ok(I, (int)S)) {
+      const void* xop = last ? b.xt : b.xpad;
+      GramArgs ga = gram_plan_pipe(E_BF16, A, I, Bp, (int)S, cu_count());
       ga.X = xop;
       ga.omegaT = b.omegaT;
       ga.partial = b.partial;
       {
         ProfScope ps("gram", st);
-        HIPCHK(launch_gram_pipe(ga, st));
+        HIPCHK(launch_gram_pipe(E_BF16, ga, st));
       }
       HIPCHK(launch_gram_pipe_reduce(ga, b.C, b.Yt, st));
     } else {
+      const void* xop = last ? b.xt : b.xpad;
       GramArgs ga = gram_plan(E_BF16, A, I, Bp, (int)S, cu_count());
       ga.X = xop;
       ga.omegaT = b.omegaT;
@@ -625,7 +680,11 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
   const void* xsrc = X;
   if (P.need_pad) {
     ProfScope ps("convert", st);
-    HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
+    if (P.need_fp8)
+      HIPCHK(launch_pad_copies_fp8(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, b.xp8, b.sp8,
+                                   b.xt8, b.st8, st));
+    else
+      HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
   }
   s = run_mode(P, b, xsrc, mode, false, st);
   if (s != RBKI_OK) return s;
@@ -671,7 +730,11 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   const void* xsrc = X;
   if (P.need_pad) {
     ProfScope ps("convert", st);
-    HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
+    if (P.need_fp8)
+      HIPCHK(launch_pad_copies_fp8(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, b.xp8, b.sp8,
+                                   b.xt8, b.st8, st));
+    else
+      HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
   }
   HIPCHK(fill_zero(b.info, 64, st));
   for (int n = 0; n < P.N; ++n) {

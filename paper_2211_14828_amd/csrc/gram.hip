@@ -328,8 +328,7 @@ int gram_bk(int elem) {
   switch (elem) {
     case E_F64: return Mma<E_F64>::BK;
     case E_F32: return Mma<E_F32>::BK;
-    case E_BF16: return Mma<E_BF16>::BK;
-    default: return Mma<E_FP8>::BK;
+    default: return Mma<E_BF16>::BK;       // the 128-tile kernel has no fp8 form
   }
 }
 

@@ -31,6 +31,14 @@
 // XOR-swizzled with bits 2..3 of the row index, so the 32 rows read by one
 // MFMA operand load hit distinct LDS banks.
 //
+// FP8 form.  The same kernel runs on e4m3 copies: a stage row then holds 64
+// values, one MFMA K step of 64 (block-scaled 32x32x64 f8f6f4).  Every run
+// of 32 values along a storage row has its own power-of-two (E8M0) scale,
+// chosen so that the run's largest magnitude maps to at most 448.  For each
+// mode the scales are gathered once into [K tile][row][2] order, so each
+// wave fetches the scales of 128 rows for a stage with one more 4-byte
+// direct-to-LDS load.
+//
 // Split-K partials (float32) are reduced in a fixed order in float64 by a
 // second kernel: results are deterministic.
 #include "rbki_kernels.h"
@@ -58,6 +66,28 @@ __shared__ __attribute__((aligned(1024))) char pb1[PSTAGE];
 __shared__ __attribute__((aligned(1024))) char pb2[PSTAGE];
 __shared__ __attribute__((aligned(1024))) char pb3[PSTAGE];
 
+__shared__ __attribute__((aligned(16))) unsigned char psa0[512];
+__shared__ __attribute__((aligned(16))) unsigned char psa1[512];
+__shared__ __attribute__((aligned(16))) unsigned char psa2[512];
+__shared__ __attribute__((aligned(16))) unsigned char psa3[512];
+__shared__ __attribute__((aligned(16))) unsigned char psb0[512];
+__shared__ __attribute__((aligned(16))) unsigned char psb1[512];
+__shared__ __attribute__((aligned(16))) unsigned char psb2[512];
+__shared__ __attribute__((aligned(16))) unsigned char psb3[512];
+
+template <int ST> __device__ inline unsigned char* stage_sa() {
+  if constexpr (ST == 0) return psa0;
+  else if constexpr (ST == 1) return psa1;
+  else if constexpr (ST == 2) return psa2;
+  else return psa3;
+}
+template <int ST> __device__ inline unsigned char* stage_sb() {
+  if constexpr (ST == 0) return psb0;
+  else if constexpr (ST == 1) return psb1;
+  else if constexpr (ST == 2) return psb2;
+  else return psb3;
+}
+
 template <int ST> __device__ inline char* stage_a() {
   if constexpr (ST == 0) return pa0;
   else if constexpr (ST == 1) return pa1;
@@ -82,37 +112,50 @@ __device__ inline void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(15 | (7 << 4) |
 __device__ inline int swz(int r, int c) { return r * PROW + ((c ^ ((r >> 2) & 3)) << 4); }
 
 struct PipeCtx {
-  const bf16_t* X;        // padded operand view [A, I, Bp]
-  const bf16_t* Om;       // padded Omega^T, S rows of Jp
-  int64_t IBp, Bp;        // slab stride I * Bp, row pitch
-  int64_t na, nk0;        // next K tile to load: slab a, first column k0
+  const char* X;          // padded operand view [A, I, Bp] (bytes)
+  const char* Om;         // padded Omega^T, S rows of Jp (bytes)
+  int64_t IBp, Bp;        // slab stride I * Bp and row pitch, in elements
+  int64_t na, nk0;        // next K tile to load: slab a, first column k0 (elements)
   int64_t left;           // K tiles of this split not yet loaded (the last one is reloaded after)
-  int64_t offa[4], offb[4];   // per-lane element offsets of this lane's rows and chunks
+  int64_t kt;             // global index of the next K tile (scale lookup)
+  int64_t offa[4], offb[4];   // per-lane byte offsets of this lane's rows and chunks
+  const unsigned char* sc;    // fp8: this lane's scale source at K tile 0
+  int64_t sc_step;            // fp8: bytes per K tile of that source
+  int sc_dst;                 // fp8: 0..3 = A scales low/high half, B scales low/high half
   int wave;
 };
 
+template <int E> struct PipeElem {
+  static constexpr int ES = E == E_FP8 ? 1 : 2;      // bytes per value
+  static constexpr int KT = PROW / ES;               // values per stage row
+};
+
 // Advance the next K tile (a, k0) by one tile, holding at the split's last.
+template <int E>
 __device__ __attribute__((always_inline)) inline void advance(PipeCtx& c) {
   if (c.left > 1) {
-    c.nk0 += PK;
+    c.nk0 += PipeElem<E>::KT;
     if (c.nk0 == c.Bp) { c.nk0 = 0; ++c.na; }
+    ++c.kt;
     --c.left;
   }
 }
 
 // Issue the loads of the next K tile into stage ST: A rows r0..r0+255 (4
 // loads per wave), B rows c0..c0+255 (off-diagonal, 4 per wave) or sketch rows
-// 0..63 (diagonal, 1 per wave).  Lane l of load q covers row 16 q + l / 4
-// and the 16-byte chunk at position l % 4 of that row.
-template <bool DIAG, int ST>
+// 0..63 (diagonal, 1 per wave), and for fp8 one load of scales per wave.
+// Lane l of load q covers row 16 q + l / 4 and the 16-byte chunk at position
+// l % 4 of that row.
+template <int E, bool DIAG, int ST>
 __device__ __attribute__((always_inline)) inline void issue(PipeCtx& c) {
-  const bf16_t* xa = c.X + c.na * c.IBp + c.nk0;
+  constexpr int ES = PipeElem<E>::ES;
+  const char* xa = c.X + (c.na * c.IBp + c.nk0) * ES;
 #pragma unroll
   for (int j = 0; j < 4; ++j)
     __builtin_amdgcn_global_load_lds((const void*)(xa + c.offa[j]),
                                      (lds_void*)(stage_a<ST>() + (j * 4 + c.wave) * 1024), 16, 0, 0);
   if (DIAG) {
-    __builtin_amdgcn_global_load_lds((const void*)(c.Om + c.na * c.Bp + c.nk0 + c.offb[0]),
+    __builtin_amdgcn_global_load_lds((const void*)(c.Om + (c.na * c.Bp + c.nk0) * ES + c.offb[0]),
                                      (lds_void*)(stage_b<ST>() + c.wave * 1024), 16, 0, 0);
   } else {
 #pragma unroll
@@ -120,82 +163,143 @@ __device__ __attribute__((always_inline)) inline void issue(PipeCtx& c) {
       __builtin_amdgcn_global_load_lds((const void*)(xa + c.offb[j]),
                                        (lds_void*)(stage_b<ST>() + (j * 4 + c.wave) * 1024), 16, 0, 0);
   }
-  advance(c);
+  if (E == E_FP8) {
+    unsigned char* dst = (c.sc_dst < 2 ? stage_sa<ST>() : stage_sb<ST>()) + (c.sc_dst & 1) * 256;
+    __builtin_amdgcn_global_load_lds((const void*)(c.sc + c.kt * c.sc_step), (lds_void*)dst, 4, 0, 0);
+  }
+  advance<E>(c);
 }
 
-// Multiply the K tile held in stage ST (two MFMA K steps of 16).
+// fp8 operand of the block-scaled 32x32x64 MFMA (layout measured on gfx950):
+// lane half h supplies K values 16h..16h+15 in its bytes 0..15 and
+// 32+16h..47+16h in its bytes 16..31, and the scale of K block b (values
+// 32b..32b+31) is the one passed by lane half b.  So half h takes chunks h
+// and 2+h of the stage row (the h-th 16 values of each 32-value run) and
+// passes the scale of run h.
+__device__ inline i32x8_t frag8(const char* l, int row, int half) {
+  union { i32x8_t v; uint4 q[2]; } u;
+  u.q[0] = *(const uint4*)(l + swz(row, half));
+  u.q[1] = *(const uint4*)(l + swz(row, 2 + half));
+  return u.v;
+}
+
+// Multiply the K tile held in stage ST.
 //   C waves (WW false): acc[m][n] += A(ra + 32 m) . B(rb + 32 n)
 //   sketch wave (WW true): acc[m][n] += A(128 (n / 2) + 32 m) . Omega(32 (n % 2))
-template <bool DIAG, bool WW, int ST>
+// bf16: two MFMA K steps of 16 per stage; fp8: one block-scaled K step of 64
+// (operands as frag8 describes).
+template <int E, bool DIAG, bool WW, int ST>
 __device__ __attribute__((always_inline)) inline void compute(f32x16_t (&acc)[4][4], int lane, int ra, int rb) {
   const char* la = stage_a<ST>();
   const char* lb = (DIAG && !WW) ? stage_a<ST>() : stage_b<ST>();
   const int half = lane >> 5, lr = lane & 31;
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int ch = 2 * t + half;
+  if constexpr (E == E_FP8) {
+    const unsigned char* sa = stage_sa<ST>();
+    const unsigned char* sb = (DIAG && !WW) ? stage_sa<ST>() : stage_sb<ST>();
     if (WW) {
-      bf16x8_t av[8], bv[2];
+      i32x8_t av[8], bv[2];
+      int ea[8], eb[2];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) av[m] = *(const bf16x8_t*)(la + swz(m * 32 + lr, ch));
+      for (int m = 0; m < 8; ++m) {
+        av[m] = frag8(la, m * 32 + lr, half);
+        ea[m] = sa[(m * 32 + lr) * 2 + half];
+      }
 #pragma unroll
-      for (int n = 0; n < 2; ++n) bv[n] = *(const bf16x8_t*)(lb + swz(n * 32 + lr, ch));
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m + 4 * (n >> 1)], bv[n & 1], acc[m][n], 0, 0, 0);
-    } else {
-      bf16x8_t av[4], bv[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        av[m] = *(const bf16x8_t*)(la + swz(ra + m * 32 + lr, ch));
-        bv[m] = *(const bf16x8_t*)(lb + swz(rb + m * 32 + lr, ch));
+      for (int n = 0; n < 2; ++n) {
+        bv[n] = frag8(lb, n * 32 + lr, half);
+        eb[n] = sb[(n * 32 + lr) * 2 + half];
       }
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < 4; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
+          acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+              av[m + 4 * (n >> 1)], bv[n & 1], acc[m][n], 0, 0, 0, ea[m + 4 * (n >> 1)], 0, eb[n & 1]);
+    } else {
+      i32x8_t av[4], bv[4];
+      int ea[4], eb[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        av[m] = frag8(la, ra + m * 32 + lr, half);
+        bv[m] = frag8(lb, rb + m * 32 + lr, half);
+        ea[m] = sa[(ra + m * 32 + lr) * 2 + half];
+        eb[m] = sb[(rb + m * 32 + lr) * 2 + half];
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[m], bv[n], acc[m][n], 0, 0, 0, ea[m], 0,
+                                                                      eb[n]);
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int ch = 2 * t + half;
+      if (WW) {
+        bf16x8_t av[8], bv[2];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) av[m] = *(const bf16x8_t*)(la + swz(m * 32 + lr, ch));
+#pragma unroll
+        for (int n = 0; n < 2; ++n) bv[n] = *(const bf16x8_t*)(lb + swz(n * 32 + lr, ch));
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int n = 0; n < 4; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m + 4 * (n >> 1)], bv[n & 1], acc[m][n], 0, 0, 0);
+      } else {
+        bf16x8_t av[4], bv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          av[m] = *(const bf16x8_t*)(la + swz(ra + m * 32 + lr, ch));
+          bv[m] = *(const bf16x8_t*)(lb + swz(rb + m * 32 + lr, ch));
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int n = 0; n < 4; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
+      }
     }
   }
 }
 
 // One K step of the ring: wait for stage ST, barrier, refill the stage that
 // was read in the previous step, multiply stage ST if this step is real.
-template <bool DIAG, bool WW, int ST>
+template <int E, bool DIAG, bool WW, int ST>
 __device__ __attribute__((always_inline)) inline void ring_step(PipeCtx& c, f32x16_t (&acc)[4][4], bool real,
                                                                 int lane, int ra, int rb) {
-  constexpr int PER = DIAG ? 5 : 8;          // loads per wave per stage
+  constexpr int PER = (DIAG ? 5 : 8) + (E == E_FP8 ? 1 : 0);   // loads per wave per stage
   wait_vm<2 * PER>();
   __builtin_amdgcn_s_barrier();
-  issue<DIAG, (ST + 3) & 3>(c);
-  if (real) compute<DIAG, WW, ST>(acc, lane, ra, rb);
+  issue<E, DIAG, (ST + 3) & 3>(c);
+  if (real) compute<E, DIAG, WW, ST>(acc, lane, ra, rb);
   wait_lgkm0();
 }
 
-template <bool DIAG, bool WW>
+template <int E, bool DIAG, bool WW>
 __device__ __attribute__((always_inline)) inline void ring(PipeCtx& c, f32x16_t (&acc)[4][4], int64_t nk, int lane,
                                                            int ra, int rb) {
-  issue<DIAG, 0>(c);
-  issue<DIAG, 1>(c);
-  issue<DIAG, 2>(c);
+  issue<E, DIAG, 0>(c);
+  issue<E, DIAG, 1>(c);
+  issue<E, DIAG, 2>(c);
   for (int64_t k = 0; k < nk; k += 4) {
-    ring_step<DIAG, WW, 0>(c, acc, true, lane, ra, rb);
-    ring_step<DIAG, WW, 1>(c, acc, k + 1 < nk, lane, ra, rb);
-    ring_step<DIAG, WW, 2>(c, acc, k + 2 < nk, lane, ra, rb);
-    ring_step<DIAG, WW, 3>(c, acc, k + 3 < nk, lane, ra, rb);
+    ring_step<E, DIAG, WW, 0>(c, acc, true, lane, ra, rb);
+    ring_step<E, DIAG, WW, 1>(c, acc, k + 1 < nk, lane, ra, rb);
+    ring_step<E, DIAG, WW, 2>(c, acc, k + 2 < nk, lane, ra, rb);
+    ring_step<E, DIAG, WW, 3>(c, acc, k + 3 < nk, lane, ra, rb);
   }
   // every load must have landed before the workgroup's LDS is released
   wait_vm<0>();
   __builtin_amdgcn_s_barrier();
 }
 
-template <bool DIAG>
+template <int E, bool DIAG>
 __device__ __attribute__((always_inline)) inline void run_tile(const GramArgs& g, int split, int ti, int tj) {
+  constexpr int ES = PipeElem<E>::ES;
   PipeCtx c;
-  c.X = (const bf16_t*)g.X;
-  c.Om = (const bf16_t*)g.omegaT;
+  c.X = (const char*)g.X;
+  c.Om = (const char*)g.omegaT;
   c.IBp = g.I * g.B;
   c.Bp = g.B;
   c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -203,8 +307,9 @@ __device__ __attribute__((always_inline)) inline void run_tile(const GramArgs& g
   const int64_t kt0 = (int64_t)split * g.nkt / g.splits;
   const int64_t kt1 = (int64_t)(split + 1) * g.nkt / g.splits;     // kt1 > kt0 (splits <= nkt)
   c.na = kt0 / g.nbt;
-  c.nk0 = (kt0 - c.na * g.nbt) * PK;
+  c.nk0 = (kt0 - c.na * g.nbt) * PipeElem<E>::KT;
   c.left = kt1 - kt0;
+  c.kt = kt0;
   const int64_t r0 = (int64_t)ti * PT, c0 = (int64_t)tj * PT;
   {
     const int rl = lane >> 2, p = lane & 3;
@@ -215,13 +320,29 @@ __device__ __attribute__((always_inline)) inline void run_tile(const GramArgs& g
       int64_t ra_ = r0 + row, rb_ = c0 + row;
       ra_ = ra_ < g.I ? ra_ : g.I - 1;        // rows past I: a valid row, output discarded
       rb_ = rb_ < g.I ? rb_ : g.I - 1;
-      c.offa[j] = ra_ * g.B + ch * 8;
-      c.offb[j] = rb_ * g.B + ch * 8;
+      c.offa[j] = ra_ * g.B * ES + ch * 16;
+      c.offb[j] = rb_ * g.B * ES + ch * 16;
     }
     if (DIAG) {
       const int row = c.wave * 16 + rl;       // sketch row 0..63
       const int sr = row < g.S ? row : g.S - 1;
-      c.offb[0] = (int64_t)sr * g.J + (p ^ ((row >> 2) & 3)) * 8;
+      c.offb[0] = (int64_t)sr * g.J * ES + (p ^ ((row >> 2) & 3)) * 16;
+    }
+    if (E == E_FP8) {
+      // scales: [K tile][Ipad rows][2] for X, [K tile][64][2] for Omega; a lane
+      // fetches 4 bytes = the two runs of two consecutive rows
+      const int64_t ipad = (int64_t)g.nt * PT;
+      if (DIAG && c.wave >= 2) {
+        const int l = lane < 32 ? lane : 31;
+        c.sc = g.xexp_om + 4 * l;
+        c.sc_step = 64 * 2;
+        c.sc_dst = c.wave == 2 ? 2 : 3;       // wave 3 reloads the same bytes into an unused half
+      } else {
+        const int64_t base = (c.wave < 2 ? r0 : c0) + (c.wave & 1) * 128 + 2 * lane;
+        c.sc = g.xexp + 2 * base;
+        c.sc_step = ipad * 2;
+        c.sc_dst = c.wave;
+      }
     }
   }
   const bool wwave = DIAG && c.wave == 1;
@@ -240,10 +361,10 @@ __device__ __attribute__((always_inline)) inline void run_tile(const GramArgs& g
 
   const int64_t nk = kt1 - kt0;
   if (DIAG) {
-    if (wwave) ring<true, true>(c, acc, nk, lane, ra, rb);
-    else ring<true, false>(c, acc, nk, lane, ra, rb);
+    if (wwave) ring<E, true, true>(c, acc, nk, lane, ra, rb);
+    else ring<E, true, false>(c, acc, nk, lane, ra, rb);
   } else {
-    ring<false, false>(c, acc, nk, lane, ra, rb);
+    ring<E, false, false>(c, acc, nk, lane, ra, rb);
   }
 
   const int half = lane >> 5, lr = lane & 31;
@@ -284,6 +405,7 @@ __device__ inline void decode_tri(int tile, int& ti, int& tj) {
   tj = tile - t * (t + 1) / 2;
 }
 
+template <int E>
 __global__ void __launch_bounds__(256, 1) gram_pipe_kernel(GramArgs g) {
   const int w = blockIdx.x;
   int split, tile;
@@ -299,8 +421,8 @@ __global__ void __launch_bounds__(256, 1) gram_pipe_kernel(GramArgs g) {
   }
   int ti, tj;
   decode_tri(tile, ti, tj);
-  if (ti == tj) run_tile<true>(g, split, ti, tj);
-  else run_tile<false>(g, split, ti, tj);
+  if (ti == tj) run_tile<E, true>(g, split, ti, tj);
+  else run_tile<E, false>(g, split, ti, tj);
 }
 
 // C (I x I, both triangles) and W^T (S x I) from the partials, float64,
@@ -400,11 +522,106 @@ __global__ void omega_pad_kernel(uint64_t seed, uint32_t mode, int64_t S, int64_
   }
 }
 
+
+// E8M0 scale byte for a run whose largest magnitude is amax: the smallest
+// power of two 2^s with amax / 2^s <= 448 (the largest e4m3 value), biased
+// by 127.  With amax = f 2^e, f in [0.5, 1): s = e - 9 if f <= 0.875, else
+// e - 8 (448 = 0.875 2^9).  An all-zero run gets the smallest scale.
+__device__ inline int e8m0_for(float amax) {
+  if (!(amax > 0.f)) return 0;
+  int e;
+  const float f = frexpf(amax, &e);
+  int s = f <= 0.875f ? e - 9 : e - 8;
+  s = s < -127 ? -127 : (s > 127 ? 127 : s);
+  return s + 127;
+}
+
+// max over each half (32 lanes) of a wave
+__device__ inline float half_max(float v) {
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Padded copies as in pad_copies_kernel, in bf16 and / or e4m3 with per-32
+// scales (runs of 32 along each storage row: lanes 0-31 and 32-63 of a wave).
+template <class T>
+__global__ void pad_copies_fp8_kernel(const T* X, int64_t R, int64_t L, bf16_t* Xpad, int64_t Lp, bf16_t* Xt,
+                                      int64_t Rp, fp8_t* Xp8, unsigned char* Sp, fp8_t* Xt8, unsigned char* St) {
+  __shared__ float tile[64][65];
+  const int64_t tl = Lp / 64;
+  const int64_t br = blockIdx.x / tl, bl = blockIdx.x - br * tl;
+  const int64_t r0 = br * 64, l0 = bl * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int y = ty; y < 64; y += 4) {
+    const int64_t r = r0 + y, l = l0 + tx;
+    float v = 0.f;
+    if (r < R && l < L) {
+      if constexpr (sizeof(T) == 2) v = bf16_to_f32(((const bf16_t*)X)[r * L + l]);
+      else v = (float)X[r * L + l];
+    }
+    tile[y][tx] = v;
+    if (r < R) {                                   // uniform over the wave
+      if (Xpad) Xpad[r * Lp + l] = f32_to_bf16(v);
+      if (Xp8) {
+        const int sc = e8m0_for(half_max(fabsf(v)));
+        Xp8[r * Lp + l] = f32_to_e4m3(ldexpf(v, 127 - sc));
+        if ((tx & 31) == 0) Sp[r * (Lp / 32) + (l >> 5)] = (unsigned char)sc;
+      }
+    }
+  }
+  if (!Xt && !Xt8) return;
+  __syncthreads();
+  for (int y = ty; y < 64; y += 4) {
+    const int64_t l = l0 + y, r = r0 + tx;
+    if (l < L) {                                   // uniform over the wave
+      const float v = tile[tx][y];
+      if (Xt) Xt[l * Rp + r] = f32_to_bf16(v);
+      if (Xt8) {
+        const int sc = e8m0_for(half_max(fabsf(v)));
+        Xt8[l * Rp + r] = f32_to_e4m3(ldexpf(v, 127 - sc));
+        if ((tx & 31) == 0) St[l * (Rp / 32) + (r >> 5)] = (unsigned char)sc;
+      }
+    }
+  }
+}
+
+// bf16 rows (total a multiple of 32) -> e4m3 + per-32 scales; one wave per 64 values.
+__global__ void quantize_rows_kernel(const bf16_t* src, int64_t total, fp8_t* q, unsigned char* scales) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nchunk = (total + 63) / 64;
+  for (int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ch < nchunk;
+       ch += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+    const int64_t i = ch * 64 + lane;
+    const float v = i < total ? bf16_to_f32(src[i]) : 0.f;
+    const int sc = e8m0_for(half_max(fabsf(v)));
+    if (i < total) {
+      q[i] = f32_to_e4m3(ldexpf(v, 127 - sc));
+      if ((lane & 31) == 0) scales[i >> 5] = (unsigned char)sc;
+    }
+  }
+}
+
+// out[kt][i][h] = plane[((a I + min(i, I-1)) Bp + k0) / 32 + h], kt = a (Bp / 64) + k0 / 64
+__global__ void gather_scales_kernel(const unsigned char* plane, int64_t I, int64_t Bp, int64_t ipad,
+                                     int64_t total, unsigned char* out) {
+  const int64_t nbt = Bp / 64;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int h = (int)(e & 1);
+    const int64_t ri = e >> 1;
+    const int64_t kt = ri / ipad, i = ri - kt * ipad;
+    const int64_t a = kt / nbt, k0 = (kt - a * nbt) * 64;
+    const int64_t ic = i < I ? i : I - 1;
+    out[e] = plane[((a * I + ic) * Bp + k0) / 32 + h];
+  }
+}
+
 }  // namespace
 
 int64_t pad64(int64_t v) { return (v + 63) / 64 * 64; }
 
-GramArgs gram_plan_pipe(int64_t A, int64_t I, int64_t Bp, int S, int cu_count) {
+GramArgs gram_plan_pipe(int elem, int64_t A, int64_t I, int64_t Bp, int S, int cu_count) {
   GramArgs g = {};
   g.A = A;
   g.I = I;
@@ -414,7 +631,7 @@ GramArgs gram_plan_pipe(int64_t A, int64_t I, int64_t Bp, int S, int cu_count) {
   g.nt = (int)ceil_div(I, PT);
   g.ntri = g.nt * (g.nt + 1) / 2;
   g.ntiles = g.ntri;
-  g.nbt = Bp / PK;
+  g.nbt = Bp / (elem == E_FP8 ? 64 : PK);
   g.nkt = A * g.nbt;
   // splits: minimise rounds(tiles x splits over the CUs) x (K tiles per split
   // + a fixed cost of 8 tiles) + the partials each split adds to the
@@ -440,9 +657,53 @@ size_t gram_pipe_partial_bytes(const GramArgs& g) { return (size_t)g.splits * g.
 
 bool gram_pipe_ok(int64_t I, int S) { return S >= 1 && S <= PW && I > 128; }
 
-hipError_t launch_gram_pipe(const GramArgs& g, hipStream_t s) {
-  if (g.nkt < 1 || g.splits > g.nkt || g.S > PW || g.B % PK) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gram_pipe_kernel, dim3((unsigned)(g.ntiles * g.splits)), dim3(256), 0, s, g);
+hipError_t launch_gram_pipe(int elem, const GramArgs& g, hipStream_t s) {
+  if (g.nkt < 1 || g.splits > g.nkt || g.S > PW || g.B % 64) return hipErrorInvalidValue;
+  if (elem == E_FP8) {
+    if (!g.xexp || !g.xexp_om) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(gram_pipe_kernel<E_FP8>, dim3((unsigned)(g.ntiles * g.splits)), dim3(256), 0, s, g);
+  } else {
+    hipLaunchKernelGGL(gram_pipe_kernel<E_BF16>, dim3((unsigned)(g.ntiles * g.splits)), dim3(256), 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_copies_fp8(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, void* Xp8,
+                                 void* Sp, void* Xt8, void* St, hipStream_t s) {
+  const int64_t Lp = pad64(L), Rp = pad64(R);
+  const int64_t blocks = (Rp / 64) * (Lp / 64);
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
+#define PCF(T)                                                                                               \
+  hipLaunchKernelGGL(pad_copies_fp8_kernel<T>, grid, dim3(256), 0, s, (const T*)X, R, L, (bf16_t*)Xpad, Lp, \
+                     (bf16_t*)Xt, Rp, (fp8_t*)Xp8, (unsigned char*)Sp, (fp8_t*)Xt8, (unsigned char*)St)
+  switch (src_elem) {
+    case E_F64: PCF(double); break;
+    case E_F32: PCF(float); break;
+    default: PCF(bf16_t); break;
+  }
+#undef PCF
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize_rows_fp8(const void* src, int64_t rows, int64_t cols, void* q, void* scales,
+                                    hipStream_t s) {
+  const int64_t total = rows * cols;
+  if (total <= 0) return hipSuccess;
+  if (cols % 32) return hipErrorInvalidValue;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(ceil_div(total, 64), 4), 16384);
+  hipLaunchKernelGGL(quantize_rows_kernel, dim3(grid), dim3(256), 0, s, (const bf16_t*)src, total, (fp8_t*)q,
+                     (unsigned char*)scales);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_scales(const void* plane, int64_t A, int64_t I, int64_t Bp, int64_t ipad, void* out,
+                                hipStream_t s) {
+  if (Bp % 64 || ipad < I) return hipErrorInvalidValue;
+  const int64_t total = A * (Bp / 64) * ipad * 2;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 16384);
+  hipLaunchKernelGGL(gather_scales_kernel, dim3(grid), dim3(256), 0, s, (const unsigned char*)plane, I, Bp, ipad,
+                     total, (unsigned char*)out);
   return hipGetLastError();
 }
 

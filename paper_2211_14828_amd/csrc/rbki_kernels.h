@@ -9,7 +9,8 @@ namespace rbki {
 struct GramArgs {
   const void* X;            // mode view source (element type of the product)
   const void* omegaT;       // S x J sketch rows (same element type), may be null if S == 0
-  const unsigned char* xexp;  // fp8 only: per-block E8M0 exponents of X
+  const unsigned char* xexp;     // fp8 pipelined form: E8M0 scales of X, [K tile][row pad][2]
+  const unsigned char* xexp_om;  // fp8 pipelined form: E8M0 scales of Omega^T, [K tile][64][2]
   int64_t A, I, B, J;
   int S;
   int nt, ntri, nw, ntiles;
@@ -36,13 +37,26 @@ hipError_t launch_omega(int elem, uint64_t seed, int mode, int64_t total, void* 
 // are the zero-padded bf16 views described there (row pitch Bp, a multiple of 64).
 int64_t pad64(int64_t v);
 bool gram_pipe_ok(int64_t I, int S);
-GramArgs gram_plan_pipe(int64_t A, int64_t I, int64_t Bp, int S, int cu_count);
+// elem: E_BF16 or E_FP8 (K tiles of 32 or 64 values)
+GramArgs gram_plan_pipe(int elem, int64_t A, int64_t I, int64_t Bp, int S, int cu_count);
 size_t gram_pipe_partial_bytes(const GramArgs& g);
-hipError_t launch_gram_pipe(const GramArgs& g, hipStream_t s);
+hipError_t launch_gram_pipe(int elem, const GramArgs& g, hipStream_t s);
 hipError_t launch_gram_pipe_reduce(const GramArgs& g, double* C, double* Wt, hipStream_t s);
 // X viewed as R rows of length L -> Xpad (R x pad64(L)) and Xt (L x pad64(R)),
 // bf16 with zero padding (either output may be null).
 hipError_t launch_pad_copies(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, hipStream_t s);
+// The same copies in e4m3 with one E8M0 scale per 32 consecutive values of a
+// storage row: Xp8 (R x pad64(L)) + Sp (R x pad64(L)/32), Xt8 (L x pad64(R)) +
+// St (L x pad64(R)/32); bf16 Xpad / Xt alongside when non-null.
+hipError_t launch_pad_copies_fp8(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, void* Xp8,
+                                 void* Sp, void* Xt8, void* St, hipStream_t s);
+// rows x cols bf16 (cols a multiple of 32) -> e4m3 with per-32 E8M0 scales
+hipError_t launch_quantize_rows_fp8(const void* src, int64_t rows, int64_t cols, void* q, void* scales, hipStream_t s);
+// Scales of the mode view [A, I, Bp] (per-32 plane of the e4m3 copy) in the
+// order the fp8 Gram kernel reads them: out[kt][i][h], kt < A Bp / 64,
+// i < ipad (rows past I repeat row I-1), h in {0, 1}.
+hipError_t launch_gather_scales(const void* plane, int64_t A, int64_t I, int64_t Bp, int64_t ipad, void* out,
+                                hipStream_t s);
 // Omega^T (S x J) of one mode as bf16 in the padded column layout S x Jp
 // (B: the mode's trailing size, IN: the last dimension; B = 1 for the last mode).
 hipError_t launch_omega_pad(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t Jp,

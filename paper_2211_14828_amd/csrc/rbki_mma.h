@@ -111,54 +111,6 @@ template <> struct Mma<E_BF16> {
   }
 };
 
-// ---------------------------------------------------------------- fp8 e4m3
-// Block-scaled: each lane passes the E8M0 exponent of its row's (A) or
-// column's (B) 32-element K run; scale_a / scale_b arrays give it per row of
-// the LDS tile (one byte per row per half).
-template <> struct Mma<E_FP8> {
-  typedef fp8_t T;
-  typedef float Out;
-  typedef Mma<E_F32>::Frag Frag;
-  static constexpr int BK = ROW_BYTES;         // 128 k per LDS tile
-  static constexpr int NACC = 64;
-  __device__ static inline void zero(Frag& f) { Mma<E_F32>::zero(f); }
-  __device__ static inline float get(const Frag& f, int j) { return f.c[j >> 4][j & 15]; }
-  // sa, sb: LDS scale bytes [row][4] for the 4 runs of 32 k in the tile
-  __device__ static inline void step(Frag& f, const char* lds_a, const char* lds_b, int lane,
-                                     int wr, int wc, const unsigned char* sa, const unsigned char* sb) {
-    const int half = lane >> 5, r = lane & 31;
-    // lane reads 64 contiguous bytes: 2 MFMA steps of 32 (runs half*2 + t)
-    i32x8_t a[2][2], b[2][2];
-    int ea[2][2], eb[2][2];
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const i32x8_t* pa = (const i32x8_t*)(lds_a + (wr + m * 32 + r) * LDS_ROW + half * 64);
-      const i32x8_t* pb = (const i32x8_t*)(lds_b + (wc + m * 32 + r) * LDS_ROW + half * 64);
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        a[m][q] = pa[q];
-        b[m][q] = pb[q];
-        ea[m][q] = sa[(wr + m * 32 + r) * 4 + half * 2 + q];
-        eb[m][q] = sb[(wc + m * 32 + r) * 4 + half * 2 + q];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-#pragma unroll
-        for (int n = 0; n < 2; ++n) {
-          f.c[m * 2 + n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-              a[m][t], b[n][t], f.c[m * 2 + n], 0, 0, 0, ea[m][t], 0, eb[n][t]);
-        }
-      }
-    }
-  }
-  __device__ static inline void coord(int j, int lane, int& row, int& col) {
-    Mma<E_F32>::coord(j, lane, row, col);
-  }
-};
-
 // ---------------------------------------------------------------- fp64
 template <> struct Mma<E_F64> {
   typedef double T;
