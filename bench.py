@@ -192,7 +192,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tucker1000_f32")
-    ap.add_argument("--precision", default="mixed_bf16")
+    ap.add_argument("--precision", default="mixed_fp8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 and plain-form runs that follow the timed region")

@@ -465,43 +465,18 @@ __global__ void gram_pipe_reduce_kernel(GramArgs g, double* C, double* Wt) {
   }
 }
 
-// Padded bf16 copies of X viewed as R rows of length L (R = T / I_N, L = I_N):
-// Xpad (R x Lp) and Xt (L x Rp), zeros in the padding.  64 x 64 tiles through LDS.
-template <class T>
-__global__ void pad_copies_kernel(const T* X, int64_t R, int64_t L, bf16_t* Xpad, int64_t Lp, bf16_t* Xt,
-                                  int64_t Rp) {
-  __shared__ float tile[64][65];
-  const int64_t tl = Lp / 64;
-  const int64_t br = blockIdx.x / tl, bl = blockIdx.x - br * tl;
-  const int64_t r0 = br * 64, l0 = bl * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int y = ty; y < 64; y += 4) {
-    const int64_t r = r0 + y, l = l0 + tx;
-    float v = 0.f;
-    if (r < R && l < L) {
-      if constexpr (sizeof(T) == 2) v = bf16_to_f32(((const bf16_t*)X)[r * L + l]);
-      else v = (float)X[r * L + l];
-    }
-    tile[y][tx] = v;
-    if (Xpad && r < R) Xpad[r * Lp + l] = f32_to_bf16(v);
-  }
-  if (!Xt) return;
-  __syncthreads();
-  for (int y = ty; y < 64; y += 4) {
-    const int64_t l = l0 + y, r = r0 + tx;
-    if (l < L) Xt[l * Rp + r] = f32_to_bf16(tile[tx][y]);
-  }
-}
-
 // Omega^T (S x J) of one mode in the padded column layout (S x Jp): the
 // value of stream index L = s J + j goes to column jp(j); padded columns
 // must be zero beforehand.  B = 1: jp = j.  B > 1: j = a B + b with
 // b = bh I_N + bl, jp = a Bp + bh I_Npad + bl.
-__global__ void omega_pad_kernel(uint64_t seed, uint32_t mode, int64_t S, int64_t J, int64_t B, int64_t IN,
-                                 int64_t INp, int64_t Jp, bf16_t* out) {
-  const int64_t total = S * J;
+// Index arithmetic in 32 bits when every index fits (the common case), else 64.
+template <class IT>
+__global__ void omega_pad_kernel(uint64_t seed, uint32_t mode, int64_t S, int64_t J_, int64_t B_, int64_t IN_,
+                                 int64_t INp_, int64_t Jp, bf16_t* out) {
+  const IT J = (IT)J_, B = (IT)B_, IN = (IT)IN_, INp = (IT)INp_;
+  const int64_t total = S * J_;
   const int64_t npairs = (total + 1) / 2;
-  const int64_t Bp = B > 1 ? (B / IN) * INp : 1;
+  const IT Bp = B > 1 ? (B / IN) * INp : 1;
   for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < npairs;
        m += (int64_t)gridDim.x * blockDim.x) {
     float z[2];
@@ -510,18 +485,18 @@ __global__ void omega_pad_kernel(uint64_t seed, uint32_t mode, int64_t S, int64_
     for (int h = 0; h < 2; ++h) {
       const int64_t L = 2 * m + h;
       if (L >= total) break;
-      const int64_t s = L / J, j = L - s * J;
-      int64_t jp = j;
+      const IT Lt = (IT)L;
+      const IT sv = Lt / J, j = Lt - sv * J;
+      IT jp = j;
       if (B > 1) {
-        const int64_t a = j / B, b = j - a * B;
-        const int64_t bh = b / IN, bl = b - bh * IN;
+        const IT a = j / B, b = j - a * B;
+        const IT bh = b / IN, bl = b - bh * IN;
         jp = a * Bp + bh * INp + bl;
       }
-      out[s * Jp + jp] = f32_to_bf16(z[h]);
+      out[(int64_t)sv * Jp + jp] = f32_to_bf16(z[h]);
     }
   }
 }
-
 
 // E8M0 scale byte for a run whose largest magnitude is amax: the smallest
 // power of two 2^s with amax / 2^s <= 448 (the largest e4m3 value), biased
@@ -543,44 +518,115 @@ __device__ inline float half_max(float v) {
   return v;
 }
 
-// Padded copies as in pad_copies_kernel, in bf16 and / or e4m3 with per-32
-// scales (runs of 32 along each storage row: lanes 0-31 and 32-63 of a wave).
+// 2^-s for the scale exponent s in [-127, 127] (exact; 2^-127 is subnormal)
+__device__ inline float pow2_neg(int s) {
+  return s < 127 ? __uint_as_float((uint32_t)(127 - s) << 23) : __uint_as_float(0x00400000u);
+}
+
+// e8m0_for with the exponent read from the float's bits (normal amax)
+__device__ inline int e8m0_fast(float amax) {
+  const uint32_t u = __float_as_uint(amax);
+  const int ex = (int)((u >> 23) & 0xFF);
+  if (ex == 0 || ex == 0xFF) return e8m0_for(amax);
+  const int e = ex - 126;                                  // amax = f 2^e, f = 1.m / 2
+  int sc = ((u & 0x7FFFFFu) <= 0x600000u ? e - 9 : e - 8);   // f <= 0.875 <=> 1.m <= 1.75
+  sc = sc < -127 ? -127 : (sc > 127 ? 127 : sc);
+  return sc + 127;
+}
+
+// max over the 8 lanes of an aligned group
+__device__ inline float group8_max(float v) {
+  v = fmaxf(v, __shfl_xor(v, 1, 64));
+  v = fmaxf(v, __shfl_xor(v, 2, 64));
+  v = fmaxf(v, __shfl_xor(v, 4, 64));
+  return v;
+}
+
+// Four values -> packed e4m3 (scale byte sc, shared by the 8 lanes of a run of 32)
+__device__ inline uint32_t pack_e4m3(const float* v, int sc) {
+  const float mul = pow2_neg(sc - 127);
+  uint32_t w = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w |= (uint32_t)f32_to_e4m3(v[k] * mul) << (8 * k);
+  return w;
+}
+
+__device__ inline uint2 pack_bf16(const float* v) {
+  return make_uint2((uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16),
+                    (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16));
+}
+
+// Padded copies of X viewed as R rows of length L (R = T / I_N, L = I_N), in
+// bf16 and / or e4m3 with per-32 scales, any output may be null:
+//   Xpad, Xp8 (+ Sp): R x Lp, zero padding;  Xt, Xt8 (+ St): L x Rp.
+// 64 x 64 tiles through LDS; a thread handles 4 consecutive values (16 per
+// tile row), so a run of 32 is 8 lanes of one wave.
 template <class T>
-__global__ void pad_copies_fp8_kernel(const T* X, int64_t R, int64_t L, bf16_t* Xpad, int64_t Lp, bf16_t* Xt,
-                                      int64_t Rp, fp8_t* Xp8, unsigned char* Sp, fp8_t* Xt8, unsigned char* St) {
+__global__ void __launch_bounds__(256) pad_copies_kernel(const T* X, int64_t R, int64_t L, bool vec, bf16_t* Xpad,
+                                                         int64_t Lp, bf16_t* Xt, int64_t Rp, fp8_t* Xp8,
+                                                         unsigned char* Sp, fp8_t* Xt8, unsigned char* St) {
   __shared__ float tile[64][65];
   const int64_t tl = Lp / 64;
   const int64_t br = blockIdx.x / tl, bl = blockIdx.x - br * tl;
   const int64_t r0 = br * 64, l0 = bl * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int y = ty; y < 64; y += 4) {
-    const int64_t r = r0 + y, l = l0 + tx;
-    float v = 0.f;
-    if (r < R && l < L) {
-      if constexpr (sizeof(T) == 2) v = bf16_to_f32(((const bf16_t*)X)[r * L + l]);
-      else v = (float)X[r * L + l];
+  const int t = threadIdx.x, q4 = (t & 15) * 4;
+#pragma unroll
+  for (int pass = 0; pass < 4; ++pass) {
+    const int y = pass * 16 + (t >> 4);
+    const int64_t r = r0 + y, l = l0 + q4;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (r < R) {
+      const T* src = X + r * L + l;
+      if (vec && l + 3 < L) {
+        if constexpr (sizeof(T) == 4) {
+          const float4 f = *(const float4*)src;
+          v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+        } else if constexpr (sizeof(T) == 2) {
+          const uint2 h = *(const uint2*)src;
+          v[0] = bf16_to_f32((bf16_t)(h.x & 0xFFFF)); v[1] = bf16_to_f32((bf16_t)(h.x >> 16));
+          v[2] = bf16_to_f32((bf16_t)(h.y & 0xFFFF)); v[3] = bf16_to_f32((bf16_t)(h.y >> 16));
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] = (float)src[k];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (l + k < L) {
+            if constexpr (sizeof(T) == 2) v[k] = bf16_to_f32(((const bf16_t*)src)[k]);
+            else v[k] = (float)src[k];
+          }
+      }
     }
-    tile[y][tx] = v;
-    if (r < R) {                                   // uniform over the wave
-      if (Xpad) Xpad[r * Lp + l] = f32_to_bf16(v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tile[y][q4 + k] = v[k];
+    // the run's scale: all lanes take part (rows past R hold zeros)
+    int sc = 0;
+    if (Xp8) sc = e8m0_fast(group8_max(fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])))));
+    if (r < R) {
+      if (Xpad) *(uint2*)(Xpad + r * Lp + l) = pack_bf16(v);
       if (Xp8) {
-        const int sc = e8m0_for(half_max(fabsf(v)));
-        Xp8[r * Lp + l] = f32_to_e4m3(ldexpf(v, 127 - sc));
-        if ((tx & 31) == 0) Sp[r * (Lp / 32) + (l >> 5)] = (unsigned char)sc;
+        *(uint32_t*)(Xp8 + r * Lp + l) = pack_e4m3(v, sc);
+        if ((t & 7) == 0) Sp[r * (Lp / 32) + (l >> 5)] = (unsigned char)sc;
       }
     }
   }
   if (!Xt && !Xt8) return;
   __syncthreads();
-  for (int y = ty; y < 64; y += 4) {
-    const int64_t l = l0 + y, r = r0 + tx;
-    if (l < L) {                                   // uniform over the wave
-      const float v = tile[tx][y];
-      if (Xt) Xt[l * Rp + r] = f32_to_bf16(v);
+#pragma unroll
+  for (int pass = 0; pass < 4; ++pass) {
+    const int y = pass * 16 + (t >> 4);            // output row l0 + y, values r0 + q4 .. + 3
+    const int64_t l = l0 + y, r = r0 + q4;
+    float v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = tile[q4 + k][y];
+    int sc = 0;
+    if (Xt8) sc = e8m0_fast(group8_max(fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])))));
+    if (l < L) {
+      if (Xt) *(uint2*)(Xt + l * Rp + r) = pack_bf16(v);
       if (Xt8) {
-        const int sc = e8m0_for(half_max(fabsf(v)));
-        Xt8[l * Rp + r] = f32_to_e4m3(ldexpf(v, 127 - sc));
-        if ((tx & 31) == 0) St[l * (Rp / 32) + (r >> 5)] = (unsigned char)sc;
+        *(uint32_t*)(Xt8 + l * Rp + r) = pack_e4m3(v, sc);
+        if ((t & 7) == 0) St[l * (Rp / 32) + (r >> 5)] = (unsigned char)sc;
       }
     }
   }
@@ -602,18 +648,22 @@ __global__ void quantize_rows_kernel(const bf16_t* src, int64_t total, fp8_t* q,
   }
 }
 
-// out[kt][i][h] = plane[((a I + min(i, I-1)) Bp + k0) / 32 + h], kt = a (Bp / 64) + k0 / 64
-__global__ void gather_scales_kernel(const unsigned char* plane, int64_t I, int64_t Bp, int64_t ipad,
+// out[kt][i][h] = plane[((a I + min(i, I-1)) Bp + k0) / 32 + h], kt = a (Bp / 64) + k0 / 64;
+// IT: the index type (32 bits when the plane and the output fit)
+template <class IT>
+__global__ void gather_scales_kernel(const unsigned char* plane, int64_t I_, int64_t Bp_, int64_t ipad_,
                                      int64_t total, unsigned char* out) {
-  const int64_t nbt = Bp / 64;
+  const IT I = (IT)I_, Bp = (IT)Bp_, ipad = (IT)ipad_;
+  const IT nbt = Bp / 64;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int h = (int)(e & 1);
-    const int64_t ri = e >> 1;
-    const int64_t kt = ri / ipad, i = ri - kt * ipad;
-    const int64_t a = kt / nbt, k0 = (kt - a * nbt) * 64;
-    const int64_t ic = i < I ? i : I - 1;
-    out[e] = plane[((a * I + ic) * Bp + k0) / 32 + h];
+    const IT et = (IT)e;
+    const IT h = et & 1;
+    const IT ri = et >> 1;
+    const IT kt = ri / ipad, i = ri - kt * ipad;
+    const IT a = kt / nbt, k0 = (kt - a * nbt) * 64;
+    const IT ic = i < I ? i : I - 1;
+    out[e] = plane[((uint64_t)(a * I + ic) * (uint64_t)Bp + k0) / 32 + h];
   }
 }
 
@@ -674,8 +724,10 @@ hipError_t launch_pad_copies_fp8(int src_elem, const void* X, int64_t R, int64_t
   const int64_t blocks = (Rp / 64) * (Lp / 64);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
-#define PCF(T)                                                                                               \
-  hipLaunchKernelGGL(pad_copies_fp8_kernel<T>, grid, dim3(256), 0, s, (const T*)X, R, L, (bf16_t*)Xpad, Lp, \
+  const int es = src_elem == E_F64 ? 8 : src_elem == E_F32 ? 4 : 2;
+  const bool vec = (L % 4) == 0 && ((uintptr_t)X % (4 * es)) == 0;
+#define PCF(T)                                                                                                   \
+  hipLaunchKernelGGL(pad_copies_kernel<T>, grid, dim3(256), 0, s, (const T*)X, R, L, vec, (bf16_t*)Xpad, Lp,      \
                      (bf16_t*)Xt, Rp, (fp8_t*)Xp8, (unsigned char*)Sp, (fp8_t*)Xt8, (unsigned char*)St)
   switch (src_elem) {
     case E_F64: PCF(double); break;
@@ -702,8 +754,12 @@ hipError_t launch_gather_scales(const void* plane, int64_t A, int64_t I, int64_t
   if (Bp % 64 || ipad < I) return hipErrorInvalidValue;
   const int64_t total = A * (Bp / 64) * ipad * 2;
   const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 16384);
-  hipLaunchKernelGGL(gather_scales_kernel, dim3(grid), dim3(256), 0, s, (const unsigned char*)plane, I, Bp, ipad,
-                     total, (unsigned char*)out);
+  if (total < ((int64_t)1 << 31) && A * I < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(gather_scales_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, (const unsigned char*)plane, I, Bp,
+                       ipad, total, (unsigned char*)out);
+  else
+    hipLaunchKernelGGL(gather_scales_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, (const unsigned char*)plane, I, Bp,
+                       ipad, total, (unsigned char*)out);
   return hipGetLastError();
 }
 
@@ -715,25 +771,7 @@ hipError_t launch_gram_pipe_reduce(const GramArgs& g, double* C, double* Wt, hip
 }
 
 hipError_t launch_pad_copies(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, hipStream_t s) {
-  const int64_t Lp = pad64(L), Rp = pad64(R);
-  const int64_t blocks = (Rp / 64) * (Lp / 64);
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)blocks);
-  switch (src_elem) {
-    case E_F64:
-      hipLaunchKernelGGL(pad_copies_kernel<double>, grid, dim3(256), 0, s, (const double*)X, R, L, (bf16_t*)Xpad, Lp,
-                         (bf16_t*)Xt, Rp);
-      break;
-    case E_F32:
-      hipLaunchKernelGGL(pad_copies_kernel<float>, grid, dim3(256), 0, s, (const float*)X, R, L, (bf16_t*)Xpad, Lp,
-                         (bf16_t*)Xt, Rp);
-      break;
-    default:
-      hipLaunchKernelGGL(pad_copies_kernel<bf16_t>, grid, dim3(256), 0, s, (const bf16_t*)X, R, L, (bf16_t*)Xpad, Lp,
-                         (bf16_t*)Xt, Rp);
-      break;
-  }
-  return hipGetLastError();
+  return launch_pad_copies_fp8(src_elem, X, R, L, Xpad, Xt, nullptr, nullptr, nullptr, nullptr, s);
 }
 
 hipError_t launch_omega_pad(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t Jp,
@@ -743,8 +781,12 @@ hipError_t launch_omega_pad(uint64_t seed, int mode, int64_t S, int64_t J, int64
   const int64_t npairs = (S * J + 1) / 2;
   unsigned grid = (unsigned)std::min<int64_t>(ceil_div(npairs, 256), 16384);
   if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(omega_pad_kernel, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN, pad64(IN), Jp,
-                     (bf16_t*)out);
+  if (S * J < ((int64_t)1 << 31) && Jp < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(omega_pad_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
+                       pad64(IN), Jp, (bf16_t*)out);
+  else
+    hipLaunchKernelGGL(omega_pad_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
+                       pad64(IN), Jp, (bf16_t*)out);
   return hipGetLastError();
 }
 
