@@ -186,6 +186,112 @@ def cpu_baseline(X, w, target_s=20.0):
 METRIC = "rBKI-TK TFLOP/s + rel err vs FP64 oracle; served solves/s, p50/p99 latency"
 
 
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def serving_leg(torch, rb, synth, count, slots, budget_gib, load, precision):
+    """The served mix: `count` third-order requests (dims U{32..256}, ranks
+    U{4..32} capped at dim/2, Gaussian core, orthonormal factors, SNR U[5,30]
+    dB, bf16 storage, p = 5, q U{1,2,3}), all resident in HBM before timing.
+
+    1. one-at-a-time: each request solved alone by the plain form on its
+       float32 copy, in arrival order, one after the other;
+    2. saturated: every request submitted to the request server at once
+       (capacity in solves/s);
+    3. Poisson: arrivals at `load` x the saturated rate with the recipe's
+       exponential gaps; latency is from the scheduled arrival to completion.
+    The served results' relative errors are compared with the plain ones."""
+    import threading
+    reqs = synth.served_requests(count=count)
+    Xb, X32 = [], []
+    for i, w in enumerate(reqs):
+        x = synth.make_device(w)
+        Xb.append(x)
+        X32.append(x.float())
+        if (i + 1) % 500 == 0:
+            torch.cuda.synchronize()
+            print(f"[serve] generated {i + 1}/{count} requests", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    def args_of(w):
+        return dict(p=w["p"], q=w["q"], seed=w["seeds"][1])
+
+    for w, x in list(zip(reqs, X32))[:8]:
+        rb.tucker(x, w["ranks"], precision="plain", **args_of(w))
+    torch.cuda.synchronize()
+    lat_plain, err_plain = [], []
+    t0 = time.perf_counter()
+    for w, x in zip(reqs, X32):
+        t = time.perf_counter()
+        _, _, e = rb.tucker(x, w["ranks"], precision="plain", **args_of(w))
+        lat_plain.append((time.perf_counter() - t) * 1e3)
+        err_plain.append(e)
+    t_plain = time.perf_counter() - t0
+    plain_rate = count / t_plain
+    print(f"[serve] one-at-a-time plain f32: {plain_rate:.1f} solves/s", file=sys.stderr, flush=True)
+    del X32
+    torch.cuda.empty_cache()
+
+    budget = int(budget_gib * (1 << 30))
+    out = {}
+    with rb.Server(budget, slots=slots) as sv:
+        for w, x in list(zip(reqs, Xb))[:2 * slots]:
+            sv.wait(sv.submit(x, w["ranks"], precision=precision, **args_of(w)))
+        t0 = time.perf_counter()
+        tickets = [sv.submit(x, w["ranks"], precision=precision, **args_of(w)) for w, x in zip(reqs, Xb)]
+        res = [sv.wait(t) for t in tickets]
+        t_sat = time.perf_counter() - t0
+        sat_rate = count / t_sat
+        err_served = [r[2] for r in res]
+        print(f"[serve] saturated: {sat_rate:.1f} solves/s", file=sys.stderr, flush=True)
+        del res
+
+        rate = load * sat_rate
+        arrivals = [w["arrival"] / rate for w in reqs]
+        lat = [None] * count
+        lag = [0.0] * count
+        done_at = [0.0] * count
+        tick = [None] * count
+        ready = threading.Semaphore(0)
+
+        def collect():
+            for i in range(count):
+                ready.acquire()
+                r = sv.wait(tick[i])
+                done_at[i] = time.perf_counter()
+                lat[i] = lag[i] + r[3]
+
+        th = threading.Thread(target=collect)
+        th.start()
+        t0 = time.perf_counter()
+        for i, (w, x) in enumerate(zip(reqs, Xb)):
+            d = t0 + arrivals[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            lag[i] = (time.perf_counter() - t0 - arrivals[i]) * 1e3
+            tick[i] = sv.submit(x, w["ranks"], precision=precision, **args_of(w))
+            ready.release()
+        th.join()
+        achieved = count / (max(done_at) - t0)
+    ex = [(a - b) / b for a, b in zip(err_served, err_plain) if b > 0]
+    out = {"requests": count, "mix": "3rd-order, dims U{32..256}, ranks U{4..32} capped at dim/2, bf16, p=5, "
+                                      "q U{1,2,3}, SNR U[5,30] dB",
+           "precision": precision, "slots": slots, "hbm_budget_gib": budget_gib,
+           "solves_per_s": round(sat_rate, 2),
+           "plain_one_at_a_time_solves_per_s": round(plain_rate, 2),
+           "speedup_vs_plain": round(sat_rate / plain_rate, 3),
+           "offered_rate": round(rate, 2), "achieved_rate": round(achieved, 2),
+           "p50_ms": round(_pct(lat, 50), 4), "p99_ms": round(_pct(lat, 99), 4),
+           "plain_p50_ms": round(_pct(lat_plain, 50), 4), "plain_p99_ms": round(_pct(lat_plain, 99), 4),
+           "excess_vs_plain_median": _pct(ex, 50), "excess_vs_plain_max": max(ex) if ex else None}
+    print(f"[serve] {out}", file=sys.stderr, flush=True)
+    del Xb
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +308,16 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc counter CSVs and exit")
     ap.add_argument("--traffic-command", default="")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the served mix (0: skip the serving leg)")
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-hw-queues", type=int, default=0,
+                    help="hardware queues of the process (default: one per slot, at most 32)")
+    ap.add_argument("--serve-budget-gib", type=float, default=16.0)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of the saturated rate")
+    ap.add_argument("--serve-precision", default="plain")
+    ap.add_argument("--serve-only", action="store_true")
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from(args.traffic_from[0], args.traffic_from[1], args.workload, args.precision,
@@ -212,11 +328,21 @@ def main():
               "run is the same kernel at a smaller shape); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # one hardware queue per server slot: with fewer, the slots' streams share
+    # queues and their solves run one after the other.  The HIP runtime reads
+    # this when it starts, so it is set before torch is imported.
+    if args.serve_requests > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(max(4, min(args.serve_hw_queues or args.serve_slots, 32)))
     import torch
     import paper_2211_14828_amd as rb
     import synth
 
     rb.load_library(build_if_missing=True)
+    if args.serve_only:
+        print(json.dumps({"serving": serving_leg(torch, rb, synth, args.serve_requests, args.serve_slots,
+                                                 args.serve_budget_gib, args.serve_load, args.serve_precision)}),
+              flush=True)
+        return
     w = synth.WORKLOADS[args.workload]
     dims, ranks, p, q = tuple(w["dims"]), tuple(w["ranks"]), w["p"], w["q"]
     print(f"[bench] generating {args.workload} {dims} on the device", file=sys.stderr, flush=True)
@@ -290,6 +416,11 @@ def main():
             compare["plain_ms_per_step"] = round((time.perf_counter() - t1) / n_plain * 1e3, 4)
         print(f"[bench] compare {compare}", file=sys.stderr, flush=True)
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = serving_leg(torch, rb, synth, args.serve_requests, args.serve_slots, args.serve_budget_gib,
+                              args.serve_load, args.serve_precision)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a slab", file=sys.stderr, flush=True)
@@ -316,6 +447,7 @@ def main():
                      "kernel": kernel, "avg_launch_ms": round(avg_gram_ms, 5),
                      "launches": nlaunch, "alg_flops_per_launch": alg_gram},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(rec), flush=True)
 

@@ -11,7 +11,8 @@
  *   parameter says "host".  Tensors are row-major (last index fastest).
  *   The caller owns every buffer; the library never allocates or frees caller
  *   memory, and never allocates device memory in these calls (all scratch
- *   space comes from the caller's workspace).
+ *   space comes from the caller's workspace).  The one exception is
+ *   rbki_server_create, which allocates the server's arena once.
  * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   Work is enqueued asynchronously on it; an entry point that returns a host
  *   value (rel_err, widths) synchronises that stream before returning.
@@ -158,6 +159,47 @@ rbki_status rbki_htr(const void *X, int xtype, const rbki_params *prm, const int
 size_t rbki_sym_eig_workspace(int64_t n);
 rbki_status rbki_sym_eig(const double *Z, int64_t n, double *lam, double *Vt, void *workspace,
                          size_t ws_bytes, int *sweeps, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving form: a request server for many small decompositions (continuous
+ * batching).  Not in the paper; it serves the same Alg. 2 decomposition
+ * (rbki_tucker, with rel_err) to a stream of requests of different shapes.
+ *
+ * rbki_server_create allocates, once, a device arena of hbm_budget_bytes on
+ * the current device and starts `slots` worker threads, each with its own
+ * stream (1 <= slots <= 64).  rbki_server_submit queues a request and returns
+ * at once with a ticket.  A free worker admits the oldest queued request as
+ * soon as its footprint (rbki_server_request_bytes, the rbki_tucker
+ * workspace) fits into the arena's free memory, and runs it on its stream;
+ * requests admitted by different workers overlap on the device.  No device
+ * memory is allocated after create.  The overlap is bounded by the hardware
+ * queues the HIP runtime gives the process (GPU_MAX_HW_QUEUES, 4 unless set
+ * before the runtime starts): streams beyond that share queues and run one
+ * after the other, so set it to about `slots`.
+ *   X, core, factors : device buffers as for rbki_tucker; they must stay
+ *                      valid, and X unchanged, until the request is done.
+ *                      X must be complete when submit is called: the
+ *                      workers' streams are non-blocking and do not wait for
+ *                      work on any other stream.
+ *   poll             : *done = 1 once finished; then rel_err (host, nullable)
+ *                      and latency_ms (host, nullable: submit to completion)
+ *                      are written, the request's status is returned and the
+ *                      ticket is released.  *done = 0: RBKI_OK, nothing else.
+ *   wait             : blocks until done, then as poll.
+ *   destroy          : finishes every submitted request, stops the workers,
+ *                      frees the arena.
+ * Errors: submit validates like rbki_tucker (RBKI_E_INVALID, also for a
+ * footprint above the budget); a failing request reports its status
+ * through poll / wait.  The server object is thread safe.
+ */
+typedef struct rbki_server rbki_server;
+size_t rbki_server_request_bytes(const rbki_params *prm, int xtype);
+rbki_status rbki_server_create(size_t hbm_budget_bytes, int slots, rbki_server **out);
+rbki_status rbki_server_submit(rbki_server *server, const void *X, int xtype, const rbki_params *prm, void *core,
+                               void *const *factors, int out_type, uint64_t *ticket);
+rbki_status rbki_server_poll(rbki_server *server, uint64_t ticket, int *done, double *rel_err, double *latency_ms);
+rbki_status rbki_server_wait(rbki_server *server, uint64_t ticket, double *rel_err, double *latency_ms);
+rbki_status rbki_server_destroy(rbki_server *server);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing.  When enabled, the library records HIP events around every

@@ -8,13 +8,15 @@ the library is missing or no GPU is visible, the calls raise.
     core, factors, rel_err = tucker(X, ranks, p=5, q=2, seed=0)
     cores, rel_err = htr(X, tucker_ranks, tr_ranks, p=6, q=2, seed=0)
     Qt, width = basis(X, mode, ranks, p, q, seed)          # Alg. 1, one mode
+    with Server(hbm_bytes, slots) as sv:                    # many small solves
+        t = sv.submit(X, ranks); core, factors, err, ms = sv.wait(t)
 """
 import ctypes
 import os
 import threading
 
 __all__ = ["tucker", "htr", "basis", "sym_eig", "omega", "philox", "workspace_bytes", "profile_enable",
-           "profile_reset", "profile_read", "library_path", "load_library", "RbkiError",
+           "profile_reset", "profile_read", "Server", "library_path", "load_library", "RbkiError",
            "PLAIN", "MIXED_BF16", "MIXED_FP8", "SYMBOLS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,7 +33,8 @@ _STATUS = {0: "RBKI_OK", 1: "RBKI_E_INVALID", 2: "RBKI_E_NOMEM", 3: "RBKI_E_HIP"
 SYMBOLS = ("rbki_version", "rbki_last_error", "rbki_omega", "rbki_philox", "rbki_basis_workspace",
            "rbki_basis", "rbki_tucker_workspace", "rbki_tucker", "rbki_htr_workspace", "rbki_htr",
            "rbki_sym_eig_workspace", "rbki_sym_eig", "rbki_profile_enable", "rbki_profile_reset",
-           "rbki_profile_read")
+           "rbki_profile_read", "rbki_server_request_bytes", "rbki_server_create", "rbki_server_submit",
+           "rbki_server_poll", "rbki_server_wait", "rbki_server_destroy")
 
 
 class RbkiError(RuntimeError):
@@ -84,6 +87,12 @@ def load_library(build_if_missing=True):
             "rbki_profile_enable": (None, [ci]),
             "rbki_profile_reset": (None, []),
             "rbki_profile_read": (ci, [ctypes.c_char_p, P(i64), P(dbl)]),
+            "rbki_server_request_bytes": (sz, [P(_Params), ci]),
+            "rbki_server_create": (ci, [sz, ci, P(vp)]),
+            "rbki_server_submit": (ci, [vp, vp, ci, P(_Params), vp, P(vp), ci, P(u64)]),
+            "rbki_server_poll": (ci, [vp, u64, P(ci), P(dbl), P(dbl)]),
+            "rbki_server_wait": (ci, [vp, u64, P(dbl), P(dbl)]),
+            "rbki_server_destroy": (ci, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -302,3 +311,98 @@ def profile_read(kernel):
     ms = ctypes.c_double(0.0)
     _check(lib.rbki_profile_read(kernel.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+class Server:
+    """Request server for many small rBKI-TK solves (continuous batching).
+
+    One device arena of ``hbm_bytes`` is allocated at construction; ``slots``
+    worker threads, each with its own stream, admit queued requests in order as
+    their workspace fits the free arena memory, so several solves run on the
+    device at once.  ``submit`` returns a ticket at once; ``wait`` / ``poll``
+    return (core, factors, rel_err, latency_ms).  The output tensors and the
+    input are held until the ticket is collected."""
+
+    def __init__(self, hbm_bytes, slots=4, device=None):
+        torch = _torch()
+        self._torch = torch
+        self._lib = load_library()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        h = ctypes.c_void_p(None)
+        with torch.cuda.device(self.device):
+            _check(self._lib.rbki_server_create(int(hbm_bytes), int(slots), ctypes.byref(h)))
+        self._h = h
+        self._held = {}
+
+    def request_bytes(self, dims, ranks, p=5, q=2, dtype=None, precision="plain"):
+        dtype = dtype or self._torch.float32
+        prm = _params(dims, ranks, p, q, 0, precision)
+        return self._lib.rbki_server_request_bytes(ctypes.byref(prm), _dtype_code(self._torch, dtype))
+
+    def submit(self, X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None):
+        torch = self._torch
+        if self._h is None:
+            raise RuntimeError("server is closed")
+        X = _as_input(torch, X)
+        code = _dtype_code(torch, X.dtype)
+        if out_dtype is None:
+            out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
+        ocode = _dtype_code(torch, out_dtype)
+        prm = _params(X.shape, ranks, p, q, seed, precision)
+        core = torch.empty(tuple(int(r) for r in ranks), dtype=out_dtype, device=X.device)
+        factors = [torch.empty((int(I), int(R)), dtype=out_dtype, device=X.device) for I, R in zip(X.shape, ranks)]
+        fptr = (ctypes.c_void_p * len(factors))(*[f.data_ptr() for f in factors])
+        # the request reads X on the server's (non-blocking) streams: wait
+        # for the work queued so far on the caller's stream, which produced X,
+        # and only for that
+        ev = torch.cuda.Event()
+        ev.record(torch.cuda.current_stream(X.device))
+        ev.synchronize()
+        ticket = ctypes.c_uint64(0)
+        _check(self._lib.rbki_server_submit(self._h, ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm),
+                                            ctypes.c_void_p(core.data_ptr()), fptr, ocode, ctypes.byref(ticket)))
+        self._held[ticket.value] = (X, core, factors)
+        return ticket.value
+
+    def _collect(self, ticket):
+        _, core, factors = self._held.pop(ticket, (None, None, None))
+        return core, factors
+
+    def poll(self, ticket):
+        """None while running, else (core, factors, rel_err, latency_ms)."""
+        done = ctypes.c_int(0)
+        err = ctypes.c_double(0.0)
+        ms = ctypes.c_double(0.0)
+        st = self._lib.rbki_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(done), ctypes.byref(err),
+                                        ctypes.byref(ms))
+        if st == 0 and not done.value:
+            return None
+        core, factors = self._collect(ticket)
+        _check(st)
+        return core, factors, err.value, ms.value
+
+    def wait(self, ticket):
+        err = ctypes.c_double(0.0)
+        ms = ctypes.c_double(0.0)
+        st = self._lib.rbki_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(err), ctypes.byref(ms))
+        core, factors = self._collect(ticket)
+        _check(st)
+        return core, factors, err.value, ms.value
+
+    def close(self):
+        if self._h is not None:
+            _check(self._lib.rbki_server_destroy(self._h))
+            self._h = None
+            self._held.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -7,12 +7,14 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
 #include "rbki_kernels.h"
+#include "rbki_api_internal.h"
 
 namespace rbki {
 hipError_t tr_svd_device(const void* Gcore, int core_elem, int N, const int64_t* S, const int64_t* r,
@@ -55,7 +57,7 @@ struct ProfRec {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
 };
 std::mutex g_prof_mu;
-bool g_prof_on = false;
+std::atomic<bool> g_prof_on{false};
 std::map<std::string, ProfRec> g_prof;
 
 struct ProfScope {
@@ -93,14 +95,15 @@ void prof_drain() {
 }
 
 int cu_count() {
-  static int cached = 0;
-  if (cached) return cached;
-  int dev = 0, n = 0;
-  if (hipGetDevice(&dev) == hipSuccess &&
-      hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
-    cached = n;
-  else
-    cached = 256;
+  // thread-safe one-time initialisation (the request server plans from
+  // several host threads)
+  static const int cached = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+      return n;
+    return 256;
+  }();
   return cached;
 }
 
@@ -122,6 +125,7 @@ struct Plan {
   bool need_pad = false;     // zero-padded bf16 copy Xpad (bf16 Gram products, first mode product)
   bool need_xt16 = false;    // zero-padded bf16 transposed copy Xt (last mode on the bf16 Gram path)
   bool need_fp8 = false;     // e4m3 copies with per-32 scales (fp8 Gram products)
+  bool concurrent = false;   // runs beside other solves on the device (request server)
   int64_t xscl_bytes = 0, oscl_bytes = 0;   // gathered scales of one mode
   int64_t in_pad = 0;        // last dimension padded to a multiple of 64
   int64_t rows_pad = 0;      // T / I_N padded to a multiple of 64 (row length of Xt)
@@ -286,6 +290,7 @@ struct Buffers {
   double* Vt[8] = {};
   void* jwork[8] = {};
   int* info = nullptr;
+  int* used = nullptr;       // per mode, q + 2 slots: directions kept by blocks 0..j-1
   double* Ut64[8] = {};
   void* Uop = nullptr;     // one factor in a product element type
   void* chainA = nullptr;
@@ -294,6 +299,10 @@ struct Buffers {
   void* rpartial = nullptr;
   double* sums = nullptr;
 };
+
+// Jacobi info (2 ints per mode) and the per-mode direction counts, zeroed
+// together before a decomposition.
+size_t counters_bytes(const Plan& P) { return 256 + (size_t)P.N * (P.q + 2) * 4; }
 
 void carve(const Plan& P, Arena& ar, Buffers& b) {
   const int es_g = elem_size(P.gelem);
@@ -332,7 +341,8 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
     b.Vt[n] = (double*)ar.take((size_t)Sp * Sp * 8);
     b.jwork[n] = ar.take(jacobi_work_bytes(Sp));
   }
-  b.info = (int*)ar.take(256);
+  b.info = (int*)ar.take(counters_bytes(P));
+  b.used = b.info + 64;
   for (int n = 0; n < P.N; ++n) b.Ut64[n] = (double*)ar.take((size_t)P.m[n].R * P.m[n].I * 8);
   b.Uop = ar.take((size_t)P.maxRI * 8);
   const size_t ce = P.celem == E_F64 ? 8 : 4;
@@ -435,9 +445,12 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
     HIPCHK(launch_gram_reduce(P.gelem, ga, b.C, b.Yt, st));
   }
 
-  // block 0: Q_0 = orth(W)
+  // block 0: Q_0 = orth(W).  The first pass of every block's CholeskyQR2
+  // also keeps the basis at most I_n wide: once it spans the whole space the
+  // later blocks are rounding noise and are dropped whatever their norm.
+  int* used = b.used + (size_t)n * (P.q + 2);
   HIPCHK(row_norms2(b.Yt, S, I, b.ref2, st));
-  HIPCHK(chol_orth(b.Yt, b.Ytmp, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st));
+  HIPCHK(chol_orth(b.Yt, b.Ytmp, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st, DimBudget{used, used + 1, I}));
   HIPCHK(chol_orth(b.Ytmp, Qt, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
   for (int j = 1; j <= P.q; ++j) {
     const int64_t m = S * j;                     // rows of the basis so far
@@ -450,7 +463,8 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
       HIPCHK(dgemm(0, 1, S, m, I, 1.0, b.Yt, I, Qt, I, 0.0, b.Pm, m, st));
       HIPCHK(dgemm(0, 0, S, I, m, -1.0, b.Pm, m, Qt, I, 1.0, b.Yt, I, st));
     }
-    HIPCHK(chol_orth(b.Yt, b.Ytmp, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st));
+    HIPCHK(chol_orth(b.Yt, b.Ytmp, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st,
+                     DimBudget{used + j, used + j + 1, I}));
     HIPCHK(chol_orth(b.Ytmp, Qt + m * I, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
   }
   if (!with_factor) return RBKI_OK;
@@ -479,7 +493,12 @@ rbki_status run_factors(const Plan& P, const Buffers& b, hipStream_t st) {
   }
   {
     ProfScope ps("jacobi", st);
-    HIPCHK(jacobi_eig_batched(P.N, Zs, ns, ls, vs, ws, is, 40, st));
+    // beside other solves (the request server) small matrices take the
+    // ordinary per-matrix launch: a cooperative grid does not share the
+    // device with work on other streams
+    int64_t nmax = 0;
+    for (int n = 0; n < P.N; ++n) nmax = std::max(nmax, ns[n]);
+    HIPCHK(jacobi_eig_batched(P.N, Zs, ns, ls, vs, ws, is, 40, st, P.concurrent && nmax <= 192));
   }
   for (int n = 0; n < P.N; ++n) {
     const ModeGeom& g = P.m[n];
@@ -492,7 +511,7 @@ rbki_status run_factors(const Plan& P, const Buffers& b, hipStream_t st) {
 
 // Core chain and error.  Returns the core (chain element type) in *core_out.
 rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, const void* xsrc, void* core,
-                               int out_elem, double* rel_err, void** core_out, hipStream_t st) {
+                               int out_elem, bool want_err, double* sums_host, void** core_out, hipStream_t st) {
   const size_t ce = P.celem == E_F64 ? 8 : 4;
   int64_t cur[8];
   for (int n = 0; n < P.N; ++n) cur[n] = P.dims[n];
@@ -540,7 +559,7 @@ rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, c
     HIPCHK(convert_tensor(P.celem, G, P.celem, b.gkeep, nc, st));
     *core_out = b.gkeep;
   }
-  if (!rel_err) return RBKI_OK;
+  if (!want_err) return RBKI_OK;
   // reconstruction chain H = G x_2 U2 ... x_N UN into the other buffer(s)
   void* src = G;
   int wsrc = which;
@@ -567,10 +586,7 @@ rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, c
     ProfScope ps("error", st);
     HIPCHK(launch_residual(P.xelem, X, P.celem, b.Uop, src, I0, J0, R0, b.sums, b.rpartial, 0, st));
   }
-  double h[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(h, b.sums, 16, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  *rel_err = h[1] > 0 ? std::sqrt(h[0] / h[1]) : 0.0;
+  HIPCHK(hipMemcpyAsync(sums_host, b.sums, 16, hipMemcpyDeviceToHost, st));
   (void)ce;
   return RBKI_OK;
 }
@@ -686,6 +702,7 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
     else
       HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
   }
+  HIPCHK(fill_zero(b.info, counters_bytes(P), st));
   s = run_mode(P, b, xsrc, mode, false, st);
   if (s != RBKI_OK) return s;
   const ModeGeom& g = P.m[mode];
@@ -714,11 +731,30 @@ size_t rbki_tucker_workspace(const rbki_params* prm, int xtype) {
   return plan_bytes(P);
 }
 
+}  // extern "C"
+
+namespace rbki {
+rbki_status finish_result(const HostResult& hr, double* rel_err) {
+  if (rel_err) *rel_err = hr.sums[1] > 0 ? std::sqrt(hr.sums[0] / hr.sums[1]) : 0.0;
+  for (int n = 0; n < hr.nmodes; ++n) {
+    if (g_prof_on) {
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof["jacobi_sweeps"].launches += hr.info[2 * n + 1];
+    }
+    if (hr.info[2 * n]) return fail(RBKI_E_NOCONV, "Jacobi reached its sweep limit in mode %d", n);
+  }
+  return RBKI_OK;
+}
+
+void set_error(rbki_status s, const char* msg) { fail(s, "%s", msg); }
+}  // namespace rbki
+
 static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
-                               int out_type, void* workspace, size_t ws_bytes, double* rel_err, hipStream_t st,
-                               Plan& P, Buffers& b, void** core_chain) {
+                        int out_type, void* workspace, size_t ws_bytes, double* rel_err, hipStream_t st, Plan& P,
+                        Buffers& b, void** core_chain, HostResult* async_res) {
   rbki_status s = make_plan(prm, xtype, P);
   if (s != RBKI_OK) return s;
+  P.concurrent = async_res != nullptr;        // enqueued by the request server
   if (!X) return fail(RBKI_E_INVALID, "X is NULL");
   if (out_type != RBKI_F64 && out_type != RBKI_F32) return fail(RBKI_E_INVALID, "out_type must be F64 or F32");
   const size_t need = plan_bytes(P);
@@ -736,7 +772,7 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
     else
       HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
   }
-  HIPCHK(fill_zero(b.info, 64, st));
+  HIPCHK(fill_zero(b.info, counters_bytes(P), st));
   for (int n = 0; n < P.N; ++n) {
     s = run_mode(P, b, xsrc, n, true, st);
     if (s != RBKI_OK) return s;
@@ -746,29 +782,37 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   for (int n = 0; n < P.N; ++n)
     if (factors && factors[n])
       HIPCHK(store_factor(b.Ut64[n], P.m[n].R, P.m[n].I, factors[n], dtype_elem(out_type), st));
-  s = run_core_and_error(P, b, X, xsrc, core, dtype_elem(out_type), rel_err, core_chain, st);
+  HostResult local;
+  HostResult* hr = async_res ? async_res : &local;
+  const bool want_err = rel_err || async_res;
+  s = run_core_and_error(P, b, X, xsrc, core, dtype_elem(out_type), want_err, hr->sums, core_chain, st);
   if (s != RBKI_OK) return s;
-  if (rel_err) {
-    int info[16] = {0};
-    HIPCHK(hipMemcpyAsync(info, b.info, 2 * P.N * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    for (int n = 0; n < P.N; ++n) {
-      if (g_prof_on) {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        g_prof["jacobi_sweeps"].launches += info[2 * n + 1];
-      }
-      if (info[2 * n]) return fail(RBKI_E_NOCONV, "Jacobi reached its sweep limit in mode %d", n);
-    }
-  }
-  return RBKI_OK;
+  if (!want_err) return RBKI_OK;
+  HIPCHK(hipMemcpyAsync(hr->info, b.info, 2 * P.N * sizeof(int), hipMemcpyDeviceToHost, st));
+  hr->nmodes = P.N;
+  if (async_res) return RBKI_OK;              // the caller reads the results after the stream completes
+  HIPCHK(hipStreamSynchronize(st));
+  return finish_result(*hr, rel_err);
 }
+
+
+namespace rbki {
+rbki_status tucker_enqueue(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
+                           int out_type, void* workspace, size_t ws_bytes, hipStream_t st, HostResult* hr) {
+  Plan P;
+  Buffers b;
+  return tucker_impl(X, xtype, prm, core, factors, out_type, workspace, ws_bytes, nullptr, st, P, b, nullptr, hr);
+}
+}  // namespace rbki
+
+extern "C" {
 
 rbki_status rbki_tucker(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
                         int out_type, void* workspace, size_t ws_bytes, double* rel_err, void* stream) {
   Plan P;
   Buffers b;
   return tucker_impl(X, xtype, prm, core, factors, out_type, workspace, ws_bytes, rel_err, (hipStream_t)stream, P,
-                     b, nullptr);
+                     b, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------- Alg. 3
@@ -812,7 +856,7 @@ rbki_status rbki_htr(const void* X, int xtype, const rbki_params* prm, const int
   void* Gchain = nullptr;
   double e_tk = 0.0;
   s = tucker_impl(X, xtype, prm, nullptr, nullptr, RBKI_F64, workspace, ws_bytes, rel_err ? &e_tk : nullptr, st, P, b,
-                  &Gchain);
+                  &Gchain, nullptr);
   if (s != RBKI_OK && s != RBKI_E_NOCONV) return s;
   // the remaining workspace after the Tucker plan
   size_t off = (plan_bytes(P) + 255) & ~(size_t)255;

@@ -104,7 +104,8 @@ __global__ void dgemm_reduce_kernel(int64_t m, int64_t n, int splits, const doub
 constexpr int CHOL_MAX = 96;
 
 __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t s, double* Linv, int* flags,
-                                                        const double* ref2, double tau_rel, double tau_abs) {
+                                                        const double* ref2, double tau_rel, double tau_abs,
+                                                        DimBudget bud) {
   __shared__ double Ls[CHOL_MAX][CHOL_MAX + 1];
   __shared__ double Xs[CHOL_MAX][CHOL_MAX + 1];
   __shared__ double d0[CHOL_MAX];
@@ -130,9 +131,12 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
   }
   __syncthreads();
   const double abs_floor = tau_abs * tau_abs * sh_ref;
+  const int64_t allowed = bud.allowed();
+  int64_t nkept = 0;
   for (int k = 0; k < s; ++k) {
     const double d = Ls[k][k];
-    const int kp = (d0[k] > 0.0) && (d > tau_rel * d0[k]) && (d > abs_floor);
+    const int kp = (d0[k] > 0.0) && (d > tau_rel * d0[k]) && (d > abs_floor) && nkept < allowed;
+    nkept += kp;
     const double piv = kp ? sqrt(d) : 0.0;
     __syncthreads();
     for (int i = k + tid; i < s; i += blockDim.x) Ls[i][k] = kp ? (i == k ? piv : Ls[i][k] / piv) : 0.0;
@@ -179,6 +183,7 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
     Linv[e] = keep[i] ? Xs[i][j] : 0.0;
   }
   for (int64_t i = tid; i < s; i += blockDim.x) flags[i] = keep[i];
+  if (tid == 0) bud.record(nkept);
 }
 
 // CholeskyQR step for s <= 64 in one launch: Yout = L^{-1} Y where G = L L^T
@@ -192,7 +197,7 @@ constexpr int CS_MAX = 64;
 
 __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s, const double* Y, int64_t n,
                                                          double* Yout, int* flags, const double* ref2,
-                                                         double tau_rel, double tau_abs) {
+                                                         double tau_rel, double tau_abs, DimBudget bud) {
   __shared__ double Ls[CS_MAX][CS_MAX + 1];
   __shared__ double dinv[CS_MAX];
   __shared__ int keep[CS_MAX];
@@ -208,6 +213,8 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
     mx = warp_max(mx);
     const double abs_floor = tau_abs * tau_abs * mx;
     const double d0 = i < s ? Ls[i][i] : 0.0;
+    const int64_t allowed = bud.allowed();
+    int64_t nkept = 0;
     for (int k = 0; k < s; ++k) {
       double v = 0.0;
       if (i >= k && i < s) {
@@ -216,7 +223,8 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
       }
       const double d = __shfl(v, k, 64);
       const double dk0 = __shfl(d0, k, 64);
-      const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor);
+      const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor) && nkept < allowed;
+      nkept += kp;
       const double piv = kp ? sqrt(d) : 0.0;
       if (i >= k && i < s) Ls[i][k] = kp ? (i == k ? piv : v / piv) : 0.0;
       if (i == k) {
@@ -224,6 +232,9 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
         dinv[k] = kp ? 1.0 / piv : 0.0;
       }
     }
+    // every workgroup reads the count of earlier blocks and writes a
+    // different slot, so they agree without synchronising
+    if (blockIdx.x == 0 && i == 0) bud.record(nkept);
   }
   __syncthreads();
   if (blockIdx.x == 0)
@@ -248,7 +259,8 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
 // Left-looking Cholesky of the s x s Gram matrix G with column dropping, one
 // workgroup, for s beyond the LDS variant (same drop rule).
 __global__ void __launch_bounds__(1024) chol_drop_kernel(const double* G, int64_t s, double* L, int* flags,
-                                                         const double* ref2, double tau_rel, double tau_abs) {
+                                                         const double* ref2, double tau_rel, double tau_abs,
+                                                         DimBudget bud) {
   __shared__ double red[16];
   __shared__ double sh_ref;
   __shared__ int sh_keep;
@@ -268,12 +280,15 @@ __global__ void __launch_bounds__(1024) chol_drop_kernel(const double* G, int64_
   for (int64_t i = tid; i < s * s; i += blockDim.x) L[i] = 0.0;
   __syncthreads();
   const double abs_floor = tau_abs * tau_abs * sh_ref;
+  const int64_t allowed = bud.allowed();
+  int64_t nkept = 0;                               // meaningful in thread 0
   for (int64_t kc = 0; kc < s; ++kc) {
     if (tid == 0) {
       double d = G[kc * s + kc];
       for (int64_t j = 0; j < kc; ++j) d -= L[kc * s + j] * L[kc * s + j];
       const double gkk = G[kc * s + kc];
-      const int keep = (gkk > 0.0) && (d > tau_rel * gkk) && (d > abs_floor);
+      const int keep = (gkk > 0.0) && (d > tau_rel * gkk) && (d > abs_floor) && nkept < allowed;
+      nkept += keep;
       sh_keep = keep;
       sh_piv = keep ? sqrt(d) : 0.0;
       flags[kc] = keep;
@@ -290,6 +305,7 @@ __global__ void __launch_bounds__(1024) chol_drop_kernel(const double* G, int64_
     }
     __syncthreads();
   }
+  if (tid == 0) bud.record(nkept);
 }
 
 // Y (s x n rows) <- L^{-1} Y row-wise (forward substitution along the s
@@ -378,15 +394,22 @@ __device__ inline bool jacobi_rotation(double al, double be, double ga, double t
   return true;
 }
 
+// COOP: one workgroup per (matrix, pair position), rounds separated by grid
+// barriers (cooperative launch).  !COOP: one workgroup per matrix walks every
+// position of a round itself; an ordinary launch, so that solves on other
+// streams can run beside it.  The pairs of a round touch disjoint columns and
+// every pair does the same arithmetic in either form, so the two give
+// bit-identical results.
+template <bool COOP>
 __global__ void __launch_bounds__(1024) jacobi_kernel(JacobiArgs J) {
   extern __shared__ double sm[];
   __shared__ double sh_off[16];
   __shared__ int sh_done[JAC_MAXB];
   __shared__ double rot_c[16], rot_s[16];
   __shared__ int rot_p[16], rot_q[16];
-  cg::grid_group grid = cg::this_grid();
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int m = blockIdx.x / J.npos, pos = blockIdx.x % J.npos;
+  const int m = COOP ? blockIdx.x / J.npos : blockIdx.x;
+  const int pos0 = COOP ? blockIdx.x % J.npos : 0;
   const int nb = J.nb, two = 2 * nb;
   const int nbk = (two + 15) / 16;                 // 16-wide MFMA blocks across the pair
   const int64_t n = J.n[m];
@@ -400,10 +423,13 @@ __global__ void __launch_bounds__(1024) jacobi_kernel(JacobiArgs J) {
   __syncthreads();
   int sweep;
   for (sweep = 0; sweep < J.max_sweeps; ++sweep) {
-    if (blockIdx.x == 0 && tid < J.nmat) J.offmax[((sweep + 1) % 3) * JAC_MAXB + tid] = 0ull;
+    if (COOP && blockIdx.x == 0 && tid < J.nmat) J.offmax[((sweep + 1) % 3) * JAC_MAXB + tid] = 0ull;
     double local_off = 0.0;
-    const bool mine = !sh_done[m] && pos < J.nblk[m] / 2;
-    for (int round = 0; round < J.max_nblk - 1; ++round) {
+    const int npos_m = J.nblk[m] / 2;
+    const bool mine = !sh_done[m] && pos0 < npos_m;
+    const int pos_end = COOP ? pos0 + 1 : npos_m;
+    for (int round = 0; round < (COOP ? J.max_nblk : J.nblk[m]) - 1; ++round) {
+      for (int pos = pos0; pos < pos_end; ++pos) {
       unsigned long long t0 = wall_clock64();
       if (mine && round < J.nblk[m] - 1) {
         const int bp = circle_block(pos, round, J.nblk[m]);
@@ -569,17 +595,35 @@ __global__ void __launch_bounds__(1024) jacobi_kernel(JacobiArgs J) {
           J.prof[3] += t4 - t3;
           J.prof[5] += 1;
         }
+        if (!COOP) __syncthreads();               // P, G and V are reused by the next position
       }
-      unsigned long long tg = wall_clock64();
-      grid.sync();
-      if (J.prof && blockIdx.x == 0 && tid == 0) J.prof[4] += wall_clock64() - tg;
+      }
+      if constexpr (COOP) {
+        unsigned long long tg = wall_clock64();
+        cg::this_grid().sync();
+        if (J.prof && blockIdx.x == 0 && tid == 0) J.prof[4] += wall_clock64() - tg;
+      }
+    }
+    if constexpr (!COOP) {
+      // local_off is uniform across the workgroup: the sweep's largest |cos|
+      // over every pair of this matrix
+      if (!sh_done[m] && local_off <= J.tol && tid == 0) {
+        J.info[m][0] = 0;
+        J.info[m][1] = sweep + 1;
+      }
+      __syncthreads();
+      if (local_off <= J.tol) {
+        if (tid == 0) sh_done[m] = 1;
+        break;
+      }
+      continue;
     }
     // publish this workgroup's largest |cos| of the sweep (first inner sweep of
     // each round: the state before any rotation of that round)
     if (tid == 0 && mine)
       atomicMax(&J.offmax[(sweep % 3) * JAC_MAXB + m], (unsigned long long)__double_as_longlong(local_off));
     __threadfence();
-    grid.sync();
+    cg::this_grid().sync();
     if (tid < J.nmat && !sh_done[tid]) {
       const double v = __longlong_as_double(
           (long long)__atomic_load_n(&J.offmax[(sweep % 3) * JAC_MAXB + tid], __ATOMIC_RELAXED));
@@ -596,9 +640,13 @@ __global__ void __launch_bounds__(1024) jacobi_kernel(JacobiArgs J) {
     for (int k = 0; k < J.nmat; ++k) all = all && sh_done[k];
     if (all) break;
   }
-  if (blockIdx.x == 0 && tid < J.nmat && !sh_done[tid]) {
+  if (COOP && blockIdx.x == 0 && tid < J.nmat && !sh_done[tid]) {
     J.info[tid][0] = sweep;
     J.info[tid][1] = sweep;
+  }
+  if (!COOP && tid == 0 && !sh_done[m]) {
+    J.info[m][0] = sweep;
+    J.info[m][1] = sweep;
   }
 }
 
@@ -748,21 +796,21 @@ hipError_t row_norms2(const double* Y, int64_t s, int64_t n, double* out, hipStr
 }
 
 hipError_t chol_orth(double* Y, double* Yout, int64_t s, int64_t n, double* G, double* Lm, int* flags,
-                     const double* ref2, double tau_rel, double tau_abs, hipStream_t st) {
+                     const double* ref2, double tau_rel, double tau_abs, hipStream_t st, DimBudget bud) {
   if (s <= 0) return hipSuccess;
   hipError_t e = dgemm(0, 1, s, s, n, 1.0, Y, n, Y, n, 0.0, G, s, st);
   if (e != hipSuccess) return e;
   if (s <= CS_MAX) {
     hipLaunchKernelGGL(chol_solve_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, G, (int)s, Y, n, Yout,
-                       flags, ref2, tau_rel, tau_abs);
+                       flags, ref2, tau_rel, tau_abs, bud);
     return hipGetLastError();
   }
   if (s <= CHOL_MAX) {
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, G, s, Lm, flags, ref2, tau_rel, tau_abs);
+    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), 0, st, G, s, Lm, flags, ref2, tau_rel, tau_abs, bud);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return dgemm(0, 0, s, n, s, 1.0, Lm, s, Y, n, 0.0, Yout, n, st);
   }
-  hipLaunchKernelGGL(chol_drop_kernel, dim3(1), dim3(1024), 0, st, G, s, Lm, flags, ref2, tau_rel, tau_abs);
+  hipLaunchKernelGGL(chol_drop_kernel, dim3(1), dim3(1024), 0, st, G, s, Lm, flags, ref2, tau_rel, tau_abs, bud);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(trsm_rows_kernel, dim3(grid_for(n)), dim3(256), 0, st, Y, s, n, Lm, flags);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -793,7 +841,8 @@ size_t jacobi_work_bytes(int64_t n) {
 }
 
 hipError_t jacobi_eig_batched(int nmat, const double* const* Z, const int64_t* ns, double* const* lam,
-                              double* const* Vt, void* const* work, int* const* info, int max_sweeps, hipStream_t st) {
+                              double* const* Vt, void* const* work, int* const* info, int max_sweeps, hipStream_t st,
+                              bool per_matrix) {
   if (nmat <= 0) return hipSuccess;
   if (nmat > JAC_MAXB) return hipErrorInvalidValue;
   int64_t nmax = 0;
@@ -845,11 +894,21 @@ hipError_t jacobi_eig_batched(int nmat, const double* const* Z, const int64_t* n
   ja.npos = ja.max_nblk / 2;
   ja.ld = (nmax & 1) ? nmax : nmax + 1;
   const size_t shmem = jacobi_lds_bytes(nmax, nb);
-  e = hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-  if (e != hipSuccess) return e;
-  void* args[] = {&ja};
-  e = hipLaunchCooperativeKernel((const void*)jacobi_kernel, dim3(ja.npos * nmat), dim3(1024), args, shmem, st);
-  if (e != hipSuccess) return e;
+  if (per_matrix) {
+    e = hipFuncSetAttribute((const void*)jacobi_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(nmat), dim3(1024), shmem, st, ja);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    e = hipFuncSetAttribute((const void*)jacobi_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)shmem);
+    if (e != hipSuccess) return e;
+    void* args[] = {&ja};
+    e = hipLaunchCooperativeKernel((const void*)jacobi_kernel<true>, dim3(ja.npos * nmat), dim3(1024), args, shmem,
+                                   st);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(jacobi_finish_kernel, dim3(nmat), dim3(1024), 0, st, fa);
   return hipGetLastError();
 }

@@ -78,8 +78,24 @@ hipError_t dgemm(int opA, int opB, int64_t m, int64_t n, int64_t k, double alpha
 // Gram diagonal or below tau_abs^2 times the largest ref2 entry.  G and Lm
 // are s x s scratch; flags (int[s]) receives 1 for kept vectors; ref2
 // (device, s doubles, nullable) holds squared reference norms.
+//
+// DimBudget caps the kept directions of a basis built block by block at the
+// dimension of the space: `used_in` (device int) holds the count kept by
+// the earlier blocks, at most `limit - *used_in` vectors of this block are
+// kept (in order), and `*used_out = *used_in + kept` is written for the next
+// block (a different slot, so every workgroup reads the same count).  The
+// default (used_in == nullptr) keeps no count.
+struct DimBudget {
+  const int* used_in = nullptr;
+  int* used_out = nullptr;
+  int64_t limit = 0;
+  __device__ int64_t allowed() const { return used_in ? limit - *used_in : (int64_t)1 << 62; }
+  __device__ void record(int64_t kept) const {
+    if (used_out) *used_out = (int)((used_in ? *used_in : 0) + kept);
+  }
+};
 hipError_t chol_orth(double* Y, double* Yout, int64_t s, int64_t n, double* G, double* Lm, int* flags,
-                     const double* ref2, double tau_rel, double tau_abs, hipStream_t st);
+                     const double* ref2, double tau_rel, double tau_abs, hipStream_t st, DimBudget bud = {});
 
 // Scratch for split-K float64 GEMMs (nullptr disables split-K).
 void dgemm_set_scratch(double* p, size_t bytes);
@@ -95,10 +111,12 @@ size_t jacobi_work_bytes(int64_t n);
 hipError_t jacobi_eig(const double* Z, int64_t n, double* lam, double* Vt, void* work, int* info,
                       int max_sweeps, hipStream_t st);
 // The same for up to 8 matrices in one launch (each with its own scratch;
-// info[k] points at two ints per matrix).
+// info[k] points at two ints per matrix).  per_matrix: one workgroup per
+// matrix in an ordinary launch instead of the cooperative grid (same
+// results; lets solves on other streams run beside it).
 hipError_t jacobi_eig_batched(int nmat, const double* const* Z, const int64_t* n, double* const* lam,
                               double* const* Vt, void* const* work, int* const* info, int max_sweeps,
-                              hipStream_t st);
+                              hipStream_t st, bool per_matrix = false);
 
 // Copy / convert helpers.
 hipError_t copy_rows_f64(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows,

@@ -93,3 +93,27 @@ def test_unknown_dtype_and_null_tensor_are_rejected():
     assert lib.rbki_tucker(ctypes.c_void_p(256), 9, ctypes.byref(prm), None, None, 1, None, 0, None, None) == 1
     assert lib.rbki_tucker(None, 1, ctypes.byref(prm), None, None, 1, None, 0, None, None) == 1
     assert lib.rbki_tucker(ctypes.c_void_p(256), 1, ctypes.byref(prm), None, None, 2, None, 0, None, None) == 1
+
+
+def test_server_rejects_bad_arguments_before_touching_the_device():
+    lib = rb.load_library()
+    out = ctypes.c_void_p(None)
+    assert lib.rbki_server_create(1 << 30, 0, ctypes.byref(out)) == 1
+    assert lib.rbki_server_create(1 << 30, 65, ctypes.byref(out)) == 1
+    assert lib.rbki_server_create(1 << 10, 2, ctypes.byref(out)) == 1
+    assert lib.rbki_server_create(1 << 30, 2, None) == 1
+    assert out.value is None
+    t = ctypes.c_uint64(0)
+    prm = _params((20, 20, 20), (3, 3, 3))
+    assert lib.rbki_server_submit(None, ctypes.c_void_p(256), 1, ctypes.byref(prm), None, None, 1, ctypes.byref(t)) == 1
+    assert lib.rbki_server_destroy(None) == 0
+
+
+def test_server_footprint_is_the_decomposition_workspace():
+    lib = rb.load_library()
+    for dims, ranks, q in [((20, 20, 20), (3, 3, 3), 2), ((256, 32, 100), (16, 16, 32), 3)]:
+        prm = _params(dims, ranks, 5, q)
+        for xt in (0, 1, 2):
+            assert lib.rbki_server_request_bytes(ctypes.byref(prm), xt) == lib.rbki_tucker_workspace(ctypes.byref(prm), xt)
+    bad = _params((10, 10, 10), (11, 3, 3))
+    assert lib.rbki_server_request_bytes(ctypes.byref(bad), 1) == 0

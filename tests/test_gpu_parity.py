@@ -140,6 +140,14 @@ CASES = [
     ((300, 200, 90), (60, 50, 20), 10, 1, "float32", "mixed_fp8", "widesketch"),
     ((160, 160, 160), (20, 20, 20), 10, 3, "float32", "mixed_fp8", "c2small"),
     ((8, 20, 20), (8, 5, 5), 2, 1, "float64", "plain", "full_rank_mode"),
+    # the Krylov basis spans the whole mode space before its last block
+    # (S (q+1) > I_n): the later blocks are rounding noise and must be dropped
+    ((52, 210, 45), (26, 25, 22), 5, 2, "float64", "plain", "capped"),
+    ((52, 210, 45), (26, 25, 22), 5, 2, "float32", "plain", "capped"),
+    ((63, 120, 146), (28, 14, 28), 5, 3, "float64", "plain", "capped"),
+    ((63, 120, 146), (28, 14, 28), 5, 3, "bfloat16", "plain", "capped"),
+    ((72, 52, 228), (23, 15, 19), 5, 3, "float32", "plain", "capped"),
+    ((172, 237, 112), (8, 32, 24), 5, 3, "bfloat16", "mixed_bf16", "capped"),
     ((5, 300, 7), (2, 3, 2), 5, 2, "float64", "plain", "thin"),
 ]
 
