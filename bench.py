@@ -82,7 +82,7 @@ def step_flops(dims, ranks, p, q):
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("gram.hip", "rbki_mma.h"):
+    for f in ("gram.hip", "gram_pipe.hip", "rbki_mma.h"):
         with open(os.path.join(ROOT, "paper_2211_14828_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
