@@ -110,6 +110,9 @@ int cu_count() {
 // ------------------------------------------------------------------ planning
 struct ModeGeom {
   int64_t A, I, B, J, R, S, Sp;   // Sp = S * (q + 1): rows of the Krylov basis buffer
+  bool pipe = false;              // mixed forms: the pipelined Gram kernel on a blocked copy
+  int pelem = 0;                  // its element type (E_BF16 or E_FP8)
+  int64_t nkt = 0;                // its K tiles
 };
 
 struct Plan {
@@ -122,11 +125,12 @@ struct Plan {
   int gelem = 0;     // Gram / sketch product
   int telem = 0;     // first mode product (reads X)
   int celem = 0;     // later mode products, reconstruction and error
-  bool need_pad = false;     // zero-padded bf16 copy Xpad (bf16 Gram products, first mode product)
-  bool need_xt16 = false;    // zero-padded bf16 transposed copy Xt (last mode on the bf16 Gram path)
-  bool need_fp8 = false;     // e4m3 copies with per-32 scales (fp8 Gram products)
+  bool need_pad = false;     // mixed forms: zero-padded bf16 copy Xpad (first mode product, Gram fallback)
+  bool need_xt16 = false;    // zero-padded bf16 transposed copy Xt (last mode on the Gram fallback)
+  bool need_fp8 = false;     // e4m3 blocked copies with per-32 scales (fp8 Gram products)
+  bool lead_pipe = false;    // some leading mode is pipelined: the one-pass blocked copy also writes Xpad
   bool concurrent = false;   // runs beside other solves on the device (request server)
-  int64_t xscl_bytes = 0, oscl_bytes = 0;   // gathered scales of one mode
+  int64_t oblk_bytes = 0;                   // one mode's blocked bf16 sketch (the largest)
   int64_t in_pad = 0;        // last dimension padded to a multiple of 64
   int64_t rows_pad = 0;      // T / I_N padded to a multiple of 64 (row length of Xt)
   int64_t T = 1;
@@ -210,18 +214,17 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     if (P.need_pad) {
       int64_t A, Bp;
       padded_view(P, n, A, Bp);
-      P.maxSJ = std::max(P.maxSJ, g.S * A * Bp);
-      const bool fp8 = P.need_fp8 && gram_pipe_ok(g.I, (int)g.S);
-      if (n == P.N - 1 && !fp8) P.need_xt16 = true;
-      if (fp8) {
-        const int64_t ipad = pad64(g.I) + (256 - pad64(g.I) % 256) % 256;   // rows of whole 256-row tiles
-        P.xscl_bytes = std::max(P.xscl_bytes, A * (Bp / 64) * ipad * 2);
-        P.oscl_bytes = std::max(P.oscl_bytes, A * (Bp / 64) * 64 * 2);
-      }
-      if (gram_pipe_ok(g.I, (int)g.S)) {
-        const int e = fp8 ? E_FP8 : E_BF16;
-        P.partial_bytes = std::max(P.partial_bytes, gram_pipe_partial_bytes(gram_plan_pipe(e, A, g.I, Bp, (int)g.S, cu_count())));
+      g.pipe = gram_pipe_ok(g.I, (int)g.S);
+      if (g.pipe) {
+        g.pelem = P.need_fp8 ? E_FP8 : E_BF16;
+        const int64_t KT = g.pelem == E_FP8 ? 64 : 32;
+        g.nkt = A * Bp / KT;
+        P.oblk_bytes = std::max(P.oblk_bytes, g.nkt * 64 * KT * 2);
+        P.partial_bytes = std::max(P.partial_bytes,
+                                   gram_pipe_partial_bytes(gram_plan_pipe(g.pelem, A, g.I, Bp, (int)g.S, cu_count())));
       } else {
+        P.maxSJ = std::max(P.maxSJ, g.S * A * Bp);
+        if (n == P.N - 1) P.need_xt16 = true;
         GramArgs ga = gram_plan(E_BF16, A, g.I, Bp, (int)g.S, cu_count());
         P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(ga, E_BF16));
       }
@@ -231,6 +234,8 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
       P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(ga, P.gelem));
     }
   }
+  if (P.need_pad)
+    for (int n = 0; n + 1 < P.N; ++n) P.lead_pipe = P.lead_pipe || P.m[n].pipe;
   // chain sizes: core chain starting with first_mode, then ascending; the
   // reconstruction chain expands modes 1..N-1 from the core.
   int64_t cur[8];
@@ -263,14 +268,11 @@ struct Arena {
 
 struct Buffers {
   void* xpad = nullptr;    // bf16, (T / I_N) x I_Npad, zero-padded
-  void* xp8 = nullptr;     // e4m3 copies and their per-32 scale planes
-  void* sp8 = nullptr;
-  void* xt8 = nullptr;
-  void* st8 = nullptr;
-  void* om8 = nullptr;     // e4m3 Omega^T, its scale plane and the gathered scales
-  void* osc = nullptr;
+  void* xb[8] = {};        // each pipelined mode's blocked copy (bf16 or e4m3) and its e4m3 scales
+  void* xs[8] = {};
+  void* oblk = nullptr;    // the current mode's blocked sketch: bf16, then e4m3 + scales
+  void* om8 = nullptr;
   void* oscl = nullptr;
-  void* xscl = nullptr;    // gathered scales of X for the current mode
   void* xt = nullptr;      // bf16, I_N x rows_pad: the last mode, transposed and zero-padded
   void* omegaT = nullptr;
   void* partial = nullptr;
@@ -310,18 +312,19 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
     const size_t rows = (size_t)(P.T / P.dims[P.N - 1]);
     b.xpad = ar.take(rows * P.in_pad * 2);
     if (P.need_xt16) b.xt = ar.take((size_t)P.dims[P.N - 1] * P.rows_pad * 2);
-    if (P.need_fp8) {
-      b.xp8 = ar.take(rows * P.in_pad);
-      b.sp8 = ar.take(rows * P.in_pad / 32);
-      b.xt8 = ar.take((size_t)P.dims[P.N - 1] * P.rows_pad);
-      b.st8 = ar.take((size_t)P.dims[P.N - 1] * P.rows_pad / 32);
-      b.om8 = ar.take((size_t)P.maxSJ);
-      b.osc = ar.take((size_t)P.maxSJ / 32 + 64);
-      b.oscl = ar.take((size_t)P.oscl_bytes);
-      b.xscl = ar.take((size_t)P.xscl_bytes);
+    for (int n = 0; n < P.N; ++n) {
+      const ModeGeom& g = P.m[n];
+      if (!g.pipe) continue;
+      b.xb[n] = ar.take(block_copy_bytes(g.nkt, g.I));
+      if (g.pelem == E_FP8) b.xs[n] = ar.take((size_t)g.nkt * block_rows(g.I) * 2);
+    }
+    if (P.oblk_bytes) b.oblk = ar.take((size_t)P.oblk_bytes);
+    if (P.need_fp8 && P.oblk_bytes) {
+      b.om8 = ar.take((size_t)P.oblk_bytes / 2);
+      b.oscl = ar.take((size_t)P.oblk_bytes / 32 + 256);    // 256 bytes per K tile
     }
   }
-  b.omegaT = ar.take((size_t)P.maxSJ * (P.need_pad ? 2 : es_g));   // the padded forms stage Omega in bf16
+  b.omegaT = ar.take((size_t)P.maxSJ * (P.need_pad ? 2 : es_g));   // the fallback of the mixed forms: bf16
   b.partial = ar.take(P.partial_bytes);
   b.C = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
   for (int n = 0; n < P.N; ++n) b.Qt[n] = (double*)ar.take((size_t)P.m[n].Sp * P.m[n].I * 8);
@@ -362,6 +365,31 @@ size_t plan_bytes(const Plan& P) {
   return ar.off + 256;
 }
 
+// The copies of X the mixed forms read, made once per decomposition: the
+// blocked copies of every pipelined mode (one pass over X for the leading
+// modes, which also writes the padded bf16 copy Xpad; a transposing pass for
+// the last), and Xpad / Xt by the plain padding pass where no blocked pass
+// writes them.
+rbki_status convert_input(const Plan& P, const Buffers& b, const void* X, hipStream_t st) {
+  const int64_t IN = P.dims[P.N - 1];
+  if (P.lead_pipe) {
+    bool want[8] = {};
+    void* outs[8] = {};
+    void* scs[8] = {};
+    for (int n = 0; n + 1 < P.N; ++n) {
+      want[n] = P.m[n].pipe;
+      outs[n] = b.xb[n];
+      scs[n] = b.xs[n];
+    }
+    HIPCHK(launch_block_copy_lead(P.xelem, P.need_fp8 ? E_FP8 : E_BF16, X, P.N, P.dims, want, outs, scs, b.xpad, st));
+  }
+  if (!P.lead_pipe || P.need_xt16)
+    HIPCHK(launch_pad_copies(P.xelem, X, P.T / IN, IN, P.lead_pipe ? nullptr : b.xpad, b.xt, st));
+  const ModeGeom& gl = P.m[P.N - 1];
+  if (gl.pipe) HIPCHK(launch_block_copy_last(P.xelem, gl.pelem, X, P.T / IN, IN, b.xb[P.N - 1], b.xs[P.N - 1], st));
+  return RBKI_OK;
+}
+
 // ------------------------------------------------------------------ one mode
 // Alg. 1 + Alg. 2 steps 3-5 for mode n.  Leaves the basis in b.Qt (Sp rows),
 // C Q in b.CQt, and (if with_factor) U^(n)T in b.Ut64[n].
@@ -375,52 +403,39 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
   double* Qt = b.Qt[n];
   // C -> b.C (I x I), W^T -> b.Yt (S x I)
   if (P.need_pad) {
-    // zero-padded operands: Xpad / Xp8 for the leading modes, Xt / Xt8 for the last
     int64_t A, Bp;
     padded_view(P, n, A, Bp);
-    const int64_t Jp = A * Bp;
     const bool last = n == P.N - 1;
-    const bool fp8 = P.need_fp8 && gram_pipe_ok(I, (int)S);
-    {
-      ProfScope ps("omega", st);
-      HIPCHK(launch_omega_pad(P.seed, n, S, g.J, g.B, P.dims[P.N - 1], Jp, b.omegaT, st));
-      if (fp8) {
-        HIPCHK(launch_quantize_rows_fp8(b.omegaT, S, Jp, b.om8, b.osc, st));
-        HIPCHK(launch_gather_scales(b.osc, 1, S, Jp, 64, b.oscl, st));
-      }
-    }
-    if (fp8) {
-      GramArgs ga = gram_plan_pipe(E_FP8, A, I, Bp, (int)S, cu_count());
-      const int64_t ipad = (int64_t)ga.nt * 256;
+    if (g.pipe) {
+      // the blocked copy of this mode's unfolding was made by convert_input;
+      // the blocked sketch
+      const int KT = g.pelem == E_FP8 ? 64 : 32;
+      const int64_t IN = P.dims[P.N - 1];
+      (void)last;
       {
         ProfScope ps("omega", st);
-        HIPCHK(launch_gather_scales(last ? b.st8 : b.sp8, A, I, Bp, ipad, b.xscl, st));
+        HIPCHK(launch_omega_block(P.seed, n, S, g.J, g.B, IN, g.nkt, KT, b.oblk, st));
+        if (g.pelem == E_FP8) HIPCHK(launch_quantize_omega(b.oblk, g.nkt, b.om8, b.oscl, st));
       }
-      ga.X = last ? b.xt8 : b.xp8;
-      ga.omegaT = b.om8;
-      ga.xexp = (const unsigned char*)b.xscl;
+      GramArgs ga = gram_plan_pipe(g.pelem, A, I, Bp, (int)S, cu_count());
+      ga.X = b.xb[n];
+      ga.omegaT = g.pelem == E_FP8 ? b.om8 : b.oblk;
+      ga.xexp = (const unsigned char*)b.xs[n];
       ga.xexp_om = (const unsigned char*)b.oscl;
       ga.partial = b.partial;
       {
         ProfScope ps("gram", st);
-        HIPCHK(launch_gram_pipe(E_FP8, ga, st));
-      }
-      HIPCHK(launch_gram_pipe_reduce(ga, b.C, b.Yt, st));
-    } else if (gram_pipe_ok(I, (int)S)) {
-      const void* xop = last ? b.xt : b.xpad;
-      GramArgs ga = gram_plan_pipe(E_BF16, A, I, Bp, (int)S, cu_count());
-      ga.X = xop;
-      ga.omegaT = b.omegaT;
-      ga.partial = b.partial;
-      {
-        ProfScope ps("gram", st);
-        HIPCHK(launch_gram_pipe(E_BF16, ga, st));
+        HIPCHK(launch_gram_pipe(g.pelem, ga, st));
       }
       HIPCHK(launch_gram_pipe_reduce(ga, b.C, b.Yt, st));
     } else {
-      const void* xop = last ? b.xt : b.xpad;
+      // small I or a sketch wider than 64: the bf16 kernel on the padded copies
+      {
+        ProfScope ps("omega", st);
+        HIPCHK(launch_omega_pad(P.seed, n, S, g.J, g.B, P.dims[P.N - 1], A * Bp, b.omegaT, st));
+      }
       GramArgs ga = gram_plan(E_BF16, A, I, Bp, (int)S, cu_count());
-      ga.X = xop;
+      ga.X = last ? b.xt : b.xpad;
       ga.omegaT = b.omegaT;
       ga.partial = b.partial;
       {
@@ -696,11 +711,8 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
   const void* xsrc = X;
   if (P.need_pad) {
     ProfScope ps("convert", st);
-    if (P.need_fp8)
-      HIPCHK(launch_pad_copies_fp8(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, b.xp8, b.sp8,
-                                   b.xt8, b.st8, st));
-    else
-      HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
+    s = convert_input(P, b, X, st);
+    if (s != RBKI_OK) return s;
   }
   HIPCHK(fill_zero(b.info, counters_bytes(P), st));
   s = run_mode(P, b, xsrc, mode, false, st);
@@ -766,11 +778,8 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   const void* xsrc = X;
   if (P.need_pad) {
     ProfScope ps("convert", st);
-    if (P.need_fp8)
-      HIPCHK(launch_pad_copies_fp8(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, b.xp8, b.sp8,
-                                   b.xt8, b.st8, st));
-    else
-      HIPCHK(launch_pad_copies(P.xelem, X, P.T / P.dims[P.N - 1], P.dims[P.N - 1], b.xpad, b.xt, st));
+    s = convert_input(P, b, X, st);
+    if (s != RBKI_OK) return s;
   }
   HIPCHK(fill_zero(b.info, counters_bytes(P), st));
   for (int n = 0; n < P.N; ++n) {

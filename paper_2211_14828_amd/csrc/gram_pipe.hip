@@ -2,19 +2,20 @@
 // step 2: W = X_(n) Omega^(n)), streamed through LDS by direct global->LDS
 // loads in a four-stage ring.
 //
-// Operands.  The products read zero-padded bf16 copies of the tensor, built
-// once per decomposition:
-//   * Xpad: X viewed as (T / I_N) rows of its last dimension I_N, each row
-//     padded with zeros to I_Npad (a multiple of 64).  Mode n < N-1 reads it
-//     as [A_n, I_n, Bp_n] with Bp_n = (B_n / I_N) I_Npad: row (a, i) is
-//     contiguous, and the padding adds zero columns to X_(n), which change
-//     neither C nor W.
-//   * Xt: the last mode, X_(N) stored as I_N rows of A_pad = (T / I_N)
-//     rounded up to a multiple of 64, zero-padded.
-//   * Omega^T in the same padded column layout (zero in padded columns).
-// Every K tile (32 columns) is therefore whole: no bounds checks, no masking.
-// Rows past I_n (the last row tile) and sketch rows past S read a clamped,
-// valid row; the outputs they produce are never reduced.
+// Operands.  For each mode the products read a K-blocked copy of the
+// mode's unfolding, built just before its Gram pass:
+//   * the columns of X_(n) are taken in the zero-padded order of the view
+//     [A_n, I_n, Bp_n], Bp_n = (B_n / I_N) I_Npad (I_Npad = I_N rounded up to
+//     64; the last mode: A = 1, Bp = T / I_N rounded up to 64).  Padding adds
+//     zero columns, which change neither C nor W;
+//   * K tile kt holds 64 bytes of every row (32 bf16 or 64 e4m3 values), and
+//     the copy is stored [kt][row][64 bytes] with the rows padded with zeros
+//     to whole 256-row tiles.  One wave's 1 KB load of 16 rows is then one
+//     contiguous block of whole cache lines (a row-major copy costs a 128-byte
+//     line for every 64-byte row chunk, about half the load throughput);
+//   * Omega^T in the same column order, blocked [kt][64 sketch rows][64
+//     bytes], rows past S zero.
+// Every K tile is therefore whole: no bounds checks, no masking.
 //
 // Tiles.  A workgroup (4 waves) owns one 256 x 256 lower-triangle tile of C
 // and a slice of the contraction (split-K).  Off-diagonal tiles give each
@@ -34,13 +35,19 @@
 // FP8 form.  The same kernel runs on e4m3 copies: a stage row then holds 64
 // values, one MFMA K step of 64 (block-scaled 32x32x64 f8f6f4).  Every run
 // of 32 values along a storage row has its own power-of-two (E8M0) scale,
-// chosen so that the run's largest magnitude maps to at most 448.  For each
-// mode the scales are gathered once into [K tile][row][2] order, so each
-// wave fetches the scales of 128 rows for a stage with one more 4-byte
-// direct-to-LDS load.
+// chosen so that the run's largest magnitude maps to at most 448.  The copy
+// stores the scales of a K tile and 256-row tile as [half][row % 32][row / 32]
+// (512 bytes; half: the first or second run of 32 of the 64-value row), the
+// sketch's as [half][row % 32][4] (rows 0..63: bytes 0, 1; 256 bytes).  A
+// lane's four fragments of a 128-row block then take their scales from one
+// 4-byte LDS read, held in one register: the MFMA's scale op_sel picks the
+// byte (measured on gfx950: op_sel k selects byte k).  Each wave fetches 256
+// bytes of scales for a stage with one more 4-byte direct-to-LDS load.
 //
 // Split-K partials (float32) are reduced in a fixed order in float64 by a
 // second kernel: results are deterministic.
+#include <type_traits>
+
 #include "rbki_kernels.h"
 #include "rbki_mma.h"
 #include "rbki_philox.h"
@@ -112,13 +119,12 @@ __device__ inline void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(15 | (7 << 4) |
 __device__ inline int swz(int r, int c) { return r * PROW + ((c ^ ((r >> 2) & 3)) << 4); }
 
 struct PipeCtx {
-  const char* X;          // padded operand view [A, I, Bp] (bytes)
-  const char* Om;         // padded Omega^T, S rows of Jp (bytes)
-  int64_t IBp, Bp;        // slab stride I * Bp and row pitch, in elements
-  int64_t na, nk0;        // next K tile to load: slab a, first column k0 (elements)
+  const char* xk;         // next K tile of the blocked operand
+  const char* ok;         // next K tile of the blocked sketch
+  int64_t xstep, ostep;   // bytes per K tile of each
   int64_t left;           // K tiles of this split not yet loaded (the last one is reloaded after)
   int64_t kt;             // global index of the next K tile (scale lookup)
-  int64_t offa[4], offb[4];   // per-lane byte offsets of this lane's rows and chunks
+  int offa[4], offb[4];   // per-lane byte offsets of this lane's rows and chunks within a K tile
   const unsigned char* sc;    // fp8: this lane's scale source at K tile 0
   int64_t sc_step;            // fp8: bytes per K tile of that source
   int sc_dst;                 // fp8: 0..3 = A scales low/high half, B scales low/high half
@@ -130,15 +136,16 @@ template <int E> struct PipeElem {
   static constexpr int KT = PROW / ES;               // values per stage row
 };
 
-// Advance the next K tile (a, k0) by one tile, holding at the split's last.
-template <int E>
+// Advance the next K tile by one, holding at the split's last.  Branch-free:
+// a branch would split the K step into basic blocks, and the compiler then
+// sinks the MFMAs of several steps past their barriers into one block (all
+// their fragments live at once, and no overlap with the loads).
 __device__ __attribute__((always_inline)) inline void advance(PipeCtx& c) {
-  if (c.left > 1) {
-    c.nk0 += PipeElem<E>::KT;
-    if (c.nk0 == c.Bp) { c.nk0 = 0; ++c.na; }
-    ++c.kt;
-    --c.left;
-  }
+  const int64_t d = c.left > 1 ? 1 : 0;
+  c.xk += d * c.xstep;
+  c.ok += d * c.ostep;
+  c.kt += d;
+  c.left -= d;
 }
 
 // Issue the loads of the next K tile into stage ST: A rows r0..r0+255 (4
@@ -148,26 +155,24 @@ __device__ __attribute__((always_inline)) inline void advance(PipeCtx& c) {
 // l % 4 of that row.
 template <int E, bool DIAG, int ST>
 __device__ __attribute__((always_inline)) inline void issue(PipeCtx& c) {
-  constexpr int ES = PipeElem<E>::ES;
-  const char* xa = c.X + (c.na * c.IBp + c.nk0) * ES;
 #pragma unroll
   for (int j = 0; j < 4; ++j)
-    __builtin_amdgcn_global_load_lds((const void*)(xa + c.offa[j]),
+    __builtin_amdgcn_global_load_lds((const void*)(c.xk + c.offa[j]),
                                      (lds_void*)(stage_a<ST>() + (j * 4 + c.wave) * 1024), 16, 0, 0);
   if (DIAG) {
-    __builtin_amdgcn_global_load_lds((const void*)(c.Om + (c.na * c.Bp + c.nk0) * ES + c.offb[0]),
-                                     (lds_void*)(stage_b<ST>() + c.wave * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(c.ok + c.offb[0]), (lds_void*)(stage_b<ST>() + c.wave * 1024),
+                                     16, 0, 0);
   } else {
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      __builtin_amdgcn_global_load_lds((const void*)(xa + c.offb[j]),
+      __builtin_amdgcn_global_load_lds((const void*)(c.xk + c.offb[j]),
                                        (lds_void*)(stage_b<ST>() + (j * 4 + c.wave) * 1024), 16, 0, 0);
   }
   if (E == E_FP8) {
     unsigned char* dst = (c.sc_dst < 2 ? stage_sa<ST>() : stage_sb<ST>()) + (c.sc_dst & 1) * 256;
     __builtin_amdgcn_global_load_lds((const void*)(c.sc + c.kt * c.sc_step), (lds_void*)dst, 4, 0, 0);
   }
-  advance<E>(c);
+  advance(c);
 }
 
 // fp8 operand of the block-scaled 32x32x64 MFMA (layout measured on gfx950):
@@ -183,111 +188,221 @@ __device__ inline i32x8_t frag8(const char* l, int row, int half) {
   return u.v;
 }
 
-// Multiply the K tile held in stage ST.
-//   C waves (WW false): acc[m][n] += A(ra + 32 m) . B(rb + 32 n)
-//   sketch wave (WW true): acc[m][n] += A(128 (n / 2) + 32 m) . Omega(32 (n % 2))
-// bf16: two MFMA K steps of 16 per stage; fp8: one block-scaled K step of 64
-// (operands as frag8 describes).
+// Operand fragments of one K tile, held in registers.
+//   C waves (WW false): A rows ra + 32 m and B rows rb + 32 n, m, n < 4
+//   sketch wave (WW true): A rows 32 m, m < 8, and sketch rows 32 n, n < 2
+// bf16 keeps the two MFMA K steps of 16 of a stage; fp8 one block-scaled K
+// step of 64 with the E8M0 scale of each fragment's lane half.
+template <int E, bool WW> struct Frags;
+template <> struct Frags<E_FP8, false> { i32x8_t a[4], b[4]; int ea, eb; };   // scales: byte m of ea / eb
+template <> struct Frags<E_FP8, true> { i32x8_t a[8], b[2]; int ea[2], eb; };
+template <> struct Frags<E_BF16, false> { bf16x8_t a[2][4], b[2][4]; };
+template <> struct Frags<E_BF16, true> { bf16x8_t a[2][8], b[2][2]; };
+
+// The packed scales of the fp8 fragments of the K tile in stage ST.
+template <bool DIAG, bool WW, int ST>
+__device__ __attribute__((always_inline)) inline void load_scales(Frags<E_FP8, WW>& f, int lane, int ra, int rb) {
+  const int half = lane >> 5, lr = lane & 31;
+  const int sl = (half * 32 + lr) * 8;             // this lane's 8 bytes of a 256-row tile
+  if constexpr (WW) {
+    f.ea[0] = *(const int*)(stage_sa<ST>() + sl);
+    f.ea[1] = *(const int*)(stage_sa<ST>() + sl + 4);
+    f.eb = *(const int*)(stage_sb<ST>() + (half * 32 + lr) * 4);
+  } else {
+    f.ea = *(const int*)(stage_sa<ST>() + sl + (ra >> 5));
+    f.eb = *(const int*)((DIAG ? stage_sa<ST>() : stage_sb<ST>()) + sl + (rb >> 5));
+  }
+}
+
+// Read the fragments of the K tile held in stage ST (fp8 operands as frag8
+// describes).  Fragment rows are r0 + 32 m + (lane % 32) with r0 a multiple of
+// 32, so the swizzle depends on the lane only and every address is a per-lane
+// base plus a constant.
 template <int E, bool DIAG, bool WW, int ST>
-__device__ __attribute__((always_inline)) inline void compute(f32x16_t (&acc)[4][4], int lane, int ra, int rb) {
+__device__ __attribute__((always_inline)) inline void load_frags(Frags<E, WW>& f, int lane, int ra, int rb) {
   const char* la = stage_a<ST>();
   const char* lb = (DIAG && !WW) ? stage_a<ST>() : stage_b<ST>();
   const int half = lane >> 5, lr = lane & 31;
+  constexpr int NA = WW ? 8 : 4, NB = WW ? 2 : 4;
+  const int a0 = WW ? 0 : ra, b0 = WW ? 0 : rb;
+  const int sw = (lr >> 2) & 3;
+  const char* pa = la + (a0 + lr) * PROW;
+  const char* pb = lb + (b0 + lr) * PROW;
   if constexpr (E == E_FP8) {
-    const unsigned char* sa = stage_sa<ST>();
-    const unsigned char* sb = (DIAG && !WW) ? stage_sa<ST>() : stage_sb<ST>();
-    if (WW) {
-      i32x8_t av[8], bv[2];
-      int ea[8], eb[2];
+    const int c0 = (half ^ sw) << 4, c1 = ((2 + half) ^ sw) << 4;
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        av[m] = frag8(la, m * 32 + lr, half);
-        ea[m] = sa[(m * 32 + lr) * 2 + half];
-      }
-#pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        bv[n] = frag8(lb, n * 32 + lr, half);
-        eb[n] = sb[(n * 32 + lr) * 2 + half];
-      }
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-              av[m + 4 * (n >> 1)], bv[n & 1], acc[m][n], 0, 0, 0, ea[m + 4 * (n >> 1)], 0, eb[n & 1]);
-    } else {
-      i32x8_t av[4], bv[4];
-      int ea[4], eb[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        av[m] = frag8(la, ra + m * 32 + lr, half);
-        bv[m] = frag8(lb, rb + m * 32 + lr, half);
-        ea[m] = sa[(ra + m * 32 + lr) * 2 + half];
-        eb[m] = sb[(rb + m * 32 + lr) * 2 + half];
-      }
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[m], bv[n], acc[m][n], 0, 0, 0, ea[m], 0,
-                                                                      eb[n]);
+    for (int m = 0; m < NA; ++m) {
+      union { i32x8_t v; uint4 q[2]; } u;
+      u.q[0] = *(const uint4*)(pa + m * 32 * PROW + c0);
+      u.q[1] = *(const uint4*)(pa + m * 32 * PROW + c1);
+      f.a[m] = u.v;
     }
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      union { i32x8_t v; uint4 q[2]; } u;
+      u.q[0] = *(const uint4*)(pb + n * 32 * PROW + c0);
+      u.q[1] = *(const uint4*)(pb + n * 32 * PROW + c1);
+      f.b[n] = u.v;
+    }
+    load_scales<DIAG, WW, ST>(f, lane, ra, rb);
   } else {
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      const int ch = 2 * t + half;
-      if (WW) {
-        bf16x8_t av[8], bv[2];
+      const int ch = ((2 * t + half) ^ sw) << 4;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) av[m] = *(const bf16x8_t*)(la + swz(m * 32 + lr, ch));
+      for (int m = 0; m < NA; ++m) f.a[t][m] = *(const bf16x8_t*)(pa + m * 32 * PROW + ch);
 #pragma unroll
-        for (int n = 0; n < 2; ++n) bv[n] = *(const bf16x8_t*)(lb + swz(n * 32 + lr, ch));
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int n = 0; n < 4; ++n)
-            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m + 4 * (n >> 1)], bv[n & 1], acc[m][n], 0, 0, 0);
-      } else {
-        bf16x8_t av[4], bv[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          av[m] = *(const bf16x8_t*)(la + swz(ra + m * 32 + lr, ch));
-          bv[m] = *(const bf16x8_t*)(lb + swz(rb + m * 32 + lr, ch));
-        }
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-#pragma unroll
-          for (int n = 0; n < 4; ++n)
-            acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[m], bv[n], acc[m][n], 0, 0, 0);
-      }
+      for (int n = 0; n < NB; ++n) f.b[t][n] = *(const bf16x8_t*)(pb + n * 32 * PROW + ch);
     }
   }
 }
 
-// One K step of the ring: wait for stage ST, barrier, refill the stage that
-// was read in the previous step, multiply stage ST if this step is real.
-template <int E, bool DIAG, bool WW, int ST>
-__device__ __attribute__((always_inline)) inline void ring_step(PipeCtx& c, f32x16_t (&acc)[4][4], bool real,
+// Compile-time loop: f(integral_constant<int, T>) for T = B .. N-1.
+template <int B, int N> struct Unroll {
+  template <class F> __device__ __attribute__((always_inline)) static void run(F&& f) {
+    if constexpr (B < N) {
+      f(std::integral_constant<int, B>{});
+      Unroll<B + 1, N>::run(f);
+    }
+  }
+};
+
+// One DMA of the loads issue() makes for stage ST (q < loads per wave).
+template <int E, bool DIAG, int ST, int q>
+__device__ __attribute__((always_inline)) inline void dma_one(PipeCtx& c) {
+  if constexpr (q < 4) {
+    __builtin_amdgcn_global_load_lds((const void*)(c.xk + c.offa[q]),
+                                     (lds_void*)(stage_a<ST>() + (q * 4 + c.wave) * 1024), 16, 0, 0);
+  } else if constexpr (DIAG ? q == 4 : q < 8) {
+    if constexpr (DIAG)
+      __builtin_amdgcn_global_load_lds((const void*)(c.ok + c.offb[0]), (lds_void*)(stage_b<ST>() + c.wave * 1024),
+                                       16, 0, 0);
+    else
+      __builtin_amdgcn_global_load_lds((const void*)(c.xk + c.offb[DIAG ? 0 : q - 4]),
+                                       (lds_void*)(stage_b<ST>() + ((DIAG ? 0 : q - 4) * 4 + c.wave) * 1024), 16, 0, 0);
+  } else if constexpr (E == E_FP8) {
+    unsigned char* dst = (c.sc_dst < 2 ? stage_sa<ST>() : stage_sb<ST>()) + (c.sc_dst & 1) * 256;
+    __builtin_amdgcn_global_load_lds((const void*)(c.sc + c.kt * c.sc_step), (lds_void*)dst, 4, 0, 0);
+  }
+}
+
+// Fragment f (< NA + NB) of the K tile in stage ST (load_frags, one at a time).
+template <int E, bool DIAG, bool WW, int ST, int f>
+__device__ __attribute__((always_inline)) inline void frag_one(Frags<E, WW>& fr, int lane, int ra, int rb) {
+  constexpr int NA = WW ? 8 : 4;
+  const int half = lane >> 5, lr = lane & 31;
+  const int sw = (lr >> 2) & 3;
+  constexpr bool isa = f < NA;
+  constexpr int idx = isa ? f : f - NA;
+  const int r0 = isa ? (WW ? 0 : ra) : (WW ? 0 : rb);
+  const char* base = (isa || (DIAG && !WW)) ? stage_a<ST>() : stage_b<ST>();
+  const char* pr = base + (r0 + idx * 32 + lr) * PROW;
+  if constexpr (E == E_FP8) {
+    union { i32x8_t v; uint4 q[2]; } u;
+    u.q[0] = *(const uint4*)(pr + ((half ^ sw) << 4));
+    u.q[1] = *(const uint4*)(pr + (((2 + half) ^ sw) << 4));
+    if constexpr (isa) fr.a[idx] = u.v;
+    else fr.b[idx] = u.v;
+    if constexpr (f == NA) load_scales<DIAG, WW, ST>(fr, lane, ra, rb);   // with the first fragment read
+  } else {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const bf16x8_t v = *(const bf16x8_t*)(pr + (((2 * t + half) ^ sw) << 4));
+      if constexpr (isa) fr.a[t][idx] = v;
+      else fr.b[t][idx] = v;
+    }
+  }
+}
+
+// MFMA tile t (< 16) of one K tile: (m, n) = (t / 4, t % 4), as in mma().
+template <int E, bool WW, int t>
+__device__ __attribute__((always_inline)) inline void mma_one(f32x16_t (&acc)[4][4], const Frags<E, WW>& f) {
+  constexpr int m = t >> 2, n = t & 3;
+  constexpr int ia = WW ? m + 4 * (n >> 1) : m, ib = WW ? (n & 1) : n;
+  if constexpr (E == E_FP8) {
+    int ea;
+    if constexpr (WW) ea = f.ea[ia >> 2];
+    else ea = f.ea;
+    acc[m][n] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(f.a[ia], f.b[ib], acc[m][n], 0, 0, ia & 3, ea, ib & 3,
+                                                                f.eb);
+  } else {
+    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[0][ia], f.b[0][ib], acc[m][n], 0, 0, 0);
+    acc[m][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.a[1][ia], f.b[1][ib], acc[m][n], 0, 0, 0);
+  }
+}
+
+// Which fragment of the next tile is read after MFMA slot t (-1: none).  MFMAs
+// run m-major (t = 4 m + n), so the current tile's A fragments die one by one
+// (C waves: a[m] after slot 4 m + 3; the sketch wave: a[m] after 4 m + 1 and
+// a[m + 4] after 4 m + 3) and the next tile's A fragments are read right
+// after, into the freed registers; its B fragments (live to the end of the
+// step) are read first.  Fragment index: a[i] = i, b[j] = NA + j.
+template <bool WW> __device__ constexpr int next_frag_at(int t) {
+  if (WW) {
+    constexpr int at[16] = {8, 9, 0, -1, 4, -1, 1, -1, 5, -1, 2, -1, 6, 3, 7, -1};
+    return at[t];
+  } else {
+    constexpr int at[16] = {4, 5, 6, 7, 0, -1, -1, -1, 1, -1, -1, -1, 2, 3, -1, -1};
+    return at[t];
+  }
+}
+
+// K step k of the ring (ST = k mod 4).  On entry the fragments of tile k are
+// in `cur` and tiles k+1..k+3 are loaded or in flight.  Wait for tile k+1,
+// barrier (every wave has read tile k into registers and sees tile k+1),
+// then multiply tile k while refilling stage ST with tile k+4 and reading
+// tile k+1 into `nxt`.  A global->LDS load holds the wave's issue until the
+// address unit accepts it, so the loads and the LDS reads are interleaved one
+// by one with the MFMAs (scheduling barriers keep the order): the address
+// unit works while the matrix cores run, and the next tile's LDS reads are
+// in flight under this tile's MFMAs.  REAL false (past the end of the split)
+// skips the MFMAs.
+template <int E, bool DIAG, bool WW, int ST, bool REAL>
+__device__ __attribute__((always_inline)) inline void ring_step(PipeCtx& c, f32x16_t (&acc)[4][4],
+                                                                const Frags<E, WW>& cur, Frags<E, WW>& nxt,
                                                                 int lane, int ra, int rb) {
   constexpr int PER = (DIAG ? 5 : 8) + (E == E_FP8 ? 1 : 0);   // loads per wave per stage
   wait_vm<2 * PER>();
   __builtin_amdgcn_s_barrier();
-  issue<E, DIAG, (ST + 3) & 3>(c);
-  if (real) compute<E, DIAG, WW, ST>(acc, lane, ra, rb);
+  Unroll<0, 16>::run([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    constexpr int f = next_frag_at<WW>(t);
+    if constexpr (REAL) mma_one<E, WW, t>(acc, cur);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (t < PER) dma_one<E, DIAG, ST, t>(c);
+    if constexpr (f >= 0) frag_one<E, DIAG, WW, (ST + 1) & 3, f>(nxt, lane, ra, rb);
+    __builtin_amdgcn_sched_barrier(0);
+  });
+  advance(c);
   wait_lgkm0();
 }
 
 template <int E, bool DIAG, bool WW>
 __device__ __attribute__((always_inline)) inline void ring(PipeCtx& c, f32x16_t (&acc)[4][4], int64_t nk, int lane,
                                                            int ra, int rb) {
+  constexpr int PER = (DIAG ? 5 : 8) + (E == E_FP8 ? 1 : 0);
   issue<E, DIAG, 0>(c);
   issue<E, DIAG, 1>(c);
   issue<E, DIAG, 2>(c);
-  for (int64_t k = 0; k < nk; k += 4) {
-    ring_step<E, DIAG, WW, 0>(c, acc, true, lane, ra, rb);
-    ring_step<E, DIAG, WW, 1>(c, acc, k + 1 < nk, lane, ra, rb);
-    ring_step<E, DIAG, WW, 2>(c, acc, k + 2 < nk, lane, ra, rb);
-    ring_step<E, DIAG, WW, 3>(c, acc, k + 3 < nk, lane, ra, rb);
+  issue<E, DIAG, 3>(c);
+  Frags<E, WW> f0, f1;
+  wait_vm<3 * PER>();
+  __builtin_amdgcn_s_barrier();
+  load_frags<E, DIAG, WW, 0>(f0, lane, ra, rb);
+  wait_lgkm0();
+  int64_t k = 0;
+  for (; k + 4 <= nk; k += 4) {
+    ring_step<E, DIAG, WW, 0, true>(c, acc, f0, f1, lane, ra, rb);
+    ring_step<E, DIAG, WW, 1, true>(c, acc, f1, f0, lane, ra, rb);
+    ring_step<E, DIAG, WW, 2, true>(c, acc, f0, f1, lane, ra, rb);
+    ring_step<E, DIAG, WW, 3, true>(c, acc, f1, f0, lane, ra, rb);
+  }
+  if (k < nk) {                                   // 1..3 tiles left
+    ring_step<E, DIAG, WW, 0, true>(c, acc, f0, f1, lane, ra, rb);
+    if (k + 1 < nk) ring_step<E, DIAG, WW, 1, true>(c, acc, f1, f0, lane, ra, rb);
+    else ring_step<E, DIAG, WW, 1, false>(c, acc, f1, f0, lane, ra, rb);
+    if (k + 2 < nk) ring_step<E, DIAG, WW, 2, true>(c, acc, f0, f1, lane, ra, rb);
+    else ring_step<E, DIAG, WW, 2, false>(c, acc, f0, f1, lane, ra, rb);
   }
   // every load must have landed before the workgroup's LDS is released
   wait_vm<0>();
@@ -296,51 +411,48 @@ __device__ __attribute__((always_inline)) inline void ring(PipeCtx& c, f32x16_t 
 
 template <int E, bool DIAG>
 __device__ __attribute__((always_inline)) inline void run_tile(const GramArgs& g, int split, int ti, int tj) {
-  constexpr int ES = PipeElem<E>::ES;
   PipeCtx c;
-  c.X = (const char*)g.X;
-  c.Om = (const char*)g.omegaT;
-  c.IBp = g.I * g.B;
-  c.Bp = g.B;
   c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t kt0 = (int64_t)split * g.nkt / g.splits;
   const int64_t kt1 = (int64_t)(split + 1) * g.nkt / g.splits;     // kt1 > kt0 (splits <= nkt)
-  c.na = kt0 / g.nbt;
-  c.nk0 = (kt0 - c.na * g.nbt) * PipeElem<E>::KT;
+  const int64_t ipad = (int64_t)g.nt * PT;                          // rows of a K tile of the operand
+  c.xstep = ipad * PROW;
+  c.ostep = (int64_t)PW * PROW;
+  c.xk = (const char*)g.X + kt0 * c.xstep;
+  c.ok = (const char*)g.omegaT + kt0 * c.ostep;
   c.left = kt1 - kt0;
   c.kt = kt0;
-  const int64_t r0 = (int64_t)ti * PT, c0 = (int64_t)tj * PT;
+  const int r0 = ti * PT, c0 = tj * PT;
   {
+    // rows past I and sketch rows past S are zero in the blocked copies
     const int rl = lane >> 2, p = lane & 3;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = (j * 4 + c.wave) * 16 + rl;
       const int ch = p ^ ((row >> 2) & 3);
-      int64_t ra_ = r0 + row, rb_ = c0 + row;
-      ra_ = ra_ < g.I ? ra_ : g.I - 1;        // rows past I: a valid row, output discarded
-      rb_ = rb_ < g.I ? rb_ : g.I - 1;
-      c.offa[j] = ra_ * g.B * ES + ch * 16;
-      c.offb[j] = rb_ * g.B * ES + ch * 16;
+      c.offa[j] = (r0 + row) * PROW + ch * 16;
+      c.offb[j] = (c0 + row) * PROW + ch * 16;
     }
     if (DIAG) {
       const int row = c.wave * 16 + rl;       // sketch row 0..63
-      const int sr = row < g.S ? row : g.S - 1;
-      c.offb[0] = (int64_t)sr * g.J * ES + (p ^ ((row >> 2) & 3)) * 16;
+      c.offb[0] = row * PROW + (p ^ ((row >> 2) & 3)) * 16;
     }
     if (E == E_FP8) {
       // scales: [K tile][Ipad rows][2] for X, [K tile][64][2] for Omega; a lane
       // fetches 4 bytes = the two runs of two consecutive rows
-      const int64_t ipad = (int64_t)g.nt * PT;
+      // per K tile: 512 bytes per 256-row tile of the operand, 256 for the
+      // sketch; waves 0, 1 fetch the A tile's, waves 2, 3 the B tile's (or,
+      // in a diagonal tile, wave 2 the sketch's and wave 3 the same bytes
+      // again into an unused half, so that every wave issues the same loads)
       if (DIAG && c.wave >= 2) {
-        const int l = lane < 32 ? lane : 31;
-        c.sc = g.xexp_om + 4 * l;
-        c.sc_step = 64 * 2;
-        c.sc_dst = c.wave == 2 ? 2 : 3;       // wave 3 reloads the same bytes into an unused half
+        c.sc = g.xexp_om + 4 * lane;
+        c.sc_step = 256;
+        c.sc_dst = c.wave == 2 ? 2 : 3;
       } else {
-        const int64_t base = (c.wave < 2 ? r0 : c0) + (c.wave & 1) * 128 + 2 * lane;
-        c.sc = g.xexp + 2 * base;
-        c.sc_step = ipad * 2;
+        const int tile = c.wave < 2 ? ti : tj;
+        c.sc = g.xexp + (int64_t)tile * 512 + (c.wave & 1) * 256 + 4 * lane;
+        c.sc_step = (int64_t)g.nt * 512;
         c.sc_dst = c.wave;
       }
     }
@@ -465,18 +577,20 @@ __global__ void gram_pipe_reduce_kernel(GramArgs g, double* C, double* Wt) {
   }
 }
 
-// Omega^T (S x J) of one mode in the padded column layout (S x Jp): the
-// value of stream index L = s J + j goes to column jp(j); padded columns
-// must be zero beforehand.  B = 1: jp = j.  B > 1: j = a B + b with
-// b = bh I_N + bl, jp = a Bp + bh I_Npad + bl.
+// Omega^T (S x J) of one mode, blocked: the value of stream index L = s J + j
+// goes to padded column jp(j), stored at [jp / KT][s][jp % KT] (KT values per
+// 64 sketch rows of a K tile); padded columns and rows s >= S must be zero
+// beforehand.  B = 1: jp = j.  B > 1: j = a B + b with b = bh I_N + bl,
+// jp = a Bp + bh I_Npad + bl.
 // Index arithmetic in 32 bits when every index fits (the common case), else 64.
 template <class IT>
-__global__ void omega_pad_kernel(uint64_t seed, uint32_t mode, int64_t S, int64_t J_, int64_t B_, int64_t IN_,
-                                 int64_t INp_, int64_t Jp, bf16_t* out) {
+__global__ void omega_block_kernel(uint64_t seed, uint32_t mode, int64_t S, int64_t J_, int64_t B_, int64_t IN_,
+                                   int64_t INp_, int KT, bf16_t* out) {
   const IT J = (IT)J_, B = (IT)B_, IN = (IT)IN_, INp = (IT)INp_;
   const int64_t total = S * J_;
   const int64_t npairs = (total + 1) / 2;
   const IT Bp = B > 1 ? (B / IN) * INp : 1;
+  const IT kt_sz = (IT)KT;
   for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < npairs;
        m += (int64_t)gridDim.x * blockDim.x) {
     float z[2];
@@ -493,7 +607,8 @@ __global__ void omega_pad_kernel(uint64_t seed, uint32_t mode, int64_t S, int64_
         const IT bh = b / IN, bl = b - bh * IN;
         jp = a * Bp + bh * INp + bl;
       }
-      out[(int64_t)sv * Jp + jp] = f32_to_bf16(z[h]);
+      const IT kt = jp / kt_sz, kk = jp - kt * kt_sz;
+      out[((int64_t)kt * PW + sv) * KT + kk] = f32_to_bf16(z[h]);
     }
   }
 }
@@ -551,20 +666,50 @@ __device__ inline uint32_t pack_e4m3(const float* v, int sc) {
   return w;
 }
 
+// Four values X[off .. off+3] as float; values at or past `avail` (the
+// elements left in the row) are zero.  vec: X and the row length are such
+// that every 4-aligned offset is 4-element aligned (float4 / 8-byte loads).
+template <class T>
+__device__ inline void load4(const T* X, int64_t off, int64_t avail, bool vec, float* v) {
+  const T* src = X + off;
+  if (vec && avail >= 4) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 f = *(const float4*)src;
+      v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+    } else if constexpr (sizeof(T) == 2) {
+      const uint2 h = *(const uint2*)src;
+      v[0] = bf16_to_f32((bf16_t)(h.x & 0xFFFF)); v[1] = bf16_to_f32((bf16_t)(h.x >> 16));
+      v[2] = bf16_to_f32((bf16_t)(h.y & 0xFFFF)); v[3] = bf16_to_f32((bf16_t)(h.y >> 16));
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = (float)src[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (k < avail) {
+        if constexpr (sizeof(T) == 2) v[k] = bf16_to_f32(((const bf16_t*)src)[k]);
+        else v[k] = (float)src[k];
+      } else {
+        v[k] = 0.f;
+      }
+    }
+  }
+}
+
 __device__ inline uint2 pack_bf16(const float* v) {
   return make_uint2((uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16),
                     (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16));
 }
 
-// Padded copies of X viewed as R rows of length L (R = T / I_N, L = I_N), in
-// bf16 and / or e4m3 with per-32 scales, any output may be null:
-//   Xpad, Xp8 (+ Sp): R x Lp, zero padding;  Xt, Xt8 (+ St): L x Rp.
-// 64 x 64 tiles through LDS; a thread handles 4 consecutive values (16 per
-// tile row), so a run of 32 is 8 lanes of one wave.
+// Padded bf16 copies of X viewed as R rows of length L (R = T / I_N,
+// L = I_N), either may be null: Xpad R x Lp (the first mode product reads it,
+// and the bf16 Gram fallback of the leading modes), Xt L x Rp (the bf16 Gram
+// fallback of the last mode); zero padding.  64 x 64 tiles through LDS; a
+// thread handles 4 consecutive values.
 template <class T>
 __global__ void __launch_bounds__(256) pad_copies_kernel(const T* X, int64_t R, int64_t L, bool vec, bf16_t* Xpad,
-                                                         int64_t Lp, bf16_t* Xt, int64_t Rp, fp8_t* Xp8,
-                                                         unsigned char* Sp, fp8_t* Xt8, unsigned char* St) {
+                                                         int64_t Lp, bf16_t* Xt, int64_t Rp) {
   __shared__ float tile[64][65];
   const int64_t tl = Lp / 64;
   const int64_t br = blockIdx.x / tl, bl = blockIdx.x - br * tl;
@@ -575,43 +720,12 @@ __global__ void __launch_bounds__(256) pad_copies_kernel(const T* X, int64_t R, 
     const int y = pass * 16 + (t >> 4);
     const int64_t r = r0 + y, l = l0 + q4;
     float v[4] = {0.f, 0.f, 0.f, 0.f};
-    if (r < R) {
-      const T* src = X + r * L + l;
-      if (vec && l + 3 < L) {
-        if constexpr (sizeof(T) == 4) {
-          const float4 f = *(const float4*)src;
-          v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
-        } else if constexpr (sizeof(T) == 2) {
-          const uint2 h = *(const uint2*)src;
-          v[0] = bf16_to_f32((bf16_t)(h.x & 0xFFFF)); v[1] = bf16_to_f32((bf16_t)(h.x >> 16));
-          v[2] = bf16_to_f32((bf16_t)(h.y & 0xFFFF)); v[3] = bf16_to_f32((bf16_t)(h.y >> 16));
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) v[k] = (float)src[k];
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (l + k < L) {
-            if constexpr (sizeof(T) == 2) v[k] = bf16_to_f32(((const bf16_t*)src)[k]);
-            else v[k] = (float)src[k];
-          }
-      }
-    }
+    if (r < R) load4(X, r * L + l, L - l, vec, v);
 #pragma unroll
     for (int k = 0; k < 4; ++k) tile[y][q4 + k] = v[k];
-    // the run's scale: all lanes take part (rows past R hold zeros)
-    int sc = 0;
-    if (Xp8) sc = e8m0_fast(group8_max(fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])))));
-    if (r < R) {
-      if (Xpad) *(uint2*)(Xpad + r * Lp + l) = pack_bf16(v);
-      if (Xp8) {
-        *(uint32_t*)(Xp8 + r * Lp + l) = pack_e4m3(v, sc);
-        if ((t & 7) == 0) Sp[r * (Lp / 32) + (l >> 5)] = (unsigned char)sc;
-      }
-    }
+    if (r < R && Xpad) *(uint2*)(Xpad + r * Lp + l) = pack_bf16(v);
   }
-  if (!Xt && !Xt8) return;
+  if (!Xt) return;
   __syncthreads();
 #pragma unroll
   for (int pass = 0; pass < 4; ++pass) {
@@ -620,14 +734,172 @@ __global__ void __launch_bounds__(256) pad_copies_kernel(const T* X, int64_t R, 
     float v[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] = tile[q4 + k][y];
-    int sc = 0;
-    if (Xt8) sc = e8m0_fast(group8_max(fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])))));
-    if (l < L) {
-      if (Xt) *(uint2*)(Xt + l * Rp + r) = pack_bf16(v);
-      if (Xt8) {
-        *(uint32_t*)(Xt8 + l * Rp + r) = pack_e4m3(v, sc);
-        if ((t & 7) == 0) St[l * (Rp / 32) + (r >> 5)] = (unsigned char)sc;
-      }
+    if (l < L) *(uint2*)(Xt + l * Rp + r) = pack_bf16(v);
+  }
+}
+
+// Position of the scale of run h of row `rowid` (= K tile x rows + row, rows a
+// multiple of 256) in the operand's scale layout [K tile][256-row tile][h]
+// [row % 32][row / 32 within the tile].
+__device__ inline int64_t scale_pos(int64_t rowid, int h) {
+  const int rr = (int)(rowid & 255);
+  return ((rowid >> 8) * 2 + h) * 256 + (rr & 31) * 8 + (rr >> 5);
+}
+
+// 16 output bytes of a blocked copy: VPC values (16 e4m3 or 8 bf16), for
+// e4m3 with the scale of its run of 32 (the lane and its neighbour lane^1
+// hold the two halves of a run).  Returns the scale byte (e4m3) or 0.
+template <int E>
+__device__ inline int store_chunk(const float* v, char* dst, bool store = true) {
+  if constexpr (E == E_FP8) {
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m = fmaxf(m, fabsf(v[k]));
+    m = fmaxf(m, __shfl_xor(m, 1, 64));
+    const int sc = e8m0_fast(m);
+    uint4 w;
+    w.x = pack_e4m3(v, sc);
+    w.y = pack_e4m3(v + 4, sc);
+    w.z = pack_e4m3(v + 8, sc);
+    w.w = pack_e4m3(v + 12, sc);
+    if (store) *(uint4*)dst = w;
+    return sc;
+  } else {
+    const uint2 lo = pack_bf16(v), hi = pack_bf16(v + 4);
+    if (store) *(uint4*)dst = make_uint4(lo.x, lo.y, hi.x, hi.y);
+    return 0;
+  }
+}
+
+// Blocked copies of X_(n) for the leading modes n < N-1, one pass over X.
+// X is read as R = T / I_N rows r of its last dimension; row r of mode n's
+// view [A_n, I_n, B_n] is (a, i, bh) with r = (a I_n + i) Bh_n + bh, Bh_n =
+// B_n / I_N, and padded column b' = bh I_Npad + c holds X[r][c] (zero for
+// c >= I_N).  Copy n is [kt][i][64 bytes] with kt = a (Bh_n I_Npad / KT) +
+// b' / KT, rows padded to ipad_n (the padding rows are zeroed separately);
+// e4m3 scales in the layout scale_pos describes.  xpad (nullable): the
+// row-major padded bf16 copy.  One thread per VPC values of a row (16 e4m3
+// or 8 bf16): neighbouring threads write neighbouring 16-byte chunks of
+// every copy.
+struct LeadModes {
+  int n;
+  int64_t I[7], Bh[7], ipad[7], nbt[7];
+  char* out[7];
+  unsigned char* sc[7];
+};
+
+template <class T, int E, class IT>
+__global__ void __launch_bounds__(256) block_copy_lead_kernel(const T* X, int64_t H_, int64_t L_, int64_t IN_,
+                                                              int64_t INp_, bool vec, LeadModes lm, bf16_t* xpad) {
+  // rows r = h L + l (L: the last leading dimension).  A wave takes 4 x 4
+  // rows (h, l) and one K-tile-wide column chunk: lane = 16 hh + 4 ll + q.
+  // Mode 0's copy (rows along h) and mode N-2's (rows along l) then both
+  // receive 256 contiguous bytes per 4 lanes x 4 rows.
+  constexpr int VPC = E == E_FP8 ? 16 : 8;
+  constexpr int KT = 4 * VPC;
+  constexpr int ES = E == E_FP8 ? 1 : 2;
+  const IT H = (IT)H_, L = (IT)L_, IN = (IT)IN_, INp = (IT)INp_;
+  const IT nh = (H + 3) / 4, nl = (L + 3) / 4, nc = INp / KT;
+  const int64_t ntask = (int64_t)nh * nc * nl;
+  const int lane = threadIdx.x & 63;
+  const IT q = lane & 3, ll = (lane >> 2) & 3, hh = lane >> 4;
+  for (int64_t task = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); task < ntask;
+       task += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+    const IT tk = (IT)task;
+    const IT lb = tk % nl, rest = tk / nl;
+    const IT cc = rest % nc, hb = rest / nc;
+    const IT h = hb * 4 + hh, l = lb * 4 + ll;
+    const bool ok = h < H && l < L;
+    const IT r = h * L + l, c = cc * KT + q * VPC;
+    float v[VPC];
+#pragma unroll
+    for (int k = 0; k < VPC; ++k) v[k] = 0.f;
+    if (ok) {
+#pragma unroll
+      for (int k = 0; k < VPC; k += 4) load4(X, (int64_t)r * IN + c + k, IN_ - (int64_t)c - k, vec, v + k);
+    }
+    for (int m = 0; m < lm.n; ++m) {
+      // every lane takes part (the scale pairs lanes q, q ^ 1); only valid
+      // rows store
+      const IT Bh = (IT)lm.Bh[m], Im = (IT)lm.I[m];
+      const IT t = r / Bh, bh = r - t * Bh;
+      const IT a = t / Im, i = t - a * Im;
+      const IT bp = bh * INp + c;
+      const IT kt = a * (IT)lm.nbt[m] + bp / KT, kk = bp - (bp / KT) * KT;
+      const int64_t rowid = (int64_t)kt * lm.ipad[m] + i;
+      const int sc = store_chunk<E>(v, lm.out[m] + rowid * 64 + kk * ES, ok);
+      if (ok && E == E_FP8 && ((kk >> 4) & 1) == 0) lm.sc[m][scale_pos(rowid, (int)(kk >> 5))] = (unsigned char)sc;
+    }
+    if (xpad && ok) {
+      bf16_t* dst = xpad + (int64_t)r * INp + c;
+#pragma unroll
+      for (int k = 0; k < VPC; k += 4) *(uint2*)(dst + k) = pack_bf16(v + k);
+    }
+  }
+}
+
+// Zero the padding rows I..ipad-1 of every K tile of a blocked copy (and of
+// its e4m3 scales).
+__global__ void zero_pad_rows_kernel(char* out, unsigned char* scales, int64_t nkt, int64_t I, int64_t ipad) {
+  const int64_t rows = ipad - I;
+  const int64_t total = nkt * rows * 4;           // 16-byte chunks
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = e & 3, rr = e >> 2;
+    const int64_t kt = rr / rows, i = I + (rr - kt * rows);
+    const int64_t rowid = kt * ipad + i;
+    *(uint4*)(out + rowid * 64 + q * 16) = make_uint4(0, 0, 0, 0);
+    if (scales && q < 2) scales[scale_pos(rowid, (int)q)] = 0;
+  }
+}
+
+// Blocked copy of X_(N) for the last mode: X viewed as R rows of I_N; the
+// operand's rows are the I_N columns of that matrix and its K index the R
+// rows (padded to Rp, zero).  out[kt][i][64 bytes] holds X[kt KT + k][i],
+// i < ipad (zero past I_N).  A workgroup transposes KT x 64 values through
+// LDS; each thread then writes 16 bytes (four threads per output row).
+template <class T, int E>
+__global__ void __launch_bounds__(256) block_copy_last_kernel(const T* X, int64_t R, int64_t IN, int64_t ipad,
+                                                              bool vec, char* out, unsigned char* scales) {
+  constexpr int VPC = E == E_FP8 ? 16 : 8;
+  constexpr int KT = 4 * VPC;
+  __shared__ float tile[KT][65];
+  const int64_t ib = ipad / 64;
+  const int64_t kt = blockIdx.x / ib, i0 = (blockIdx.x - kt * ib) * 64;
+  const int t = threadIdx.x, q4 = (t & 15) * 4;
+#pragma unroll
+  for (int pass = 0; pass < KT / 16; ++pass) {
+    const int y = pass * 16 + (t >> 4);            // K row kt KT + y, columns i0 + q4 .. + 3
+    const int64_t r = kt * KT + y, i = i0 + q4;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (r < R && i < IN) load4(X, r * IN + i, IN - i, vec, v);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tile[y][q4 + k] = v[k];
+  }
+  __syncthreads();
+  const int row = t >> 2, q = t & 3;               // output row i0 + row, values q VPC .. + VPC - 1
+  float v[VPC];
+#pragma unroll
+  for (int k = 0; k < VPC; ++k) v[k] = tile[q * VPC + k][row];
+  const int64_t rowid = kt * ipad + i0 + row;
+  const int sc = store_chunk<E>(v, out + rowid * 64 + q * 16);
+  if (E == E_FP8 && (q & 1) == 0) scales[scale_pos(rowid, q >> 1)] = (unsigned char)sc;
+}
+
+// The blocked bf16 sketch [kt][64][64] -> e4m3 in the same layout, scales
+// [kt][h][row % 32][4] (byte row / 32; bytes 2, 3 stay zero).  One wave per
+// 64-value row; lane half h is run h.
+__global__ void quantize_omega_kernel(const bf16_t* src, int64_t nrows, fp8_t* q, unsigned char* scales) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < nrows;
+       r += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+    const int64_t i = r * 64 + lane;
+    const float v = bf16_to_f32(src[i]);
+    const int sc = e8m0_for(half_max(fabsf(v)));
+    q[i] = f32_to_e4m3(ldexpf(v, 127 - sc));
+    if ((lane & 31) == 0) {
+      const int64_t kt = r >> 6;
+      const int s = (int)(r & 63), h = lane >> 5;
+      scales[kt * 256 + (h * 32 + (s & 31)) * 4 + (s >> 5)] = (unsigned char)sc;
     }
   }
 }
@@ -645,25 +917,6 @@ __global__ void quantize_rows_kernel(const bf16_t* src, int64_t total, fp8_t* q,
       q[i] = f32_to_e4m3(ldexpf(v, 127 - sc));
       if ((lane & 31) == 0) scales[i >> 5] = (unsigned char)sc;
     }
-  }
-}
-
-// out[kt][i][h] = plane[((a I + min(i, I-1)) Bp + k0) / 32 + h], kt = a (Bp / 64) + k0 / 64;
-// IT: the index type (32 bits when the plane and the output fit)
-template <class IT>
-__global__ void gather_scales_kernel(const unsigned char* plane, int64_t I_, int64_t Bp_, int64_t ipad_,
-                                     int64_t total, unsigned char* out) {
-  const IT I = (IT)I_, Bp = (IT)Bp_, ipad = (IT)ipad_;
-  const IT nbt = Bp / 64;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const IT et = (IT)e;
-    const IT h = et & 1;
-    const IT ri = et >> 1;
-    const IT kt = ri / ipad, i = ri - kt * ipad;
-    const IT a = kt / nbt, k0 = (kt - a * nbt) * 64;
-    const IT ic = i < I ? i : I - 1;
-    out[e] = plane[((uint64_t)(a * I + ic) * (uint64_t)Bp + k0) / 32 + h];
   }
 }
 
@@ -718,23 +971,110 @@ hipError_t launch_gram_pipe(int elem, const GramArgs& g, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pad_copies_fp8(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, void* Xp8,
-                                 void* Sp, void* Xt8, void* St, hipStream_t s) {
+namespace {
+bool vec_ok(const void* X, int64_t L, int es) { return (L % 4) == 0 && ((uintptr_t)X % (4 * es)) == 0; }
+}  // namespace
+
+hipError_t launch_pad_copies(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, hipStream_t s) {
+  if (!Xpad && !Xt) return hipSuccess;
   const int64_t Lp = pad64(L), Rp = pad64(R);
   const int64_t blocks = (Rp / 64) * (Lp / 64);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
   const int es = src_elem == E_F64 ? 8 : src_elem == E_F32 ? 4 : 2;
-  const bool vec = (L % 4) == 0 && ((uintptr_t)X % (4 * es)) == 0;
-#define PCF(T)                                                                                                   \
-  hipLaunchKernelGGL(pad_copies_kernel<T>, grid, dim3(256), 0, s, (const T*)X, R, L, vec, (bf16_t*)Xpad, Lp,      \
-                     (bf16_t*)Xt, Rp, (fp8_t*)Xp8, (unsigned char*)Sp, (fp8_t*)Xt8, (unsigned char*)St)
+  const bool vec = vec_ok(X, L, es);
+#define PC(T)                                                                                                    \
+  hipLaunchKernelGGL(pad_copies_kernel<T>, grid, dim3(256), 0, s, (const T*)X, R, L, vec, (bf16_t*)Xpad, Lp,     \
+                     (bf16_t*)Xt, Rp)
   switch (src_elem) {
-    case E_F64: PCF(double); break;
-    case E_F32: PCF(float); break;
-    default: PCF(bf16_t); break;
+    case E_F64: PC(double); break;
+    case E_F32: PC(float); break;
+    default: PC(bf16_t); break;
   }
-#undef PCF
+#undef PC
+  return hipGetLastError();
+}
+
+int64_t block_rows(int64_t I) { return ceil_div(I, PT) * PT; }
+
+size_t block_copy_bytes(int64_t nkt, int64_t I) { return (size_t)nkt * block_rows(I) * PROW; }
+
+hipError_t launch_block_copy_lead(int src_elem, int elem, const void* X, int order, const int64_t* dims,
+                                  const bool* want, void* const* out, void* const* scales, void* xpad, hipStream_t s) {
+  if (elem != E_FP8 && elem != E_BF16) return hipErrorInvalidValue;
+  const int64_t IN = dims[order - 1], INp = pad64(IN), KT = elem == E_FP8 ? 64 : 32;
+  int64_t R = 1;
+  for (int k = 0; k + 1 < order; ++k) R *= dims[k];
+  LeadModes lm = {};
+  hipError_t e;
+  for (int n = 0; n + 1 < order; ++n) {
+    if (!want[n]) continue;
+    if (!out[n] || (elem == E_FP8 && !scales[n])) return hipErrorInvalidValue;
+    int64_t A = 1, B = 1;
+    for (int k = 0; k < n; ++k) A *= dims[k];
+    for (int k = n + 1; k < order; ++k) B *= dims[k];
+    const int m = lm.n++;
+    lm.I[m] = dims[n];
+    lm.Bh[m] = B / IN;
+    lm.ipad[m] = block_rows(dims[n]);
+    lm.nbt[m] = (B / IN) * INp / KT;
+    lm.out[m] = (char*)out[n];
+    lm.sc[m] = (unsigned char*)scales[n];
+    const int64_t nkt = A * lm.nbt[m];
+    if (lm.ipad[m] > dims[n]) {
+      const int64_t total = nkt * (lm.ipad[m] - dims[n]) * 4;
+      const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 16384);
+      hipLaunchKernelGGL(zero_pad_rows_kernel, dim3(grid), dim3(256), 0, s, (char*)out[n],
+                         elem == E_FP8 ? (unsigned char*)scales[n] : nullptr, nkt, dims[n], lm.ipad[m]);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  if (lm.n == 0 && !xpad) return hipSuccess;
+  const int64_t L = dims[order - 2], H = R / L;
+  const int64_t ntask = ceil_div(H, 4) * (INp / KT) * ceil_div(L, 4);
+  if (ntask <= 0) return hipSuccess;
+  const int es = src_elem == E_F64 ? 8 : src_elem == E_F32 ? 4 : 2;
+  const bool vec = vec_ok(X, IN, es);
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(ntask, 4), 65536);
+  const bool small = ntask * 64 < ((int64_t)1 << 31) && (H + 4) * (L + 4) * INp < ((int64_t)1 << 31);
+#define BC(T, EE, IT)                                                                                            \
+  hipLaunchKernelGGL((block_copy_lead_kernel<T, EE, IT>), dim3(grid), dim3(256), 0, s, (const T*)X, H, L, IN, INp, \
+                     vec, lm, (bf16_t*)xpad)
+#define BC_E(T)                                                                  \
+  if (elem == E_FP8) { if (small) BC(T, E_FP8, uint32_t); else BC(T, E_FP8, uint64_t); } \
+  else { if (small) BC(T, E_BF16, uint32_t); else BC(T, E_BF16, uint64_t); }
+  switch (src_elem) {
+    case E_F64: BC_E(double); break;
+    case E_F32: BC_E(float); break;
+    default: BC_E(bf16_t); break;
+  }
+#undef BC_E
+#undef BC
+  return hipGetLastError();
+}
+
+hipError_t launch_block_copy_last(int src_elem, int elem, const void* X, int64_t R, int64_t IN, void* out,
+                                  void* scales, hipStream_t s) {
+  if (elem != E_FP8 && elem != E_BF16) return hipErrorInvalidValue;
+  if (elem == E_FP8 && !scales) return hipErrorInvalidValue;
+  const int64_t KT = elem == E_FP8 ? 64 : 32;
+  const int64_t nkt = pad64(R) / KT, ipad = block_rows(IN);
+  const int64_t blocks = nkt * (ipad / 64);
+  if (blocks <= 0) return hipSuccess;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const int es = src_elem == E_F64 ? 8 : src_elem == E_F32 ? 4 : 2;
+  const bool vec = vec_ok(X, IN, es);
+#define BL(T, EE)                                                                                              \
+  hipLaunchKernelGGL((block_copy_last_kernel<T, EE>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)X, R, IN, \
+                     ipad, vec, (char*)out, (unsigned char*)scales)
+#define BL_E(T) if (elem == E_FP8) BL(T, E_FP8); else BL(T, E_BF16);
+  switch (src_elem) {
+    case E_F64: BL_E(double); break;
+    case E_F32: BL_E(float); break;
+    default: BL_E(bf16_t); break;
+  }
+#undef BL_E
+#undef BL
   return hipGetLastError();
 }
 
@@ -749,17 +1089,14 @@ hipError_t launch_quantize_rows_fp8(const void* src, int64_t rows, int64_t cols,
   return hipGetLastError();
 }
 
-hipError_t launch_gather_scales(const void* plane, int64_t A, int64_t I, int64_t Bp, int64_t ipad, void* out,
-                                hipStream_t s) {
-  if (Bp % 64 || ipad < I) return hipErrorInvalidValue;
-  const int64_t total = A * (Bp / 64) * ipad * 2;
-  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 16384);
-  if (total < ((int64_t)1 << 31) && A * I < ((int64_t)1 << 31))
-    hipLaunchKernelGGL(gather_scales_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, (const unsigned char*)plane, I, Bp,
-                       ipad, total, (unsigned char*)out);
-  else
-    hipLaunchKernelGGL(gather_scales_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, (const unsigned char*)plane, I, Bp,
-                       ipad, total, (unsigned char*)out);
+hipError_t launch_quantize_omega(const void* src, int64_t nkt, void* q, void* scales, hipStream_t s) {
+  if (nkt <= 0) return hipSuccess;
+  hipError_t e = fill_zero(scales, (size_t)nkt * 256, s);
+  if (e != hipSuccess) return e;
+  const int64_t nrows = nkt * 64;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(nrows, 4), 16384);
+  hipLaunchKernelGGL(quantize_omega_kernel, dim3(grid), dim3(256), 0, s, (const bf16_t*)src, nrows, (fp8_t*)q,
+                     (unsigned char*)scales);
   return hipGetLastError();
 }
 
@@ -770,23 +1107,39 @@ hipError_t launch_gram_pipe_reduce(const GramArgs& g, double* C, double* Wt, hip
   return hipGetLastError();
 }
 
-hipError_t launch_pad_copies(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, hipStream_t s) {
-  return launch_pad_copies_fp8(src_elem, X, R, L, Xpad, Xt, nullptr, nullptr, nullptr, nullptr, s);
-}
-
 hipError_t launch_omega_pad(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t Jp,
                             void* out, hipStream_t s) {
+  // the row-major S x Jp layout is the blocked one with a single K tile of Jp
+  // columns: [0][s][jp]
+  if (Jp >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   hipError_t e = fill_zero(out, (size_t)S * Jp * 2, s);
   if (e != hipSuccess) return e;
   const int64_t npairs = (S * J + 1) / 2;
   unsigned grid = (unsigned)std::min<int64_t>(ceil_div(npairs, 256), 16384);
   if (grid == 0) return hipSuccess;
-  if (S * J < ((int64_t)1 << 31) && Jp < ((int64_t)1 << 31))
-    hipLaunchKernelGGL(omega_pad_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
-                       pad64(IN), Jp, (bf16_t*)out);
+  if (S * J < ((int64_t)1 << 31) && S * Jp < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(omega_block_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
+                       pad64(IN), (int)Jp, (bf16_t*)out);
   else
-    hipLaunchKernelGGL(omega_pad_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
-                       pad64(IN), Jp, (bf16_t*)out);
+    hipLaunchKernelGGL(omega_block_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
+                       pad64(IN), (int)Jp, (bf16_t*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_omega_block(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t nkt,
+                              int KT, void* out, hipStream_t s) {
+  if (S > PW || (KT != 32 && KT != 64)) return hipErrorInvalidValue;
+  hipError_t e = fill_zero(out, (size_t)nkt * PW * KT * 2, s);
+  if (e != hipSuccess) return e;
+  const int64_t npairs = (S * J + 1) / 2;
+  unsigned grid = (unsigned)std::min<int64_t>(ceil_div(npairs, 256), 16384);
+  if (grid == 0) return hipSuccess;
+  if (S * J < ((int64_t)1 << 31) && nkt * KT < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(omega_block_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
+                       pad64(IN), KT, (bf16_t*)out);
+  else
+    hipLaunchKernelGGL(omega_block_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
+                       pad64(IN), KT, (bf16_t*)out);
   return hipGetLastError();
 }
 

@@ -32,11 +32,16 @@ size_t gram_partial_bytes(const GramArgs& g, int elem);
 hipError_t launch_gram_main(int elem, const GramArgs& g, hipStream_t s);
 hipError_t launch_gram_reduce(int elem, const GramArgs& g, double* C, double* Wt, hipStream_t s);
 hipError_t launch_omega(int elem, uint64_t seed, int mode, int64_t total, void* out, hipStream_t s);
-// bf16 pipelined form (gram_pipe.hip): 256 x 256 lower-triangle tiles, the
-// sketch (S <= 64) computed by the spare wave of each diagonal tile; operands
-// are the zero-padded bf16 views described there (row pitch Bp, a multiple of 64).
+// Pipelined bf16 / e4m3 form (gram_pipe.hip): 256 x 256 lower-triangle tiles,
+// the sketch (S <= 64) computed by the spare wave of each diagonal tile.
+// Operands are K-blocked copies of the mode's zero-padded unfolding (view
+// [A, I, Bp], Bp a multiple of 64): [K tile][block_rows(I) rows][64 bytes],
+// and the sketch [K tile][64][64 bytes]; e4m3 scales per K tile: 512 bytes per
+// 256-row tile ([half][row % 32][row / 32]), the sketch's 256 ([half][row % 32][4]).
 int64_t pad64(int64_t v);
 bool gram_pipe_ok(int64_t I, int S);
+int64_t block_rows(int64_t I);                       // I rounded up to whole 256-row tiles
+size_t block_copy_bytes(int64_t nkt, int64_t I);     // nkt K tiles of block_rows(I) rows
 // elem: E_BF16 or E_FP8 (K tiles of 32 or 64 values)
 GramArgs gram_plan_pipe(int elem, int64_t A, int64_t I, int64_t Bp, int S, int cu_count);
 size_t gram_pipe_partial_bytes(const GramArgs& g);
@@ -45,22 +50,27 @@ hipError_t launch_gram_pipe_reduce(const GramArgs& g, double* C, double* Wt, hip
 // X viewed as R rows of length L -> Xpad (R x pad64(L)) and Xt (L x pad64(R)),
 // bf16 with zero padding (either output may be null).
 hipError_t launch_pad_copies(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, hipStream_t s);
-// The same copies in e4m3 with one E8M0 scale per 32 consecutive values of a
-// storage row: Xp8 (R x pad64(L)) + Sp (R x pad64(L)/32), Xt8 (L x pad64(R)) +
-// St (L x pad64(R)/32); bf16 Xpad / Xt alongside when non-null.
-hipError_t launch_pad_copies_fp8(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, void* Xp8,
-                                 void* Sp, void* Xt8, void* St, hipStream_t s);
+// Blocked copies (elem E_BF16 or E_FP8, with scales) of the leading modes
+// n < order-1 with want[n], in one pass over X (out[n], scales[n] per mode);
+// xpad (nullable): the row-major padded bf16 copy as well.
+hipError_t launch_block_copy_lead(int src_elem, int elem, const void* X, int order, const int64_t* dims,
+                                  const bool* want, void* const* out, void* const* scales, void* xpad, hipStream_t s);
+// Blocked copy of the last mode's unfolding (X as R rows of IN; K runs over R).
+hipError_t launch_block_copy_last(int src_elem, int elem, const void* X, int64_t R, int64_t IN, void* out,
+                                  void* scales, hipStream_t s);
+// The blocked bf16 sketch ([nkt][64][64]) -> e4m3, scales [nkt][2][32][4].
+hipError_t launch_quantize_omega(const void* src, int64_t nkt, void* q, void* scales, hipStream_t s);
 // rows x cols bf16 (cols a multiple of 32) -> e4m3 with per-32 E8M0 scales
 hipError_t launch_quantize_rows_fp8(const void* src, int64_t rows, int64_t cols, void* q, void* scales, hipStream_t s);
-// Scales of the mode view [A, I, Bp] (per-32 plane of the e4m3 copy) in the
-// order the fp8 Gram kernel reads them: out[kt][i][h], kt < A Bp / 64,
-// i < ipad (rows past I repeat row I-1), h in {0, 1}.
-hipError_t launch_gather_scales(const void* plane, int64_t A, int64_t I, int64_t Bp, int64_t ipad, void* out,
-                                hipStream_t s);
 // Omega^T (S x J) of one mode as bf16 in the padded column layout S x Jp
-// (B: the mode's trailing size, IN: the last dimension; B = 1 for the last mode).
+// (row-major; the Gram fallback of the mixed forms).
 hipError_t launch_omega_pad(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t Jp,
                             void* out, hipStream_t s);
+// Omega^T (S x J, S <= 64) of one mode as bf16, blocked [nkt][64][KT] in the
+// padded column order (B: the mode's trailing size, IN: the last dimension;
+// B = 1 for the last mode); zero in padded columns and rows past S.
+hipError_t launch_omega_block(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t nkt,
+                              int KT, void* out, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint64_t seed, uint32_t* out, hipStream_t s);
 
 // ------------------------------------------------------------ linalg.hip (float64)
