@@ -29,26 +29,36 @@ __global__ void __launch_bounds__(256) dgemm_kernel(int opA, int opB, int64_t m,
   const int64_t row0 = (int64_t)blockIdx.y * GT, col0 = (int64_t)blockIdx.x * GT;
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = kb + kchunk < k ? kb + kchunk : k;
-  double acc[4][4] = {};
-  for (int64_t k0 = kb; k0 < ke; k0 += GK) {
-    // stage A tile: As[kk][i] = op(A)[row0 + i, k0 + kk]
-    for (int e = threadIdx.x; e < GK * GT; e += 256) {
-      int kk, i;
-      if (opA == 0) { i = e / GK; kk = e % GK; } else { kk = e / GT; i = e % GT; }
-      const int64_t r = row0 + i, c = k0 + kk;
-      double v = 0.0;
-      if (r < m && c < ke) v = opA == 0 ? A[r * lda + c] : A[c * lda + r];
-      As[kk][i] = v;
+  // this thread's four elements of each staged tile: A (i, kk), B (kk, j)
+  int ai[4], ak[4], bk[4], bj[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = threadIdx.x + 256 * t;
+    if (opA == 0) { ai[t] = e / GK; ak[t] = e % GK; } else { ak[t] = e / GT; ai[t] = e % GT; }
+    if (opB == 0) { bk[t] = e / GT; bj[t] = e % GT; } else { bj[t] = e / GK; bk[t] = e % GK; }
+  }
+  // the next K tile is loaded into registers while the current one is
+  // multiplied, so only the first tile's memory latency is exposed
+  double ra[4], rb[4];
+  auto fetch = [&](int64_t k0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t r = row0 + ai[t], c = k0 + ak[t];
+      ra[t] = (r < m && c < ke) ? (opA == 0 ? A[r * lda + c] : A[c * lda + r]) : 0.0;
+      const int64_t r2 = k0 + bk[t], c2 = col0 + bj[t];
+      rb[t] = (r2 < ke && c2 < n) ? (opB == 0 ? B[r2 * ldb + c2] : B[c2 * ldb + r2]) : 0.0;
     }
-    for (int e = threadIdx.x; e < GK * GT; e += 256) {
-      int kk, j;
-      if (opB == 0) { kk = e / GT; j = e % GT; } else { j = e / GK; kk = e % GK; }
-      const int64_t r = k0 + kk, c = col0 + j;
-      double v = 0.0;
-      if (r < ke && c < n) v = opB == 0 ? B[r * ldb + c] : B[c * ldb + r];
-      Bs[kk][j] = v;
+  };
+  double acc[4][4] = {};
+  if (kb < ke) fetch(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += GK) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      As[ak[t]][ai[t]] = ra[t];
+      Bs[bk[t]][bj[t]] = rb[t];
     }
     __syncthreads();
+    if (k0 + GK < ke) fetch(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; ++kk) {
       double a[4], b[4];
@@ -188,11 +198,12 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
 
 // CholeskyQR step for s <= 64 in one launch: Yout = L^{-1} Y where G = L L^T
 // (same drop rule as above: a dropped vector gets a zero row of Yout).
-// Every workgroup factors G itself: wave 0, lane i owning row i, runs a
-// left-looking Cholesky in LDS (within one wave LDS accesses complete in
-// order, so no barriers are needed).  Then each thread solves L y = Y(:, c)
-// for one column c by forward substitution, with y in registers and L read
-// by LDS broadcast.  flags is written by workgroup 0.
+// Every workgroup factors G itself: wave 0, lane i owning row i in
+// registers, runs a right-looking Cholesky, publishing each finished column
+// in LDS (within one wave LDS accesses complete in order, so no barriers are
+// needed).  Then each thread solves L y = Y(:, c) for one column c by forward
+// substitution, with y in registers and L read by LDS broadcast.  flags is
+// written by workgroup 0.  All global loads are issued before their use.
 constexpr int CS_MAX = 64;
 
 __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s, const double* Y, int64_t n,
@@ -200,11 +211,24 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
                                                          double tau_rel, double tau_abs, DimBudget bud) {
   __shared__ double Ls[CS_MAX][CS_MAX + 1];
   __shared__ double dinv[CS_MAX];
+  __shared__ double col[CS_MAX];
   __shared__ int keep[CS_MAX];
   const int tid = threadIdx.x;
-  for (int e = tid; e < s * s; e += blockDim.x) {
-    const int i = e / s, j = e - i * s;
-    Ls[i][j] = G[e];
+  {
+    double g[CS_MAX * CS_MAX / 256];
+#pragma unroll
+    for (int t = 0; t < CS_MAX * CS_MAX / 256; ++t) {
+      const int e = tid + t * 256;
+      g[t] = e < s * s ? G[e] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < CS_MAX * CS_MAX / 256; ++t) {
+      const int e = tid + t * 256;
+      if (e < s * s) {
+        const int i = e / s, j = e - i * s;
+        Ls[i][j] = g[t];
+      }
+    }
   }
   __syncthreads();
   if (tid < 64) {
@@ -213,25 +237,35 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
     mx = warp_max(mx);
     const double abs_floor = tau_abs * tau_abs * mx;
     const double d0 = i < s ? Ls[i][i] : 0.0;
+    double row[CS_MAX];
+#pragma unroll
+    for (int j = 0; j < CS_MAX; ++j) row[j] = (i < s && j < s) ? Ls[i][j] : 0.0;
     const int64_t allowed = bud.allowed();
     int64_t nkept = 0;
-    for (int k = 0; k < s; ++k) {
-      double v = 0.0;
-      if (i >= k && i < s) {
-        v = Ls[i][k];
-        for (int j = 0; j < k; ++j) v -= Ls[i][j] * Ls[k][j];
-      }
-      const double d = __shfl(v, k, 64);
-      const double dk0 = __shfl(d0, k, 64);
-      const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor) && nkept < allowed;
-      nkept += kp;
-      const double piv = kp ? sqrt(d) : 0.0;
-      if (i >= k && i < s) Ls[i][k] = kp ? (i == k ? piv : v / piv) : 0.0;
-      if (i == k) {
-        keep[k] = kp;
-        dinv[k] = kp ? 1.0 / piv : 0.0;
+#pragma unroll
+    for (int k = 0; k < CS_MAX; ++k) {
+      if (k < s) {
+        const double v = row[k];                 // G(i, k) minus the earlier columns' terms
+        const double d = __shfl(v, k, 64);
+        const double dk0 = __shfl(d0, k, 64);
+        const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor) && nkept < allowed;
+        nkept += kp;
+        const double piv = kp ? sqrt(d) : 0.0;
+        const double inv = kp ? 1.0 / piv : 0.0;
+        const double lik = (i > k && i < s) ? v * inv : (i == k ? piv : 0.0);
+        row[k] = lik;
+        if (i == k) {
+          keep[k] = kp;
+          dinv[k] = inv;
+        }
+        col[i] = lik;
+#pragma unroll
+        for (int j = k + 1; j < CS_MAX; ++j) row[j] -= lik * col[j];
       }
     }
+#pragma unroll
+    for (int j = 0; j < CS_MAX; ++j)
+      if (i < s && j < s) Ls[i][j] = j <= i ? row[j] : 0.0;
     // every workgroup reads the count of earlier blocks and writes a
     // different slot, so they agree without synchronising
     if (blockIdx.x == 0 && i == 0) bud.record(nkept);
@@ -243,12 +277,21 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
   if (c >= n) return;
   double y[CS_MAX];
 #pragma unroll
+  for (int k = 0; k < CS_MAX; ++k) y[k] = k < s ? Y[(int64_t)k * n + c] : 0.0;
+#pragma unroll
   for (int k = 0; k < CS_MAX; ++k) {
     if (k < s) {
-      double acc = Y[(int64_t)k * n + c];
+      double a0 = y[k], a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-      for (int j = 0; j < k; ++j) acc -= Ls[k][j] * y[j];
-      y[k] = acc * dinv[k];                      // zero for a dropped vector
+      for (int j = 0; j + 3 < k; j += 4) {
+        a0 -= Ls[k][j] * y[j];
+        a1 -= Ls[k][j + 1] * y[j + 1];
+        a2 -= Ls[k][j + 2] * y[j + 2];
+        a3 -= Ls[k][j + 3] * y[j + 3];
+      }
+#pragma unroll
+      for (int j = k & ~3; j < k; ++j) a0 -= Ls[k][j] * y[j];
+      y[k] = ((a0 + a1) + (a2 + a3)) * dinv[k];   // zero for a dropped vector
       Yout[(int64_t)k * n + c] = y[k];
     } else {
       y[k] = 0.0;
@@ -376,20 +419,44 @@ __device__ inline int circle_block(int pos, int round, int nblk) {
   return 1 + v;
 }
 
+// 1/x and 1/sqrt(x) in float64 from the hardware estimates refined by two
+// Newton-Raphson steps each (r <- r (2 - x r); r <- r (3 - x r^2) / 2), full
+// double precision from an estimate good to half of it, in a few dependent
+// FMAs instead of the correctly rounded divide / square-root sequences.
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ inline double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  r = r * fma(-hx * r, r, 1.5);
+  r = r * fma(-hx * r, r, 1.5);
+  return r;
+}
+
 // Rotation (c, s) zeroing the (p, q) entry of a 2x2 Gram block
 // [al ga; ga be]: new_p = c p - s q, new_q = s p + c q.  Returns false when
 // |ga| <= tol sqrt(al be) (the pair is already orthogonal to tolerance).
+// The rotation is the standard one: zeta = (be - al) / (2 ga),
+// t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t.
 __device__ inline bool jacobi_rotation(double al, double be, double ga, double tol, double& c, double& s,
                                        double& cosang) {
   c = 1.0;
   s = 0.0;
-  const double nrm = sqrt(fmax(al, 0.0) * fmax(be, 0.0));
-  if (!(nrm > 1e-300)) { cosang = 0.0; return false; }
-  cosang = fabs(ga) / nrm;
+  al = fmax(al, 0.0);
+  be = fmax(be, 0.0);
+  if (!(al > 1e-300 && be > 1e-300)) { cosang = 0.0; return false; }
+  cosang = fabs(ga) * rsq_nr(al) * rsq_nr(be);
   if (cosang <= tol) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  c = rsqrt(1.0 + t * t);
+  const double zeta = (be - al) * rcp_nr(2.0 * ga);
+  const double z2 = fma(zeta, zeta, 1.0);
+  const double root = z2 < 1e300 ? z2 * rsq_nr(z2) : fabs(zeta);   // sqrt(1 + zeta^2)
+  const double tm = rcp_nr(fabs(zeta) + root);
+  const double t = zeta >= 0.0 ? tm : -tm;
+  c = rsq_nr(fma(t, t, 1.0));
   s = c * t;
   return true;
 }
