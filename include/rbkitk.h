@@ -160,6 +160,21 @@ size_t rbki_sym_eig_workspace(int64_t n);
 rbki_status rbki_sym_eig(const double *Z, int64_t n, double *lam, double *Vt, void *workspace,
                          size_t ws_bytes, int *sweeps, void *stream);
 
+/* The k leading eigenpairs only, which is what Alg. 2, step 5 keeps (k = R_n
+ * of Z's n = S (q + 1)): Householder reduction to tridiagonal form, bisection
+ * on Sturm counts and inverse iteration, one workgroup per matrix.  The
+ * factor step of rbki_tucker / rbki_htr uses this solver when n <= 512.
+ *   Z        : device, n x n row-major (read only; only the upper triangle
+ *              is read; symmetric PSD).
+ *   lam      : device, k doubles, descending.
+ *   Vt       : device, k x n row-major; row j is the unit eigenvector of
+ *              lam[j], signed so that its largest-magnitude entry is positive.
+ * 1 <= k <= n <= 512; anything else returns RBKI_E_INVALID.
+ */
+size_t rbki_sym_eig_top_workspace(int64_t n, int64_t k);
+rbki_status rbki_sym_eig_top(const double *Z, int64_t n, int64_t k, double *lam, double *Vt,
+                             void *workspace, size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Serving form: a request server for many small decompositions (continuous
  * batching).  Not in the paper; it serves the same Alg. 2 decomposition

@@ -15,7 +15,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["tucker", "htr", "basis", "sym_eig", "omega", "philox", "workspace_bytes", "profile_enable",
+__all__ = ["tucker", "htr", "basis", "sym_eig", "sym_eig_top", "omega", "philox", "workspace_bytes", "profile_enable",
            "profile_reset", "profile_read", "Server", "library_path", "load_library", "RbkiError",
            "PLAIN", "MIXED_BF16", "MIXED_FP8", "SYMBOLS"]
 
@@ -32,8 +32,8 @@ _STATUS = {0: "RBKI_OK", 1: "RBKI_E_INVALID", 2: "RBKI_E_NOMEM", 3: "RBKI_E_HIP"
 # Every symbol the header declares.
 SYMBOLS = ("rbki_version", "rbki_last_error", "rbki_omega", "rbki_philox", "rbki_basis_workspace",
            "rbki_basis", "rbki_tucker_workspace", "rbki_tucker", "rbki_htr_workspace", "rbki_htr",
-           "rbki_sym_eig_workspace", "rbki_sym_eig", "rbki_profile_enable", "rbki_profile_reset",
-           "rbki_profile_read", "rbki_server_request_bytes", "rbki_server_create", "rbki_server_submit",
+           "rbki_sym_eig_workspace", "rbki_sym_eig", "rbki_sym_eig_top_workspace", "rbki_sym_eig_top",
+           "rbki_profile_enable", "rbki_profile_reset", "rbki_profile_read", "rbki_server_request_bytes", "rbki_server_create", "rbki_server_submit",
            "rbki_server_poll", "rbki_server_wait", "rbki_server_destroy")
 
 
@@ -84,6 +84,8 @@ def load_library(build_if_missing=True):
             "rbki_htr": (ci, [vp, ci, P(_Params), P(i64), P(vp), ci, vp, sz, P(dbl), vp]),
             "rbki_sym_eig_workspace": (sz, [i64]),
             "rbki_sym_eig": (ci, [vp, i64, vp, vp, vp, sz, P(ci), vp]),
+            "rbki_sym_eig_top_workspace": (sz, [i64, i64]),
+            "rbki_sym_eig_top": (ci, [vp, i64, i64, vp, vp, vp, sz, vp]),
             "rbki_profile_enable": (None, [ci]),
             "rbki_profile_reset": (None, []),
             "rbki_profile_read": (ci, [ctypes.c_char_p, P(i64), P(dbl)]),
@@ -270,6 +272,25 @@ def sym_eig(Z, stream=None):
                             ctypes.c_void_p(Vt.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                             ctypes.byref(sweeps), _stream(torch, stream)))
     return lam, Vt, sweeps.value
+
+
+def sym_eig_top(Z, k, stream=None):
+    """The k largest eigenvalues (descending) and their eigenvectors (rows) of
+    a symmetric PSD float64 device matrix (tridiagonal reduction, bisection,
+    inverse iteration).  Returns (lam, Vt)."""
+    torch = _torch()
+    lib = load_library()
+    Z = Z.contiguous()
+    if Z.dtype != torch.float64 or Z.dim() != 2 or Z.shape[0] != Z.shape[1]:
+        raise ValueError("Z must be a square float64 tensor")
+    n, k = int(Z.shape[0]), int(k)
+    ws = _workspace(torch, Z.device, lib.rbki_sym_eig_top_workspace(n, k))
+    lam = torch.empty(max(k, 0), dtype=torch.float64, device=Z.device)
+    Vt = torch.empty((max(k, 0), n), dtype=torch.float64, device=Z.device)
+    _check(lib.rbki_sym_eig_top(ctypes.c_void_p(Z.data_ptr()), n, k, ctypes.c_void_p(lam.data_ptr()),
+                                ctypes.c_void_p(Vt.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                _stream(torch, stream)))
+    return lam, Vt
 
 
 def omega(seed, mode, J, S, dtype=None, device="cuda", stream=None):

@@ -342,7 +342,8 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
     b.Z[n] = (double*)ar.take((size_t)Sp * Sp * 8);
     b.lam[n] = (double*)ar.take((size_t)Sp * 8);
     b.Vt[n] = (double*)ar.take((size_t)Sp * Sp * 8);
-    b.jwork[n] = ar.take(jacobi_work_bytes(Sp));
+    const int64_t R = P.m[n].R;
+    b.jwork[n] = ar.take(std::max(jacobi_work_bytes(Sp), eig_top_ok(Sp, R) ? eig_top_work_bytes(Sp, R) : (size_t)0));
   }
   b.info = (int*)ar.take(counters_bytes(P));
   b.used = b.info + 64;
@@ -489,31 +490,40 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
   return RBKI_OK;
 }
 
-// Alg. 2, steps 4-5 for all modes: the eigenvectors of every Z in one batched
-// Jacobi launch, then U^T = Vt(1:R, :) Q^T with the sign rule.
+// Alg. 2, steps 4-5 for all modes: the R leading eigenvectors of every Z in
+// one launch (tridiagonal reduction, bisection, inverse iteration; block
+// Jacobi for matrices beyond that solver's sizes), then U^T = Vt(1:R, :) Q^T
+// with the sign rule.
 rbki_status run_factors(const Plan& P, const Buffers& b, hipStream_t st) {
   const double* Zs[8];
-  int64_t ns[8];
+  int64_t ns[8], rs[8];
   double* ls[8];
   double* vs[8];
   void* ws[8];
   int* is[8];
+  bool top = true;
   for (int n = 0; n < P.N; ++n) {
     Zs[n] = b.Z[n];
     ns[n] = P.m[n].Sp;
+    rs[n] = P.m[n].R;
     ls[n] = b.lam[n];
     vs[n] = b.Vt[n];
     ws[n] = b.jwork[n];
     is[n] = b.info + 2 * n;
+    top = top && eig_top_ok(ns[n], rs[n]);
   }
   {
-    ProfScope ps("jacobi", st);
-    // beside other solves (the request server) small matrices take the
-    // ordinary per-matrix launch: a cooperative grid does not share the
-    // device with work on other streams
-    int64_t nmax = 0;
-    for (int n = 0; n < P.N; ++n) nmax = std::max(nmax, ns[n]);
-    HIPCHK(jacobi_eig_batched(P.N, Zs, ns, ls, vs, ws, is, 40, st, P.concurrent && nmax <= 192));
+    ProfScope ps("eig", st);
+    if (top) {
+      HIPCHK(eig_top_batched(P.N, Zs, ns, rs, ls, vs, ws, is, st));
+    } else {
+      // beside other solves (the request server) small matrices take the
+      // ordinary per-matrix launch: a cooperative grid does not share the
+      // device with work on other streams
+      int64_t nmax = 0;
+      for (int n = 0; n < P.N; ++n) nmax = std::max(nmax, ns[n]);
+      HIPCHK(jacobi_eig_batched(P.N, Zs, ns, ls, vs, ws, is, 40, st, P.concurrent && nmax <= 192));
+    }
   }
   for (int n = 0; n < P.N; ++n) {
     const ModeGeom& g = P.m[n];
@@ -686,6 +696,28 @@ rbki_status rbki_sym_eig(const double* Z, int64_t n, double* lam, double* Vt, vo
   return RBKI_OK;
 }
 
+size_t rbki_sym_eig_top_workspace(int64_t n, int64_t k) {
+  if (!eig_top_ok(n, k)) return 0;
+  return eig_top_work_bytes(n, k);
+}
+
+rbki_status rbki_sym_eig_top(const double* Z, int64_t n, int64_t k, double* lam, double* Vt, void* workspace,
+                             size_t ws_bytes, void* stream) {
+  if (!eig_top_ok(n, k))
+    return fail(RBKI_E_INVALID, "need 1 <= k <= n <= 512 (n = %lld, k = %lld)", (long long)n, (long long)k);
+  if (!Z || !lam || !Vt) return fail(RBKI_E_INVALID, "NULL matrix or output");
+  const size_t need = rbki_sym_eig_top_workspace(n, k);
+  if (!workspace || ws_bytes < need) return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  void* ws[1] = {workspace};
+  {
+    ProfScope ps("eig", st);
+    HIPCHK(eig_top_batched(1, &Z, &n, &k, &lam, &Vt, ws, nullptr, st));
+  }
+  HIPCHK(canonical_sign_rows(Vt, k, n, st));
+  return RBKI_OK;
+}
+
 size_t rbki_basis_workspace(const rbki_params* prm, int xtype, int mode) {
   Plan P;
   if (make_plan(prm, xtype, P) != RBKI_OK) return 0;
@@ -753,7 +785,7 @@ rbki_status finish_result(const HostResult& hr, double* rel_err) {
       std::lock_guard<std::mutex> lk(g_prof_mu);
       g_prof["jacobi_sweeps"].launches += hr.info[2 * n + 1];
     }
-    if (hr.info[2 * n]) return fail(RBKI_E_NOCONV, "Jacobi reached its sweep limit in mode %d", n);
+    if (hr.info[2 * n]) return fail(RBKI_E_NOCONV, "the eigen-solver did not finish in mode %d", n);
   }
   return RBKI_OK;
 }

@@ -86,4 +86,22 @@ template <class T> __device__ inline T warp_max(T v) {
   return v;
 }
 
+// 1/x and 1/sqrt(x) in float64 from the hardware estimates refined by two
+// Newton-Raphson steps each (r <- r (2 - x r); r <- r (3 - x r^2) / 2), full
+// double precision from an estimate good to half of it, in a few dependent
+// FMAs instead of the correctly rounded divide / square-root sequences.
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ inline double rsq_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  r = r * fma(-hx * r, r, 1.5);
+  r = r * fma(-hx * r, r, 1.5);
+  return r;
+}
+
 }  // namespace rbki

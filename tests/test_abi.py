@@ -117,3 +117,18 @@ def test_server_footprint_is_the_decomposition_workspace():
             assert lib.rbki_server_request_bytes(ctypes.byref(prm), xt) == lib.rbki_tucker_workspace(ctypes.byref(prm), xt)
     bad = _params((10, 10, 10), (11, 3, 3))
     assert lib.rbki_server_request_bytes(ctypes.byref(bad), 1) == 0
+
+
+def test_top_eigensolver_rejects_bad_sizes_before_any_launch():
+    lib = rb.load_library()
+    assert lib.rbki_sym_eig_top_workspace(0, 1) == 0
+    assert lib.rbki_sym_eig_top_workspace(10, 11) == 0
+    assert lib.rbki_sym_eig_top_workspace(513, 4) == 0
+    need = lib.rbki_sym_eig_top_workspace(300, 50)
+    assert need >= 300 * 300 * 8
+    p = ctypes.c_void_p(256)
+    assert lib.rbki_sym_eig_top(p, 300, 0, p, p, p, need, None) == 1
+    assert lib.rbki_sym_eig_top(p, 600, 50, p, p, p, need, None) == 1
+    assert lib.rbki_sym_eig_top(None, 300, 50, p, p, p, need, None) == 1
+    assert lib.rbki_sym_eig_top(p, 300, 50, p, p, p, need - 1, None) == 1
+    assert "workspace" in lib.rbki_last_error().decode()

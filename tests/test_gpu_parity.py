@@ -278,6 +278,68 @@ def test_htr_zero_pads_ring_ranks_beyond_the_core(env):
 
 # ------------------------------------------------------------------ eigen-solver
 
+def _psd(rng, lam):
+    n = len(lam)
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    Z = (Q * np.asarray(lam, float)) @ Q.T
+    return (Z + Z.T) / 2
+
+
+def _top_case(kind, n, rng):
+    if kind == "gauss":          # Wishart-like, spread spectrum
+        A = rng.standard_normal((n, 2 * n + 3)) * np.linspace(1.0, 0.05, n)[:, None]
+        return A @ A.T
+    if kind == "decay":          # the projected Gram of the workloads: geometric decay over a noise floor
+        r = max(1, n // 6)
+        return _psd(rng, np.concatenate([1e6 * 0.95 ** (2 * np.arange(r)), 1e2 * rng.uniform(0.5, 1.5, n - r)]))
+    if kind == "repeated":       # a multiple leading eigenvalue, then a zero block
+        r = max(1, n // 8)
+        return _psd(rng, np.concatenate([np.full(r, 4.0), np.zeros(n - r)]))
+    if kind == "lowrank":        # rank below k: zero eigenvalues among the k leading
+        B = rng.standard_normal((n, max(1, n // 10)))
+        return B @ B.T
+    if kind == "diagonal":       # already tridiagonal (every reflector is the identity)
+        return np.diag(rng.uniform(0.0, 1.0, n))
+    if kind == "zero":
+        return np.zeros((n, n))
+    raise ValueError(kind)
+
+
+TOP_CASES = ([("gauss", n, k) for n, k in [(1, 1), (2, 2), (3, 1), (5, 5), (7, 3), (63, 20), (64, 64), (65, 10),
+                                            (128, 40), (130, 65), (300, 50), (448, 60), (449, 30), (512, 100)]]
+             + [(kind, n, k) for kind in ("decay", "repeated", "lowrank", "diagonal", "zero")
+                for n, k in [(40, 12), (300, 50)]])
+
+
+@pytest.mark.parametrize("kind,n,k", TOP_CASES)
+def test_top_eigenpairs_match_lapack(env, kind, n, k):
+    """The k-leading-eigenpair solver of the factor step (tridiagonal
+    reduction, bisection, inverse iteration) against LAPACK's full
+    eigendecomposition: eigenvalues to n u lambda_max, unit residuals and
+    orthonormality at float64 level, and the projector onto the leading k
+    eigenvectors wherever lambda_k is separated from lambda_{k+1}."""
+    torch, rb = env
+    rng = np.random.default_rng(1000 * n + k)
+    Z = _top_case(kind, n, rng)
+    print(kind, n, k, flush=True)
+    lam, Vt = rb.sym_eig_top(torch.from_numpy(Z).cuda(), k)
+    lam, V = lam.cpu().numpy(), Vt.cpu().numpy().T
+    w, U = np.linalg.eigh(Z)
+    w, U = w[::-1], U[:, ::-1]
+    scale = max(abs(w[0]), 1e-300)
+    # (1e-300: the zero matrix, whose bisection ends within a few DBL_MIN of 0)
+    assert np.max(np.abs(lam - w[:k])) <= 4 * n * 2.0 ** -52 * scale + 1e-300
+    assert np.all(np.diff(lam) <= 0)
+    assert orthonormality_defect(V) <= 1e-12
+    assert np.linalg.norm(Z @ V - V * lam, axis=0).max() <= 1e-12 * scale + 1e-300
+    if k < n and w[k - 1] - w[k] > 1e-6 * scale:
+        P, Q = V @ V.T, U[:, :k] @ U[:, :k].T
+        assert np.linalg.norm(P - Q, 2) <= 1e-9
+    # rows are signed by their largest-magnitude entry
+    idx = np.argmax(np.abs(V), axis=0)
+    assert np.all(V[idx, np.arange(k)] > 0)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 6, 7, 18, 27, 31, 32, 33, 40, 64, 120, 300])
 def test_sym_eig_matches_lapack(env, n):
     """The device Jacobi solver (Alg. 2, steps 3-4) against LAPACK's
