@@ -28,8 +28,8 @@ namespace {
 
 constexpr int EIG_MAXB = 8;
 constexpr int EIG_NS_MAX = 8;                // n <= 64 * EIG_NS_MAX
-constexpr int EIG_THREADS = 1024;
-constexpr int EIG_WAVES = EIG_THREADS / 64;
+constexpr int SOLVE_THREADS = 512;          // eigenvalue / eigenvector workgroup (R <= 512)
+constexpr int SOLVE_WAVES = SOLVE_THREADS / 64;
 constexpr int EIG_ITERS = 3;                 // inverse-iteration solves
 constexpr int RED_THREADS = 1024;            // reduction workgroup
 constexpr int RED_WAVES = RED_THREADS / 64;
@@ -101,6 +101,14 @@ template <class T> __device__ inline T warp_min(T v) {
 // Number of eigenvalues of T (diagonal dl, squared off-diagonal e2l) below
 // x0 and x1, evaluated together.  A pivot smaller than pivmin in magnitude is
 // replaced by -pivmin, which keeps the recurrence finite.
+// 1/x from the hardware estimate and one Newton-Raphson step (relative
+// error about 2^-50, which perturbs the counts as a change of e^2 in the last
+// bits would)
+__device__ inline double rcp_nr1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 __device__ inline void sturm2(const double* dl, const double* e2l, int n, double pivmin, double x0, double x1,
                               int& c0, int& c1) {
   double q0 = dl[0] - x0, q1 = dl[0] - x1;
@@ -110,8 +118,8 @@ __device__ inline void sturm2(const double* dl, const double* e2l, int n, double
   c1 = q1 < 0.0;
   for (int i = 1; i < n; ++i) {
     const double di = dl[i], ee = e2l[i - 1];
-    q0 = (di - x0) - ee * rcp_nr(q0);
-    q1 = (di - x1) - ee * rcp_nr(q1);
+    q0 = (di - x0) - ee * rcp_nr1(q0);
+    q1 = (di - x1) - ee * rcp_nr1(q1);
     if (fabs(q0) < pivmin) q0 = -pivmin;
     if (fabs(q1) < pivmin) q1 = -pivmin;
     c0 += q0 < 0.0;
@@ -379,7 +387,7 @@ __global__ void __launch_bounds__(RED_THREADS) eig_reduce_kernel(EigArgs g) {
 
 // Steps 2-3 for one matrix per workgroup, from d and e of T.
 template <int NS>
-__global__ void __launch_bounds__(EIG_THREADS) eig_solve_kernel(EigArgs g) {
+__global__ void __launch_bounds__(SOLVE_THREADS) eig_solve_kernel(EigArgs g) {
   constexpr int NM = 64 * NS;
   extern __shared__ __attribute__((aligned(16))) double sm[];
   double* dl = sm;
@@ -393,7 +401,7 @@ __global__ void __launch_bounds__(EIG_THREADS) eig_solve_kernel(EigArgs g) {
   const int m = blockIdx.x;
   const int n = g.n[m], R = g.R[m];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int i = tid; i < n; i += EIG_THREADS) {
+  for (int i = tid; i < n; i += SOLVE_THREADS) {
     dl[i] = g.d[m][i];
     el[i] = g.e[m][i];
   }
@@ -499,28 +507,22 @@ __global__ void __launch_bounds__(EIG_THREADS) eig_solve_kernel(EigArgs g) {
     const double s = shl[r];
     double* xr = X + r * n;
     double acur = dl[0] - s, bcur = n > 1 ? el[0] : 0.0;
+    // branch-free: the pivot choice only selects operands
     for (int k = 0; k + 1 < n; ++k) {
       const double ck = el[k], an = dl[k + 1] - s, bn = k + 2 < n ? el[k + 1] : 0.0;
       const int o = k * R + r;
-      if (fabs(acur) >= fabs(ck)) {
-        const double mult = acur != 0.0 ? ck * rcp_nr(acur) : 0.0;
-        ainv[o] = rcp_nr(away_from_zero(acur, ptol));
-        bu[o] = bcur;
-        du[o] = 0.0;
-        cm[o] = mult;
-        piv[o] = 0;
-        acur = fma(-mult, bcur, an);
-        bcur = bn;
-      } else {
-        const double mult = acur * rcp_nr(ck);
-        ainv[o] = rcp_nr(away_from_zero(ck, ptol));
-        bu[o] = an;
-        du[o] = bn;
-        cm[o] = mult;
-        piv[o] = 1;
-        acur = fma(-mult, an, bcur);
-        bcur = -mult * bn;
-      }
+      const bool swap = fabs(acur) < fabs(ck);
+      const double piv_v = swap ? ck : acur;          // U(k, k)
+      const double other = swap ? acur : ck;          // entry eliminated below it
+      const double mult = piv_v != 0.0 ? other * rcp_nr(piv_v) : 0.0;
+      ainv[o] = rcp_nr(away_from_zero(piv_v, ptol));
+      bu[o] = swap ? an : bcur;
+      du[o] = swap ? bn : 0.0;
+      cm[o] = mult;
+      piv[o] = swap ? 1 : 0;
+      const double na = swap ? fma(-mult, an, bcur) : fma(-mult, bcur, an);
+      bcur = swap ? -mult * bn : bn;
+      acur = na;
       xr[k] = start_entry(k, r);
     }
     const int o = (n - 1) * R + r;
@@ -536,36 +538,57 @@ __global__ void __launch_bounds__(EIG_THREADS) eig_solve_kernel(EigArgs g) {
       const int r = tid;
       double* xr = X + r * n;
       double* yr = Y + r * n;
+      // blocks of 16 steps: all inputs of a block are loaded before any of
+      // its results is stored, so that the loads overlap
+      constexpr int B = 16;
       double yk = xr[0] * ptol;
-#pragma unroll 16
-      for (int k = 0; k + 1 < n; ++k) {
-        const int o = k * R + r;
-        double yn = xr[k + 1] * ptol;
-        const double mult = cm[o];
-        if (piv[o]) {
-          const double t = yk;
-          yk = yn;
-          yn = fma(-mult, yk, t);
-        } else {
-          yn = fma(-mult, yk, yn);
+      for (int k0 = 0; k0 + 1 < n; k0 += B) {
+        double xv[B], mv[B];
+        bool sv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int k = k0 + u < n - 1 ? k0 + u : n - 2;
+          xv[u] = xr[k + 1];
+          mv[u] = cm[k * R + r];
+          sv[u] = piv[k * R + r] != 0;
         }
-        yr[k] = yk;
-        yk = yn;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          if (k0 + u + 1 < n) {
+            // rows k and k+1 exchanged when piv: (top, bottom) = (y_{k+1}, y_k)
+            const double yn = xv[u] * ptol;
+            const double top = sv[u] ? yn : yk, bot = sv[u] ? yk : yn;
+            yr[k0 + u] = top;
+            yk = fma(-mv[u], top, bot);
+          }
+        }
       }
       yr[n - 1] = yk;
       double x1 = 0.0, x2 = 0.0;
-#pragma unroll 16
-      for (int k = n - 1; k >= 0; --k) {
-        const int o = k * R + r;
-        const double xk = fma(-du[o], x2, fma(-bu[o], x1, yr[k])) * ainv[o];
-        xr[k] = xk;
-        x2 = x1;
-        x1 = xk;
+      for (int k0 = n - 1; k0 >= 0; k0 -= B) {
+        double yv[B], dv[B], bv[B], av[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int k = k0 - u >= 0 ? k0 - u : 0;
+          yv[u] = yr[k];
+          dv[u] = du[k * R + r];
+          bv[u] = bu[k * R + r];
+          av[u] = ainv[k * R + r];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          if (k0 - u >= 0) {
+            const double xk = fma(-dv[u], x2, fma(-bv[u], x1, yv[u])) * av[u];
+            xr[k0 - u] = xk;
+            x2 = x1;
+            x1 = xk;
+          }
+        }
       }
     }
     __syncthreads();
     // modified Gram-Schmidt inside each cluster, then unit 2-norm
-    for (int c = wave; c < ncl; c += EIG_WAVES) {
+    for (int c = wave; c < ncl; c += SOLVE_WAVES) {
       const int s0 = cl[c], s1 = cl[c + 1];
       for (int j = s0; j < s1; ++j) {
         double xj[NS];
@@ -746,7 +769,7 @@ hipError_t launch_ns(EigArgs& a, int nmat, int gmax, int64_t rows_cap, int rmax,
   if ((e = hipFuncSetAttribute((const void*)eig_solve_kernel<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)sshm)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(eig_solve_kernel<NS>, dim3(nmat), dim3(EIG_THREADS), sshm, st, a);
+  hipLaunchKernelGGL(eig_solve_kernel<NS>, dim3(nmat), dim3(SOLVE_THREADS), sshm, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(eig_back_kernel<NS>, dim3(rmax, nmat), dim3(64), 0, st, a);
   return hipGetLastError();
