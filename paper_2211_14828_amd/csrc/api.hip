@@ -266,18 +266,15 @@ struct Arena {
   }
 };
 
-struct Buffers {
-  void* xpad = nullptr;    // bf16, (T / I_N) x I_Npad, zero-padded
-  void* xb[8] = {};        // each pipelined mode's blocked copy (bf16 or e4m3) and its e4m3 scales
-  void* xs[8] = {};
-  void* oblk = nullptr;    // the current mode's blocked sketch: bf16, then e4m3 + scales
+// Scratch of one mode's sketch, Gram and Krylov steps.  Large problems get
+// one set per concurrently running mode (see mode_lanes).
+struct Lane {
+  void* oblk = nullptr;    // the mode's blocked sketch: bf16, then e4m3 + scales
   void* om8 = nullptr;
   void* oscl = nullptr;
-  void* xt = nullptr;      // bf16, I_N x rows_pad: the last mode, transposed and zero-padded
   void* omegaT = nullptr;
   void* partial = nullptr;
   double* C = nullptr;
-  double* Qt[8] = {};      // per mode: S'_n x I_n basis rows
   double* CQt = nullptr;
   double* Yt = nullptr;
   double* Ytmp = nullptr;
@@ -287,6 +284,17 @@ struct Buffers {
   double* L = nullptr;
   int* flags = nullptr;
   double* ref2 = nullptr;
+};
+constexpr int kMaxLanes = 3;
+
+struct Buffers {
+  void* xpad = nullptr;    // bf16, (T / I_N) x I_Npad, zero-padded
+  void* xb[8] = {};        // each pipelined mode's blocked copy (bf16 or e4m3) and its e4m3 scales
+  void* xs[8] = {};
+  void* xt = nullptr;      // bf16, I_N x rows_pad: the last mode, transposed and zero-padded
+  Lane ln[kMaxLanes];
+  int lanes = 1;
+  double* Qt[8] = {};      // per mode: S'_n x I_n basis rows
   double* Z[8] = {};       // per mode: S'_n x S'_n
   double* lam[8] = {};
   double* Vt[8] = {};
@@ -301,6 +309,13 @@ struct Buffers {
   void* rpartial = nullptr;
   double* sums = nullptr;
 };
+
+// Modes whose sketch, Gram and Krylov steps may run at the same time on
+// their own streams: on large tensors the Krylov steps are chains of small
+// latency-bound kernels that overlap well with each other and with the next
+// mode's Gram kernel.  Fixed by the problem alone, so that the workspace is
+// the same for every caller.
+int mode_lanes(const Plan& P) { return (P.T >= ((int64_t)1 << 26) && P.N > 1) ? std::min(P.N, kMaxLanes) : 1; }
 
 // Jacobi info (2 ints per mode) and the per-mode direction counts, zeroed
 // together before a decomposition.
@@ -318,25 +333,31 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
       b.xb[n] = ar.take(block_copy_bytes(g.nkt, g.I));
       if (g.pelem == E_FP8) b.xs[n] = ar.take((size_t)g.nkt * block_rows(g.I) * 2);
     }
-    if (P.oblk_bytes) b.oblk = ar.take((size_t)P.oblk_bytes);
-    if (P.need_fp8 && P.oblk_bytes) {
-      b.om8 = ar.take((size_t)P.oblk_bytes / 2);
-      b.oscl = ar.take((size_t)P.oblk_bytes / 32 + 256);    // 256 bytes per K tile
-    }
   }
-  b.omegaT = ar.take((size_t)P.maxSJ * (P.need_pad ? 2 : es_g));   // the fallback of the mixed forms: bf16
-  b.partial = ar.take(P.partial_bytes);
-  b.C = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
+  b.lanes = mode_lanes(P);
+  for (int l = 0; l < b.lanes; ++l) {
+    Lane& L = b.ln[l];
+    if (P.need_pad && P.oblk_bytes) {
+      L.oblk = ar.take((size_t)P.oblk_bytes);
+      if (P.need_fp8) {
+        L.om8 = ar.take((size_t)P.oblk_bytes / 2);
+        L.oscl = ar.take((size_t)P.oblk_bytes / 32 + 256);    // 256 bytes per K tile
+      }
+    }
+    L.omegaT = ar.take((size_t)P.maxSJ * (P.need_pad ? 2 : es_g));   // the fallback of the mixed forms: bf16
+    L.partial = ar.take(P.partial_bytes);
+    L.C = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
+    L.CQt = (double*)ar.take((size_t)P.maxSp * P.maxI * 8);
+    L.Yt = (double*)ar.take((size_t)P.maxS * P.maxI * 8);
+    L.Ytmp = (double*)ar.take((size_t)P.maxS * P.maxI * 8);
+    L.Pm = (double*)ar.take((size_t)P.maxS * P.maxSp * 8);
+    L.dscratch = (double*)ar.take(kDgemmScratch);
+    L.G = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
+    L.L = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
+    L.flags = (int*)ar.take((size_t)P.maxSp * 4);
+    L.ref2 = (double*)ar.take((size_t)P.maxS * 8);
+  }
   for (int n = 0; n < P.N; ++n) b.Qt[n] = (double*)ar.take((size_t)P.m[n].Sp * P.m[n].I * 8);
-  b.CQt = (double*)ar.take((size_t)P.maxSp * P.maxI * 8);
-  b.Yt = (double*)ar.take((size_t)P.maxS * P.maxI * 8);
-  b.Ytmp = (double*)ar.take((size_t)P.maxS * P.maxI * 8);
-  b.Pm = (double*)ar.take((size_t)P.maxS * P.maxSp * 8);
-  b.dscratch = (double*)ar.take(kDgemmScratch);
-  b.G = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
-  b.L = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
-  b.flags = (int*)ar.take((size_t)P.maxSp * 4);
-  b.ref2 = (double*)ar.take((size_t)P.maxS * 8);
   for (int n = 0; n < P.N; ++n) {
     const int64_t Sp = P.m[n].Sp;
     b.Z[n] = (double*)ar.take((size_t)Sp * Sp * 8);
@@ -397,12 +418,18 @@ rbki_status convert_input(const Plan& P, const Buffers& b, const void* X, hipStr
 constexpr double TAU_REL = 1e-12;   // pivot vs its own column: direction already spanned
 constexpr double TAU_ABS = 1e-10;   // pivot vs the block before projection (matches the oracle)
 
-rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, bool with_factor,
-                     hipStream_t st) {
+// heavy_wait / heavy_done (nullable): events that the sketch and Gram
+// kernels wait for and record, so that those throughput-bound kernels of
+// concurrently running modes follow each other.
+rbki_status run_mode(const Plan& P, const Buffers& b, int lane, const void* xsrc, int n, bool with_factor,
+                     hipStream_t st, hipEvent_t heavy_wait = nullptr, hipEvent_t heavy_done = nullptr) {
+  const Lane& L = b.ln[lane];
+  dgemm_set_scratch(L.dscratch, kDgemmScratch);
+  if (heavy_wait) HIPCHK(hipStreamWaitEvent(st, heavy_wait, 0));
   const ModeGeom& g = P.m[n];
   const int64_t I = g.I, S = g.S, Sp = g.Sp;
   double* Qt = b.Qt[n];
-  // C -> b.C (I x I), W^T -> b.Yt (S x I)
+  // C -> L.C (I x I), W^T -> L.Yt (S x I)
   if (P.need_pad) {
     int64_t A, Bp;
     padded_view(P, n, A, Bp);
@@ -415,78 +442,80 @@ rbki_status run_mode(const Plan& P, const Buffers& b, const void* xsrc, int n, b
       (void)last;
       {
         ProfScope ps("omega", st);
-        HIPCHK(launch_omega_block(P.seed, n, S, g.J, g.B, IN, g.nkt, KT, b.oblk, st));
-        if (g.pelem == E_FP8) HIPCHK(launch_quantize_omega(b.oblk, g.nkt, b.om8, b.oscl, st));
+        HIPCHK(launch_omega_block(P.seed, n, S, g.J, g.B, IN, g.nkt, KT, L.oblk, st));
+        if (g.pelem == E_FP8) HIPCHK(launch_quantize_omega(L.oblk, g.nkt, L.om8, L.oscl, st));
       }
       GramArgs ga = gram_plan_pipe(g.pelem, A, I, Bp, (int)S, cu_count());
       ga.X = b.xb[n];
-      ga.omegaT = g.pelem == E_FP8 ? b.om8 : b.oblk;
+      ga.omegaT = g.pelem == E_FP8 ? L.om8 : L.oblk;
       ga.xexp = (const unsigned char*)b.xs[n];
-      ga.xexp_om = (const unsigned char*)b.oscl;
-      ga.partial = b.partial;
+      ga.xexp_om = (const unsigned char*)L.oscl;
+      ga.partial = L.partial;
       {
         ProfScope ps("gram", st);
         HIPCHK(launch_gram_pipe(g.pelem, ga, st));
       }
-      HIPCHK(launch_gram_pipe_reduce(ga, b.C, b.Yt, st));
+      HIPCHK(launch_gram_pipe_reduce(ga, L.C, L.Yt, st));
     } else {
       // small I or a sketch wider than 64: the bf16 kernel on the padded copies
       {
         ProfScope ps("omega", st);
-        HIPCHK(launch_omega_pad(P.seed, n, S, g.J, g.B, P.dims[P.N - 1], A * Bp, b.omegaT, st));
+        HIPCHK(launch_omega_pad(P.seed, n, S, g.J, g.B, P.dims[P.N - 1], A * Bp, L.omegaT, st));
       }
       GramArgs ga = gram_plan(E_BF16, A, I, Bp, (int)S, cu_count());
       ga.X = last ? b.xt : b.xpad;
-      ga.omegaT = b.omegaT;
-      ga.partial = b.partial;
+      ga.omegaT = L.omegaT;
+      ga.partial = L.partial;
       {
         ProfScope ps("gram", st);
         HIPCHK(launch_gram_main(E_BF16, ga, st));
       }
-      HIPCHK(launch_gram_reduce(E_BF16, ga, b.C, b.Yt, st));
+      HIPCHK(launch_gram_reduce(E_BF16, ga, L.C, L.Yt, st));
     }
   } else {
     {
       ProfScope ps("omega", st);
-      HIPCHK(launch_omega(P.gelem, P.seed, n, S * g.J, b.omegaT, st));
+      HIPCHK(launch_omega(P.gelem, P.seed, n, S * g.J, L.omegaT, st));
     }
     GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)S, cu_count());
     ga.X = xsrc;
-    ga.omegaT = b.omegaT;
-    ga.partial = b.partial;
+    ga.omegaT = L.omegaT;
+    ga.partial = L.partial;
     {
       ProfScope ps("gram", st);
       HIPCHK(launch_gram_main(P.gelem, ga, st));
     }
-    HIPCHK(launch_gram_reduce(P.gelem, ga, b.C, b.Yt, st));
+    HIPCHK(launch_gram_reduce(P.gelem, ga, L.C, L.Yt, st));
   }
+
+  if (heavy_done) HIPCHK(hipEventRecord(heavy_done, st));
 
   // block 0: Q_0 = orth(W).  The first pass of every block's CholeskyQR2
   // also keeps the basis at most I_n wide: once it spans the whole space the
   // later blocks are rounding noise and are dropped whatever their norm.
   int* used = b.used + (size_t)n * (P.q + 2);
-  HIPCHK(row_norms2(b.Yt, S, I, b.ref2, st));
-  HIPCHK(chol_orth(b.Yt, b.Ytmp, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st, DimBudget{used, used + 1, I}));
-  HIPCHK(chol_orth(b.Ytmp, Qt, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
+  HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
+  HIPCHK(chol_orth(L.Yt, L.Ytmp, S, I, L.G, L.L, L.flags, L.ref2, TAU_REL, TAU_ABS, st, DimBudget{used, used + 1, I}));
+  HIPCHK(chol_orth(L.Ytmp, Qt, S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
   for (int j = 1; j <= P.q; ++j) {
     const int64_t m = S * j;                     // rows of the basis so far
     const double* Qlast = Qt + (m - S) * I;
     // Y_j^T = Q_{j-1}^T C  (C symmetric)
-    HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qlast, I, b.C, I, 0.0, b.Yt, I, st));
-    HIPCHK(copy_rows_f64(b.CQt + (m - S) * I, I, b.Yt, I, S, I, st));
-    HIPCHK(row_norms2(b.Yt, S, I, b.ref2, st));
+    HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qlast, I, L.C, I, 0.0, L.Yt, I, st));
+    HIPCHK(copy_rows_f64(L.CQt + (m - S) * I, I, L.Yt, I, S, I, st));
+    HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
     for (int pass = 0; pass < 2; ++pass) {       // remove earlier blocks, twice
-      HIPCHK(dgemm(0, 1, S, m, I, 1.0, b.Yt, I, Qt, I, 0.0, b.Pm, m, st));
-      HIPCHK(dgemm(0, 0, S, I, m, -1.0, b.Pm, m, Qt, I, 1.0, b.Yt, I, st));
+      HIPCHK(dgemm(0, 1, S, m, I, 1.0, L.Yt, I, Qt, I, 0.0, L.Pm, m, st));
+      HIPCHK(dgemm(0, 0, S, I, m, -1.0, L.Pm, m, Qt, I, 1.0, L.Yt, I, st));
     }
-    HIPCHK(chol_orth(b.Yt, b.Ytmp, S, I, b.G, b.L, b.flags, b.ref2, TAU_REL, TAU_ABS, st,
+    HIPCHK(chol_orth(L.Yt, L.Ytmp, S, I, L.G, L.L, L.flags, L.ref2, TAU_REL, TAU_ABS, st,
                      DimBudget{used + j, used + j + 1, I}));
-    HIPCHK(chol_orth(b.Ytmp, Qt + m * I, S, I, b.G, b.L, b.flags, nullptr, TAU_REL, 0.0, st));
+    HIPCHK(chol_orth(L.Ytmp, Qt + m * I, S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
   }
   if (!with_factor) return RBKI_OK;
   // C Q_q, then Z = Q^T (C Q) (Alg. 2, step 3)
-  HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt + (Sp - S) * I, I, b.C, I, 0.0, b.CQt + (Sp - S) * I, I, st));
-  HIPCHK(dgemm(0, 1, Sp, Sp, I, 1.0, Qt, I, b.CQt, I, 0.0, b.Z[n], Sp, st));
+  HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt + (Sp - S) * I, I, L.C, I, 0.0, L.CQt + (Sp - S) * I, I, st));
+  HIPCHK(dgemm(0, 1, Sp, Sp, I, 1.0, Qt, I, L.CQt, I, 0.0, b.Z[n], Sp, st));
   return RBKI_OK;
 }
 
@@ -739,7 +768,7 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
   Arena ar(workspace, ws_bytes);
   Buffers b;
   carve(P, ar, b);
-  dgemm_set_scratch(b.dscratch, kDgemmScratch);
+  dgemm_set_scratch(b.ln[0].dscratch, kDgemmScratch);
   const void* xsrc = X;
   if (P.need_pad) {
     ProfScope ps("convert", st);
@@ -747,7 +776,7 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
     if (s != RBKI_OK) return s;
   }
   HIPCHK(fill_zero(b.info, counters_bytes(P), st));
-  s = run_mode(P, b, xsrc, mode, false, st);
+  s = run_mode(P, b, 0, xsrc, mode, false, st);
   if (s != RBKI_OK) return s;
   const ModeGeom& g = P.m[mode];
   // compact the kept basis vectors (rows whose norm is nonzero) into Qt
@@ -793,6 +822,60 @@ rbki_status finish_result(const HostResult& hr, double* rel_err) {
 void set_error(rbki_status s, const char* msg) { fail(s, "%s", msg); }
 }  // namespace rbki
 
+// Helper streams of the current device for modes that run beside the
+// caller's stream (created once, default priority, non-blocking).
+static hipStream_t lane_stream(int lane) {
+  static std::mutex mu;
+  static std::map<int, std::vector<hipStream_t>> pool;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  std::vector<hipStream_t>& v = pool[dev];
+  while ((int)v.size() < kMaxLanes - 1) {
+    hipStream_t h = nullptr;
+    if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    v.push_back(h);
+  }
+  return v[lane - 1];
+}
+
+// Alg. 2, steps 1-3 for every mode.  Mode n uses scratch set n % lanes; with
+// more than one set the sets run on their own streams, forked from and
+// joined back to st by events (the request server keeps one stream per
+// request).  Each mode does the same work either way.
+static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, hipStream_t st) {
+  const int lanes = P.concurrent ? 1 : b.lanes;
+  hipStream_t ls[kMaxLanes] = {st, st, st};
+  hipEvent_t ev[kMaxLanes] = {};
+  for (int l = 1; l < lanes; ++l) {
+    ls[l] = lane_stream(l);
+    if (!ls[l]) return fail(RBKI_E_HIP, "cannot create a helper stream");
+  }
+  if (lanes > 1) {
+    for (int l = 0; l < lanes; ++l) HIPCHK(hipEventCreateWithFlags(&ev[l], hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ev[0], st));
+    for (int l = 1; l < lanes; ++l) HIPCHK(hipStreamWaitEvent(ls[l], ev[0], 0));
+  }
+  // the sketch and Gram kernels of successive modes one after the other,
+  // the Krylov steps beside them
+  hipEvent_t heavy[8] = {};
+  if (lanes > 1)
+    for (int n = 0; n < P.N; ++n) HIPCHK(hipEventCreateWithFlags(&heavy[n], hipEventDisableTiming));
+  rbki_status s = RBKI_OK;
+  for (int n = 0; n < P.N && s == RBKI_OK; ++n)
+    s = run_mode(P, b, n % b.lanes, xsrc, n, true, ls[n % lanes], n > 0 ? heavy[n - 1] : nullptr, heavy[n]);
+  if (lanes > 1) {
+    for (int l = 1; l < lanes; ++l) {
+      HIPCHK(hipEventRecord(ev[l], ls[l]));
+      HIPCHK(hipStreamWaitEvent(st, ev[l], 0));
+    }
+    for (int l = 0; l < lanes; ++l) HIPCHK(hipEventDestroy(ev[l]));
+    for (int n = 0; n < P.N; ++n) HIPCHK(hipEventDestroy(heavy[n]));
+  }
+  dgemm_set_scratch(b.ln[0].dscratch, kDgemmScratch);
+  return s;
+}
+
 static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
                         int out_type, void* workspace, size_t ws_bytes, double* rel_err, hipStream_t st, Plan& P,
                         Buffers& b, void** core_chain, HostResult* async_res) {
@@ -806,7 +889,7 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
     return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
   Arena ar(workspace, ws_bytes);
   carve(P, ar, b);
-  dgemm_set_scratch(b.dscratch, kDgemmScratch);
+  dgemm_set_scratch(b.ln[0].dscratch, kDgemmScratch);
   const void* xsrc = X;
   if (P.need_pad) {
     ProfScope ps("convert", st);
@@ -814,10 +897,8 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
     if (s != RBKI_OK) return s;
   }
   HIPCHK(fill_zero(b.info, counters_bytes(P), st));
-  for (int n = 0; n < P.N; ++n) {
-    s = run_mode(P, b, xsrc, n, true, st);
-    if (s != RBKI_OK) return s;
-  }
+  s = run_modes(P, b, xsrc, st);
+  if (s != RBKI_OK) return s;
   s = run_factors(P, b, st);
   if (s != RBKI_OK) return s;
   for (int n = 0; n < P.N; ++n)
