@@ -638,7 +638,8 @@ rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, c
     const int64_t I0 = P.dims[0], J0 = P.T / P.dims[0], R0 = P.m[0].R;
     HIPCHK(convert_tensor(E_F64, b.Ut64[0], P.celem, b.Uop, R0 * I0, st));
     ProfScope ps("error", st);
-    HIPCHK(launch_residual(P.xelem, X, P.celem, b.Uop, src, I0, J0, R0, b.sums, b.rpartial, 0, st));
+    // precision forms: U H from split bfloat16 operands, x and the sums exact
+    HIPCHK(launch_residual(P.xelem, X, P.celem, b.Uop, src, I0, J0, R0, b.sums, b.rpartial, 0, st, P.need_pad));
   }
   HIPCHK(hipMemcpyAsync(sums_host, b.sums, 16, hipMemcpyDeviceToHost, st));
   (void)ce;

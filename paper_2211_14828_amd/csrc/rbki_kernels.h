@@ -163,9 +163,11 @@ hipError_t launch_ttm_padded(const void* Xpad, int64_t A, int64_t I, int64_t B, 
 // Sum over all entries of (X - Uh)^2 and X^2 where Uh[i, j] = sum_r U[i, r] H[r, j]
 // (X viewed as I x J row-major, the mode-0 unfolding); partial sums in
 // float64, returned in out[0] (residual) and out[1] (norm), reduced in a fixed order.
+// bf16_products: the streaming form forms U H from split bfloat16 operands
+// (hi + lo parts, relative error about 2^-16).
 hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* Ut, const void* H,
                            int64_t I, int64_t J, int64_t R, double* out, void* work,
-                           size_t work_bytes, hipStream_t s);
+                           size_t work_bytes, hipStream_t s, bool bf16_products = false);
 size_t residual_work_bytes(int64_t I, int64_t J);
 
 // Element conversions of the whole tensor.

@@ -250,19 +250,24 @@ __global__ void sum_pairs_kernel(const double* partial, int64_t n, double* out) 
 }
 
 // ------------------------------------------------------------------------
-// Streaming reconstruction-error pass for float32 operands and R <= 64.
-// Workgroup w owns columns j0 .. j0+127 of X_(0) (I x J) and walks every
-// 128-row tile of it: H(:, j0..j0+127) is staged once in LDS as [j][k], the
-// rows of U (I x 64, zero-padded) are read straight from L2 into MFMA
-// fragments, and the tile of X is requested before the MFMAs so that its HBM
-// reads are in flight while Xhat = U H is formed.  (x - xhat)^2 and x^2 are
-// accumulated in float64; Xhat is never written.
+// Streaming reconstruction-error pass for R <= 64.  Workgroup w owns columns
+// j0 .. j0+127 of X_(0) (I x J) and walks every 128-row tile of it: H(:,
+// j0..j0+127) is staged once in LDS as [j][k], the rows of U (I x 64,
+// zero-padded) are read straight from L2 into MFMA fragments, and the tile of
+// X is requested before the MFMAs so that its HBM reads are in flight while
+// Xhat = U H is formed.  (x - xhat)^2 and x^2 are accumulated in float64;
+// Xhat is never written.  PE is the product type: float32 (32x32x2 MFMA) or,
+// for the precision forms, split bfloat16: each operand is hi + lo with both
+// parts bfloat16, and U H = Uh Hh + Uh Hl + Ul Hh on 32x32x16 MFMA with
+// float32 accumulation (relative error about 2^-16; a fifth of the
+// matrix-core time of the float32 form).
 struct ResArgs {
-  const float* Up;      // I x 64 row-major, columns >= R zero
+  const void* Up;       // I x 64 row-major, columns >= R zero: float32, or split
+                        // bfloat16 (hi parts, then the I x 64 lo parts)
   const float* H;       // R x J row-major
   const void* X;        // I x J row-major
   int64_t I, J;
-  int R, nkt;           // nkt = ceil(R / 32) K tiles of 32
+  int R, nkt;           // nkt = ceil(R / 32) K tiles of 32 (float32 products)
   double* partial;      // [gridDim.x] x 2
 };
 
@@ -271,8 +276,8 @@ __device__ inline float x_to_f(XT v);
 template <> __device__ inline float x_to_f<float>(float v) { return v; }
 template <> __device__ inline float x_to_f<bf16_t>(bf16_t v) { return bf16_to_f32(v); }
 
-template <class XT>
-__global__ void __launch_bounds__(256, 2) residual_kernel(ResArgs a) {
+template <class XT, int PE>
+__global__ void __launch_bounds__(256, PE == E_F32 ? 2 : 1) residual_kernel(ResArgs a) {
   __shared__ __attribute__((aligned(16))) char ldsB[2][TILE * LDS_ROW];
   __shared__ double red[2][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -280,7 +285,8 @@ __global__ void __launch_bounds__(256, 2) residual_kernel(ResArgs a) {
   const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
   const int64_t j0 = (int64_t)blockIdx.x * TILE;
 
-  // H block -> LDS, transposed: chunk c holds 4 consecutive j at one k
+  // H block -> LDS, transposed: chunk c holds 4 consecutive j at one k.
+  // float32: [k / 32][j][k % 32]; bfloat16: [j][k] (64 k in one row)
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int c = tid + 256 * q;
@@ -290,21 +296,31 @@ __global__ void __launch_bounds__(256, 2) residual_kernel(ResArgs a) {
     const int64_t jc = j0 + jj < a.J ? j0 + jj : 0;
     float4 v = *(const float4*)(a.H + (int64_t)kc * a.J + jc);
     if (!ok) v = make_float4(0.f, 0.f, 0.f, 0.f);
-    char* base = ldsB[kk >> 5] + (kk & 31) * 4;
-    *(float*)(base + (jj + 0) * LDS_ROW) = v.x;
-    *(float*)(base + (jj + 1) * LDS_ROW) = v.y;
-    *(float*)(base + (jj + 2) * LDS_ROW) = v.z;
-    *(float*)(base + (jj + 3) * LDS_ROW) = v.w;
+    if (PE == E_F32) {
+      char* base = ldsB[kk >> 5] + (kk & 31) * 4;
+      *(float*)(base + (jj + 0) * LDS_ROW) = v.x;
+      *(float*)(base + (jj + 1) * LDS_ROW) = v.y;
+      *(float*)(base + (jj + 2) * LDS_ROW) = v.z;
+      *(float*)(base + (jj + 3) * LDS_ROW) = v.w;
+    } else {
+      // hi parts in ldsB[0], lo parts in ldsB[1], [j][k] with 64 k per row
+      const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bf16_t hi = f32_to_bf16(vv[e]);
+        *(bf16_t*)(ldsB[0] + kk * 2 + (jj + e) * LDS_ROW) = hi;
+        *(bf16_t*)(ldsB[1] + kk * 2 + (jj + e) * LDS_ROW) = f32_to_bf16(vv[e] - bf16_to_f32(hi));
+      }
+    }
   }
   __syncthreads();
 
   const XT* X = (const XT*)a.X;
   double res = 0.0, nrm = 0.0;
   const int64_t nit = ceil_div(a.I, TILE);
-  for (int64_t it = 0; it < nit; ++it) {
+  // a tile of X in the accumulator layout (rows clamped into the matrix)
+  auto load_x = [&](int64_t it, XT (&xv)[64]) {
     const int64_t i0 = it * TILE;
-    // 1. this tile of X, in the accumulator layout (clamped, masked later)
-    XT xv[64];
 #pragma unroll
     for (int j = 0; j < 64; ++j) {
       int row, col;
@@ -314,33 +330,73 @@ __global__ void __launch_bounds__(256, 2) residual_kernel(ResArgs a) {
       jj = jj < a.J ? jj : a.J - 1;
       xv[j] = X[i * a.J + jj];
     }
-    // 2. Xhat tile = U(i0.., :) H(:, j0..)
+  };
+  // Xhat tile = U(i0.., :) H(:, j0..), then (x - xhat)^2 and x^2 into the
+  // sums; rows past I (a tile past the end included) add nothing
+  auto tile = [&](int64_t it, const XT (&xv)[64]) {
+    const int64_t i0 = it * TILE;
     Mma<E_F32>::Frag f;
     Mma<E_F32>::zero(f);
-    for (int kt = 0; kt < a.nkt; ++kt) {
-      float av[2][16], bv[2][16];
+    if (PE == E_F32) {
+      const float* Up = (const float*)a.Up;
+      for (int kt = 0; kt < a.nkt; ++kt) {
+        float av[2][16], bv[2][16];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          int64_t i = i0 + wr + m * 32 + lr;
+          i = i < a.I ? i : a.I - 1;
+          const float4* pa = (const float4*)(Up + i * 64 + kt * 32 + half * 16);
+          const float4* pb = (const float4*)(ldsB[kt] + (wc + m * 32 + lr) * LDS_ROW + half * 64);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float4 va = pa[q], vb = pb[q];
+            av[m][4 * q] = va.x; av[m][4 * q + 1] = va.y; av[m][4 * q + 2] = va.z; av[m][4 * q + 3] = va.w;
+            bv[m][4 * q] = vb.x; bv[m][4 * q + 1] = vb.y; bv[m][4 * q + 2] = vb.z; bv[m][4 * q + 3] = vb.w;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t)
+#pragma unroll
+          for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+              f.c[m * 2 + n] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[m][t], bv[n][t], f.c[m * 2 + n], 0, 0, 0);
+      }
+    } else {
+      // lane half h takes k = 32 h .. 32 h + 31 of both operands, 8 per MFMA
+      const bf16_t* Uh = (const bf16_t*)a.Up;
+      const bf16_t* Ul = Uh + a.I * 64;
+      bf16x8_t ah[2][4], al[2][4];
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
         int64_t i = i0 + wr + m * 32 + lr;
-        i = i < a.I ? i : a.I - 1;          // rows past I are never accumulated
-        const float4* pa = (const float4*)(a.Up + i * 64 + kt * 32 + half * 16);
-        const float4* pb = (const float4*)(ldsB[kt] + (wc + m * 32 + lr) * LDS_ROW + half * 64);
+        i = i < a.I ? i : a.I - 1;
+        const bf16x8_t* ph = (const bf16x8_t*)(Uh + i * 64 + half * 32);
+        const bf16x8_t* pl = (const bf16x8_t*)(Ul + i * 64 + half * 32);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const float4 va = pa[q], vb = pb[q];
-          av[m][4 * q] = va.x; av[m][4 * q + 1] = va.y; av[m][4 * q + 2] = va.z; av[m][4 * q + 3] = va.w;
-          bv[m][4 * q] = vb.x; bv[m][4 * q + 1] = vb.y; bv[m][4 * q + 2] = vb.z; bv[m][4 * q + 3] = vb.w;
+          ah[m][q] = ph[q];
+          al[m][q] = pl[q];
         }
       }
 #pragma unroll
-      for (int t = 0; t < 16; ++t)
+      for (int t = 0; t < 4; ++t) {
+        bf16x8_t bh[2], bl[2];
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+          bh[n] = ((const bf16x8_t*)(ldsB[0] + (wc + n * 32 + lr) * LDS_ROW + half * 64))[t];
+          bl[n] = ((const bf16x8_t*)(ldsB[1] + (wc + n * 32 + lr) * LDS_ROW + half * 64))[t];
+        }
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-          for (int n = 0; n < 2; ++n)
-            f.c[m * 2 + n] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[m][t], bv[n][t], f.c[m * 2 + n], 0, 0, 0);
+          for (int n = 0; n < 2; ++n) {
+            f.c[m * 2 + n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[m][t], bh[n], f.c[m * 2 + n], 0, 0, 0);
+            f.c[m * 2 + n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[m][t], bl[n], f.c[m * 2 + n], 0, 0, 0);
+            f.c[m * 2 + n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[m][t], bh[n], f.c[m * 2 + n], 0, 0, 0);
+          }
+      }
     }
-    // 3. fold the tile into the sums
 #pragma unroll
     for (int j = 0; j < 64; ++j) {
       int row, col;
@@ -350,6 +406,23 @@ __global__ void __launch_bounds__(256, 2) residual_kernel(ResArgs a) {
       const double d = ok ? x - (double)Mma<E_F32>::get(f, j) : 0.0;
       res = fma(d, d, res);
       nrm = fma(x, x, nrm);
+    }
+  };
+  if (PE == E_F32) {
+    for (int64_t it = 0; it < nit; ++it) {
+      XT xv[64];
+      load_x(it, xv);
+      tile(it, xv);
+    }
+  } else {
+    // two tiles per round, each tile's X requested a tile ahead of its use
+    XT xa[64], xb[64];
+    load_x(0, xa);
+    for (int64_t it = 0; it < nit; it += 2) {
+      load_x(it + 1 < nit ? it + 1 : nit - 1, xb);
+      tile(it, xa);
+      load_x(it + 2 < nit ? it + 2 : nit - 1, xa);
+      tile(it + 1, xb);
     }
   }
   res = warp_sum(res);
@@ -365,12 +438,22 @@ __global__ void __launch_bounds__(256, 2) residual_kernel(ResArgs a) {
   }
 }
 
-// U (given as Ut, R x I float32) -> Up (I x 64 float32, zero-padded columns)
-__global__ void pad_u_kernel(const float* Ut, int64_t R, int64_t I, float* Up) {
+// U (given as Ut, R x I float32) -> Up (I x 64, zero-padded columns): float32,
+// or split bfloat16 (hi = rounded value, lo = rounded remainder, the lo block
+// after the hi block)
+template <class T>
+__global__ void pad_u_kernel(const float* Ut, int64_t R, int64_t I, T* Up) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < I * 64;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e >> 6, k = e & 63;
-    Up[e] = k < R ? Ut[k * I + i] : 0.f;
+    const float v = k < R ? Ut[k * I + i] : 0.f;
+    if constexpr (sizeof(T) == 4) {
+      Up[e] = v;
+    } else {
+      const bf16_t hi = f32_to_bf16(v);
+      Up[e] = hi;
+      Up[I * 64 + e] = f32_to_bf16(v - bf16_to_f32(hi));
+    }
   }
 }
 
@@ -503,15 +586,16 @@ size_t residual_work_bytes(int64_t I, int64_t J) {
 }
 
 hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* Ut, const void* H, int64_t I,
-                           int64_t J, int64_t R, double* out, void* work, size_t, hipStream_t s) {
+                           int64_t J, int64_t R, double* out, void* work, size_t, hipStream_t s, bool bf16_products) {
   const int64_t tiles = std::max<int64_t>(ceil_div(I, TILE) * ceil_div(J, TILE), ceil_div(J, TILE));
   double* partial = (double*)work;
   if (op_elem == E_F32 && R <= 64 && (x_elem == E_F32 || x_elem == E_BF16) && J % 4 == 0 && aligned16(H) &&
       ceil_div(J, TILE) <= 0x7fffffff) {
     // streaming form
-    float* Up = (float*)((char*)work + ((tiles * 16 + 255) / 256) * 256);
-    hipLaunchKernelGGL(pad_u_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(I * 64, 256), 4096)), dim3(256), 0,
-                       s, (const float*)Ut, R, I, Up);
+    void* Up = (char*)work + ((tiles * 16 + 255) / 256) * 256;
+    const dim3 pgrid((unsigned)std::min<int64_t>(ceil_div(I * 64, 256), 4096));
+    if (bf16_products) hipLaunchKernelGGL(pad_u_kernel<bf16_t>, pgrid, dim3(256), 0, s, (const float*)Ut, R, I, (bf16_t*)Up);
+    else hipLaunchKernelGGL(pad_u_kernel<float>, pgrid, dim3(256), 0, s, (const float*)Ut, R, I, (float*)Up);
     ResArgs ra;
     ra.Up = Up;
     ra.H = (const float*)H;
@@ -522,8 +606,13 @@ hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* U
     ra.nkt = (int)ceil_div(R, 32);
     ra.partial = partial;
     const dim3 grid((unsigned)ceil_div(J, TILE));
-    if (x_elem == E_F32) hipLaunchKernelGGL(residual_kernel<float>, grid, dim3(256), 0, s, ra);
-    else hipLaunchKernelGGL(residual_kernel<bf16_t>, grid, dim3(256), 0, s, ra);
+    if (bf16_products) {
+      if (x_elem == E_F32) hipLaunchKernelGGL((residual_kernel<float, E_BF16>), grid, dim3(256), 0, s, ra);
+      else hipLaunchKernelGGL((residual_kernel<bf16_t, E_BF16>), grid, dim3(256), 0, s, ra);
+    } else {
+      if (x_elem == E_F32) hipLaunchKernelGGL((residual_kernel<float, E_F32>), grid, dim3(256), 0, s, ra);
+      else hipLaunchKernelGGL((residual_kernel<bf16_t, E_F32>), grid, dim3(256), 0, s, ra);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(1024), 0, s, (const double*)partial, (int64_t)grid.x, out);
