@@ -129,6 +129,8 @@ struct Plan {
   bool need_xt16 = false;    // zero-padded bf16 transposed copy Xt (last mode on the Gram fallback)
   bool need_fp8 = false;     // e4m3 blocked copies with per-32 scales (fp8 Gram products)
   bool lead_pipe = false;    // some leading mode is pipelined: the one-pass blocked copy also writes Xpad
+  bool first_blocked = false;   // the first mode product reads that mode's blocked copy
+  bool need_xpad = false;    // some reader of Xpad remains (a Gram fallback or the first product)
   bool concurrent = false;   // runs beside other solves on the device (request server)
   int64_t oblk_bytes = 0;                   // one mode's blocked bf16 sketch (the largest)
   int64_t in_pad = 0;        // last dimension padded to a multiple of 64
@@ -234,8 +236,16 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
       P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(ga, P.gelem));
     }
   }
-  if (P.need_pad)
-    for (int n = 0; n + 1 < P.N; ++n) P.lead_pipe = P.lead_pipe || P.m[n].pipe;
+  if (P.need_pad) {
+    bool fallback_lead = false;
+    for (int n = 0; n + 1 < P.N; ++n) {
+      P.lead_pipe = P.lead_pipe || P.m[n].pipe;
+      fallback_lead = fallback_lead || !P.m[n].pipe;
+    }
+    const ModeGeom& gf = P.m[P.first_mode];
+    P.first_blocked = P.first_mode < P.N - 1 && gf.pipe && gf.R <= 64;
+    P.need_xpad = fallback_lead || !P.first_blocked;
+  }
   // chain sizes: core chain starting with first_mode, then ascending; the
   // reconstruction chain expands modes 1..N-1 from the core.
   int64_t cur[8];
@@ -292,6 +302,7 @@ struct Buffers {
   void* xb[8] = {};        // each pipelined mode's blocked copy (bf16 or e4m3) and its e4m3 scales
   void* xs[8] = {};
   void* xt = nullptr;      // bf16, I_N x rows_pad: the last mode, transposed and zero-padded
+  void* u16 = nullptr;     // the first product's factor as bf16 [64][block rows]
   Lane ln[kMaxLanes];
   int lanes = 1;
   double* Qt[8] = {};      // per mode: S'_n x I_n basis rows
@@ -325,7 +336,8 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
   const int es_g = elem_size(P.gelem);
   if (P.need_pad) {
     const size_t rows = (size_t)(P.T / P.dims[P.N - 1]);
-    b.xpad = ar.take(rows * P.in_pad * 2);
+    if (P.need_xpad) b.xpad = ar.take(rows * P.in_pad * 2);
+    if (P.first_blocked) b.u16 = ar.take((size_t)64 * block_rows(P.m[P.first_mode].I) * 2);
     if (P.need_xt16) b.xt = ar.take((size_t)P.dims[P.N - 1] * P.rows_pad * 2);
     for (int n = 0; n < P.N; ++n) {
       const ModeGeom& g = P.m[n];
@@ -403,7 +415,8 @@ rbki_status convert_input(const Plan& P, const Buffers& b, const void* X, hipStr
       outs[n] = b.xb[n];
       scs[n] = b.xs[n];
     }
-    HIPCHK(launch_block_copy_lead(P.xelem, P.need_fp8 ? E_FP8 : E_BF16, X, P.N, P.dims, want, outs, scs, b.xpad, st));
+    HIPCHK(launch_block_copy_lead(P.xelem, P.need_fp8 ? E_FP8 : E_BF16, X, P.N, P.dims, want, outs, scs,
+                                  P.need_xpad ? b.xpad : nullptr, st));
   }
   if (!P.lead_pipe || P.need_xt16)
     HIPCHK(launch_pad_copies(P.xelem, X, P.T / IN, IN, P.lead_pipe ? nullptr : b.xpad, b.xt, st));
@@ -583,7 +596,13 @@ rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, c
     const int n = P.first_mode;
     int64_t A, I, B;
     view(n, A, I, B);
-    if (P.need_pad) {
+    if (P.first_blocked) {
+      // precision form: the product reads the mode's blocked copy (the Gram
+      // operand), decoded to bf16, on bf16 MFMA
+      ProfScope ps("ttm", st);
+      HIPCHK(launch_ttm_first_blocked(P.m[n].pelem, b.xb[n], b.xs[n], A, I, B, P.dims[P.N - 1], b.Ut64[n],
+                                      P.m[n].R, b.u16, bufs[which], st));
+    } else if (P.need_pad) {
       // precision form: the product reads the padded bf16 copy on bf16 MFMA
       HIPCHK(convert_tensor(E_F64, b.Ut64[n], E_BF16, b.Uop, P.m[n].R * I, st));
       ProfScope ps("ttm", st);

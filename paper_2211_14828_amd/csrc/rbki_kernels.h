@@ -160,6 +160,14 @@ size_t ttm_work_bytes(int elem, int64_t A, int64_t I, int64_t B, int64_t R);
 hipError_t launch_ttm_padded(const void* Xpad, int64_t A, int64_t I, int64_t B, int64_t IN, const void* Ut,
                              int64_t R, void* Y, hipStream_t s);
 
+// First mode product of the precision forms from a leading mode's blocked
+// copy xb (E_FP8 with its scales, or E_BF16), view [A, I, B] of X with last
+// dimension IN: Y[a, r, b] = sum_i U[i, r] X[a, i, b] as float, R <= 64.
+// Ut: R x I float64; U16: scratch of 64 x block_rows(I) bfloat16.
+hipError_t launch_ttm_first_blocked(int elem, const void* xb, const void* scales, int64_t A, int64_t I,
+                                    int64_t B, int64_t IN, const double* Ut, int64_t R, void* U16, void* Y,
+                                    hipStream_t s);
+
 // Sum over all entries of (X - Uh)^2 and X^2 where Uh[i, j] = sum_r U[i, r] H[r, j]
 // (X viewed as I x J row-major, the mode-0 unfolding); partial sums in
 // float64, returned in out[0] (residual) and out[1] (norm), reduced in a fixed order.

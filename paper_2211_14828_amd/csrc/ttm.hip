@@ -474,6 +474,147 @@ __global__ void convert_kernel(const S* src, D* dst, int64_t n) {
     dst[i] = conv<S, D>(src[i]);
 }
 
+// ------------------------------------------------------------------------
+// First mode product of the precision forms from the mode's K-blocked copy
+// (the Gram operand, [K tile][ipad rows][64 bytes], bfloat16 or block-scaled
+// e4m3): Y[a, r, b] = sum_i U[i, r] X[a, i, b], R <= 64.  A workgroup owns 64
+// padded columns (one e4m3 K tile or two bfloat16 ones) and all R rows of Y.
+// The contraction over the ipad rows runs in chunks of 256: each chunk is
+// decoded to bfloat16 and transposed into LDS as [column][row] (a thread
+// decodes 8 rows x 8 columns and writes 8 16-byte column pieces), the next
+// chunk's loads in flight meanwhile.  Wave w forms the 32 x 32 block rows
+// 32 (w >> 1).., columns 32 (w & 1).. on 32x32x16 bfloat16 MFMA, U rows read
+// from L2 ([64][ipad] bfloat16, zero past R and I).
+struct FirstArgs {
+  const unsigned char* X;    // blocked copy
+  const unsigned char* sc;   // e4m3 scales (the Gram operand's layout), or null
+  const bf16_t* U;           // [64][ipad]
+  float* Y;                  // [A][R][B]
+  int64_t ipad, Bp, B, IN, INp;
+  int R;
+};
+
+constexpr int F_CH = 256;                    // rows per chunk
+constexpr int F_ROW = F_CH * 2 + 16;         // LDS bytes per column row (padded)
+
+// e4m3 (bias 7) byte -> float times a power of two, branch-free: normal
+// values as 1.m 2^(e-7), subnormals (e = 0) as m 2^-9
+__device__ inline float e4m3_scaled(uint32_t q, float mul) {
+  const uint32_t sgn = (q & 0x80u) << 24, e = (q >> 3) & 0xFu, m = q & 7u;
+  const float nv = __uint_as_float(sgn | ((e + 120u) << 23) | (m << 20));
+  const float sv = __uint_as_float(sgn | 0x3F800000u) * (float)m * 0x1p-9f;
+  return (e ? nv : sv) * mul;
+}
+
+__device__ inline int64_t first_scale_pos(int64_t rowid, int h) {
+  const int rr = (int)(rowid & 255);
+  return ((rowid >> 8) * 2 + h) * 256 + (rr & 31) * 8 + (rr >> 5);
+}
+
+template <int E>
+__global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
+  __shared__ __attribute__((aligned(16))) char lds[2][64 * F_ROW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rg = tid >> 3, cg = tid & 7;           // staging: rows 8 rg.., columns 8 cg..
+  const int half = lane >> 5, lr = lane & 31;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int64_t blk = blockIdx.x;                  // 64 padded columns
+  const int nch = (int)(a.ipad / F_CH);
+
+  // raw chunk data of this thread: 8 rows of 8 values (e4m3: 8 bytes + the
+  // row's scale; bfloat16: 16 bytes)
+  uint4 raw[8];
+  int scl[8];
+  auto load = [&](int ch) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t i = (int64_t)ch * F_CH + rg * 8 + e;
+      if (E == E_FP8) {
+        const int64_t rowid = blk * a.ipad + i;
+        const uint2 v = *(const uint2*)(a.X + rowid * 64 + cg * 8);
+        raw[e] = make_uint4(v.x, v.y, 0u, 0u);
+        scl[e] = a.sc[first_scale_pos(rowid, cg >> 2)];
+      } else {
+        const int64_t kt = blk * 2 + (cg >> 2);
+        raw[e] = *(const uint4*)(a.X + (kt * a.ipad + i) * 64 + (cg & 3) * 16);
+        scl[e] = 0;
+      }
+    }
+  };
+  // decode and write the transposed pieces: column 8 cg + c, rows 8 rg .. 8 rg + 7
+  auto store = [&](char* buf) {
+    float v[8][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (E == E_FP8) {
+        const float mul = __uint_as_float((uint32_t)(scl[e] > 0 ? scl[e] : 1) << 23) * (scl[e] > 0 ? 1.f : 0.5f);
+        const uint32_t w[2] = {raw[e].x, raw[e].y};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[e][c] = e4m3_scaled((w[c >> 2] >> (8 * (c & 3))) & 0xFFu, mul);
+      } else {
+        const uint32_t w[4] = {raw[e].x, raw[e].y, raw[e].z, raw[e].w};
+#pragma unroll
+        for (int c = 0; c < 8; ++c) v[e][c] = bf16_to_f32((bf16_t)((w[c >> 1] >> (16 * (c & 1))) & 0xFFFFu));
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      uint4 o;
+      o.x = (uint32_t)f32_to_bf16(v[0][c]) | ((uint32_t)f32_to_bf16(v[1][c]) << 16);
+      o.y = (uint32_t)f32_to_bf16(v[2][c]) | ((uint32_t)f32_to_bf16(v[3][c]) << 16);
+      o.z = (uint32_t)f32_to_bf16(v[4][c]) | ((uint32_t)f32_to_bf16(v[5][c]) << 16);
+      o.w = (uint32_t)f32_to_bf16(v[6][c]) | ((uint32_t)f32_to_bf16(v[7][c]) << 16);
+      *(uint4*)(buf + (cg * 8 + c) * F_ROW + rg * 16) = o;
+    }
+  };
+
+  f32x16_t acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  const bf16_t* Urow = a.U + (int64_t)(wr + lr) * a.ipad;
+  load(0);
+  store(lds[0]);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const bool more = ch + 1 < nch;
+    if (more) load(ch + 1);
+    const char* buf = lds[ch & 1];
+    // K steps of 16 rows: lane half h takes rows 16 s + 8 h .. + 7
+#pragma unroll
+    for (int st = 0; st < F_CH / 16; ++st) {
+      const int k = st * 16 + half * 8;
+      const bf16x8_t av = *(const bf16x8_t*)(Urow + (int64_t)ch * F_CH + k);
+      const bf16x8_t bv = *(const bf16x8_t*)(buf + (wc + lr) * F_ROW + k * 2);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+    if (more) store(lds[(ch + 1) & 1]);
+    __syncthreads();
+  }
+
+  // value v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+  const int64_t g0 = blk * 64;                     // first padded column (over all a)
+  const int64_t av_ = g0 / a.Bp, bp0 = g0 - av_ * a.Bp;
+  const int64_t bp = bp0 + wc + lr;
+  const int64_t hi = bp / a.INp, lo = bp - hi * a.INp;
+  if (lo < a.IN) {
+    float* out = a.Y + av_ * a.R * a.B + hi * a.IN + lo;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int r = wr + 8 * (v >> 2) + 4 * half + (v & 3);
+      if (r < a.R) out[(int64_t)r * a.B] = acc[v];
+    }
+  }
+}
+
+// U (given as Ut, R x I float64) -> [64][ipad] bfloat16, zero past R and I
+__global__ void u_first_kernel(const double* Ut, int64_t R, int64_t I, int64_t ipad, bf16_t* U) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 64 * ipad;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / ipad, i = e - r * ipad;
+    U[e] = (r < R && i < I) ? f32_to_bf16((float)Ut[r * I + i]) : (bf16_t)0;
+  }
+}
+
 template <int E, int EPI, class XT>
 hipError_t launch_prod(const ProdArgs& p, int64_t batches, hipStream_t s) {
   // the batch index runs on grid.y (at most 65535 per launch)
@@ -578,6 +719,34 @@ hipError_t launch_ttm_padded(const void* Xpad, int64_t A, int64_t I, int64_t B, 
     batches = 1;
   }
   return launch_prod<E_BF16, 0, float>(p, batches, s);
+}
+
+hipError_t launch_ttm_first_blocked(int elem, const void* xb, const void* scales, int64_t A, int64_t I,
+                                    int64_t B, int64_t IN, const double* Ut, int64_t R, void* U16, void* Y,
+                                    hipStream_t s) {
+  if (R < 1 || R > 64 || (elem != E_FP8 && elem != E_BF16)) return hipErrorInvalidValue;
+  const int64_t INp = pad64(IN), ipad = block_rows(I);
+  const int64_t Bp = (B / IN) * INp;
+  hipLaunchKernelGGL(u_first_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(64 * ipad, 256), 2048)), dim3(256), 0,
+                     s, Ut, R, I, ipad, (bf16_t*)U16);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  FirstArgs fa;
+  fa.X = (const unsigned char*)xb;
+  fa.sc = (const unsigned char*)scales;
+  fa.U = (const bf16_t*)U16;
+  fa.Y = (float*)Y;
+  fa.ipad = ipad;
+  fa.Bp = Bp;
+  fa.B = B;
+  fa.IN = IN;
+  fa.INp = INp;
+  fa.R = (int)R;
+  const int64_t blocks = A * Bp / 64;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (elem == E_FP8) hipLaunchKernelGGL(ttm_first_kernel<E_FP8>, dim3((unsigned)blocks), dim3(256), 0, s, fa);
+  else hipLaunchKernelGGL(ttm_first_kernel<E_BF16>, dim3((unsigned)blocks), dim3(256), 0, s, fa);
+  return hipGetLastError();
 }
 
 size_t residual_work_bytes(int64_t I, int64_t J) {
