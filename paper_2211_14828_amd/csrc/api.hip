@@ -350,7 +350,7 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
   for (int l = 0; l < b.lanes; ++l) {
     Lane& L = b.ln[l];
     if (P.need_pad && P.oblk_bytes) {
-      L.oblk = ar.take((size_t)P.oblk_bytes);
+      if (!P.need_fp8) L.oblk = ar.take((size_t)P.oblk_bytes);   // the fp8 sketch is made in one pass
       if (P.need_fp8) {
         L.om8 = ar.take((size_t)P.oblk_bytes / 2);
         L.oscl = ar.take((size_t)P.oblk_bytes / 32 + 256);    // 256 bytes per K tile
@@ -455,8 +455,11 @@ rbki_status run_mode(const Plan& P, const Buffers& b, int lane, const void* xsrc
       (void)last;
       {
         ProfScope ps("omega", st);
-        HIPCHK(launch_omega_block(P.seed, n, S, g.J, g.B, IN, g.nkt, KT, L.oblk, st));
-        if (g.pelem == E_FP8) HIPCHK(launch_quantize_omega(L.oblk, g.nkt, L.om8, L.oscl, st));
+        if (g.pelem == E_FP8) {
+          HIPCHK(launch_omega_fp8(P.seed, n, S, g.J, g.B, IN, g.nkt, L.om8, L.oscl, st));
+        } else {
+          HIPCHK(launch_omega_block(P.seed, n, S, g.J, g.B, IN, g.nkt, KT, L.oblk, st));
+        }
       }
       GramArgs ga = gram_plan_pipe(g.pelem, A, I, Bp, (int)S, cu_count());
       ga.X = b.xb[n];

@@ -888,6 +888,64 @@ __global__ void __launch_bounds__(256) block_copy_last_kernel(const T* X, int64_
 // The blocked bf16 sketch [kt][64][64] -> e4m3 in the same layout, scales
 // [kt][h][row % 32][4] (byte row / 32; bytes 2, 3 stay zero).  One wave per
 // 64-value row; lane half h is run h.
+// The e4m3 sketch in one pass.  Row r = (K tile kt, sketch row sv) of the
+// blocked Omega^T holds the values at padded columns jp = kt KT + kk, drawn
+// from the sketch stream at L = sv J + j (j the unpadded column; zero in
+// padded columns and rows past S), rounded to bf16 and then to e4m3 exactly
+// as the two-pass form (bf16 sketch, then quantize_omega_kernel) does, with
+// the scale of each run of 32 in the same layout.  A wave takes two rows,
+// a lane two neighbouring columns (one draw of a Gaussian pair when L is even).
+template <class IT>
+__global__ void omega_fp8_kernel(uint64_t seed, uint32_t mode, int64_t S_, int64_t J_, int64_t B_, int64_t IN_,
+                                 int64_t INp_, int64_t nrows, fp8_t* q, unsigned char* scales) {
+  const IT S = (IT)S_, J = (IT)J_, B = (IT)B_, IN = (IT)IN_, INp = (IT)INp_;
+  const IT Bp = B > 1 ? (B / IN) * INp : 1;
+  const int lane = threadIdx.x & 63, pl = lane & 31;
+  for (int64_t r2 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); 2 * r2 < nrows;
+       r2 += (int64_t)gridDim.x * (blockDim.x >> 6)) {
+    const int64_t r = 2 * r2 + (lane >> 5);
+    const IT kt = (IT)(r >> 6), sv = (IT)(r & 63);
+    const IT jp = kt * 64 + (IT)(2 * pl);             // even: jp and jp + 1 share a and bh
+    IT j = jp, cols_left = J > jp ? J - jp : 0;
+    bool rowok = sv < S;
+    if (B > 1) {
+      const IT a = jp / Bp, bp = jp - a * Bp;
+      const IT bh = bp / INp, bl = bp - bh * INp;
+      j = a * B + bh * IN + bl;
+      cols_left = bl < IN ? IN - bl : 0;               // valid columns from jp on within this run of I_N
+    }
+    float v[2] = {0.f, 0.f};
+    if (rowok && cols_left > 0) {
+      const int64_t L = (int64_t)sv * J_ + (int64_t)j;
+      float z0, z1;
+      gauss_pair_f32((uint64_t)(L >> 1), mode, 0u, seed, z0, z1);
+      if ((L & 1) == 0) {
+        v[0] = z0;
+        v[1] = z1;
+      } else {
+        v[0] = z1;
+        float w0, w1;
+        gauss_pair_f32((uint64_t)((L + 1) >> 1), mode, 0u, seed, w0, w1);
+        v[1] = w0;
+      }
+      if (cols_left < 2) v[1] = 0.f;
+      v[0] = bf16_to_f32(f32_to_bf16(v[0]));
+      v[1] = bf16_to_f32(f32_to_bf16(v[1]));
+    }
+    // runs of 32 values: 16 lanes
+    float m = fmaxf(fabsf(v[0]), fabsf(v[1]));
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    const int sc = e8m0_for(m);
+    const uint32_t b0 = f32_to_e4m3(ldexpf(v[0], 127 - sc)), b1 = f32_to_e4m3(ldexpf(v[1], 127 - sc));
+    *(unsigned short*)(q + r * 64 + 2 * pl) = (unsigned short)(b0 | (b1 << 8));
+    if ((pl & 15) == 0) {
+      const int h = pl >> 4;
+      scales[(int64_t)kt * 256 + (h * 32 + (int)(sv & 31)) * 4 + (int)(sv >> 5)] = (unsigned char)sc;
+    }
+  }
+}
+
 __global__ void quantize_omega_kernel(const bf16_t* src, int64_t nrows, fp8_t* q, unsigned char* scales) {
   const int lane = threadIdx.x & 63;
   for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < nrows;
@@ -1086,6 +1144,23 @@ hipError_t launch_quantize_rows_fp8(const void* src, int64_t rows, int64_t cols,
   const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(ceil_div(total, 64), 4), 16384);
   hipLaunchKernelGGL(quantize_rows_kernel, dim3(grid), dim3(256), 0, s, (const bf16_t*)src, total, (fp8_t*)q,
                      (unsigned char*)scales);
+  return hipGetLastError();
+}
+
+hipError_t launch_omega_fp8(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t nkt,
+                            void* q, void* scales, hipStream_t s) {
+  if (S > PW) return hipErrorInvalidValue;
+  if (nkt <= 0) return hipSuccess;
+  hipError_t e = fill_zero(scales, (size_t)nkt * 256, s);   // the bytes no row writes stay zero
+  if (e != hipSuccess) return e;
+  const int64_t nrows = nkt * 64;
+  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(nrows, 8), 65535);
+  if (nrows * 64 < ((int64_t)1 << 31) && S * J < ((int64_t)1 << 31))
+    hipLaunchKernelGGL(omega_fp8_kernel<uint32_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
+                       pad64(IN), nrows, (fp8_t*)q, (unsigned char*)scales);
+  else
+    hipLaunchKernelGGL(omega_fp8_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
+                       pad64(IN), nrows, (fp8_t*)q, (unsigned char*)scales);
   return hipGetLastError();
 }
 

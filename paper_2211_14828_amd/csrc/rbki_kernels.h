@@ -58,6 +58,10 @@ hipError_t launch_block_copy_lead(int src_elem, int elem, const void* X, int ord
 // Blocked copy of the last mode's unfolding (X as R rows of IN; K runs over R).
 hipError_t launch_block_copy_last(int src_elem, int elem, const void* X, int64_t R, int64_t IN, void* out,
                                   void* scales, hipStream_t s);
+// The e4m3 blocked sketch of one mode in one pass (the values and scales the
+// bf16 sketch followed by launch_quantize_omega gives).
+hipError_t launch_omega_fp8(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t nkt,
+                            void* q, void* scales, hipStream_t s);
 // The blocked bf16 sketch ([nkt][64][64]) -> e4m3, scales [nkt][2][32][4].
 hipError_t launch_quantize_omega(const void* src, int64_t nkt, void* q, void* scales, hipStream_t s);
 // rows x cols bf16 (cols a multiple of 32) -> e4m3 with per-32 E8M0 scales
