@@ -426,22 +426,23 @@ rbki_status convert_input(const Plan& P, const Buffers& b, const void* X, hipStr
 }
 
 // ------------------------------------------------------------------ one mode
-// Alg. 1 + Alg. 2 steps 3-5 for mode n.  Leaves the basis in b.Qt (Sp rows),
-// C Q in b.CQt, and (if with_factor) U^(n)T in b.Ut64[n].
+// Alg. 1 + Alg. 2 steps 1-3 for mode n, in two parts: run_mode_heavy (the
+// sketch and the Gram / sketch products, C and W into the scratch set) and
+// run_mode_chain (the Krylov basis in b.Qt, Sp rows, C Q in the set's CQt,
+// and Z).
 constexpr double TAU_REL = 1e-12;   // pivot vs its own column: direction already spanned
 constexpr double TAU_ABS = 1e-10;   // pivot vs the block before projection (matches the oracle)
 
 // heavy_wait / heavy_done (nullable): events that the sketch and Gram
 // kernels wait for and record, so that those throughput-bound kernels of
 // concurrently running modes follow each other.
-rbki_status run_mode(const Plan& P, const Buffers& b, int lane, const void* xsrc, int n, bool with_factor,
-                     hipStream_t st, hipEvent_t heavy_wait = nullptr, hipEvent_t heavy_done = nullptr) {
+rbki_status run_mode_heavy(const Plan& P, const Buffers& b, int lane, const void* xsrc, int n, hipStream_t st,
+                           hipEvent_t heavy_wait = nullptr, hipEvent_t heavy_done = nullptr) {
   const Lane& L = b.ln[lane];
   dgemm_set_scratch(L.dscratch, kDgemmScratch);
   if (heavy_wait) HIPCHK(hipStreamWaitEvent(st, heavy_wait, 0));
   const ModeGeom& g = P.m[n];
-  const int64_t I = g.I, S = g.S, Sp = g.Sp;
-  double* Qt = b.Qt[n];
+  const int64_t I = g.I, S = g.S;
   // C -> L.C (I x I), W^T -> L.Yt (S x I)
   if (P.need_pad) {
     int64_t A, Bp;
@@ -505,7 +506,17 @@ rbki_status run_mode(const Plan& P, const Buffers& b, int lane, const void* xsrc
   }
 
   if (heavy_done) HIPCHK(hipEventRecord(heavy_done, st));
+  return RBKI_OK;
+}
 
+// Alg. 2, steps 2-3 of mode n after run_mode_heavy: the Krylov basis from C
+// and W in the scratch set, and Z.
+rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, bool with_factor, hipStream_t st) {
+  const Lane& L = b.ln[lane];
+  dgemm_set_scratch(L.dscratch, kDgemmScratch);
+  const ModeGeom& g = P.m[n];
+  const int64_t I = g.I, S = g.S, Sp = g.Sp;
+  double* Qt = b.Qt[n];
   // block 0: Q_0 = orth(W).  The first pass of every block's CholeskyQR2
   // also keeps the basis at most I_n wide: once it spans the whole space the
   // later blocks are rounding noise and are dropped whatever their norm.
@@ -533,6 +544,13 @@ rbki_status run_mode(const Plan& P, const Buffers& b, int lane, const void* xsrc
   HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt + (Sp - S) * I, I, L.C, I, 0.0, L.CQt + (Sp - S) * I, I, st));
   HIPCHK(dgemm(0, 1, Sp, Sp, I, 1.0, Qt, I, L.CQt, I, 0.0, b.Z[n], Sp, st));
   return RBKI_OK;
+}
+
+rbki_status run_mode(const Plan& P, const Buffers& b, int lane, const void* xsrc, int n, bool with_factor,
+                     hipStream_t st) {
+  rbki_status s = run_mode_heavy(P, b, lane, xsrc, n, st);
+  if (s != RBKI_OK) return s;
+  return run_mode_chain(P, b, lane, n, with_factor, st);
 }
 
 // Alg. 2, steps 4-5 for all modes: the R leading eigenvectors of every Z in
@@ -884,9 +902,22 @@ static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, 
   hipEvent_t heavy[8] = {};
   if (lanes > 1)
     for (int n = 0; n < P.N; ++n) HIPCHK(hipEventCreateWithFlags(&heavy[n], hipEventDisableTiming));
+  // With several scratch sets, the modes of a round (one per set) are enqueued
+  // heavy phases first, so that the next mode's sketch and Gram kernels are
+  // queued before the long chain of small Krylov kernels of the previous one.
+  // A mode's chain follows its own heavy phase on its stream; modes sharing a
+  // set keep their order.
   rbki_status s = RBKI_OK;
-  for (int n = 0; n < P.N && s == RBKI_OK; ++n)
-    s = run_mode(P, b, n % b.lanes, xsrc, n, true, ls[n % lanes], n > 0 ? heavy[n - 1] : nullptr, heavy[n]);
+  if (lanes == 1) {
+    for (int n = 0; n < P.N && s == RBKI_OK; ++n) s = run_mode(P, b, n % b.lanes, xsrc, n, true, st);
+  } else {
+    for (int n0 = 0; n0 < P.N && s == RBKI_OK; n0 += lanes) {
+      const int n1 = std::min(P.N, n0 + lanes);
+      for (int n = n0; n < n1 && s == RBKI_OK; ++n)
+        s = run_mode_heavy(P, b, n % lanes, xsrc, n, ls[n % lanes], n > 0 ? heavy[n - 1] : nullptr, heavy[n]);
+      for (int n = n0; n < n1 && s == RBKI_OK; ++n) s = run_mode_chain(P, b, n % lanes, n, true, ls[n % lanes]);
+    }
+  }
   if (lanes > 1) {
     for (int l = 1; l < lanes; ++l) {
       HIPCHK(hipEventRecord(ev[l], ls[l]));

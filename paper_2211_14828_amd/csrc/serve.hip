@@ -123,7 +123,7 @@ struct rbki_server {
 namespace {
 
 void worker_main(rbki_server* sv, rbki::ServerSlot* slot) {
-  hipSetDevice(sv->device);
+  (void)hipSetDevice(sv->device);
   hipStream_t st = slot->stream;
   hipEvent_t fin = slot->fin;
   rbki::HostResult* hr = slot->hr;
@@ -162,7 +162,7 @@ void worker_main(rbki_server* sv, rbki::ServerSlot* slot) {
       }
     } else {
       msg = rbki_last_error();
-      hipStreamSynchronize(st);                    // nothing of it may still run on the arena
+      (void)hipStreamSynchronize(st);                    // nothing of it may still run on the arena
     }
     {
       std::lock_guard<std::mutex> lk(sv->mu);
@@ -176,14 +176,14 @@ void worker_main(rbki_server* sv, rbki::ServerSlot* slot) {
     sv->cv_work.notify_all();
     sv->cv_done.notify_all();
   }
-  hipStreamSynchronize(st);
+  (void)hipStreamSynchronize(st);
 }
 
 void free_slots(rbki_server* sv) {
   for (auto& sl : sv->slots) {
-    if (sl.fin) hipEventDestroy(sl.fin);
-    if (sl.stream) hipStreamDestroy(sl.stream);
-    if (sl.hr) hipHostFree(sl.hr);
+    if (sl.fin) (void)hipEventDestroy(sl.fin);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.hr) (void)hipHostFree(sl.hr);
   }
   sv->slots.clear();
 }
@@ -218,7 +218,7 @@ rbki_status rbki_server_create(size_t hbm_budget_bytes, int slots, rbki_server**
         hipEventCreateWithFlags(&sl.fin, hipEventBlockingSync | hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void**)&sl.hr, sizeof(rbki::HostResult)) != hipSuccess) {
       free_slots(sv.get());
-      hipFree(sv->arena);
+      (void)hipFree(sv->arena);
       rbki::set_error(RBKI_E_HIP, "server: cannot create the worker streams");
       return RBKI_E_HIP;
     }
@@ -328,7 +328,7 @@ rbki_status rbki_server_destroy(rbki_server* sv) {
   sv->cv_work.notify_all();
   for (auto& t : sv->workers) t.join();
   free_slots(sv);
-  hipFree(sv->arena);
+  (void)hipFree(sv->arena);
   delete sv;
   return RBKI_OK;
 }

@@ -515,57 +515,71 @@ template <int E>
 __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[2][64 * F_ROW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rg = tid >> 3, cg = tid & 7;           // staging: rows 8 rg.., columns 8 cg..
+  // staging: thread (rl, cg) takes rows rl + 32 e (e = 0..7) of the chunk and
+  // columns 8 cg .. 8 cg + 7.  Row rl + 32 e goes to chunk position 8 rl + e
+  // (the contraction order inside a chunk is free; U is stored in the same
+  // order), so a thread writes 8 consecutive positions of every column, and
+  // its 8 e4m3 scales are 8 consecutive bytes of the scale layout.
+  const int rl = tid >> 3, cg = tid & 7;
   const int half = lane >> 5, lr = lane & 31;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   const int64_t blk = blockIdx.x;                  // 64 padded columns
   const int nch = (int)(a.ipad / F_CH);
 
-  // raw chunk data of this thread: 8 rows of 8 values (e4m3: 8 bytes + the
-  // row's scale; bfloat16: 16 bytes)
   uint4 raw[8];
-  int scl[8];
+  uint2 scl = make_uint2(0u, 0u);
   auto load = [&](int ch) {
+    const int64_t row0 = (int64_t)ch * F_CH;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int64_t i = (int64_t)ch * F_CH + rg * 8 + e;
+      const int64_t i = row0 + rl + 32 * e;
       if (E == E_FP8) {
-        const int64_t rowid = blk * a.ipad + i;
-        const uint2 v = *(const uint2*)(a.X + rowid * 64 + cg * 8);
+        const uint2 v = *(const uint2*)(a.X + (blk * a.ipad + i) * 64 + cg * 8);
         raw[e] = make_uint4(v.x, v.y, 0u, 0u);
-        scl[e] = a.sc[first_scale_pos(rowid, cg >> 2)];
       } else {
         const int64_t kt = blk * 2 + (cg >> 2);
         raw[e] = *(const uint4*)(a.X + (kt * a.ipad + i) * 64 + (cg & 3) * 16);
-        scl[e] = 0;
       }
+    }
+    if (E == E_FP8) {
+      // scale byte e of row rl + 32 e: [K tile][256-row tile][half][row % 32][row / 32]
+      const int64_t tile = (blk * a.ipad + row0) >> 8;
+      scl = *(const uint2*)(a.sc + (tile * 2 + (cg >> 2)) * 256 + rl * 8);
     }
   };
-  // decode and write the transposed pieces: column 8 cg + c, rows 8 rg .. 8 rg + 7
+  // decode and write the transposed pieces: column 8 cg + c, positions 8 rl .. 8 rl + 7
   auto store = [&](char* buf) {
-    float v[8][8];
+    uint32_t o[8][4];                              // [column][position pair]
+    if (E == E_FP8) {
+      // e4m3 values with 8-bit-exponent scales are exact in bf16: the bf16
+      // bits are the upper half of the float's
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if (E == E_FP8) {
-        const float mul = __uint_as_float((uint32_t)(scl[e] > 0 ? scl[e] : 1) << 23) * (scl[e] > 0 ? 1.f : 0.5f);
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t sb = ((e < 4 ? scl.x : scl.y) >> (8 * (e & 3))) & 0xFFu;
+        const float mul = __uint_as_float((sb > 0 ? sb : 1u) << 23) * (sb > 0 ? 1.f : 0.5f);
         const uint32_t w[2] = {raw[e].x, raw[e].y};
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[e][c] = e4m3_scaled((w[c >> 2] >> (8 * (c & 3))) & 0xFFu, mul);
-      } else {
+        for (int c = 0; c < 8; ++c) {
+          const uint32_t h = __float_as_uint(e4m3_scaled((w[c >> 2] >> (8 * (c & 3))) & 0xFFu, mul)) >> 16;
+          if (e & 1) o[c][e >> 1] |= h << 16;
+          else o[c][e >> 1] = h;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
         const uint32_t w[4] = {raw[e].x, raw[e].y, raw[e].z, raw[e].w};
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[e][c] = bf16_to_f32((bf16_t)((w[c >> 1] >> (16 * (c & 1))) & 0xFFFFu));
+        for (int c = 0; c < 8; ++c) {
+          const uint32_t h = (w[c >> 1] >> (16 * (c & 1))) & 0xFFFFu;
+          if (e & 1) o[c][e >> 1] |= h << 16;
+          else o[c][e >> 1] = h;
+        }
       }
     }
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      uint4 o;
-      o.x = (uint32_t)f32_to_bf16(v[0][c]) | ((uint32_t)f32_to_bf16(v[1][c]) << 16);
-      o.y = (uint32_t)f32_to_bf16(v[2][c]) | ((uint32_t)f32_to_bf16(v[3][c]) << 16);
-      o.z = (uint32_t)f32_to_bf16(v[4][c]) | ((uint32_t)f32_to_bf16(v[5][c]) << 16);
-      o.w = (uint32_t)f32_to_bf16(v[6][c]) | ((uint32_t)f32_to_bf16(v[7][c]) << 16);
-      *(uint4*)(buf + (cg * 8 + c) * F_ROW + rg * 16) = o;
-    }
+    for (int c = 0; c < 8; ++c)
+      *(uint4*)(buf + (cg * 8 + c) * F_ROW + rl * 16) = make_uint4(o[c][0], o[c][1], o[c][2], o[c][3]);
   };
 
   f32x16_t acc;
@@ -579,7 +593,7 @@ __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
     const bool more = ch + 1 < nch;
     if (more) load(ch + 1);
     const char* buf = lds[ch & 1];
-    // K steps of 16 rows: lane half h takes rows 16 s + 8 h .. + 7
+    // K steps of 16 positions: lane half h takes positions 16 s + 8 h .. + 7
 #pragma unroll
     for (int st = 0; st < F_CH / 16; ++st) {
       const int k = st * 16 + half * 8;
@@ -606,11 +620,15 @@ __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
   }
 }
 
-// U (given as Ut, R x I float64) -> [64][ipad] bfloat16, zero past R and I
+// U (given as Ut, R x I float64) -> [64][ipad] bfloat16 in the chunk order of
+// ttm_first_kernel (position 8 q + e of a 256-row chunk holds row q + 32 e),
+// zero past R and I
 __global__ void u_first_kernel(const double* Ut, int64_t R, int64_t I, int64_t ipad, bf16_t* U) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 64 * ipad;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / ipad, i = e - r * ipad;
+    const int64_t r = e / ipad, p = e - r * ipad;
+    const int64_t pc = p & (F_CH - 1);
+    const int64_t i = (p - pc) + (pc >> 3) + 32 * (pc & 7);
     U[e] = (r < R && i < I) ? f32_to_bf16((float)Ut[r * I + i]) : (bf16_t)0;
   }
 }
