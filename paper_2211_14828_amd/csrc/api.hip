@@ -145,17 +145,33 @@ struct Plan {
 
 int dtype_elem(int dt) { return dt == RBKI_F64 ? E_F64 : dt == RBKI_F32 ? E_F32 : E_BF16; }
 
-// Mode n of the zero-padded bf16 operands: modes before the last read Xpad as
-// [A_n, I_n, Bp_n] with Bp_n = (B_n / I_N) I_Npad; the last mode reads Xt as
-// [1, I_N, rows_pad].
-void padded_view(const Plan& P, int n, int64_t& A, int64_t& Bp) {
+// Mode n of the zero-padded operands: modes before the last read Xpad (or
+// their blocked copy) as [A_n, I_n, Bp_n] with Bp_n = (B_n / I_N) I_Npad.
+// The last mode reads Xt as [1, I_N, rows_pad], or its blocked copy as
+// [1, I_N, H pad64(I_{N-1})] (H = T / (I_{N-1} I_N)): K runs over the rows of
+// X with every run of I_{N-1} padded, so that a K tile stays inside one run.
+void padded_view(const Plan& P, int n, bool pipe, int64_t& A, int64_t& Bp) {
   const ModeGeom& g = P.m[n];
   if (n == P.N - 1) {
+    const int64_t L = P.dims[P.N - 2];
     A = 1;
-    Bp = P.rows_pad;
+    Bp = pipe ? (P.T / (L * P.dims[P.N - 1])) * pad64(L) : P.rows_pad;
   } else {
     A = g.A;
     Bp = (g.B / P.dims[P.N - 1]) * P.in_pad;
+  }
+}
+
+// The sketch columns of mode n's blocked operand run as [A, B / IN, pad64(IN)]
+// for these (B, IN): the view of padded_view.
+void sketch_runs(const Plan& P, int n, int64_t& B, int64_t& IN) {
+  const ModeGeom& g = P.m[n];
+  if (n == P.N - 1) {
+    B = g.J;
+    IN = P.dims[P.N - 2];
+  } else {
+    B = g.B;
+    IN = P.dims[P.N - 1];
   }
 }
 
@@ -215,8 +231,8 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     P.maxRI = std::max(P.maxRI, g.R * g.I);
     if (P.need_pad) {
       int64_t A, Bp;
-      padded_view(P, n, A, Bp);
       g.pipe = gram_pipe_ok(g.I, (int)g.S);
+      padded_view(P, n, g.pipe, A, Bp);
       if (g.pipe) {
         g.pelem = P.need_fp8 ? E_FP8 : E_BF16;
         const int64_t KT = g.pelem == E_FP8 ? 64 : 32;
@@ -400,28 +416,26 @@ size_t plan_bytes(const Plan& P) {
 }
 
 // The copies of X the mixed forms read, made once per decomposition: the
-// blocked copies of every pipelined mode (one pass over X for the leading
-// modes, which also writes the padded bf16 copy Xpad; a transposing pass for
-// the last), and Xpad / Xt by the plain padding pass where no blocked pass
-// writes them.
+// blocked copies of every pipelined mode in one pass over X (which also
+// writes the padded bf16 copy Xpad where something reads it), and Xpad / Xt
+// by the plain padding pass where no blocked pass writes them.
 rbki_status convert_input(const Plan& P, const Buffers& b, const void* X, hipStream_t st) {
   const int64_t IN = P.dims[P.N - 1];
-  if (P.lead_pipe) {
+  const bool any_pipe = P.lead_pipe || P.m[P.N - 1].pipe;
+  if (any_pipe) {
     bool want[8] = {};
     void* outs[8] = {};
     void* scs[8] = {};
-    for (int n = 0; n + 1 < P.N; ++n) {
+    for (int n = 0; n < P.N; ++n) {
       want[n] = P.m[n].pipe;
       outs[n] = b.xb[n];
       scs[n] = b.xs[n];
     }
-    HIPCHK(launch_block_copy_lead(P.xelem, P.need_fp8 ? E_FP8 : E_BF16, X, P.N, P.dims, want, outs, scs,
-                                  P.need_xpad ? b.xpad : nullptr, st));
+    HIPCHK(launch_block_copies(P.xelem, P.need_fp8 ? E_FP8 : E_BF16, X, P.N, P.dims, want, outs, scs,
+                               (P.lead_pipe && P.need_xpad) ? b.xpad : nullptr, st));
   }
   if (!P.lead_pipe || P.need_xt16)
     HIPCHK(launch_pad_copies(P.xelem, X, P.T / IN, IN, P.lead_pipe ? nullptr : b.xpad, b.xt, st));
-  const ModeGeom& gl = P.m[P.N - 1];
-  if (gl.pipe) HIPCHK(launch_block_copy_last(P.xelem, gl.pelem, X, P.T / IN, IN, b.xb[P.N - 1], b.xs[P.N - 1], st));
   return RBKI_OK;
 }
 
@@ -446,20 +460,20 @@ rbki_status run_mode_heavy(const Plan& P, const Buffers& b, int lane, const void
   // C -> L.C (I x I), W^T -> L.Yt (S x I)
   if (P.need_pad) {
     int64_t A, Bp;
-    padded_view(P, n, A, Bp);
+    padded_view(P, n, g.pipe, A, Bp);
     const bool last = n == P.N - 1;
     if (g.pipe) {
       // the blocked copy of this mode's unfolding was made by convert_input;
       // the blocked sketch
       const int KT = g.pelem == E_FP8 ? 64 : 32;
-      const int64_t IN = P.dims[P.N - 1];
-      (void)last;
+      int64_t SB, SIN;
+      sketch_runs(P, n, SB, SIN);
       {
         ProfScope ps("omega", st);
         if (g.pelem == E_FP8) {
-          HIPCHK(launch_omega_fp8(P.seed, n, S, g.J, g.B, IN, g.nkt, L.om8, L.oscl, st));
+          HIPCHK(launch_omega_fp8(P.seed, n, S, g.J, SB, SIN, g.nkt, L.om8, L.oscl, st));
         } else {
-          HIPCHK(launch_omega_block(P.seed, n, S, g.J, g.B, IN, g.nkt, KT, L.oblk, st));
+          HIPCHK(launch_omega_block(P.seed, n, S, g.J, SB, SIN, g.nkt, KT, L.oblk, st));
         }
       }
       GramArgs ga = gram_plan_pipe(g.pelem, A, I, Bp, (int)S, cu_count());

@@ -657,13 +657,19 @@ __device__ inline float group8_max(float v) {
   return v;
 }
 
+// e4m3 bytes of a and b (low two bytes of the result, a first) by the
+// hardware conversion: round to nearest even into OCP e4m3, the same bytes as
+// f32_to_e4m3 for finite |x| <= 448 (every input here is scaled into that
+// range; non-finite inputs give NaN codes instead of saturating).
+__device__ inline uint32_t e4m3x2(float a, float b) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xFFFFu;
+}
+
 // Four values -> packed e4m3 (scale byte sc, shared by the 8 lanes of a run of 32)
 __device__ inline uint32_t pack_e4m3(const float* v, int sc) {
   const float mul = pow2_neg(sc - 127);
-  uint32_t w = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) w |= (uint32_t)f32_to_e4m3(v[k] * mul) << (8 * k);
-  return w;
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0] * mul, v[1] * mul, 0, false);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v[2] * mul, v[3] * mul, lo, true);
 }
 
 // Four values X[off .. off+3] as float; values at or past `avail` (the
@@ -771,69 +777,101 @@ __device__ inline int store_chunk(const float* v, char* dst, bool store = true) 
   }
 }
 
-// Blocked copies of X_(n) for the leading modes n < N-1, one pass over X.
-// X is read as R = T / I_N rows r of its last dimension; row r of mode n's
-// view [A_n, I_n, B_n] is (a, i, bh) with r = (a I_n + i) Bh_n + bh, Bh_n =
-// B_n / I_N, and padded column b' = bh I_Npad + c holds X[r][c] (zero for
-// c >= I_N).  Copy n is [kt][i][64 bytes] with kt = a (Bh_n I_Npad / KT) +
-// b' / KT, rows padded to ipad_n (the padding rows are zeroed separately);
+// Blocked copies of every pipelined mode's unfolding in one pass over X.  X
+// is read as H x L rows of its last dimension (L = I_{N-1}, the last leading
+// dimension; H the product of the others; row r = h L + l) and I_N columns c.
+//  - Leading mode n < N-1: row r of its view [A_n, I_n, B_n] is (a, i, bh)
+//    with r = (a I_n + i) Bh_n + bh, Bh_n = B_n / I_N; padded column
+//    b' = bh I_Npad + c holds X[r][c] (zero for c >= I_N).  Copy n is
+//    [kt][i][64 bytes] with kt = a (Bh_n I_Npad / KT) + b' / KT, rows padded
+//    to ipad_n (the padding rows are zeroed separately).
+//  - The last mode: operand row c (zero for c >= I_N, up to its ipad), K
+//    index k = h Lp + l with Lp = pad64(L) (zero for l >= L), so that every
+//    K tile lies inside one run of L rows; copy [k / KT][c][64 bytes].
 // e4m3 scales in the layout scale_pos describes.  xpad (nullable): the
-// row-major padded bf16 copy.  One thread per VPC values of a row (16 e4m3
-// or 8 bf16): neighbouring threads write neighbouring 16-byte chunks of
-// every copy.
-struct LeadModes {
-  int n;
+// row-major padded bf16 copy.  A workgroup takes tiles of 64 rows (h, l0 ..
+// l0+63) by 64 columns (l0, c0 multiples of 64): thread t reads 16 values of
+// row l0 + t/4 and writes the leading copies' chunks from registers (four
+// threads fill the 64 bytes of a row chunk, neighbouring rows of mode N-2
+// are neighbouring chunks); the tile then goes through LDS transposed, and
+// thread t writes 16 K values of the last mode's row c0 + t/4.
+struct CopyModes {
+  int n;                          // leading modes with a copy
   int64_t I[7], Bh[7], ipad[7], nbt[7];
   char* out[7];
   unsigned char* sc[7];
+  char* last;                     // the last mode's copy (nullable)
+  unsigned char* last_sc;
+  int64_t last_ipad;
 };
 
 template <class T, int E, class IT>
-__global__ void __launch_bounds__(256) block_copy_lead_kernel(const T* X, int64_t H_, int64_t L_, int64_t IN_,
-                                                              int64_t INp_, bool vec, LeadModes lm, bf16_t* xpad) {
-  // rows r = h L + l (L: the last leading dimension).  A wave takes 4 x 4
-  // rows (h, l) and one K-tile-wide column chunk: lane = 16 hh + 4 ll + q.
-  // Mode 0's copy (rows along h) and mode N-2's (rows along l) then both
-  // receive 256 contiguous bytes per 4 lanes x 4 rows.
-  constexpr int VPC = E == E_FP8 ? 16 : 8;
+__global__ void __launch_bounds__(256) block_copy_kernel(const T* X, int64_t H_, int64_t L_, int64_t IN_,
+                                                         int64_t INp_, bool vec, CopyModes cm, bf16_t* xpad) {
+  constexpr int VPC = E == E_FP8 ? 16 : 8;     // values per 16-byte chunk
   constexpr int KT = 4 * VPC;
   constexpr int ES = E == E_FP8 ? 1 : 2;
-  const IT H = (IT)H_, L = (IT)L_, IN = (IT)IN_, INp = (IT)INp_;
-  const IT nh = (H + 3) / 4, nl = (L + 3) / 4, nc = INp / KT;
-  const int64_t ntask = (int64_t)nh * nc * nl;
-  const int lane = threadIdx.x & 63;
-  const IT q = lane & 3, ll = (lane >> 2) & 3, hh = lane >> 4;
-  for (int64_t task = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); task < ntask;
-       task += (int64_t)gridDim.x * (blockDim.x >> 6)) {
-    const IT tk = (IT)task;
-    const IT lb = tk % nl, rest = tk / nl;
-    const IT cc = rest % nc, hb = rest / nc;
-    const IT h = hb * 4 + hh, l = lb * 4 + ll;
-    const bool ok = h < H && l < L;
-    const IT r = h * L + l, c = cc * KT + q * VPC;
-    float v[VPC];
+  __shared__ float tile[64][65];
+  const IT L = (IT)L_, IN = (IT)IN_, INp = (IT)INp_;
+  const IT Lp = (L + 63) / 64 * 64;
+  const IT nlb = Lp / 64, nlead = INp / 64;
+  const IT ncb = (IT)((cm.last ? cm.last_ipad : INp_) / 64);
+  const int64_t ntile = H_ * (int64_t)nlb * ncb;
+  const int t = threadIdx.x, rr = t >> 2, q = t & 3;
+  for (int64_t id = blockIdx.x; id < ntile; id += gridDim.x) {
+    const IT tk = (IT)id;
+    const IT cb = tk % ncb, rest = tk / ncb;
+    const IT lb = rest % nlb, h = rest / nlb;
+    const IT l = lb * 64 + (IT)rr, c = cb * 64 + (IT)q * 16;
+    const bool ok = l < L;
+    const IT r = h * L + l;
+    float v[16];
 #pragma unroll
-    for (int k = 0; k < VPC; ++k) v[k] = 0.f;
-    if (ok) {
+    for (int k = 0; k < 16; ++k) v[k] = 0.f;
+    if (ok && c < IN) {
 #pragma unroll
-      for (int k = 0; k < VPC; k += 4) load4(X, (int64_t)r * IN + c + k, IN_ - (int64_t)c - k, vec, v + k);
+      for (int k = 0; k < 16; k += 4) load4(X, (int64_t)r * IN + c + k, IN_ - (int64_t)c - k, vec, v + k);
     }
-    for (int m = 0; m < lm.n; ++m) {
-      // every lane takes part (the scale pairs lanes q, q ^ 1); only valid
-      // rows store
-      const IT Bh = (IT)lm.Bh[m], Im = (IT)lm.I[m];
-      const IT t = r / Bh, bh = r - t * Bh;
-      const IT a = t / Im, i = t - a * Im;
-      const IT bp = bh * INp + c;
-      const IT kt = a * (IT)lm.nbt[m] + bp / KT, kk = bp - (bp / KT) * KT;
-      const int64_t rowid = (int64_t)kt * lm.ipad[m] + i;
-      const int sc = store_chunk<E>(v, lm.out[m] + rowid * 64 + kk * ES, ok);
-      if (ok && E == E_FP8 && ((kk >> 4) & 1) == 0) lm.sc[m][scale_pos(rowid, (int)(kk >> 5))] = (unsigned char)sc;
-    }
-    if (xpad && ok) {
-      bf16_t* dst = xpad + (int64_t)r * INp + c;
+    if (cb < nlead) {
+      for (int m = 0; m < cm.n; ++m) {
+        // every lane takes part (the e4m3 scale pairs lanes q, q ^ 1); only
+        // rows inside X store
+        const IT Bh = (IT)cm.Bh[m], Im = (IT)cm.I[m];
+        const IT tt = r / Bh, bh = r - tt * Bh;
+        const IT a = tt / Im, i = tt - a * Im;
 #pragma unroll
-      for (int k = 0; k < VPC; k += 4) *(uint2*)(dst + k) = pack_bf16(v + k);
+        for (int u = 0; u < 16 / VPC; ++u) {
+          const IT bp = bh * INp + c + (IT)(u * VPC);
+          const IT kt = a * (IT)cm.nbt[m] + bp / KT, kk = bp - (bp / KT) * KT;
+          const int64_t rowid = (int64_t)kt * cm.ipad[m] + i;
+          const int sc = store_chunk<E>(v + u * VPC, cm.out[m] + rowid * 64 + kk * ES, ok);
+          if (ok && E == E_FP8 && ((kk >> 4) & 1) == 0)
+            cm.sc[m][scale_pos(rowid, (int)(kk >> 5))] = (unsigned char)sc;
+        }
+      }
+      if (xpad && ok) {
+        bf16_t* dst = xpad + (int64_t)r * INp + c;
+#pragma unroll
+        for (int k = 0; k < 16; k += 4) *(uint2*)(dst + k) = pack_bf16(v + k);
+      }
+    }
+    if (cm.last) {
+      __syncthreads();                             // the previous tile's readers are done
+#pragma unroll
+      for (int k = 0; k < 16; ++k) tile[q * 16 + k][rr] = v[k];
+      __syncthreads();
+      float w[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) w[k] = tile[rr][q * 16 + k];
+      const int64_t crow = (int64_t)cb * 64 + rr;
+      const int64_t k0 = (int64_t)h * Lp + (int64_t)lb * 64 + q * 16;
+#pragma unroll
+      for (int u = 0; u < 16 / VPC; ++u) {
+        const int64_t kk0 = k0 + u * VPC, kt = kk0 / KT, kk = kk0 - kt * KT;
+        const int64_t rowid = kt * cm.last_ipad + crow;
+        const int sc = store_chunk<E>(w + u * VPC, cm.last + rowid * 64 + kk * ES);
+        if (E == E_FP8 && ((kk >> 4) & 1) == 0) cm.last_sc[scale_pos(rowid, (int)(kk >> 5))] = (unsigned char)sc;
+      }
     }
   }
 }
@@ -852,48 +890,11 @@ __global__ void zero_pad_rows_kernel(char* out, unsigned char* scales, int64_t n
   }
 }
 
-// Blocked copy of X_(N) for the last mode: X viewed as R rows of I_N; the
-// operand's rows are the I_N columns of that matrix and its K index the R
-// rows (padded to Rp, zero).  out[kt][i][64 bytes] holds X[kt KT + k][i],
-// i < ipad (zero past I_N).  A workgroup transposes KT x 64 values through
-// LDS; each thread then writes 16 bytes (four threads per output row).
-template <class T, int E>
-__global__ void __launch_bounds__(256) block_copy_last_kernel(const T* X, int64_t R, int64_t IN, int64_t ipad,
-                                                              bool vec, char* out, unsigned char* scales) {
-  constexpr int VPC = E == E_FP8 ? 16 : 8;
-  constexpr int KT = 4 * VPC;
-  __shared__ float tile[KT][65];
-  const int64_t ib = ipad / 64;
-  const int64_t kt = blockIdx.x / ib, i0 = (blockIdx.x - kt * ib) * 64;
-  const int t = threadIdx.x, q4 = (t & 15) * 4;
-#pragma unroll
-  for (int pass = 0; pass < KT / 16; ++pass) {
-    const int y = pass * 16 + (t >> 4);            // K row kt KT + y, columns i0 + q4 .. + 3
-    const int64_t r = kt * KT + y, i = i0 + q4;
-    float v[4] = {0.f, 0.f, 0.f, 0.f};
-    if (r < R && i < IN) load4(X, r * IN + i, IN - i, vec, v);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) tile[y][q4 + k] = v[k];
-  }
-  __syncthreads();
-  const int row = t >> 2, q = t & 3;               // output row i0 + row, values q VPC .. + VPC - 1
-  float v[VPC];
-#pragma unroll
-  for (int k = 0; k < VPC; ++k) v[k] = tile[q * VPC + k][row];
-  const int64_t rowid = kt * ipad + i0 + row;
-  const int sc = store_chunk<E>(v, out + rowid * 64 + q * 16);
-  if (E == E_FP8 && (q & 1) == 0) scales[scale_pos(rowid, q >> 1)] = (unsigned char)sc;
-}
-
-// The blocked bf16 sketch [kt][64][64] -> e4m3 in the same layout, scales
-// [kt][h][row % 32][4] (byte row / 32; bytes 2, 3 stay zero).  One wave per
-// 64-value row; lane half h is run h.
 // The e4m3 sketch in one pass.  Row r = (K tile kt, sketch row sv) of the
 // blocked Omega^T holds the values at padded columns jp = kt KT + kk, drawn
 // from the sketch stream at L = sv J + j (j the unpadded column; zero in
-// padded columns and rows past S), rounded to bf16 and then to e4m3 exactly
-// as the two-pass form (bf16 sketch, then quantize_omega_kernel) does, with
-// the scale of each run of 32 in the same layout.  A wave takes two rows,
+// padded columns and rows past S), rounded to bf16 and then to e4m3 (the
+// scale of each run of 32 in the layout the Gram kernel reads).  A wave takes two rows,
 // a lane two neighbouring columns (one draw of a Gaussian pair when L is even).
 template <class IT>
 __global__ void omega_fp8_kernel(uint64_t seed, uint32_t mode, int64_t S_, int64_t J_, int64_t B_, int64_t IN_,
@@ -937,43 +938,11 @@ __global__ void omega_fp8_kernel(uint64_t seed, uint32_t mode, int64_t S_, int64
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     const int sc = e8m0_for(m);
-    const uint32_t b0 = f32_to_e4m3(ldexpf(v[0], 127 - sc)), b1 = f32_to_e4m3(ldexpf(v[1], 127 - sc));
-    *(unsigned short*)(q + r * 64 + 2 * pl) = (unsigned short)(b0 | (b1 << 8));
+    const float mul = pow2_neg(sc - 127);
+    *(unsigned short*)(q + r * 64 + 2 * pl) = (unsigned short)e4m3x2(v[0] * mul, v[1] * mul);
     if ((pl & 15) == 0) {
       const int h = pl >> 4;
       scales[(int64_t)kt * 256 + (h * 32 + (int)(sv & 31)) * 4 + (int)(sv >> 5)] = (unsigned char)sc;
-    }
-  }
-}
-
-__global__ void quantize_omega_kernel(const bf16_t* src, int64_t nrows, fp8_t* q, unsigned char* scales) {
-  const int lane = threadIdx.x & 63;
-  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < nrows;
-       r += (int64_t)gridDim.x * (blockDim.x >> 6)) {
-    const int64_t i = r * 64 + lane;
-    const float v = bf16_to_f32(src[i]);
-    const int sc = e8m0_for(half_max(fabsf(v)));
-    q[i] = f32_to_e4m3(ldexpf(v, 127 - sc));
-    if ((lane & 31) == 0) {
-      const int64_t kt = r >> 6;
-      const int s = (int)(r & 63), h = lane >> 5;
-      scales[kt * 256 + (h * 32 + (s & 31)) * 4 + (s >> 5)] = (unsigned char)sc;
-    }
-  }
-}
-
-// bf16 rows (total a multiple of 32) -> e4m3 + per-32 scales; one wave per 64 values.
-__global__ void quantize_rows_kernel(const bf16_t* src, int64_t total, fp8_t* q, unsigned char* scales) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nchunk = (total + 63) / 64;
-  for (int64_t ch = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); ch < nchunk;
-       ch += (int64_t)gridDim.x * (blockDim.x >> 6)) {
-    const int64_t i = ch * 64 + lane;
-    const float v = i < total ? bf16_to_f32(src[i]) : 0.f;
-    const int sc = e8m0_for(half_max(fabsf(v)));
-    if (i < total) {
-      q[i] = f32_to_e4m3(ldexpf(v, 127 - sc));
-      if ((lane & 31) == 0) scales[i >> 5] = (unsigned char)sc;
     }
   }
 }
@@ -1057,47 +1026,56 @@ int64_t block_rows(int64_t I) { return ceil_div(I, PT) * PT; }
 
 size_t block_copy_bytes(int64_t nkt, int64_t I) { return (size_t)nkt * block_rows(I) * PROW; }
 
-hipError_t launch_block_copy_lead(int src_elem, int elem, const void* X, int order, const int64_t* dims,
-                                  const bool* want, void* const* out, void* const* scales, void* xpad, hipStream_t s) {
+hipError_t launch_block_copies(int src_elem, int elem, const void* X, int order, const int64_t* dims,
+                               const bool* want, void* const* out, void* const* scales, void* xpad, hipStream_t s) {
   if (elem != E_FP8 && elem != E_BF16) return hipErrorInvalidValue;
+  if (order < 2 || order > 8) return hipErrorInvalidValue;
   const int64_t IN = dims[order - 1], INp = pad64(IN), KT = elem == E_FP8 ? 64 : 32;
-  int64_t R = 1;
-  for (int k = 0; k + 1 < order; ++k) R *= dims[k];
-  LeadModes lm = {};
+  const int64_t L = dims[order - 2], Lp = pad64(L);
+  int64_t H = 1;
+  for (int k = 0; k + 2 < order; ++k) H *= dims[k];
+  CopyModes cm = {};
   hipError_t e;
-  for (int n = 0; n + 1 < order; ++n) {
+  for (int n = 0; n < order; ++n) {
     if (!want[n]) continue;
     if (!out[n] || (elem == E_FP8 && !scales[n])) return hipErrorInvalidValue;
+    if (n == order - 1) {
+      cm.last = (char*)out[n];
+      cm.last_sc = (unsigned char*)scales[n];
+      cm.last_ipad = block_rows(IN);
+      continue;
+    }
     int64_t A = 1, B = 1;
     for (int k = 0; k < n; ++k) A *= dims[k];
     for (int k = n + 1; k < order; ++k) B *= dims[k];
-    const int m = lm.n++;
-    lm.I[m] = dims[n];
-    lm.Bh[m] = B / IN;
-    lm.ipad[m] = block_rows(dims[n]);
-    lm.nbt[m] = (B / IN) * INp / KT;
-    lm.out[m] = (char*)out[n];
-    lm.sc[m] = (unsigned char*)scales[n];
-    const int64_t nkt = A * lm.nbt[m];
-    if (lm.ipad[m] > dims[n]) {
-      const int64_t total = nkt * (lm.ipad[m] - dims[n]) * 4;
+    const int m = cm.n++;
+    cm.I[m] = dims[n];
+    cm.Bh[m] = B / IN;
+    cm.ipad[m] = block_rows(dims[n]);
+    cm.nbt[m] = (B / IN) * INp / KT;
+    cm.out[m] = (char*)out[n];
+    cm.sc[m] = (unsigned char*)scales[n];
+    const int64_t nkt = A * cm.nbt[m];
+    if (cm.ipad[m] > dims[n]) {
+      const int64_t total = nkt * (cm.ipad[m] - dims[n]) * 4;
       const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 16384);
       hipLaunchKernelGGL(zero_pad_rows_kernel, dim3(grid), dim3(256), 0, s, (char*)out[n],
-                         elem == E_FP8 ? (unsigned char*)scales[n] : nullptr, nkt, dims[n], lm.ipad[m]);
+                         elem == E_FP8 ? (unsigned char*)scales[n] : nullptr, nkt, dims[n], cm.ipad[m]);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
-  if (lm.n == 0 && !xpad) return hipSuccess;
-  const int64_t L = dims[order - 2], H = R / L;
-  const int64_t ntask = ceil_div(H, 4) * (INp / KT) * ceil_div(L, 4);
-  if (ntask <= 0) return hipSuccess;
+  if (cm.n == 0 && !cm.last && !xpad) return hipSuccess;
+  const int64_t ncols = cm.last ? cm.last_ipad : INp;
+  const int64_t ntile = H * (Lp / 64) * (ncols / 64);
+  if (ntile <= 0) return hipSuccess;
   const int es = src_elem == E_F64 ? 8 : src_elem == E_F32 ? 4 : 2;
   const bool vec = vec_ok(X, IN, es);
-  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(ntask, 4), 65536);
-  const bool small = ntask * 64 < ((int64_t)1 << 31) && (H + 4) * (L + 4) * INp < ((int64_t)1 << 31);
-#define BC(T, EE, IT)                                                                                            \
-  hipLaunchKernelGGL((block_copy_lead_kernel<T, EE, IT>), dim3(grid), dim3(256), 0, s, (const T*)X, H, L, IN, INp, \
-                     vec, lm, (bf16_t*)xpad)
+  const unsigned grid = (unsigned)std::min<int64_t>(ntile, (int64_t)1 << 20);
+  // 32-bit index arithmetic when every row, padded column and K index fits
+  const bool small = (H + 1) * Lp * std::max(INp, ncols) < ((int64_t)1 << 31);
+#define BC(T, EE, IT)                                                                                           \
+  hipLaunchKernelGGL((block_copy_kernel<T, EE, IT>), dim3(grid), dim3(256), 0, s, (const T*)X, H, L, IN, INp, vec, \
+                     cm, (bf16_t*)xpad)
 #define BC_E(T)                                                                  \
   if (elem == E_FP8) { if (small) BC(T, E_FP8, uint32_t); else BC(T, E_FP8, uint64_t); } \
   else { if (small) BC(T, E_BF16, uint32_t); else BC(T, E_BF16, uint64_t); }
@@ -1108,42 +1086,6 @@ hipError_t launch_block_copy_lead(int src_elem, int elem, const void* X, int ord
   }
 #undef BC_E
 #undef BC
-  return hipGetLastError();
-}
-
-hipError_t launch_block_copy_last(int src_elem, int elem, const void* X, int64_t R, int64_t IN, void* out,
-                                  void* scales, hipStream_t s) {
-  if (elem != E_FP8 && elem != E_BF16) return hipErrorInvalidValue;
-  if (elem == E_FP8 && !scales) return hipErrorInvalidValue;
-  const int64_t KT = elem == E_FP8 ? 64 : 32;
-  const int64_t nkt = pad64(R) / KT, ipad = block_rows(IN);
-  const int64_t blocks = nkt * (ipad / 64);
-  if (blocks <= 0) return hipSuccess;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const int es = src_elem == E_F64 ? 8 : src_elem == E_F32 ? 4 : 2;
-  const bool vec = vec_ok(X, IN, es);
-#define BL(T, EE)                                                                                              \
-  hipLaunchKernelGGL((block_copy_last_kernel<T, EE>), dim3((unsigned)blocks), dim3(256), 0, s, (const T*)X, R, IN, \
-                     ipad, vec, (char*)out, (unsigned char*)scales)
-#define BL_E(T) if (elem == E_FP8) BL(T, E_FP8); else BL(T, E_BF16);
-  switch (src_elem) {
-    case E_F64: BL_E(double); break;
-    case E_F32: BL_E(float); break;
-    default: BL_E(bf16_t); break;
-  }
-#undef BL_E
-#undef BL
-  return hipGetLastError();
-}
-
-hipError_t launch_quantize_rows_fp8(const void* src, int64_t rows, int64_t cols, void* q, void* scales,
-                                    hipStream_t s) {
-  const int64_t total = rows * cols;
-  if (total <= 0) return hipSuccess;
-  if (cols % 32) return hipErrorInvalidValue;
-  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(ceil_div(total, 64), 4), 16384);
-  hipLaunchKernelGGL(quantize_rows_kernel, dim3(grid), dim3(256), 0, s, (const bf16_t*)src, total, (fp8_t*)q,
-                     (unsigned char*)scales);
   return hipGetLastError();
 }
 
@@ -1161,17 +1103,6 @@ hipError_t launch_omega_fp8(uint64_t seed, int mode, int64_t S, int64_t J, int64
   else
     hipLaunchKernelGGL(omega_fp8_kernel<uint64_t>, dim3(grid), dim3(256), 0, s, seed, (uint32_t)mode, S, J, B, IN,
                        pad64(IN), nrows, (fp8_t*)q, (unsigned char*)scales);
-  return hipGetLastError();
-}
-
-hipError_t launch_quantize_omega(const void* src, int64_t nkt, void* q, void* scales, hipStream_t s) {
-  if (nkt <= 0) return hipSuccess;
-  hipError_t e = fill_zero(scales, (size_t)nkt * 256, s);
-  if (e != hipSuccess) return e;
-  const int64_t nrows = nkt * 64;
-  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(nrows, 4), 16384);
-  hipLaunchKernelGGL(quantize_omega_kernel, dim3(grid), dim3(256), 0, s, (const bf16_t*)src, nrows, (fp8_t*)q,
-                     (unsigned char*)scales);
   return hipGetLastError();
 }
 

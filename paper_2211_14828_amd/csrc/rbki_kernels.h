@@ -50,22 +50,17 @@ hipError_t launch_gram_pipe_reduce(const GramArgs& g, double* C, double* Wt, hip
 // X viewed as R rows of length L -> Xpad (R x pad64(L)) and Xt (L x pad64(R)),
 // bf16 with zero padding (either output may be null).
 hipError_t launch_pad_copies(int src_elem, const void* X, int64_t R, int64_t L, void* Xpad, void* Xt, hipStream_t s);
-// Blocked copies (elem E_BF16 or E_FP8, with scales) of the leading modes
-// n < order-1 with want[n], in one pass over X (out[n], scales[n] per mode);
+// Blocked copies (elem E_BF16 or E_FP8, with scales) of every mode n with
+// want[n] in one pass over X (out[n], scales[n] per mode).  Leading modes
+// take their K index along [A_n, (B_n / I_N) pad64(I_N)]; the last mode
+// along [H, pad64(I_{N-1})] with H the product of the other leading dims.
 // xpad (nullable): the row-major padded bf16 copy as well.
-hipError_t launch_block_copy_lead(int src_elem, int elem, const void* X, int order, const int64_t* dims,
-                                  const bool* want, void* const* out, void* const* scales, void* xpad, hipStream_t s);
-// Blocked copy of the last mode's unfolding (X as R rows of IN; K runs over R).
-hipError_t launch_block_copy_last(int src_elem, int elem, const void* X, int64_t R, int64_t IN, void* out,
-                                  void* scales, hipStream_t s);
-// The e4m3 blocked sketch of one mode in one pass (the values and scales the
-// bf16 sketch followed by launch_quantize_omega gives).
+hipError_t launch_block_copies(int src_elem, int elem, const void* X, int order, const int64_t* dims,
+                               const bool* want, void* const* out, void* const* scales, void* xpad, hipStream_t s);
+// The e4m3 blocked sketch of one mode in one pass (the bf16-rounded sketch,
+// quantised per run of 32 columns).
 hipError_t launch_omega_fp8(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t nkt,
                             void* q, void* scales, hipStream_t s);
-// The blocked bf16 sketch ([nkt][64][64]) -> e4m3, scales [nkt][2][32][4].
-hipError_t launch_quantize_omega(const void* src, int64_t nkt, void* q, void* scales, hipStream_t s);
-// rows x cols bf16 (cols a multiple of 32) -> e4m3 with per-32 E8M0 scales
-hipError_t launch_quantize_rows_fp8(const void* src, int64_t rows, int64_t cols, void* q, void* scales, hipStream_t s);
 // Omega^T (S x J) of one mode as bf16 in the padded column layout S x Jp
 // (row-major; the Gram fallback of the mixed forms).
 hipError_t launch_omega_pad(uint64_t seed, int mode, int64_t S, int64_t J, int64_t B, int64_t IN, int64_t Jp,

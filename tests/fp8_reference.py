@@ -5,8 +5,10 @@ copies of the tensor and of the sketch: every run of 32 consecutive values
 along a storage row gets the smallest power-of-two scale 2^s with
 max|x| / 2^s <= 448, and x / 2^s is rounded to the nearest OCP e4m3 ("fn")
 value, ties to even.  Storage rows are the last dimension for every mode but
-the last, and the flattened leading index for the last mode (the transposed
-copy).  The sketch is generated, rounded to bf16, and quantised the same way
+the last.  For the last mode (the transposed copy) they run over the
+flattened leading index, with the runs of 32 restarting at every run of the
+last leading dimension I_{N-1} (the copy pads each such run to a multiple of
+64).  The sketch is generated, rounded to bf16, and quantised the same way
 in its column layout.  A mode whose Gram product falls back to bf16 (I_n <= 128
 or S_n > 64) reads bf16-rounded operands instead.
 
@@ -69,8 +71,10 @@ def quantised_mode_operand(X, n, fp8):
         V = X.reshape(rows, IN)
         Vq = block_quantize(V) if fp8 else round_bf16(V)
         return unfold(Vq.reshape(X.shape), n)
-    T = X.reshape(rows, IN).T                  # the last mode's unfolding, I_N x A
-    return block_quantize(T) if fp8 else round_bf16(T)
+    L = X.shape[-2]
+    T = X.reshape(rows // L, L, IN).transpose(2, 0, 1)   # I_N x H x I_{N-1}
+    Tq = block_quantize(T) if fp8 else round_bf16(T)
+    return Tq.reshape(IN, rows)                # the last mode's unfolding
 
 
 def quantised_sketch(X, n, J, S, seed, fp8):
@@ -79,10 +83,8 @@ def quantised_sketch(X, n, J, S, seed, fp8):
     if not fp8:
         return Om
     N = X.ndim
-    if n == N - 1:
-        return block_quantize(Om.T).T
-    IN = X.shape[-1]
-    OmT = Om.T.reshape(S, J // IN, IN)         # runs along the last dimension
+    IN = X.shape[-2] if n == N - 1 else X.shape[-1]
+    OmT = Om.T.reshape(S, J // IN, IN)         # runs along the copy's storage rows
     return block_quantize(OmT).reshape(S, J).T
 
 
