@@ -703,6 +703,32 @@ __device__ inline void load4(const T* X, int64_t off, int64_t avail, bool vec, f
   }
 }
 
+// Sixteen values src[0 .. 15] as float, every one inside X; src is aligned
+// to four elements.
+template <class T>
+__device__ inline void load16(const T* src, float* v) {
+  if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 f = ((const float4*)src)[k];
+      v[4 * k] = f.x; v[4 * k + 1] = f.y; v[4 * k + 2] = f.z; v[4 * k + 3] = f.w;
+    }
+  } else if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint2 h = ((const uint2*)src)[k];
+      v[4 * k] = bf16_to_f32((bf16_t)(h.x & 0xFFFF)); v[4 * k + 1] = bf16_to_f32((bf16_t)(h.x >> 16));
+      v[4 * k + 2] = bf16_to_f32((bf16_t)(h.y & 0xFFFF)); v[4 * k + 3] = bf16_to_f32((bf16_t)(h.y >> 16));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double2 d = ((const double2*)src)[k];
+      v[2 * k] = (float)d.x; v[2 * k + 1] = (float)d.y;
+    }
+  }
+}
+
 __device__ inline uint2 pack_bf16(const float* v) {
   return make_uint2((uint32_t)f32_to_bf16(v[0]) | ((uint32_t)f32_to_bf16(v[1]) << 16),
                     (uint32_t)f32_to_bf16(v[2]) | ((uint32_t)f32_to_bf16(v[3]) << 16));
@@ -826,11 +852,16 @@ __global__ void __launch_bounds__(256) block_copy_kernel(const T* X, int64_t H_,
     const bool ok = l < L;
     const IT r = h * L + l;
     float v[16];
+    if (vec && (cb + 1) * 64 <= IN && (lb + 1) * 64 <= L) {
+      // interior tile (the same for the whole workgroup): unconditional loads
+      load16(X + (int64_t)r * IN + c, v);
+    } else {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = 0.f;
-    if (ok && c < IN) {
+      for (int k = 0; k < 16; ++k) v[k] = 0.f;
+      if (ok && c < IN) {
 #pragma unroll
-      for (int k = 0; k < 16; k += 4) load4(X, (int64_t)r * IN + c + k, IN_ - (int64_t)c - k, vec, v + k);
+        for (int k = 0; k < 16; k += 4) load4(X, (int64_t)r * IN + c + k, IN_ - (int64_t)c - k, vec, v + k);
+      }
     }
     if (cb < nlead) {
       for (int m = 0; m < cm.n; ++m) {
