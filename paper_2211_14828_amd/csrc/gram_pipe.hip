@@ -781,6 +781,23 @@ __device__ inline int64_t scale_pos(int64_t rowid, int h) {
 // 16 output bytes of a blocked copy: VPC values (16 e4m3 or 8 bf16), for
 // e4m3 with the scale of its run of 32 (the lane and its neighbour lane^1
 // hold the two halves of a run).  Returns the scale byte (e4m3) or 0.
+// The same 16 bytes, returned instead of stored (sc: the scale byte, or 0).
+template <int E>
+__device__ inline uint4 encode_chunk(const float* v, int& sc) {
+  if constexpr (E == E_FP8) {
+    float m = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) m = fmaxf(m, fabsf(v[k]));
+    m = fmaxf(m, __shfl_xor(m, 1, 64));
+    sc = e8m0_fast(m);
+    return make_uint4(pack_e4m3(v, sc), pack_e4m3(v + 4, sc), pack_e4m3(v + 8, sc), pack_e4m3(v + 12, sc));
+  } else {
+    sc = 0;
+    const uint2 lo = pack_bf16(v), hi = pack_bf16(v + 4);
+    return make_uint4(lo.x, lo.y, hi.x, hi.y);
+  }
+}
+
 template <int E>
 __device__ inline int store_chunk(const float* v, char* dst, bool store = true) {
   if constexpr (E == E_FP8) {
@@ -815,14 +832,20 @@ __device__ inline int store_chunk(const float* v, char* dst, bool store = true) 
 //    index k = h Lp + l with Lp = pad64(L) (zero for l >= L), so that every
 //    K tile lies inside one run of L rows; copy [k / KT][c][64 bytes].
 // e4m3 scales in the layout scale_pos describes.  xpad (nullable): the
-// row-major padded bf16 copy.  A workgroup takes tiles of 64 rows (h, l0 ..
-// l0+63) by 64 columns (l0, c0 multiples of 64): thread t reads 16 values of
-// row l0 + t/4 and writes the leading copies' chunks from registers (four
-// threads fill the 64 bytes of a row chunk, neighbouring rows of mode N-2
-// are neighbouring chunks); the tile then goes through LDS transposed, and
-// thread t writes 16 K values of the last mode's row c0 + t/4.
+// row-major padded bf16 copy.
+//
+// A workgroup takes 64 rows l0 .. l0+63 by 64 columns c0 .. c0+63 (l0, c0
+// multiples of 64) for four consecutive h in turn: thread t reads 16 values
+// of row l0 + t/4 and writes the leading copies' chunks from registers (four
+// threads fill the 64 bytes of a row chunk; neighbouring l are neighbouring
+// rows of mode N-2); the tile then goes through LDS transposed, and thread
+// t writes 16 K values of the last mode's row c0 + t/4.  Mode N-3 (cm.stage,
+// whose rows follow h) keeps its chunks of the four h in LDS and writes
+// them at the end: its rows h .. h+3 are neighbours, so each l gives one
+// 256-byte run instead of four scattered 64-byte pieces.
 struct CopyModes {
   int n;                          // leading modes with a copy
+  int stage;                      // index (< n) of mode N-3's copy, or -1
   int64_t I[7], Bh[7], ipad[7], nbt[7];
   char* out[7];
   unsigned char* sc[7];
@@ -831,78 +854,116 @@ struct CopyModes {
   int64_t last_ipad;
 };
 
+template <class IT, int KT>
+__device__ inline int64_t lead_rowid(const CopyModes& cm, int m, IT r, IT col, IT INp, IT& kk) {
+  const IT Bh = (IT)cm.Bh[m], Im = (IT)cm.I[m];
+  const IT tt = r / Bh, bh = r - tt * Bh;
+  const IT a = tt / Im, i = tt - a * Im;
+  const IT bp = bh * INp + col;
+  const IT kt = a * (IT)cm.nbt[m] + bp / KT;
+  kk = bp - (bp / KT) * KT;
+  return (int64_t)kt * cm.ipad[m] + i;
+}
+
 template <class T, int E, class IT>
 __global__ void __launch_bounds__(256) block_copy_kernel(const T* X, int64_t H_, int64_t L_, int64_t IN_,
                                                          int64_t INp_, bool vec, CopyModes cm, bf16_t* xpad) {
   constexpr int VPC = E == E_FP8 ? 16 : 8;     // values per 16-byte chunk
   constexpr int KT = 4 * VPC;
   constexpr int ES = E == E_FP8 ? 1 : 2;
+  constexpr int NCH = 16 / VPC;                // chunks per thread and tile row
+  constexpr int HB = 4;                        // h per workgroup step
   __shared__ float tile[64][65];
-  const IT L = (IT)L_, IN = (IT)IN_, INp = (IT)INp_;
+  __shared__ uint4 stg[HB][64][4 * NCH];       // mode N-3's chunks: [h][l][chunk]
+  const IT H = (IT)H_, L = (IT)L_, IN = (IT)IN_, INp = (IT)INp_;
   const IT Lp = (L + 63) / 64 * 64;
   const IT nlb = Lp / 64, nlead = INp / 64;
   const IT ncb = (IT)((cm.last ? cm.last_ipad : INp_) / 64);
-  const int64_t ntile = H_ * (int64_t)nlb * ncb;
+  const IT nhb = (H + HB - 1) / HB;
+  const int64_t ntile = (int64_t)nhb * nlb * ncb;
   const int t = threadIdx.x, rr = t >> 2, q = t & 3;
   for (int64_t id = blockIdx.x; id < ntile; id += gridDim.x) {
     const IT tk = (IT)id;
     const IT cb = tk % ncb, rest = tk / ncb;
-    const IT lb = rest % nlb, h = rest / nlb;
+    const IT lb = rest % nlb, hb = rest / nlb;
     const IT l = lb * 64 + (IT)rr, c = cb * 64 + (IT)q * 16;
     const bool ok = l < L;
-    const IT r = h * L + l;
-    float v[16];
-    if (vec && (cb + 1) * 64 <= IN && (lb + 1) * 64 <= L) {
-      // interior tile (the same for the whole workgroup): unconditional loads
-      load16(X + (int64_t)r * IN + c, v);
-    } else {
+    const bool lead = cb < nlead;              // the tile holds leading-mode columns
+    for (int hh = 0; hh < HB; ++hh) {
+      const IT h = hb * HB + (IT)hh;
+      if (h >= H) break;                         // the same for the whole workgroup
+      const IT r = h * L + l;
+      float v[16];
+      if (vec && (cb + 1) * 64 <= IN && (lb + 1) * 64 <= L) {
+        // interior tile (the same for the whole workgroup): unconditional loads
+        load16(X + (int64_t)r * IN + c, v);
+      } else {
 #pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = 0.f;
-      if (ok && c < IN) {
+        for (int k = 0; k < 16; ++k) v[k] = 0.f;
+        if (ok && c < IN) {
 #pragma unroll
-        for (int k = 0; k < 16; k += 4) load4(X, (int64_t)r * IN + c + k, IN_ - (int64_t)c - k, vec, v + k);
-      }
-    }
-    if (cb < nlead) {
-      for (int m = 0; m < cm.n; ++m) {
-        // every lane takes part (the e4m3 scale pairs lanes q, q ^ 1); only
-        // rows inside X store
-        const IT Bh = (IT)cm.Bh[m], Im = (IT)cm.I[m];
-        const IT tt = r / Bh, bh = r - tt * Bh;
-        const IT a = tt / Im, i = tt - a * Im;
-#pragma unroll
-        for (int u = 0; u < 16 / VPC; ++u) {
-          const IT bp = bh * INp + c + (IT)(u * VPC);
-          const IT kt = a * (IT)cm.nbt[m] + bp / KT, kk = bp - (bp / KT) * KT;
-          const int64_t rowid = (int64_t)kt * cm.ipad[m] + i;
-          const int sc = store_chunk<E>(v + u * VPC, cm.out[m] + rowid * 64 + kk * ES, ok);
-          if (ok && E == E_FP8 && ((kk >> 4) & 1) == 0)
-            cm.sc[m][scale_pos(rowid, (int)(kk >> 5))] = (unsigned char)sc;
+          for (int k = 0; k < 16; k += 4) load4(X, (int64_t)r * IN + c + k, IN_ - (int64_t)c - k, vec, v + k);
         }
       }
-      if (xpad && ok) {
-        bf16_t* dst = xpad + (int64_t)r * INp + c;
+      if (lead) {
+        for (int m = 0; m < cm.n; ++m) {
+          // every lane takes part (the e4m3 scale pairs lanes q, q ^ 1); only
+          // rows inside X store
 #pragma unroll
-        for (int k = 0; k < 16; k += 4) *(uint2*)(dst + k) = pack_bf16(v + k);
+          for (int u = 0; u < NCH; ++u) {
+            IT kk;
+            const int64_t rowid = lead_rowid<IT, KT>(cm, m, r, c + (IT)(u * VPC), INp, kk);
+            int sc;
+            const uint4 w = encode_chunk<E>(v + u * VPC, sc);
+            if (m == cm.stage) stg[hh][rr][q * NCH + u] = w;
+            else if (ok) *(uint4*)(cm.out[m] + rowid * 64 + kk * ES) = w;
+            if (ok && E == E_FP8 && ((kk >> 4) & 1) == 0)
+              cm.sc[m][scale_pos(rowid, (int)(kk >> 5))] = (unsigned char)sc;
+          }
+        }
+        if (xpad && ok) {
+          bf16_t* dst = xpad + (int64_t)r * INp + c;
+#pragma unroll
+          for (int k = 0; k < 16; k += 4) *(uint2*)(dst + k) = pack_bf16(v + k);
+        }
+      }
+      if (cm.last) {
+        __syncthreads();                           // the previous tile's readers are done
+#pragma unroll
+        for (int k = 0; k < 16; ++k) tile[q * 16 + k][rr] = v[k];
+        __syncthreads();
+        float w[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) w[k] = tile[rr][q * 16 + k];
+        const int64_t crow = (int64_t)cb * 64 + rr;
+        const int64_t k0 = (int64_t)h * Lp + (int64_t)lb * 64 + q * 16;
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          const int64_t kk0 = k0 + u * VPC, kt = kk0 / KT, kk = kk0 - kt * KT;
+          const int64_t rowid = kt * cm.last_ipad + crow;
+          const int sc = store_chunk<E>(w + u * VPC, cm.last + rowid * 64 + kk * ES);
+          if (E == E_FP8 && ((kk >> 4) & 1) == 0) cm.last_sc[scale_pos(rowid, (int)(kk >> 5))] = (unsigned char)sc;
+        }
       }
     }
-    if (cm.last) {
-      __syncthreads();                             // the previous tile's readers are done
-#pragma unroll
-      for (int k = 0; k < 16; ++k) tile[q * 16 + k][rr] = v[k];
+    if (cm.stage >= 0 && lead) {
+      // mode N-3's chunks: piece e = (l, h, chunk) with the chunk fastest, so
+      // that a wave writes the chunks of neighbouring rows h together
       __syncthreads();
-      float w[16];
+      constexpr int PIECES = HB * 64 * 4 * NCH;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) w[k] = tile[rr][q * 16 + k];
-      const int64_t crow = (int64_t)cb * 64 + rr;
-      const int64_t k0 = (int64_t)h * Lp + (int64_t)lb * 64 + q * 16;
-#pragma unroll
-      for (int u = 0; u < 16 / VPC; ++u) {
-        const int64_t kk0 = k0 + u * VPC, kt = kk0 / KT, kk = kk0 - kt * KT;
-        const int64_t rowid = kt * cm.last_ipad + crow;
-        const int sc = store_chunk<E>(w + u * VPC, cm.last + rowid * 64 + kk * ES);
-        if (E == E_FP8 && ((kk >> 4) & 1) == 0) cm.last_sc[scale_pos(rowid, (int)(kk >> 5))] = (unsigned char)sc;
+      for (int it = 0; it < PIECES / 256; ++it) {
+        const int e = it * 256 + t;
+        const int ch = e % (4 * NCH), hh = (e / (4 * NCH)) % HB, rl = e / (4 * NCH * HB);
+        const IT h = hb * HB + (IT)hh, l2 = lb * 64 + (IT)rl;
+        if (h < H && l2 < L) {
+          IT kk;
+          const IT col = cb * 64 + (IT)((ch / NCH) * 16 + (ch % NCH) * VPC);
+          const int64_t rowid = lead_rowid<IT, KT>(cm, cm.stage, h * L + l2, col, INp, kk);
+          *(uint4*)(cm.out[cm.stage] + rowid * 64 + kk * ES) = stg[hh][rl][ch];
+        }
       }
+      __syncthreads();                             // stg is rewritten by the next tile
     }
   }
 }
@@ -1066,6 +1127,7 @@ hipError_t launch_block_copies(int src_elem, int elem, const void* X, int order,
   int64_t H = 1;
   for (int k = 0; k + 2 < order; ++k) H *= dims[k];
   CopyModes cm = {};
+  cm.stage = -1;
   hipError_t e;
   for (int n = 0; n < order; ++n) {
     if (!want[n]) continue;
@@ -1080,6 +1142,7 @@ hipError_t launch_block_copies(int src_elem, int elem, const void* X, int order,
     for (int k = 0; k < n; ++k) A *= dims[k];
     for (int k = n + 1; k < order; ++k) B *= dims[k];
     const int m = cm.n++;
+    if (n == order - 3) cm.stage = m;
     cm.I[m] = dims[n];
     cm.Bh[m] = B / IN;
     cm.ipad[m] = block_rows(dims[n]);
@@ -1097,7 +1160,7 @@ hipError_t launch_block_copies(int src_elem, int elem, const void* X, int order,
   }
   if (cm.n == 0 && !cm.last && !xpad) return hipSuccess;
   const int64_t ncols = cm.last ? cm.last_ipad : INp;
-  const int64_t ntile = H * (Lp / 64) * (ncols / 64);
+  const int64_t ntile = ceil_div(H, 4) * (Lp / 64) * (ncols / 64);
   if (ntile <= 0) return hipSuccess;
   const int es = src_elem == E_F64 ? 8 : src_elem == E_F32 ? 4 : 2;
   const bool vec = vec_ok(X, IN, es);
