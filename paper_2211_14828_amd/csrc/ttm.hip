@@ -497,15 +497,6 @@ struct FirstArgs {
 constexpr int F_CH = 256;                    // rows per chunk
 constexpr int F_ROW = F_CH * 2 + 16;         // LDS bytes per column row (padded)
 
-// e4m3 (bias 7) byte -> float times a power of two, branch-free: normal
-// values as 1.m 2^(e-7), subnormals (e = 0) as m 2^-9
-__device__ inline float e4m3_scaled(uint32_t q, float mul) {
-  const uint32_t sgn = (q & 0x80u) << 24, e = (q >> 3) & 0xFu, m = q & 7u;
-  const float nv = __uint_as_float(sgn | ((e + 120u) << 23) | (m << 20));
-  const float sv = __uint_as_float(sgn | 0x3F800000u) * (float)m * 0x1p-9f;
-  return (e ? nv : sv) * mul;
-}
-
 __device__ inline int64_t first_scale_pos(int64_t rowid, int h) {
   const int rr = (int)(rowid & 255);
   return ((rowid >> 8) * 2 + h) * 256 + (rr & 31) * 8 + (rr >> 5);
@@ -559,10 +550,19 @@ __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
         const float mul = __uint_as_float((sb > 0 ? sb : 1u) << 23) * (sb > 0 ? 1.f : 0.5f);
         const uint32_t w[2] = {raw[e].x, raw[e].y};
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const uint32_t h = __float_as_uint(e4m3_scaled((w[c >> 2] >> (8 * (c & 3))) & 0xFFu, mul)) >> 16;
-          if (e & 1) o[c][e >> 1] |= h << 16;
-          else o[c][e >> 1] = h;
+        for (int p = 0; p < 4; ++p) {
+          // bytes 2p, 2p + 1 (columns 2p, 2p + 1): the hardware conversion of
+          // OCP e4m3 to float is exact, and so is the power-of-two scaling
+          const f32x2_t f = (p & 1) ? __builtin_amdgcn_cvt_pk_f32_fp8((int)w[p >> 1], true)
+                                    : __builtin_amdgcn_cvt_pk_f32_fp8((int)w[p >> 1], false);
+          const uint32_t h0 = __float_as_uint(f.x * mul) >> 16, h1 = __float_as_uint(f.y * mul) >> 16;
+          if (e & 1) {
+            o[2 * p][e >> 1] |= h0 << 16;
+            o[2 * p + 1][e >> 1] |= h1 << 16;
+          } else {
+            o[2 * p][e >> 1] = h0;
+            o[2 * p + 1][e >> 1] = h1;
+          }
         }
       }
     } else {
