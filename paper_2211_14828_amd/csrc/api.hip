@@ -567,6 +567,28 @@ rbki_status run_mode(const Plan& P, const Buffers& b, int lane, const void* xsrc
   return run_mode_chain(P, b, lane, n, with_factor, st);
 }
 
+// Alg. 2, steps 4-5 for mode n alone, on stream st (the mode's stream when
+// the modes run concurrently): its R leading eigenvectors (ordinary launch:
+// the solve runs beside other modes' work) and U^T = Vt(1:R, :) Q^T with the
+// sign rule.  For modes whose Z the leading-eigenpair solver takes.
+rbki_status factor_one(const Plan& P, const Buffers& b, int n, hipStream_t st) {
+  const ModeGeom& g = P.m[n];
+  const double* Z = b.Z[n];
+  int64_t sn = g.Sp, rn = g.R;
+  double* lam = b.lam[n];
+  double* Vt = b.Vt[n];
+  void* w = b.jwork[n];
+  int* info = b.info + 2 * n;
+  {
+    // the last mode's solve is the one the decomposition waits for
+    ProfScope ps(n == P.N - 1 ? "eig" : "eig_early", st);
+    HIPCHK(eig_top_batched(1, &Z, &sn, &rn, &lam, &Vt, &w, &info, st, false));
+  }
+  HIPCHK(dgemm(0, 0, g.R, g.I, g.Sp, 1.0, b.Vt[n], g.Sp, b.Qt[n], g.I, 0.0, b.Ut64[n], g.I, st));
+  HIPCHK(canonical_sign_rows(b.Ut64[n], g.R, g.I, st));
+  return RBKI_OK;
+}
+
 // Alg. 2, steps 4-5 for all modes: the R leading eigenvectors of every Z in
 // one launch (tridiagonal reduction, bisection, inverse iteration; block
 // Jacobi for matrices beyond that solver's sizes), then U^T = Vt(1:R, :) Q^T
@@ -612,8 +634,37 @@ rbki_status run_factors(const Plan& P, const Buffers& b, hipStream_t st) {
 }
 
 // Core chain and error.  Returns the core (chain element type) in *core_out.
+// Alg. 2, step 6, first product: G_1 = X x_f U^(f)T for the first mode f of
+// the core chain, into b.chainA.  It reads X (or the mode's blocked copy) and
+// U^(f) only, so it may run as soon as that factor exists.
+rbki_status first_product(const Plan& P, const Buffers& b, const void* xsrc, hipStream_t st) {
+  const int n = P.first_mode;
+  const int64_t A = P.m[n].A, I = P.m[n].I, B = P.m[n].B;
+  void* out = b.chainA;
+  if (P.first_blocked) {
+    // precision form: the product reads the mode's blocked copy (the Gram
+    // operand), decoded to bf16, on bf16 MFMA
+    ProfScope ps("ttm", st);
+    HIPCHK(launch_ttm_first_blocked(P.m[n].pelem, b.xb[n], b.xs[n], A, I, B, P.dims[P.N - 1], b.Ut64[n],
+                                    P.m[n].R, b.u16, out, st));
+  } else if (P.need_pad) {
+    // precision form: the product reads the padded bf16 copy on bf16 MFMA
+    HIPCHK(convert_tensor(E_F64, b.Ut64[n], E_BF16, b.Uop, P.m[n].R * I, st));
+    ProfScope ps("ttm", st);
+    HIPCHK(launch_ttm_padded(b.xpad, A, I, B, P.dims[P.N - 1], b.Uop, P.m[n].R, out, st));
+  } else {
+    HIPCHK(convert_tensor(E_F64, b.Ut64[n], P.telem, b.Uop, P.m[n].R * I, st));
+    ProfScope ps("ttm", st);
+    HIPCHK(launch_ttm(P.telem, xsrc, A, I, B, b.Uop, P.m[n].R, out, nullptr, 0, st));
+  }
+  return RBKI_OK;
+}
+
+// first_done: first_product has already been enqueued (on a stream that st
+// has joined).
 rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, const void* xsrc, void* core,
-                               int out_elem, bool want_err, double* sums_host, void** core_out, hipStream_t st) {
+                               int out_elem, bool want_err, double* sums_host, void** core_out, hipStream_t st,
+                               bool first_done = false) {
   const size_t ce = P.celem == E_F64 ? 8 : 4;
   int64_t cur[8];
   for (int n = 0; n < P.N; ++n) cur[n] = P.dims[n];
@@ -627,28 +678,11 @@ rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, c
   void* bufs[2] = {b.chainA, b.chainB};
   int which = 0;
   // first product reads X
-  {
-    const int n = P.first_mode;
-    int64_t A, I, B;
-    view(n, A, I, B);
-    if (P.first_blocked) {
-      // precision form: the product reads the mode's blocked copy (the Gram
-      // operand), decoded to bf16, on bf16 MFMA
-      ProfScope ps("ttm", st);
-      HIPCHK(launch_ttm_first_blocked(P.m[n].pelem, b.xb[n], b.xs[n], A, I, B, P.dims[P.N - 1], b.Ut64[n],
-                                      P.m[n].R, b.u16, bufs[which], st));
-    } else if (P.need_pad) {
-      // precision form: the product reads the padded bf16 copy on bf16 MFMA
-      HIPCHK(convert_tensor(E_F64, b.Ut64[n], E_BF16, b.Uop, P.m[n].R * I, st));
-      ProfScope ps("ttm", st);
-      HIPCHK(launch_ttm_padded(b.xpad, A, I, B, P.dims[P.N - 1], b.Uop, P.m[n].R, bufs[which], st));
-    } else {
-      HIPCHK(convert_tensor(E_F64, b.Ut64[n], P.telem, b.Uop, P.m[n].R * I, st));
-      ProfScope ps("ttm", st);
-      HIPCHK(launch_ttm(P.telem, xsrc, A, I, B, b.Uop, P.m[n].R, bufs[which], nullptr, 0, st));
-    }
-    cur[n] = P.m[n].R;
+  if (!first_done) {
+    rbki_status s = first_product(P, b, xsrc, st);
+    if (s != RBKI_OK) return s;
   }
+  cur[P.first_mode] = P.m[P.first_mode].R;
   for (int n = 0; n < P.N; ++n) {
     if (n == P.first_mode) continue;
     int64_t A, I, B;
@@ -898,7 +932,11 @@ static hipStream_t lane_stream(int lane) {
 // more than one set the sets run on their own streams, forked from and
 // joined back to st by events (the request server keeps one stream per
 // request).  Each mode does the same work either way.
-static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, hipStream_t st) {
+// inline_factors: each mode's factor step (and, for the first mode of the
+// core chain, the first product) follows its Krylov chain on its stream, so
+// that it runs beside the later modes' work.
+static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, hipStream_t st,
+                             bool inline_factors = false) {
   const int lanes = P.concurrent ? 1 : b.lanes;
   hipStream_t ls[kMaxLanes] = {st, st, st};
   hipEvent_t ev[kMaxLanes] = {};
@@ -929,7 +967,11 @@ static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, 
       const int n1 = std::min(P.N, n0 + lanes);
       for (int n = n0; n < n1 && s == RBKI_OK; ++n)
         s = run_mode_heavy(P, b, n % lanes, xsrc, n, ls[n % lanes], n > 0 ? heavy[n - 1] : nullptr, heavy[n]);
-      for (int n = n0; n < n1 && s == RBKI_OK; ++n) s = run_mode_chain(P, b, n % lanes, n, true, ls[n % lanes]);
+      for (int n = n0; n < n1 && s == RBKI_OK; ++n) {
+        s = run_mode_chain(P, b, n % lanes, n, true, ls[n % lanes]);
+        if (s == RBKI_OK && inline_factors) s = factor_one(P, b, n, ls[n % lanes]);
+        if (s == RBKI_OK && inline_factors && n == P.first_mode) s = first_product(P, b, xsrc, ls[n % lanes]);
+      }
     }
   }
   if (lanes > 1) {
@@ -965,17 +1007,25 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
     if (s != RBKI_OK) return s;
   }
   HIPCHK(fill_zero(b.info, counters_bytes(P), st));
-  s = run_modes(P, b, xsrc, st);
+  // with concurrent modes, each mode's eigenproblem and factor (and the first
+  // product of the core chain) run on its stream as soon as its Krylov basis
+  // is done
+  bool inline_factors = !P.concurrent && b.lanes > 1;
+  for (int n = 0; n < P.N; ++n) inline_factors = inline_factors && eig_top_ok(P.m[n].Sp, P.m[n].R);
+  s = run_modes(P, b, xsrc, st, inline_factors);
   if (s != RBKI_OK) return s;
-  s = run_factors(P, b, st);
-  if (s != RBKI_OK) return s;
+  if (!inline_factors) {
+    s = run_factors(P, b, st);
+    if (s != RBKI_OK) return s;
+  }
   for (int n = 0; n < P.N; ++n)
     if (factors && factors[n])
       HIPCHK(store_factor(b.Ut64[n], P.m[n].R, P.m[n].I, factors[n], dtype_elem(out_type), st));
   HostResult local;
   HostResult* hr = async_res ? async_res : &local;
   const bool want_err = rel_err || async_res;
-  s = run_core_and_error(P, b, X, xsrc, core, dtype_elem(out_type), want_err, hr->sums, core_chain, st);
+  s = run_core_and_error(P, b, X, xsrc, core, dtype_elem(out_type), want_err, hr->sums, core_chain, st,
+                         inline_factors);
   if (s != RBKI_OK) return s;
   if (!want_err) return RBKI_OK;
   HIPCHK(hipMemcpyAsync(hr->info, b.info, 2 * P.N * sizeof(int), hipMemcpyDeviceToHost, st));

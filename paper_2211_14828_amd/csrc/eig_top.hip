@@ -746,7 +746,7 @@ Layout layout(int64_t n, int64_t R) {
 }
 
 template <int NS>
-hipError_t launch_ns(EigArgs& a, int nmat, int gmax, int64_t rows_cap, int rmax, hipStream_t st) {
+hipError_t launch_ns(EigArgs& a, int nmat, int gmax, int64_t rows_cap, int rmax, bool coop, hipStream_t st) {
   hipError_t e;
   const size_t rshm = reduce_fixed_bytes(NS) + (size_t)rows_cap * 8;
   if ((e = hipFuncSetAttribute((const void*)eig_reduce_kernel<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -754,13 +754,21 @@ hipError_t launch_ns(EigArgs& a, int nmat, int gmax, int64_t rows_cap, int rmax,
     return e;
   if (gmax > 1) {
     // the workgroups of a matrix wait for each other: a cooperative launch
-    // guarantees that they are all resident
+    // guarantees that they are all resident.  An ordinary launch (coop false,
+    // for a solve that runs beside other work) relies on the few workgroups
+    // becoming resident as the device frees room; the barrier's bounded spin
+    // reports a failure rather than waiting for ever.
     for (int k = 0; k < nmat; ++k)
       if (a.G[k] > 1 && (e = fill_zero(a.cnt[k], 64, st)) != hipSuccess) return e;
-    void* args[] = {&a};
-    e = hipLaunchCooperativeKernel((const void*)eig_reduce_kernel<NS>, dim3(gmax, nmat), dim3(RED_THREADS), args,
-                                   rshm, st);
-    if (e != hipSuccess) return e;
+    if (coop) {
+      void* args[] = {&a};
+      e = hipLaunchCooperativeKernel((const void*)eig_reduce_kernel<NS>, dim3(gmax, nmat), dim3(RED_THREADS), args,
+                                     rshm, st);
+      if (e != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(eig_reduce_kernel<NS>, dim3(gmax, nmat), dim3(RED_THREADS), rshm, st, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   } else {
     hipLaunchKernelGGL(eig_reduce_kernel<NS>, dim3(1, nmat), dim3(RED_THREADS), rshm, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -786,7 +794,7 @@ size_t eig_top_work_bytes(int64_t n, int64_t R) { return layout(n, R).total; }
 
 hipError_t eig_top_batched(int nmat, const double* const* Z, const int64_t* ns, const int64_t* Rs,
                            double* const* lam, double* const* Vt, void* const* work, int* const* info,
-                           hipStream_t st) {
+                           hipStream_t st, bool coop) {
   if (nmat <= 0) return hipSuccess;
   if (nmat > EIG_MAXB) return hipErrorInvalidValue;
   EigArgs a = {};
@@ -824,14 +832,14 @@ hipError_t eig_top_batched(int nmat, const double* const* Z, const int64_t* ns, 
     rmax = std::max(rmax, Rs[k]);
   }
   switch ((int)ceil_div(nmax, 64)) {
-    case 1: return launch_ns<1>(a, nmat, gmax, rows_cap, (int)rmax, st);
-    case 2: return launch_ns<2>(a, nmat, gmax, rows_cap, (int)rmax, st);
-    case 3: return launch_ns<3>(a, nmat, gmax, rows_cap, (int)rmax, st);
-    case 4: return launch_ns<4>(a, nmat, gmax, rows_cap, (int)rmax, st);
-    case 5: return launch_ns<5>(a, nmat, gmax, rows_cap, (int)rmax, st);
-    case 6: return launch_ns<6>(a, nmat, gmax, rows_cap, (int)rmax, st);
-    case 7: return launch_ns<7>(a, nmat, gmax, rows_cap, (int)rmax, st);
-    default: return launch_ns<8>(a, nmat, gmax, rows_cap, (int)rmax, st);
+    case 1: return launch_ns<1>(a, nmat, gmax, rows_cap, (int)rmax, coop, st);
+    case 2: return launch_ns<2>(a, nmat, gmax, rows_cap, (int)rmax, coop, st);
+    case 3: return launch_ns<3>(a, nmat, gmax, rows_cap, (int)rmax, coop, st);
+    case 4: return launch_ns<4>(a, nmat, gmax, rows_cap, (int)rmax, coop, st);
+    case 5: return launch_ns<5>(a, nmat, gmax, rows_cap, (int)rmax, coop, st);
+    case 6: return launch_ns<6>(a, nmat, gmax, rows_cap, (int)rmax, coop, st);
+    case 7: return launch_ns<7>(a, nmat, gmax, rows_cap, (int)rmax, coop, st);
+    default: return launch_ns<8>(a, nmat, gmax, rows_cap, (int)rmax, coop, st);
   }
 }
 

@@ -128,15 +128,19 @@ hipError_t jacobi_eig_batched(int nmat, const double* const* Z, const int64_t* n
                               hipStream_t st, bool per_matrix = false);
 
 // The R largest eigenpairs of symmetric PSD n x n matrices (eig_top.hip):
-// Householder tridiagonalisation, multisection and inverse iteration, one
-// workgroup per matrix.  lam[k] receives R eigenvalues (descending), rows
-// 0..R-1 of Vt[k] (leading dimension n) the unit eigenvectors.  Only the
-// upper triangle of Z is read.  info[k] (nullable) gets {0, 0}.
+// Householder tridiagonalisation (one or more workgroups per matrix),
+// multisection and inverse iteration.  lam[k] receives R eigenvalues
+// (descending), rows 0..R-1 of Vt[k] (leading dimension n) the unit
+// eigenvectors.  Only the upper triangle of Z is read.  info[k] (nullable)
+// gets {0, 0}, or info[k][0] = 1 when the workgroups of a reduction did not
+// meet within the barrier's spin limit.  coop: a cooperative launch for the
+// multi-workgroup reduction; false gives an ordinary launch, for a solve
+// enqueued beside other work.
 bool eig_top_ok(int64_t n, int64_t R);                  // 1 <= R <= n <= 512
 size_t eig_top_work_bytes(int64_t n, int64_t R);
 hipError_t eig_top_batched(int nmat, const double* const* Z, const int64_t* n, const int64_t* R,
                            double* const* lam, double* const* Vt, void* const* work, int* const* info,
-                           hipStream_t st);
+                           hipStream_t st, bool coop = true);
 
 // Copy / convert helpers.
 hipError_t copy_rows_f64(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t rows,

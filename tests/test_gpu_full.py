@@ -1,0 +1,96 @@
+"""The 1000 x 1000 x 1000 float32 workload (ranks 50, p = 10, q = 4) in the
+launch configuration bench.py times: the modes run on concurrent streams,
+and each mode's eigenproblem, factor and (for the first mode of the core
+chain) first product follow its Krylov chain on its stream.  At this size the
+oracle cannot run, so the checks are properties that hold at any size:
+
+- the concurrent run gives bit for bit the factors, core and error of the
+  same request solved with the modes in order (the request server runs a
+  request on one stream), and of a second run;
+- the factors are orthonormal (Alg. 2 builds them from an orthonormal basis
+  and unit eigenvectors);
+- the core is X x_1 U1^T x_2 U2^T x_3 U3^T (Alg. 2, step 6), up to the
+  precision form's rounding of X;
+- the reported error is the error of the orthogonal projection onto the
+  factors' spans: ||X - X x_n U_n U_n^T||^2 = ||X||^2 - ||X x_n U_n^T||^2 for
+  orthonormal U_n, computed here in float64 from X and the returned factors.
+"""
+import math
+
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# relative Frobenius distance of the returned core from the float64 core of
+# the same factors: the first mode product reads X rounded to e4m3 (3
+# mantissa bits) or bf16 (8); measured 8.4e-4 and 3.8e-4
+CORE_TOL = {"mixed_fp8": 4e-3, "mixed_bf16": 2e-3}
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    import paper_2211_14828_amd as rb
+    rb.load_library(build_if_missing=False)
+    return torch, rb
+
+
+@pytest.fixture(scope="module")
+def big(env):
+    torch, _ = env
+    w = synth.WORKLOADS["tucker1000_f32"]
+    print("generating", w["dims"], flush=True)
+    X = synth.make_device(w)
+    torch.cuda.synchronize()
+    return w, X
+
+
+def identical(torch, a, b):
+    core_a, fac_a, err_a = a[:3]
+    core_b, fac_b, err_b = b[:3]
+    return (torch.equal(core_a, core_b) and all(torch.equal(x, y) for x, y in zip(fac_a, fac_b))
+            and err_a == err_b)
+
+
+@pytest.mark.parametrize("precision", ["mixed_fp8", "mixed_bf16"])
+def test_full_size_run_matches_the_modes_in_order(env, big, precision):
+    torch, rb = env
+    w, X = big
+    ranks, p, q, seed = w["ranks"], w["p"], w["q"], w["seeds"][1]
+
+    def solve():
+        return rb.tucker(X, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float64)
+
+    print(precision, "concurrent modes", flush=True)
+    a = solve()
+    b = solve()
+    torch.cuda.synchronize()
+    print(precision, "modes in order (request server)", flush=True)
+    with rb.Server(12 << 30, slots=1) as sv:
+        s = sv.wait(sv.submit(X, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float64))
+    assert identical(torch, a, b)
+    assert identical(torch, a, s)
+
+    core, factors, err = a
+    eye = torch.eye(ranks[0], dtype=torch.float64, device="cuda")
+    for U in factors:
+        assert U.shape == (1000, ranks[0])
+        assert (U.T @ U - eye).abs().max().item() <= 1e-10
+
+    # the float64 core of the returned factors, G = X x_n U_n^T
+    X64 = X.to(torch.float64)
+    x2 = X64.pow(2).sum().item()
+    G = X64
+    for n, U in enumerate(factors):
+        G = torch.movedim(torch.tensordot(U.T.contiguous(), G, dims=([1], [n])), 0, n).contiguous()
+    del X64
+    dcore = (core - G).norm().item() / G.norm().item()
+    g2 = G.pow(2).sum().item()
+    err_proj = math.sqrt(max(x2 - g2, 0.0) / x2)
+    print(precision, "err", err, "projection err", err_proj, "core distance", dcore, flush=True)
+    assert dcore <= CORE_TOL[precision]
+    assert abs(err - err_proj) <= 1e-4 * err_proj
