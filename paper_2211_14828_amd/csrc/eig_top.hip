@@ -385,7 +385,84 @@ __global__ void __launch_bounds__(RED_THREADS) eig_reduce_kernel(EigArgs g) {
   }
 }
 
-// Steps 2-3 for one matrix per workgroup, from d and e of T.
+// Bounds of the spectrum of T (wave 0 of a workgroup, from d and e in
+// global memory): out[0] = ||T|| (max row sum), out[1] = the pivot floor of
+// the Sturm counts, out[2], out[3] = Gershgorin lower and upper bounds;
+// e2l[i] = e_i^2.
+template <int NS>
+__device__ inline void spectrum_bounds(const double* d, const double* e, int n, int lane, double* e2l,
+                                       double* out) {
+  double rmax = 0.0, e2max = 0.0, lo = DBL_MAX, hi = -DBL_MAX;
+#pragma unroll
+  for (int t = 0; t < NS; ++t) {
+    const int i = 64 * t + lane;
+    if (i < n) {
+      const double ei = e[i], off = fabs(ei) + (i > 0 ? fabs(e[i - 1]) : 0.0);
+      rmax = fmax(rmax, fabs(d[i]) + off);
+      e2max = fmax(e2max, ei * ei);
+      lo = fmin(lo, d[i] - off);
+      hi = fmax(hi, d[i] + off);
+      e2l[i] = ei * ei;
+    }
+  }
+  rmax = warp_max(rmax);
+  e2max = warp_max(e2max);
+  lo = warp_min(lo);
+  hi = warp_max(hi);
+  if (lane == 0) {
+    out[0] = rmax;
+    out[1] = DBL_MIN * fmax(1.0, e2max);
+    out[2] = lo;
+    out[3] = hi;
+  }
+}
+
+// Step 2: the R largest eigenvalues of T by multisection on Sturm counts
+// (the number of negative pivots of the LDL^T factorisation of T - x I is
+// the number of eigenvalues below x).  One wave per eigenvalue tests 128
+// points a round, so the interval shrinks 129-fold per round; BIS_WAVES
+// eigenvalues per workgroup, grid (ceil(R / BIS_WAVES), matrices).
+constexpr int BIS_WAVES = 4;
+
+template <int NS>
+__global__ void __launch_bounds__(64 * BIS_WAVES) eig_bisect_kernel(EigArgs g) {
+  constexpr int NM = 64 * NS;
+  __shared__ double dl[NM], e2l[NM], bnd[4];
+  const int m = blockIdx.y;
+  const int n = g.n[m], R = g.R[m];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if ((int)blockIdx.x * BIS_WAVES >= R) return;    // the same for the whole workgroup
+  for (int i = tid; i < n; i += blockDim.x) dl[i] = g.d[m][i];
+  if (wave == 0) spectrum_bounds<NS>(g.d[m], g.e[m], n, lane, e2l, bnd);
+  __syncthreads();
+  const int r = (int)blockIdx.x * BIS_WAVES + wave;
+  if (r >= R) return;                              // no barrier follows
+  const double tnorm = bnd[0], pivmin = bnd[1];
+  const double margin = 2.0 * n * EPS * tnorm + 2.0 * pivmin;
+  const double atol = EPS * tnorm;
+  constexpr int P = 128;                           // points a round
+  const int kk = n - 1 - r;                        // ascending index of the eigenvalue
+  double lo = bnd[2] - margin, hi = bnd[3] + margin;
+  // lo and hi are the same in every lane, so the loop is uniform in the wave
+  for (int it = 0; it < 96; ++it) {
+    if (hi - lo <= fmax(atol, 2.0 * EPS * fmax(fabs(lo), fabs(hi)))) break;
+    const double wd = hi - lo;
+    const double x0 = lo + wd * ((double)(lane + 1) / (double)(P + 1));
+    const double x1 = lo + wd * ((double)(lane + 65) / (double)(P + 1));
+    int c0, c1;
+    sturm2(dl, e2l, n, pivmin, x0, x1, c0, c1);
+    const int nb = __popcll(__ballot(c0 <= kk)) + __popcll(__ballot(c1 <= kk));
+    const double nlo = nb > 0 ? lo + wd * ((double)nb / (double)(P + 1)) : lo;
+    const double nhi = nb < P ? lo + wd * ((double)(nb + 1) / (double)(P + 1)) : hi;
+    const bool progress = nhi - nlo < wd;          // false once float64 cannot split further
+    lo = nlo;
+    hi = nhi;
+    if (!progress) break;
+  }
+  if (lane == 0) g.lam[m][r] = 0.5 * (lo + hi);
+}
+
+// Step 3 for one matrix per workgroup, from d and e of T and the eigenvalues.
 template <int NS>
 __global__ void __launch_bounds__(SOLVE_THREADS) eig_solve_kernel(EigArgs g) {
   constexpr int NM = 64 * NS;
@@ -407,70 +484,11 @@ __global__ void __launch_bounds__(SOLVE_THREADS) eig_solve_kernel(EigArgs g) {
   }
   __syncthreads();
 
-  // ---- 2. the R largest eigenvalues by multisection
-  if (wave == 0) {
-    double rmax = 0.0, e2max = 0.0, lo = DBL_MAX, hi = -DBL_MAX;
-#pragma unroll
-    for (int t = 0; t < NS; ++t) {
-      const int i = 64 * t + lane;
-      if (i < n) {
-        const double off = fabs(el[i]) + (i > 0 ? fabs(el[i - 1]) : 0.0);
-        rmax = fmax(rmax, fabs(dl[i]) + off);
-        e2max = fmax(e2max, el[i] * el[i]);
-        lo = fmin(lo, dl[i] - off);
-        hi = fmax(hi, dl[i] + off);
-        e2l[i] = el[i] * el[i];
-      }
-    }
-    rmax = warp_max(rmax);
-    e2max = warp_max(e2max);
-    lo = warp_min(lo);
-    hi = warp_max(hi);
-    if (lane == 0) {
-      red[32] = rmax;
-      red[33] = DBL_MIN * fmax(1.0, e2max);
-      red[34] = lo;
-      red[35] = hi;
-    }
-  }
+  // the spectrum's bounds, and the eigenvalues from eig_bisect_kernel
+  if (wave == 0) spectrum_bounds<NS>(g.d[m], g.e[m], n, lane, e2l, red + 32);
+  for (int r = tid; r < R; r += SOLVE_THREADS) laml[r] = g.lam[m][r];
   __syncthreads();
-  const double tnorm = red[32], pivmin = red[33];
-  {
-    const double margin = 2.0 * n * EPS * tnorm + 2.0 * pivmin;
-    const double atol = EPS * tnorm;
-    // G lanes per eigenvalue, 2 G points each round; about 256 lanes in all,
-    // since the counts are bound by float64 issue beyond a few waves
-    int G = 64;
-    while (G > 1 && G * R > 256) G >>= 1;
-    const int r = tid / G, q = tid % G, P = 2 * G;
-    const int kk = n - 1 - r;   // ascending index of the eigenvalue
-    const unsigned long long gm = G == 64 ? ~0ull : (((1ull << G) - 1ull) << ((lane / G) * G));
-    double lo = red[34] - margin, hi = red[35] + margin;
-    bool act = r < R;
-    for (int it = 0; it < 96; ++it) {
-      if (act && hi - lo <= fmax(atol, 2.0 * EPS * fmax(fabs(lo), fabs(hi)))) act = false;
-      if (__ballot(act) == 0ull) break;
-      const double wd = hi - lo;
-      const double x0 = lo + wd * ((double)(q + 1) / (double)(P + 1));
-      const double x1 = lo + wd * ((double)(q + 1 + G) / (double)(P + 1));
-      int c0, c1;
-      sturm2(dl, e2l, n, pivmin, x0, x1, c0, c1);
-      const unsigned long long b0 = __ballot(c0 <= kk), b1 = __ballot(c1 <= kk);
-      const int nb = __popcll(b0 & gm) + __popcll(b1 & gm);
-      if (act) {
-        const double nlo = nb > 0 ? lo + wd * ((double)nb / (double)(P + 1)) : lo;
-        const double nhi = nb < P ? lo + wd * ((double)(nb + 1) / (double)(P + 1)) : hi;
-        if (!(nhi - nlo < wd)) act = false;   // no progress left in float64
-        lo = nlo;
-        hi = nhi;
-      }
-    }
-    if (r < R && q == 0) {
-      laml[r] = 0.5 * (lo + hi);
-      g.lam[m][r] = 0.5 * (lo + hi);
-    }
-  }
-  __syncthreads();
+  const double tnorm = red[32];
 
   // ---- 3. eigenvectors of T by inverse iteration
   if (tid == 0) {
@@ -777,6 +795,9 @@ hipError_t launch_ns(EigArgs& a, int nmat, int gmax, int64_t rows_cap, int rmax,
   if ((e = hipFuncSetAttribute((const void*)eig_solve_kernel<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)sshm)) != hipSuccess)
     return e;
+  hipLaunchKernelGGL(eig_bisect_kernel<NS>, dim3((unsigned)ceil_div(rmax, BIS_WAVES), nmat), dim3(64 * BIS_WAVES), 0,
+                     st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(eig_solve_kernel<NS>, dim3(nmat), dim3(SOLVE_THREADS), sshm, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(eig_back_kernel<NS>, dim3(rmax, nmat), dim3(64), 0, st, a);
