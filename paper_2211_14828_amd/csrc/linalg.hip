@@ -199,9 +199,9 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
 // CholeskyQR step for s <= 64 in one launch: Yout = L^{-1} Y where G = L L^T
 // (same drop rule as above: a dropped vector gets a zero row of Yout).
 // Every workgroup factors G itself: wave 0, lane i owning row i in
-// registers, runs a right-looking Cholesky, publishing each finished column
-// in LDS (within one wave LDS accesses complete in order, so no barriers are
-// needed).  Then each thread solves L y = Y(:, c) for one column c by forward
+// registers, runs a right-looking Cholesky; the update of step k reads the
+// finished column k from the lanes that hold it (v_readlane into scalar
+// registers), so no barriers or LDS round trips are needed.  Then each thread solves L y = Y(:, c) for one column c by forward
 // substitution, with y in registers and L read by LDS broadcast.  flags is
 // written by workgroup 0.  All global loads are issued before their use.
 constexpr int CS_MAX = 64;
@@ -211,7 +211,6 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
                                                          double tau_rel, double tau_abs, DimBudget bud) {
   __shared__ double Ls[CS_MAX][CS_MAX + 1];
   __shared__ double dinv[CS_MAX];
-  __shared__ double col[CS_MAX];
   __shared__ int keep[CS_MAX];
   const int tid = threadIdx.x;
   {
@@ -258,9 +257,13 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
           keep[k] = kp;
           dinv[k] = inv;
         }
-        col[i] = lik;
+        // L(j, k) is lane j's lik: read into scalar registers (no LDS trip)
+        const int lhi = __double2hiint(lik), llo = __double2loint(lik);
 #pragma unroll
-        for (int j = k + 1; j < CS_MAX; ++j) row[j] -= lik * col[j];
+        for (int j = k + 1; j < CS_MAX; ++j) {
+          const double cj = __hiloint2double(__builtin_amdgcn_readlane(lhi, j), __builtin_amdgcn_readlane(llo, j));
+          row[j] -= lik * cj;
+        }
       }
     }
 #pragma unroll
