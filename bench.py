@@ -40,8 +40,12 @@ def mode_views(dims):
     return out
 
 
-def step_flops(dims, ranks, p, q):
-    """Executed flops of the Gram route (see DESIGN: flop accounting)."""
+def step_flops(dims, ranks, p, q, variant="krylov"):
+    """Executed flops of the Gram route: per mode the symmetric Gram matrix
+    and the sketch in one pass over X, the float64 Krylov steps on the Gram
+    matrix (products, two projections, CholeskyQR), Z and the factor; then the
+    core chain and the reconstruction of the residual.  The power variant has
+    no projections, and its basis is one block wide."""
     T = 1
     for d in dims:
         T *= d
@@ -50,13 +54,14 @@ def step_flops(dims, ranks, p, q):
     for (A, I, B), R in zip(mode_views(dims), ranks):
         J = A * B
         S = min(R + p, I, J)
-        Sp = S * (q + 1)
+        Sp = S if variant == "power" else S * (q + 1)
         g = I * (I + 1) * J + 2.0 * I * J * S           # symmetric Gram + sketch
         gram.append(g)
         kry = 0.0
         for j in range(1, q + 1):
             m = S * j
-            kry += 2.0 * I * I * S + 2 * (2.0 * S * m * I * 2) + 4.0 * S * S * I
+            proj = 0.0 if variant == "power" else 2 * (2.0 * S * m * I * 2)
+            kry += 2.0 * I * I * S + proj + 4.0 * S * S * I
         kry += 2.0 * I * I * S + 2.0 * Sp * Sp * I + 2.0 * R * Sp * I
         total += g + kry
     # core chain: first product on the mode with the largest I/R, then ascending
@@ -299,6 +304,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tucker1000_f32")
     ap.add_argument("--precision", default="mixed_fp8")
+    ap.add_argument("--variant", default="krylov", choices=["krylov", "power"],
+                    help="subspace of each factor: the block Krylov space (Alg. 1) or power iteration (Sec. 3.1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 and plain-form runs that follow the timed region")
@@ -360,7 +367,8 @@ def main():
         del src, dst
 
     def step(Xin=X, precision=args.precision):
-        return rb.tucker(Xin, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float32)
+        return rb.tucker(Xin, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float32,
+                         variant=args.variant)
 
     for i in range(args.warmup):
         _, _, e = step()
@@ -376,7 +384,7 @@ def main():
     dt = time.perf_counter() - t0
     rb.profile_enable(False)
     ms = dt / args.steps * 1e3
-    flops, gram_flops = step_flops(dims, ranks, p, q)
+    flops, gram_flops = step_flops(dims, ranks, p, q, args.variant)
     tflops = flops / (dt / args.steps) / 1e12
     nlaunch, gram_ms = rb.profile_read("gram")
     avg_gram_ms = gram_ms / max(nlaunch, 1)
@@ -439,7 +447,7 @@ def main():
         "dtype": gram_dtype,
         "data": "synthetic",
         "config": {"workload": args.workload, "dims": list(dims), "ranks": list(ranks), "p": p, "q": q,
-                   "precision": args.precision, "input_dtype": w["dtype"], "rel_err": e,
+                   "precision": args.precision, "variant": args.variant, "input_dtype": w["dtype"], "rel_err": e,
                    **compare, "stage_ms_per_step": stages,
                    "flops_per_step": flops},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",

@@ -59,11 +59,19 @@ typedef enum { RBKI_F64 = 0, RBKI_F32 = 1, RBKI_BF16 = 2 } rbki_dtype;
  *                bf16 copy. */
 typedef enum { RBKI_PLAIN = 0, RBKI_MIXED_BF16 = 1, RBKI_MIXED_FP8 = 2 } rbki_precision;
 
+/* Subspace of each mode's factor.  RBKI_KRYLOV: the block Krylov space
+ * [W, (XX^T) W, ..., (XX^T)^q W] of Alg. 1 (rBKI).  RBKI_POWER: power
+ * iteration, the space of (XX^T)^q W alone, orthonormalised after every
+ * step (the power-iteration comparison of Sec. 3.1, GRpi-SVD); its basis has
+ * width S_n.  With q = 0 both are the single-sketch range finder (GR-SVD). */
+typedef enum { RBKI_KRYLOV = 0, RBKI_POWER = 1 } rbki_variant;
+
 /* Problem statement of Alg. 2: tensor order N, sizes I_n, multilinear rank
  * R_n, sketch sizes S_n = min(R_n + oversample, I_n, J_n) (Sec. 4.1 uses
  * oversample = 5), and the number of Krylov steps q ("power"; Alg. 1 gives it
  * only as Theta(log d / sqrt(eps)), Sec. 3.1 uses 2).  The Krylov basis of
- * mode n has width S'_n = min(S_n (q+1), I_n). */
+ * mode n has width S'_n = min(S_n (q+1), I_n); the power variant's has width
+ * S_n. */
 typedef struct {
   int order;              /* N >= 2 (N = 2 is the matrix rBKI-SVD case) */
   const int64_t *dims;    /* host[N], I_n >= 1 */
@@ -72,6 +80,7 @@ typedef struct {
   int power;              /* q >= 0 */
   uint64_t seed;          /* key of the Philox sketch stream */
   int precision;          /* rbki_precision */
+  int variant;            /* rbki_variant (0, the Krylov space, when zero-initialised) */
 } rbki_params;
 
 /* Library version string (static storage). */

@@ -149,21 +149,27 @@ def ritz_factor(Xn, Q, R):
     return canonical_signs(U), lam
 
 
-def mode_factor(X, n, R, p, q, seed, tau=TAU, return_info=False):
-    """Factor U^(n) of rBKI-TK for mode n (Alg. 2, steps 2-5)."""
+def mode_factor(X, n, R, p, q, seed, tau=TAU, return_info=False, variant="krylov"):
+    """Factor U^(n) of rBKI-TK for mode n (Alg. 2, steps 2-5).  variant
+    "power": the basis is the power iterate of Sec. 3.1 instead of the block
+    Krylov space of Alg. 1."""
     A, I, B = view_dims(X.shape, n)
     J = A * B
     S = sketch_size(R, p, I, J)
     Xn = unfold(X, n)
     Om = philox.omega(seed, n, J, S)
-    Q, widths = rbki_basis(Xn, Om, q, tau)
+    if variant == "power":
+        Q = power_basis(Xn, Om, q, tau)
+        widths = [Q.shape[1]]
+    else:
+        Q, widths = rbki_basis(Xn, Om, q, tau)
     U, lam = ritz_factor(Xn, Q, R)
     if return_info:
         return U, {"S": S, "widths": widths, "Q": Q, "eigenvalues": lam}
     return U
 
 
-def rbki_tucker(X, ranks, p, q, seed, tau=TAU, return_info=False):
+def rbki_tucker(X, ranks, p, q, seed, tau=TAU, return_info=False, variant="krylov"):
     """Alg. 2 (rBKI-TK).  X is converted to float64 first.  Returns the core
     G (R_1 x ... x R_N), the factors [U^(1), ..., U^(N)] and the relative
     reconstruction error ||X - [[G; U]]||_F / ||X||_F from the explicit
@@ -171,7 +177,7 @@ def rbki_tucker(X, ranks, p, q, seed, tau=TAU, return_info=False):
     X = np.asarray(X, dtype=np.float64)
     factors, infos = [], []
     for n in range(X.ndim):
-        U, info = mode_factor(X, n, ranks[n], p, q, seed, tau, return_info=True)
+        U, info = mode_factor(X, n, ranks[n], p, q, seed, tau, return_info=True, variant=variant)
         factors.append(U)
         infos.append(info)
     G = project_core(X, factors)                      # Alg. 2, step 6

@@ -46,7 +46,8 @@ class RbkiError(RuntimeError):
 class _Params(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("dims", ctypes.POINTER(ctypes.c_int64)),
                 ("ranks", ctypes.POINTER(ctypes.c_int64)), ("oversample", ctypes.c_int),
-                ("power", ctypes.c_int), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int)]
+                ("power", ctypes.c_int), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int),
+                ("variant", ctypes.c_int)]
 
 
 _lib = None
@@ -128,7 +129,10 @@ def _dtype_code(torch, dt):
     raise TypeError(f"unsupported tensor dtype {dt}")
 
 
-def _params(dims, ranks, p, q, seed, precision):
+_VARIANTS = {"krylov": 0, "power": 1}
+
+
+def _params(dims, ranks, p, q, seed, precision, variant="krylov"):
     n = len(dims)
     if len(ranks) != n:
         raise ValueError("ranks must have one entry per mode")
@@ -136,7 +140,8 @@ def _params(dims, ranks, p, q, seed, precision):
     r = (ctypes.c_int64 * n)(*[int(v) for v in ranks])
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     prm = _Params(n, ctypes.cast(d, ctypes.POINTER(ctypes.c_int64)), ctypes.cast(r, ctypes.POINTER(ctypes.c_int64)),
-                  int(p), int(q), int(seed) & 0xFFFFFFFFFFFFFFFF, prec)
+                  int(p), int(q), int(seed) & 0xFFFFFFFFFFFFFFFF, prec,
+                  _VARIANTS[variant] if isinstance(variant, str) else int(variant))
     prm._keep = (d, r)
     return prm
 
@@ -180,8 +185,10 @@ def workspace_bytes(dims, ranks, p, q, dtype, precision="plain", tr_ranks=None):
 
 
 def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_err=True, stream=None,
-           workspace=None):
-    """rBKI-TK (Alg. 2).  Returns (core, [U^(1), ..., U^(N)], rel_err or None)."""
+           workspace=None, variant="krylov"):
+    """rBKI-TK (Alg. 2).  Returns (core, [U^(1), ..., U^(N)], rel_err or None).
+    variant "power": each factor from the power iterate (XX^T)^q W alone
+    (the power-iteration comparison of Sec. 3.1)."""
     torch = _torch()
     lib = load_library()
     X = _as_input(torch, X)
@@ -189,7 +196,7 @@ def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_er
     if out_dtype is None:
         out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
     ocode = _dtype_code(torch, out_dtype)
-    prm = _params(X.shape, ranks, p, q, seed, precision)
+    prm = _params(X.shape, ranks, p, q, seed, precision, variant)
     need = lib.rbki_tucker_workspace(ctypes.byref(prm), code)
     if need == 0:
         _check(lib.rbki_tucker(None, code, ctypes.byref(prm), None, None, ocode, None, 0, None, None))

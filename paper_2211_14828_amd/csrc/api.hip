@@ -132,6 +132,7 @@ struct Plan {
   bool first_blocked = false;   // the first mode product reads that mode's blocked copy
   bool need_xpad = false;    // some reader of Xpad remains (a Gram fallback or the first product)
   bool concurrent = false;   // runs beside other solves on the device (request server)
+  bool power = false;        // power iteration: only the last block spans the factor's space
   int64_t oblk_bytes = 0;                   // one mode's blocked bf16 sketch (the largest)
   int64_t in_pad = 0;        // last dimension padded to a multiple of 64
   int64_t rows_pad = 0;      // T / I_N padded to a multiple of 64 (row length of Xt)
@@ -185,6 +186,9 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     return fail(RBKI_E_INVALID, "oversample %d / power %d out of range", prm->oversample, prm->power);
   if (prm->precision != RBKI_PLAIN && prm->precision != RBKI_MIXED_BF16 && prm->precision != RBKI_MIXED_FP8)
     return fail(RBKI_E_INVALID, "unknown precision %d", prm->precision);
+  if (prm->variant != RBKI_KRYLOV && prm->variant != RBKI_POWER)
+    return fail(RBKI_E_INVALID, "unknown variant %d", prm->variant);
+  P.power = prm->variant == RBKI_POWER;
   P.N = prm->order;
   P.p = prm->oversample;
   P.q = prm->power;
@@ -221,7 +225,7 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     if (g.R < 1 || g.R > g.I || g.R > g.J)
       return fail(RBKI_E_INVALID, "ranks[%d] = %lld outside [1, min(I_n, J_n)]", n, (long long)g.R);
     g.S = std::min<int64_t>(std::min<int64_t>(g.R + P.p, g.I), g.J);   // Sec. 2.3, Sec. 4.1
-    g.Sp = g.S * (P.q + 1);
+    g.Sp = P.power ? g.S : g.S * (P.q + 1);
     if (g.Sp > 1200) return fail(RBKI_E_UNSUPPORTED, "Krylov width %lld > 1200 (mode %d)", (long long)g.Sp, n);
     const double ratio = (double)g.I / (double)g.R;
     if (ratio > best) { best = ratio; P.first_mode = n; }
@@ -538,6 +542,21 @@ rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, boo
   HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
   HIPCHK(chol_orth(L.Yt, L.Ytmp, S, I, L.G, L.L, L.flags, L.ref2, TAU_REL, TAU_ABS, st, DimBudget{used, used + 1, I}));
   HIPCHK(chol_orth(L.Ytmp, Qt, S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
+  if (P.power) {
+    // power iteration (Sec. 3.1): Q_j = orth(C Q_{j-1}), each step's block
+    // replacing the last, with the same drop rule relative to the step's
+    // largest squared row norm
+    for (int j = 1; j <= P.q; ++j) {
+      HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt, I, L.C, I, 0.0, L.Yt, I, st));
+      HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
+      HIPCHK(chol_orth(L.Yt, L.Ytmp, S, I, L.G, L.L, L.flags, L.ref2, TAU_REL, TAU_ABS, st));
+      HIPCHK(chol_orth(L.Ytmp, Qt, S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
+    }
+    if (!with_factor) return RBKI_OK;
+    HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt, I, L.C, I, 0.0, L.CQt, I, st));
+    HIPCHK(dgemm(0, 1, S, S, I, 1.0, Qt, I, L.CQt, I, 0.0, b.Z[n], S, st));
+    return RBKI_OK;
+  }
   for (int j = 1; j <= P.q; ++j) {
     const int64_t m = S * j;                     // rows of the basis so far
     const double* Qlast = Qt + (m - S) * I;

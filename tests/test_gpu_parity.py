@@ -361,3 +361,39 @@ def test_sym_eig_matches_lapack(env, n):
     V = Vt.cpu().numpy().T
     assert np.max(np.abs(V[:, ok] - U[:, ok])) <= 1e-9
     assert orthonormality_defect(V) <= 1e-11
+
+
+POWER_CASES = [((24, 30, 28), (4, 5, 3), 4, 2, "float64", "plain"),
+               ((40, 52, 36), (6, 6, 6), 5, 3, "float32", "plain"),
+               ((150, 140, 160), (8, 8, 8), 6, 2, "float32", "mixed_bf16")]
+
+
+@pytest.mark.parametrize("dims,ranks,p,q,dtype,prec", POWER_CASES)
+def test_power_variant_matches_oracle(env, dims, ranks, p, q, dtype, prec):
+    """The power-iteration variant (Sec. 3.1) against the oracle's: error,
+    factor spans where the spectrum has a gap, orthonormal factors."""
+    torch, rb = env
+    seed = 2000 + sum(dims)
+    X = make_case(dims, ranks, dtype, "tucker", seed)
+    Xg = to_device(torch, X, dtype)
+    Xh = host_values(torch, Xg)
+    core, facs, e_g = rb.tucker(Xg, ranks, p=p, q=q, seed=seed + 1, precision=prec, out_dtype=torch.float64,
+                                variant="power")
+    G, Us, e_o, infos = rbki_tucker(Xh, ranks, p, q, seed + 1, return_info=True, variant="power")
+    print(dims, prec, e_g, e_o, flush=True)
+    assert abs(e_g - e_o) / e_o <= TOL[(dtype, prec)], (e_g, e_o)
+    Ug = [f.cpu().numpy() for f in facs]
+    for n in range(len(dims)):
+        assert orthonormality_defect(Ug[n]) <= 1e-11
+        if gap_ok(infos[n]["eigenvalues"], ranks[n]):
+            key = dtype if prec == "plain" else "bfloat16"
+            assert projector_distance(Ug[n], Us[n]) <= PROJ_TOL[key]
+
+
+def test_power_variant_at_q0_is_the_krylov_run(env):
+    torch, rb = env
+    X = make_case((30, 34, 26), (5, 4, 6), "float32", "tucker", 77)
+    Xg = to_device(torch, X, "float32")
+    a = rb.tucker(Xg, (5, 4, 6), p=5, q=0, seed=5, out_dtype=torch.float64)
+    b = rb.tucker(Xg, (5, 4, 6), p=5, q=0, seed=5, out_dtype=torch.float64, variant="power")
+    assert torch.equal(a[0], b[0]) and all(torch.equal(x, y) for x, y in zip(a[1], b[1])) and a[2] == b[2]

@@ -189,3 +189,39 @@ def test_plausible_mistakes_are_caught():
     U0, _ = ritz_factor(Xn, Q0, 4)
     assert fro(Xn - U0 @ (U0.T @ Xn)) > good * (1 + 1e-3)
     assert abs(good - fro(Xn - Ut @ (Ut.T @ Xn))) < 1e-3 * good
+
+
+def test_power_variant_reduces_to_the_range_finder_at_q0_and_recovers_exact_rank():
+    # q = 0: power iteration and the Krylov space are both range(X Omega)
+    X, _ = noisy_tucker((22, 18, 20), (4, 3, 5), 5.0, seed=31)
+    Gk, Uk, ek = rbki_tucker(X, (4, 3, 5), p=4, q=0, seed=8)
+    Gp, Up, ep = rbki_tucker(X, (4, 3, 5), p=4, q=0, seed=8, variant="power")
+    assert ep == ek and np.array_equal(Gp, Gk) and all(np.array_equal(a, b) for a, b in zip(Up, Uk))
+    # an exactly low-rank Tucker tensor is recovered by the power variant too
+    Xc, _ = synth.orthonormal_tucker((20, 24, 18), (3, 4, 2), seed=5)
+    _, _, err = rbki_tucker(Xc, (3, 4, 2), p=5, q=2, seed=11, variant="power")
+    assert err <= 1e-12
+
+
+def test_power_basis_spans_the_power_iterate():
+    # the basis is an orthonormal basis of (X X^T)^q X Omega (Sec. 3.1), here
+    # where that block is well conditioned (q = 1, a few columns)
+    X, _ = noisy_tucker((30, 26, 24), (5, 5, 5), 20.0, seed=41)
+    Xn = unfold(X, 1)
+    Om = philox.omega(3, 1, Xn.shape[1], 6)
+    Q = power_basis(Xn, Om, 1)
+    Y = Xn @ (Xn.T @ (Xn @ Om))
+    Qy, _ = np.linalg.qr(Y)
+    assert orthonormality_defect(Q) <= 1e-12
+    assert projector_distance(Q, Qy) <= 1e-8
+
+
+def test_power_variant_error_is_not_below_the_krylov_error_per_mode():
+    # the power iterate lies inside the Krylov space of the same Omega, so
+    # its per-mode Rayleigh-Ritz error is never smaller
+    X, _ = noisy_tucker((36, 30, 28), (5, 5, 5), -3.0, seed=43)
+    for q in (1, 2):
+        _, Uk, _ = rbki_tucker(X, (5, 5, 5), p=3, q=q, seed=9)
+        _, Up, _ = rbki_tucker(X, (5, 5, 5), p=3, q=q, seed=9, variant="power")
+        for n in range(3):
+            assert per_mode_error(X, n, Uk[n]) <= per_mode_error(X, n, Up[n]) * (1 + 1e-12)
