@@ -11,7 +11,8 @@
 //     through a small global buffer once per step.
 //  2. The R largest eigenvalues of T by multisection on Sturm counts (the
 //     number of negative pivots of the LDL^T factorisation of T - x I equals
-//     the number of eigenvalues below x).
+//     the number of eigenvalues below x), one wave per eigenvalue testing
+//     128 points a round, in a kernel of its own.
 //  3. Their eigenvectors of T by inverse iteration: a pivoted LU of
 //     T - lambda I per eigenvalue, one thread each, three solves.  Eigenvalues
 //     closer than 1e-3 ||T|| form a cluster whose vectors are
