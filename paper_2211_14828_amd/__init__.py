@@ -367,7 +367,7 @@ class Server:
         prm = _params(dims, ranks, p, q, 0, precision)
         return self._lib.rbki_server_request_bytes(ctypes.byref(prm), _dtype_code(self._torch, dtype))
 
-    def submit(self, X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None):
+    def submit(self, X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, variant="krylov"):
         torch = self._torch
         if self._h is None:
             raise RuntimeError("server is closed")
@@ -376,7 +376,7 @@ class Server:
         if out_dtype is None:
             out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
         ocode = _dtype_code(torch, out_dtype)
-        prm = _params(X.shape, ranks, p, q, seed, precision)
+        prm = _params(X.shape, ranks, p, q, seed, precision, variant)
         core = torch.empty(tuple(int(r) for r in ranks), dtype=out_dtype, device=X.device)
         factors = [torch.empty((int(I), int(R)), dtype=out_dtype, device=X.device) for I, R in zip(X.shape, ranks)]
         fptr = (ctypes.c_void_p * len(factors))(*[f.data_ptr() for f in factors])

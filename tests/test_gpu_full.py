@@ -56,14 +56,16 @@ def identical(torch, a, b):
             and err_a == err_b)
 
 
-@pytest.mark.parametrize("precision", ["mixed_fp8", "mixed_bf16"])
-def test_full_size_run_matches_the_modes_in_order(env, big, precision):
+@pytest.mark.parametrize("precision,variant", [("mixed_fp8", "krylov"), ("mixed_bf16", "krylov"),
+                                               ("mixed_fp8", "power")])
+def test_full_size_run_matches_the_modes_in_order(env, big, precision, variant):
     torch, rb = env
     w, X = big
     ranks, p, q, seed = w["ranks"], w["p"], w["q"], w["seeds"][1]
 
     def solve():
-        return rb.tucker(X, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float64)
+        return rb.tucker(X, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float64,
+                         variant=variant)
 
     print(precision, "concurrent modes", flush=True)
     a = solve()
@@ -71,7 +73,8 @@ def test_full_size_run_matches_the_modes_in_order(env, big, precision):
     torch.cuda.synchronize()
     print(precision, "modes in order (request server)", flush=True)
     with rb.Server(12 << 30, slots=1) as sv:
-        s = sv.wait(sv.submit(X, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float64))
+        s = sv.wait(sv.submit(X, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float64,
+                              variant=variant))
     assert identical(torch, a, b)
     assert identical(torch, a, s)
 
