@@ -132,3 +132,17 @@ def test_top_eigensolver_rejects_bad_sizes_before_any_launch():
     assert lib.rbki_sym_eig_top(None, 300, 50, p, p, p, need, None) == 1
     assert lib.rbki_sym_eig_top(p, 300, 50, p, p, p, need - 1, None) == 1
     assert "workspace" in lib.rbki_last_error().decode()
+
+
+def test_unknown_variant_is_rejected_and_the_power_basis_is_one_block_wide():
+    lib = rb.load_library()
+    prm = _params((40, 40, 40), (4, 4, 4), 4, 3, 0)
+    krylov = lib.rbki_tucker_workspace(ctypes.byref(prm), 1)
+    prm.variant = 1
+    power = lib.rbki_tucker_workspace(ctypes.byref(prm), 1)
+    # the power variant's basis is S wide instead of S (q + 1)
+    assert 0 < power < krylov
+    prm.variant = 7
+    st = lib.rbki_tucker(ctypes.c_void_p(16), 1, ctypes.byref(prm), None, None, 1, None, 0, None, None)
+    assert st == 1 and "variant" in lib.rbki_last_error().decode()
+    assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) == 0
