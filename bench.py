@@ -160,6 +160,7 @@ def cpu_baseline(X, w, target_s=20.0):
     oracle, so value_gpu / value_cpu is the speed ratio for equal work."""
     import numpy as np
     from oracle.rbki import rbki_tucker
+    from oracle.trsvd import rbki_htr
     p, q, seed = w["p"], w["q"], w["seeds"][1]
     last = X.shape[-1]
 
@@ -167,7 +168,10 @@ def cpu_baseline(X, w, target_s=20.0):
         Xs = np.ascontiguousarray(X[..., :slab].double().cpu().numpy())
         ranks = tuple(min(R, d) for R, d in zip(w["ranks"], Xs.shape))
         t0 = time.perf_counter()
-        rbki_tucker(Xs, ranks, p, q, seed)
+        if w["kind"] == "ring":
+            rbki_htr(Xs, ranks, p, q, seed, w["tr_ranks"], explicit_error="core")
+        else:
+            rbki_tucker(Xs, ranks, p, q, seed)
         return time.perf_counter() - t0, Xs.shape, ranks
 
     probe = max(1, min(last, 60))
@@ -182,13 +186,22 @@ def cpu_baseline(X, w, target_s=20.0):
         threads = os.cpu_count()
     return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": f"FP64 oracle (numpy/LAPACK, {threads} BLAS threads, host cpu_count={os.cpu_count()}): "
-                      f"whole rBKI-TK decomposition (Alg. 2: every mode's sketch, {q} Krylov steps in the "
+                      f"whole {'rBKI-TK-TR (Alg. 3)' if w['kind'] == 'ring' else 'rBKI-TK'} decomposition (Alg. 2: every mode's sketch, {q} Krylov steps in the "
                       f"streamed form, Z, eigenvectors, core, explicit error) of the slab X[..., :{slab}] "
                       f"({'x'.join(str(d) for d in shape)}, ranks {ranks}) of the same input, {dt:.2f} s; value = "
                       f"GPU-route flops of that shape ({flops:.3e}) / time"}
 
 
 METRIC = "rBKI-TK TFLOP/s + rel err vs FP64 oracle; served solves/s, p50/p99 latency"
+
+
+def load_golden(workload):
+    path = os.path.join(ROOT, "tests", "golden", "full_size.json")
+    try:
+        with open(path) as f:
+            return json.load(f).get(workload)
+    except (OSError, ValueError):
+        return None
 
 
 def _pct(v, q):
@@ -302,7 +315,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="tucker1000_f32")
+    ap.add_argument("--workload", default="tucker1000_f32",
+                    help="tucker1000_f32, tucker400_f32, tucker64_f64 (Alg. 2) or ring64x5_f32 (Alg. 3)")
+    ap.add_argument("--data", default="host", choices=["host", "device"],
+                    help="host: the bytes of synth.make_host, whose float64 oracle error is stored in "
+                         "tests/golden/full_size.json; device: a seeded torch generator on the GPU (faster, "
+                         "no oracle reference)")
     ap.add_argument("--precision", default="mixed_fp8")
     ap.add_argument("--variant", default="krylov", choices=["krylov", "power"],
                     help="subspace of each factor: the block Krylov space (Alg. 1) or power iteration (Sec. 3.1)")
@@ -352,8 +370,22 @@ def main():
         return
     w = synth.WORKLOADS[args.workload]
     dims, ranks, p, q = tuple(w["dims"]), tuple(w["ranks"]), w["p"], w["q"]
-    print(f"[bench] generating {args.workload} {dims} on the device", file=sys.stderr, flush=True)
-    X = synth.make_device(w)
+    htr = w["kind"] == "ring"
+    gold = load_golden(args.workload)
+    oracle_err = None
+    if args.data == "host":
+        # the bytes the stored oracle result was computed on
+        print(f"[bench] generating {args.workload} {dims} on the host", file=sys.stderr, flush=True)
+        Xh, _ = synth.make_host(w)
+        if gold is not None and synth.same_fingerprint(synth.fingerprint(Xh), gold["fingerprint"]):
+            oracle_err = gold["htr"]["rel_err"] if htr else gold["oracle"]["rel_err"]
+        else:
+            print("[bench] no stored oracle result for these bytes", file=sys.stderr, flush=True)
+        X = torch.from_numpy(Xh).to("cuda")
+        del Xh
+    else:
+        print(f"[bench] generating {args.workload} {dims} on the device", file=sys.stderr, flush=True)
+        X = synth.make_device(w)
     torch.cuda.synchronize()
     seed = w["seeds"][1]
 
@@ -367,6 +399,11 @@ def main():
         del src, dst
 
     def step(Xin=X, precision=args.precision):
+        if htr:
+            # Alg. 3: the Tucker step with the compress sizes, TR-SVD of the core
+            cores, e = rb.htr(Xin, ranks, w["tr_ranks"], p=p, q=q, seed=seed, precision=precision,
+                              out_dtype=torch.float32)
+            return cores, None, e
         return rb.tucker(Xin, ranks, p=p, q=q, seed=seed, precision=precision, out_dtype=torch.float32,
                          variant=args.variant)
 
@@ -403,6 +440,11 @@ def main():
           file=sys.stderr, flush=True)
 
     compare = {}
+    if oracle_err is not None:
+        # the float64 oracle's error on the same bytes, stored by
+        # tests/golden/make_full_size.py
+        compare["rel_err_oracle"] = oracle_err
+        compare["excess_vs_oracle"] = (e - oracle_err) / oracle_err
     if not args.no_compare:
         # outside the timed region: the FP64 form on the same values (parity-pinned
         # to the oracle) gives the reference error; the plain form gives the wall
@@ -411,8 +453,8 @@ def main():
         _, _, e64 = step(X64, "plain")
         del X64
         torch.cuda.empty_cache()
-        compare["rel_err_f64"] = e64
-        compare["excess_vs_f64"] = (e - e64) / e64 if e64 > 0 else None
+        compare["rel_err_gpu_f64"] = e64
+        compare["excess_vs_gpu_f64"] = (e - e64) / e64 if e64 > 0 else None
         if args.precision != "plain":
             step(X, "plain")
             torch.cuda.synchronize()

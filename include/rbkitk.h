@@ -15,12 +15,16 @@
  *   rbki_server_create, which allocates the server's arena once.
  * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *   Work is enqueued asynchronously on it; an entry point that returns a host
- *   value (rel_err, widths) synchronises that stream before returning.
+ *   value (rel_err, widths, a solver status) synchronises that stream before
+ *   returning.  rbki_tucker, rbki_htr and the eigen-solver entry points
+ *   always return the eigen-solver's status, so they always synchronise.
  * - All arguments are validated before anything is enqueued: on a status
  *   other than RBKI_OK nothing was launched, except RBKI_E_HIP (a launch or
  *   runtime error, outputs undefined) and RBKI_E_NOCONV (results written,
- *   but an eigen-solver hit its sweep limit).  rbki_last_error() returns a
- *   thread-local message for the last failing call of the calling thread.
+ *   but an eigen-solver hit its sweep limit, or the workgroups of a
+ *   multi-workgroup reduction did not meet within its bounded wait).
+ *   rbki_last_error() returns a thread-local message for the last failing
+ *   call of the calling thread.
  * - Mode indices are 0-based; the Philox "mode" word of the sketch stream is
  *   the 0-based mode index.
  * - Thread safety: calls on different streams with disjoint buffers may run
@@ -41,7 +45,7 @@ typedef enum {
   RBKI_E_INVALID = 1,     /* bad argument or workspace too small; nothing launched */
   RBKI_E_NOMEM = 2,       /* reserved */
   RBKI_E_HIP = 3,         /* HIP runtime / launch error */
-  RBKI_E_NOCONV = 4,      /* Jacobi eigen-solver reached its sweep limit */
+  RBKI_E_NOCONV = 4,      /* an eigen-solver did not finish (sweep limit, bounded wait) */
   RBKI_E_UNSUPPORTED = 5  /* valid request this build does not support */
 } rbki_status;
 
@@ -117,6 +121,9 @@ rbki_status rbki_philox(const uint32_t *ctr, int64_t count, uint64_t seed, uint3
  * X_(n)[i, a*B_n + b] = X[a, i, b] (Table 1).
  */
 size_t rbki_basis_workspace(const rbki_params *prm, int xtype, int mode);
+/* Rows of Qt that rbki_basis writes for this problem and mode: the basis
+ * width min(S'_n, I_n) (S_n for the power variant); 0 if prm is invalid. */
+int64_t rbki_basis_rows(const rbki_params *prm, int xtype, int mode);
 rbki_status rbki_basis(const void *X, int xtype, const rbki_params *prm, int mode, double *Qt,
                        int64_t *width, void *workspace, size_t ws_bytes, void *stream);
 
@@ -178,7 +185,12 @@ rbki_status rbki_sym_eig(const double *Z, int64_t n, double *lam, double *Vt, vo
  *   lam      : device, k doubles, descending.
  *   Vt       : device, k x n row-major; row j is the unit eigenvector of
  *              lam[j], signed so that its largest-magnitude entry is positive.
- * 1 <= k <= n <= 512; anything else returns RBKI_E_INVALID.
+ * 1 <= k <= n <= 512; anything else returns RBKI_E_INVALID.  For n above
+ * about 165 the reduction is shared by several workgroups that wait for each
+ * other with a bounded number of polls; if they do not meet, the call returns
+ * RBKI_E_NOCONV (the environment variable RBKI_EIG_SPIN_LIMIT, read at each
+ * call, sets that bound; 0 makes the first wait give up, for testing the
+ * error path).  Synchronises the stream.
  */
 size_t rbki_sym_eig_top_workspace(int64_t n, int64_t k);
 rbki_status rbki_sym_eig_top(const double *Z, int64_t n, int64_t k, double *lam, double *Vt,
@@ -224,6 +236,13 @@ rbki_status rbki_server_submit(rbki_server *server, const void *X, int xtype, co
 rbki_status rbki_server_poll(rbki_server *server, uint64_t ticket, int *done, double *rel_err, double *latency_ms);
 rbki_status rbki_server_wait(rbki_server *server, uint64_t ticket, double *rel_err, double *latency_ms);
 rbki_status rbki_server_destroy(rbki_server *server);
+
+/* Releases what the library holds between calls on its own (helper streams
+ * of the concurrently running modes, events of pending timing records), after
+ * the work on them has finished.  Safe to call at any time; later calls
+ * recreate what they need.  Call it before the HIP runtime shuts down (the
+ * Python binding registers it to run at interpreter exit). */
+void rbki_release(void);
 
 /* ---------------------------------------------------------------------------
  * Kernel timing.  When enabled, the library records HIP events around every

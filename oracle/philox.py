@@ -36,6 +36,7 @@ MASK32 = np.uint64(0xFFFFFFFF)
 ROUNDS = 10
 
 TAG_OMEGA = 0
+TAG_COLUMNS = 1
 
 
 def philox4x32(c0, c1, c2, c3, k0, k1, rounds=ROUNDS):
@@ -115,3 +116,34 @@ def omega(seed, mode, J, S, chunk=1 << 22):
         stop = min(total, start + chunk)
         flat[start:stop] = gaussian_at(seed, mode, np.arange(start, stop, dtype=np.uint64))
     return out
+
+
+def sample_count(J, rate):
+    """Number of sampled columns m = round(rate * J), at least 1 and at most J
+    (rate >= 1: all columns)."""
+    if rate >= 1.0:
+        return int(J)
+    return int(max(1, min(J, int(np.floor(rate * J + 0.5)))))
+
+
+def sampled_columns(seed, mode, J, rate):
+    """Uniform column sample of the mode-n unfolding (Sec. 3.1: the Krylov
+    basis may be built from m = rate * J of the J columns).
+
+    Stratified uniform sampling: the columns are split into m consecutive
+    strata [floor(k J / m), floor((k+1) J / m)) and stratum k contributes the
+    column at offset floor(w * width / 2^32), where w is the first output word
+    of the Philox block with counter (lo32(k), hi32(k), mode, tag 1).  Every
+    column is drawn with probability about m / J, exactly m distinct columns
+    come out, in increasing order, and rate = 1 gives every column.  All
+    arithmetic is on integers."""
+    m = sample_count(J, rate)
+    k = np.arange(m, dtype=np.uint64)
+    Jm = np.uint64(J)
+    lo = (k * Jm) // np.uint64(m)
+    width = ((k + np.uint64(1)) * Jm) // np.uint64(m) - lo
+    k0, k1 = seed_key(seed)
+    tag = np.full(k.shape, TAG_COLUMNS, dtype=np.uint64)
+    w0, _, _, _ = philox4x32(k & MASK32, k >> np.uint64(32), np.full(k.shape, int(mode) & 0xFFFFFFFF, np.uint64),
+                             tag, k0, k1)
+    return (lo + ((w0 * width) >> np.uint64(32))).astype(np.int64)

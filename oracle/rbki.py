@@ -149,27 +149,39 @@ def ritz_factor(Xn, Q, R):
     return canonical_signs(U), lam
 
 
-def mode_factor(X, n, R, p, q, seed, tau=TAU, return_info=False, variant="krylov"):
+def mode_factor(X, n, R, p, q, seed, tau=TAU, return_info=False, variant="krylov", sample_rate=1.0):
     """Factor U^(n) of rBKI-TK for mode n (Alg. 2, steps 2-5).  variant
     "power": the basis is the power iterate of Sec. 3.1 instead of the block
-    Krylov space of Alg. 1."""
+    Krylov space of Alg. 1.
+
+    sample_rate < 1 (Sec. 3.1, partial columns): the basis is built from the
+    m = sample_rate * J_n sampled columns Y of the unfolding
+    (philox.sampled_columns), with a sketch of m rows and S_n <= m; Z, and so
+    the factor, are taken with the whole unfolding, as Alg. 2, step 3 writes
+    them (the sampling shortens the construction of the Krylov space only)."""
     A, I, B = view_dims(X.shape, n)
     J = A * B
-    S = sketch_size(R, p, I, J)
     Xn = unfold(X, n)
-    Om = philox.omega(seed, n, J, S)
+    if sample_rate < 1.0:
+        cols = philox.sampled_columns(seed, n, J, sample_rate)
+        Y = np.ascontiguousarray(Xn[:, cols])
+    else:
+        cols, Y = None, Xn
+    m = Y.shape[1]
+    S = sketch_size(R, p, I, m)
+    Om = philox.omega(seed, n, m, S)
     if variant == "power":
-        Q = power_basis(Xn, Om, q, tau)
+        Q = power_basis(Y, Om, q, tau)
         widths = [Q.shape[1]]
     else:
-        Q, widths = rbki_basis(Xn, Om, q, tau)
+        Q, widths = rbki_basis(Y, Om, q, tau)
     U, lam = ritz_factor(Xn, Q, R)
     if return_info:
-        return U, {"S": S, "widths": widths, "Q": Q, "eigenvalues": lam}
+        return U, {"S": S, "widths": widths, "Q": Q, "eigenvalues": lam, "columns": cols}
     return U
 
 
-def rbki_tucker(X, ranks, p, q, seed, tau=TAU, return_info=False, variant="krylov"):
+def rbki_tucker(X, ranks, p, q, seed, tau=TAU, return_info=False, variant="krylov", sample_rate=1.0):
     """Alg. 2 (rBKI-TK).  X is converted to float64 first.  Returns the core
     G (R_1 x ... x R_N), the factors [U^(1), ..., U^(N)] and the relative
     reconstruction error ||X - [[G; U]]||_F / ||X||_F from the explicit
@@ -177,7 +189,8 @@ def rbki_tucker(X, ranks, p, q, seed, tau=TAU, return_info=False, variant="krylo
     X = np.asarray(X, dtype=np.float64)
     factors, infos = [], []
     for n in range(X.ndim):
-        U, info = mode_factor(X, n, ranks[n], p, q, seed, tau, return_info=True, variant=variant)
+        U, info = mode_factor(X, n, ranks[n], p, q, seed, tau, return_info=True, variant=variant,
+                              sample_rate=sample_rate)
         factors.append(U)
         infos.append(info)
     G = project_core(X, factors)                      # Alg. 2, step 6

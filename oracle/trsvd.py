@@ -99,16 +99,30 @@ def attach_factors(cores, factors):
 
 def rbki_htr(X, tucker_ranks, p, q, seed, tr_ranks, explicit_error=True):
     """Alg. 3 (rBKI-TK-TR) with the TR-SVD branch.  Returns the TR cores of
-    X, the relative error and a dict of intermediate results."""
+    X, the relative error and a dict of intermediate results.
+
+    explicit_error: True   -- ||X - TR(X_1..X_N)|| from the full ring (small
+                              tensors only: the ring is contracted whole);
+                    "core" -- sqrt(||X - [[G; U]]||^2 + ||G - TR(G_1..G_N)||^2),
+                              both terms explicit (the second on the small
+                              core), equal to the above because the Tucker
+                              factors are orthonormal;
+                    False  -- the Tucker error plus the discarded energy of
+                              the TR-SVD steps."""
     X = np.asarray(X, np.float64)
-    G, factors, e_tk = rbki_tucker(X, tucker_ranks, p, q, seed)
+    G, factors, e_tk, tk_infos = rbki_tucker(X, tucker_ranks, p, q, seed, return_info=True)
     core_cores, discarded = tr_svd(G, tr_ranks)
     cores = attach_factors(core_cores, factors)
     nx = fro(X)
-    if explicit_error:
+    gap2 = None
+    if explicit_error == "core":
+        gap2 = fro(G - tr_to_full(core_cores)) ** 2
+        err = float(np.sqrt((e_tk * nx) ** 2 + gap2)) / nx
+    elif explicit_error:
         err = fro(X - tr_to_full(cores)) / nx
     else:
         err = float(np.sqrt((e_tk * nx) ** 2 + discarded)) / nx
     info = {"G": G, "factors": factors, "core_cores": core_cores,
-            "tucker_error": e_tk, "discarded": discarded}
+            "tucker_error": e_tk, "discarded": discarded, "core_gap2": gap2,
+            "tucker_infos": tk_infos}
     return cores, err, info

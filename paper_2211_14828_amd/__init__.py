@@ -11,6 +11,7 @@ the library is missing or no GPU is visible, the calls raise.
     with Server(hbm_bytes, slots) as sv:                    # many small solves
         t = sv.submit(X, ranks); core, factors, err, ms = sv.wait(t)
 """
+import atexit
 import ctypes
 import os
 import threading
@@ -32,6 +33,7 @@ _STATUS = {0: "RBKI_OK", 1: "RBKI_E_INVALID", 2: "RBKI_E_NOMEM", 3: "RBKI_E_HIP"
 # Every symbol the header declares.
 SYMBOLS = ("rbki_version", "rbki_last_error", "rbki_omega", "rbki_philox", "rbki_basis_workspace",
            "rbki_basis", "rbki_tucker_workspace", "rbki_tucker", "rbki_htr_workspace", "rbki_htr",
+           "rbki_basis_rows", "rbki_release",
            "rbki_sym_eig_workspace", "rbki_sym_eig", "rbki_sym_eig_top_workspace", "rbki_sym_eig_top",
            "rbki_profile_enable", "rbki_profile_reset", "rbki_profile_read", "rbki_server_request_bytes", "rbki_server_create", "rbki_server_submit",
            "rbki_server_poll", "rbki_server_wait", "rbki_server_destroy")
@@ -79,6 +81,8 @@ def load_library(build_if_missing=True):
             "rbki_philox": (ci, [vp, i64, u64, vp, vp]),
             "rbki_basis_workspace": (sz, [P(_Params), ci, ci]),
             "rbki_basis": (ci, [vp, ci, P(_Params), ci, vp, P(i64), vp, sz, vp]),
+            "rbki_basis_rows": (i64, [P(_Params), ci, ci]),
+            "rbki_release": (None, []),
             "rbki_tucker_workspace": (sz, [P(_Params), ci]),
             "rbki_tucker": (ci, [vp, ci, P(_Params), vp, P(vp), ci, vp, sz, P(dbl), vp]),
             "rbki_htr_workspace": (sz, [P(_Params), ci, P(i64)]),
@@ -102,6 +106,9 @@ def load_library(build_if_missing=True):
             f.restype = res
             f.argtypes = args
         _lib = lib
+        # release the library's own streams and events while the HIP runtime
+        # is still up (atexit handlers run before the runtime's teardown)
+        atexit.register(lib.rbki_release)
         return lib
 
 
@@ -251,10 +258,8 @@ def basis(X, mode, ranks, p=5, q=2, seed=0, precision="plain", stream=None):
         _check(lib.rbki_basis(None, code, ctypes.byref(prm), int(mode), None, None, None, 0, None))
     ws = _workspace(torch, X.device, need)
     I = int(X.shape[mode])
-    J = X.numel() // I
-    S = min(int(ranks[mode]) + int(p), I, J)
-    Sp = min(S * (int(q) + 1), I)
-    Qt = torch.empty((Sp, I), dtype=torch.float64, device=X.device)
+    rows = lib.rbki_basis_rows(ctypes.byref(prm), code, int(mode))
+    Qt = torch.empty((rows, I), dtype=torch.float64, device=X.device)
     width = ctypes.c_int64(0)
     _check(lib.rbki_basis(ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm), int(mode),
                           ctypes.c_void_p(Qt.data_ptr()), ctypes.byref(width), ctypes.c_void_p(ws.data_ptr()),

@@ -633,7 +633,10 @@ rbki_status run_factors(const Plan& P, const Buffers& b, hipStream_t st) {
   {
     ProfScope ps("eig", st);
     if (top) {
-      HIPCHK(eig_top_batched(P.N, Zs, ns, rs, ls, vs, ws, is, st));
+      // beside other solves (the request server) the multi-workgroup
+      // reduction takes the ordinary launch: a cooperative grid does not
+      // share the device with work on other streams
+      HIPCHK(eig_top_batched(P.N, Zs, ns, rs, ls, vs, ws, is, st, !P.concurrent));
     } else {
       // beside other solves (the request server) small matrices take the
       // ordinary per-matrix launch: a cooperative grid does not share the
@@ -835,7 +838,7 @@ rbki_status rbki_sym_eig(const double* Z, int64_t n, double* lam, double* Vt, vo
 
 size_t rbki_sym_eig_top_workspace(int64_t n, int64_t k) {
   if (!eig_top_ok(n, k)) return 0;
-  return eig_top_work_bytes(n, k);
+  return ((eig_top_work_bytes(n, k) + 255) & ~(size_t)255) + 256;   // + the solver's status
 }
 
 rbki_status rbki_sym_eig_top(const double* Z, int64_t n, int64_t k, double* lam, double* Vt, void* workspace,
@@ -847,11 +850,17 @@ rbki_status rbki_sym_eig_top(const double* Z, int64_t n, int64_t k, double* lam,
   if (!workspace || ws_bytes < need) return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
   hipStream_t st = (hipStream_t)stream;
   void* ws[1] = {workspace};
+  int* info = (int*)((char*)workspace + ((eig_top_work_bytes(n, k) + 255) & ~(size_t)255));
+  HIPCHK(fill_zero(info, 8, st));
   {
     ProfScope ps("eig", st);
-    HIPCHK(eig_top_batched(1, &Z, &n, &k, &lam, &Vt, ws, nullptr, st));
+    HIPCHK(eig_top_batched(1, &Z, &n, &k, &lam, &Vt, ws, &info, st));
   }
   HIPCHK(canonical_sign_rows(Vt, k, n, st));
+  int h[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(h, info, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h[0]) return fail(RBKI_E_NOCONV, "the workgroups of the reduction did not meet within the spin limit");
   return RBKI_OK;
 }
 
@@ -906,6 +915,12 @@ rbki_status rbki_basis(const void* X, int xtype, const rbki_params* prm, int mod
   return RBKI_OK;
 }
 
+int64_t rbki_basis_rows(const rbki_params* prm, int xtype, int mode) {
+  Plan P;
+  if (make_plan(prm, xtype, P) != RBKI_OK || mode < 0 || mode >= P.N) return 0;
+  return std::min<int64_t>(P.m[mode].Sp, P.m[mode].I);
+}
+
 size_t rbki_tucker_workspace(const rbki_params* prm, int xtype) {
   Plan P;
   if (make_plan(prm, xtype, P) != RBKI_OK) return 0;
@@ -932,13 +947,14 @@ void set_error(rbki_status s, const char* msg) { fail(s, "%s", msg); }
 
 // Helper streams of the current device for modes that run beside the
 // caller's stream (created once, default priority, non-blocking).
+static std::mutex g_lane_mu;
+static std::map<int, std::vector<hipStream_t>> g_lane_pool;
+
 static hipStream_t lane_stream(int lane) {
-  static std::mutex mu;
-  static std::map<int, std::vector<hipStream_t>> pool;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-  std::lock_guard<std::mutex> lk(mu);
-  std::vector<hipStream_t>& v = pool[dev];
+  std::lock_guard<std::mutex> lk(g_lane_mu);
+  std::vector<hipStream_t>& v = g_lane_pool[dev];
   while ((int)v.size() < kMaxLanes - 1) {
     hipStream_t h = nullptr;
     if (hipStreamCreateWithFlags(&h, hipStreamNonBlocking) != hipSuccess) return nullptr;
@@ -1046,12 +1062,13 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   s = run_core_and_error(P, b, X, xsrc, core, dtype_elem(out_type), want_err, hr->sums, core_chain, st,
                          inline_factors);
   if (s != RBKI_OK) return s;
-  if (!want_err) return RBKI_OK;
+  // the eigen-solver's status comes back whether or not the error was asked
+  // for, so a failed solve is never returned as RBKI_OK
   HIPCHK(hipMemcpyAsync(hr->info, b.info, 2 * P.N * sizeof(int), hipMemcpyDeviceToHost, st));
   hr->nmodes = P.N;
   if (async_res) return RBKI_OK;              // the caller reads the results after the stream completes
   HIPCHK(hipStreamSynchronize(st));
-  return finish_result(*hr, rel_err);
+  return finish_result(*hr, want_err ? rel_err : nullptr);
 }
 
 
@@ -1065,6 +1082,26 @@ rbki_status tucker_enqueue(const void* X, int xtype, const rbki_params* prm, voi
 }  // namespace rbki
 
 extern "C" {
+
+// Releases what the library holds between calls: the helper streams of the
+// concurrent modes (after their work is done) and the events of pending
+// timing records.  Makes no HIP call when it holds nothing.
+void rbki_release(void) {
+  prof_drain();
+  std::lock_guard<std::mutex> lk(g_lane_mu);
+  if (g_lane_pool.empty()) return;
+  int cur = 0;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  for (auto& kv : g_lane_pool) {
+    if (hipSetDevice(kv.first) != hipSuccess) continue;
+    for (hipStream_t h : kv.second) {
+      (void)hipStreamSynchronize(h);
+      (void)hipStreamDestroy(h);
+    }
+  }
+  if (have_cur) (void)hipSetDevice(cur);
+  g_lane_pool.clear();
+}
 
 rbki_status rbki_tucker(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
                         int out_type, void* workspace, size_t ws_bytes, double* rel_err, void* stream) {

@@ -21,6 +21,7 @@
 //
 // Results are deterministic: every sum is taken in a fixed order.
 #include <cfloat>
+#include <cstdlib>
 
 #include "rbki_kernels.h"
 
@@ -36,7 +37,7 @@ constexpr int RED_THREADS = 1024;            // reduction workgroup
 constexpr int RED_WAVES = RED_THREADS / 64;
 constexpr int RED_GMAX = 32;                 // workgroups per matrix at most
 constexpr size_t LDS_BYTES = 160 * 1024;
-constexpr unsigned SPIN_LIMIT = 1u << 20;    // barrier polls before giving up
+constexpr unsigned SPIN_LIMIT = 1u << 20;    // barrier polls before giving up (default)
 constexpr double EPS = 0x1p-53;              // unit roundoff of float64
 
 struct EigArgs {
@@ -60,6 +61,7 @@ struct EigArgs {
   double* P[EIG_MAXB];       // exchange of partial products, [2][G][n]
   double* RB[EIG_MAXB];      // exchange of the next reflector's row, [2][n]
   unsigned* cnt[EIG_MAXB];   // barrier counter (zero at launch)
+  unsigned spin_limit;       // barrier polls before giving up; 0: give up at the first barrier
 };
 
 // Value of element idx of a vector spread as x[t] = v[64 t + lane].
@@ -148,13 +150,14 @@ __device__ inline double away_from_zero(double u, double tol) {
 // bounded: on time-out *failed (LDS, read by thread 0 only) is raised and
 // later barriers no longer wait, so a lost arrival ends the launch with an
 // error flag instead of a hang.
-__device__ inline void group_barrier(unsigned* cnt, unsigned target, int* failed) {
+__device__ inline void group_barrier(unsigned* cnt, unsigned target, int* failed, unsigned limit) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
+    if (limit == 0) *failed = 1;
     while (!*failed && __hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (++spins > SPIN_LIMIT) *failed = 1;
+      if (++spins > limit) *failed = 1;
       __builtin_amdgcn_s_sleep(2);
     }
   }
@@ -315,7 +318,7 @@ __global__ void __launch_bounds__(RED_THREADS) eig_reduce_kernel(EigArgs g) {
       }
     }
     if (G > 1) {
-      group_barrier(g.cnt[m], (unsigned)(k + 1) * (unsigned)G, failed);
+      group_barrier(g.cnt[m], (unsigned)(k + 1) * (unsigned)G, failed, g.spin_limit);
       for (int j = tid; j < n; j += RED_THREADS) {
         if (j > k) {
           double y = 0.0;
@@ -820,6 +823,10 @@ hipError_t eig_top_batched(int nmat, const double* const* Z, const int64_t* ns, 
   if (nmat <= 0) return hipSuccess;
   if (nmat > EIG_MAXB) return hipErrorInvalidValue;
   EigArgs a = {};
+  // RBKI_EIG_SPIN_LIMIT: barrier polls of a multi-workgroup reduction before
+  // it gives up and reports failure (0: at once), to test the error path
+  a.spin_limit = SPIN_LIMIT;
+  if (const char* lim = getenv("RBKI_EIG_SPIN_LIMIT")) a.spin_limit = (unsigned)strtoul(lim, nullptr, 10);
   int64_t nmax = 0, rmax = 0, rows_cap = 0;
   int gmax = 1;
   for (int k = 0; k < nmat; ++k) {

@@ -47,11 +47,23 @@ def tucker_full(G, factors):
 
 
 def tr_full(cores):
-    """Full tensor of a tensor ring (eq. (3)) for row-major cores (r, I, r')."""
-    T = cores[0]
-    for C in cores[1:]:
-        T = np.tensordot(T, C, axes=([T.ndim - 1], [0]))
-    return np.ascontiguousarray(np.trace(T, axis1=0, axis2=T.ndim - 1))
+    """Full tensor of a tensor ring (eq. (3)) for row-major cores (r, I, r'),
+    one slab X[i_1] at a time: the chain G_1[:, i_1, :] G_2 ... G_{N-1} keeps
+    the closing index a as a free index, and the slab is one product with
+    G_N arranged as [(a, r_{N-1}), i_N], which closes the ring (sums over a).
+    No intermediate holds the two-ended chain of the whole tensor (64 times
+    the tensor for a 64^5 ring of rank 8)."""
+    dims = [int(C.shape[1]) for C in cores]
+    r0, rl = int(cores[0].shape[0]), int(cores[-1].shape[0])
+    L = np.ascontiguousarray(np.transpose(cores[-1], (2, 0, 1)).reshape(r0 * rl, dims[-1]))
+    X = np.empty(dims, dtype=np.float64)
+    for i in range(dims[0]):
+        T = np.asarray(cores[0][:, i, :], np.float64)              # (a, r_1)
+        for C in cores[1:-1]:
+            T = np.tensordot(T, C, axes=([T.ndim - 1], [0]))       # (a, I_2..I_k, r_k)
+        T = np.moveaxis(T, 0, -2)                                  # (I_2..I_{N-1}, a, r_{N-1})
+        X[i] = (T.reshape(-1, r0 * rl) @ L).reshape(dims[1:])
+    return X
 
 
 def noise_scale(clean_norm, noise_norm, snr_db):
@@ -59,10 +71,19 @@ def noise_scale(clean_norm, noise_norm, snr_db):
     return clean_norm / (noise_norm * 10.0 ** (snr_db / 20.0))
 
 
-def add_noise(Xc, snr_db, rng):
+def add_noise(Xc, snr_db, rng, dtype=np.float64):
+    """Xc + lambda N rounded to dtype, N ~ N(0, 1) drawn in one call (row-major
+    order), lambda from the realised norms (eq. (16)).  The sum is formed in
+    float64 and rounded once, slab by slab, so that a multi-GB tensor needs
+    no full-size temporary beyond N and the result."""
     N = rng.standard_normal(Xc.shape)
     lam = noise_scale(np.linalg.norm(Xc.ravel()), np.linalg.norm(N.ravel()), snr_db)
-    return Xc + lam * N
+    out = np.empty(Xc.shape, dtype=dtype)
+    xf, nf, of = Xc.reshape(-1), N.reshape(-1), out.reshape(-1)
+    step = 1 << 24
+    for s in range(0, xf.size, step):
+        of[s:s + step] = xf[s:s + step] + lam * nf[s:s + step]
+    return out
 
 
 # ------------------------------------------------------ the paper's generators
@@ -161,8 +182,11 @@ def make_host(w):
         Xc, rng = tensor_ring_data(w["dims"], w["tr_rank"], seed, w["tr_var"])
     else:
         raise ValueError(w["kind"])
-    X = add_noise(Xc, w["snr"], rng) if w.get("snr") is not None else Xc
-    return np.ascontiguousarray(X.astype(w["dtype"])), Xc
+    if w.get("snr") is not None:
+        X = add_noise(Xc, w["snr"], rng, dtype=np.dtype(w["dtype"]))
+    else:
+        X = Xc.astype(w["dtype"])
+    return np.ascontiguousarray(X), Xc
 
 
 def make_device(w, device="cuda"):
@@ -196,12 +220,16 @@ def make_device(w, device="cuda"):
     elif w["kind"] == "ring":
         r = int(w["tr_rank"])
         cores = [torch.randn((r, I, r), **f64) * math.sqrt(w["tr_var"]) for I in dims]
-        # contract the ring mode by mode, keeping (r0, I1..Ik, rk) small enough
-        T = cores[0]
-        for C in cores[1:]:
-            T = torch.tensordot(T, C, dims=([T.ndim - 1], [0]))
-        X = torch.diagonal(T, dim1=0, dim2=T.ndim - 1).sum(-1).contiguous()
-        del T
+        # one slab X[i_1] at a time, the closing index kept free (as tr_full)
+        L = cores[-1].permute(2, 0, 1).reshape(r * r, dims[-1]).contiguous()
+        X = torch.empty(dims, dtype=torch.float64, device=device)
+        for i in range(dims[0]):
+            T = cores[0][:, i, :]
+            for C in cores[1:-1]:
+                T = torch.tensordot(T, C, dims=([T.ndim - 1], [0]))
+            T = torch.movedim(T, 0, -2).reshape(-1, r * r)
+            X[i] = (T @ L).reshape(dims[1:])
+            del T
     else:
         raise ValueError(w["kind"])
     if w.get("snr") is not None:
@@ -212,6 +240,32 @@ def make_device(w, device="cuda"):
         del N
     dt = {"float64": torch.float64, "float32": torch.float32, "bfloat16": torch.bfloat16}[w["dtype"]]
     return X.to(dt).contiguous()
+
+
+def fingerprint(X):
+    """Float64 sums over the stored values of X (slab by slab) and 32 stored
+    values at fixed linear indices: identifies a generated tensor, so that a
+    stored result computed on it elsewhere can be matched to it."""
+    flat = np.asarray(X).reshape(-1)
+    n2 = 0.0
+    a1 = 0.0
+    step = 1 << 24
+    for s in range(0, flat.size, step):
+        c = flat[s:s + step].astype(np.float64)
+        n2 += float(np.dot(c, c))
+        a1 += float(np.sum(np.abs(c)))
+    idx = np.random.default_rng(12345).integers(0, flat.size, size=32)
+    return {"norm2": n2, "abs_sum": a1, "index": [int(i) for i in idx],
+            "values": [float(flat[i]) for i in idx]}
+
+
+def same_fingerprint(a, b):
+    """The two fingerprints describe the same tensor: equal sampled values,
+    and sums that agree to 1e-10 (float64 sums of the same values taken in
+    another order, on another machine, differ by about 1e-13)."""
+    return (a["index"] == b["index"] and a["values"] == b["values"]
+            and abs(a["norm2"] - b["norm2"]) <= 1e-10 * abs(b["norm2"])
+            and abs(a["abs_sum"] - b["abs_sum"]) <= 1e-10 * abs(b["abs_sum"]))
 
 
 # ------------------------------------------------------------ served request mix

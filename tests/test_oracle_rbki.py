@@ -225,3 +225,82 @@ def test_power_variant_error_is_not_below_the_krylov_error_per_mode():
         _, Up, _ = rbki_tucker(X, (5, 5, 5), p=3, q=q, seed=9, variant="power")
         for n in range(3):
             assert per_mode_error(X, n, Uk[n]) <= per_mode_error(X, n, Up[n]) * (1 + 1e-12)
+
+
+# ------------------------------------------------------- partial columns (Sec. 3.1)
+
+def test_sampled_columns_are_one_per_stratum():
+    for J, rate in ((1000, 0.1), (997, 0.37), (64, 0.5), (10, 0.01), (5, 1.0)):
+        cols = philox.sampled_columns(3, 2, J, rate)
+        m = philox.sample_count(J, rate)
+        assert cols.size == m and m >= 1
+        assert np.all(np.diff(cols) > 0) and cols[0] >= 0 and cols[-1] < J
+        k = np.arange(m)
+        assert np.all(cols >= (k * J) // m) and np.all(cols < ((k + 1) * J) // m)
+    assert np.array_equal(philox.sampled_columns(3, 2, 77, 1.0), np.arange(77))
+
+
+def test_sampled_columns_follow_the_scalar_generator():
+    # the vectorised draw against the big-integer Philox, one stratum at a time
+    J, rate, seed, mode = 1234, 0.05, 2 ** 40 + 9, 1
+    m = philox.sample_count(J, rate)
+    cols = philox.sampled_columns(seed, mode, J, rate)
+    key = philox.seed_key(seed)
+    for k in range(m):
+        lo, hi = (k * J) // m, ((k + 1) * J) // m
+        w0 = philox.philox4x32_scalar((k & 0xFFFFFFFF, k >> 32, mode, philox.TAG_COLUMNS), key)[0]
+        assert cols[k] == lo + (w0 * (hi - lo) >> 32)
+
+
+def test_sampled_columns_are_uniform():
+    # each column is drawn with probability m / J over many seeds
+    J, rate, trials = 200, 0.1, 3000
+    counts = np.zeros(J)
+    for s in range(trials):
+        counts[philox.sampled_columns(s, 0, J, rate)] += 1
+    p = philox.sample_count(J, rate) / J
+    z = (counts - trials * p) / np.sqrt(trials * p * (1 - p))
+    assert np.abs(z).max() < 5.0
+    assert abs(np.mean(z)) < 0.2
+
+
+def test_full_sampling_rate_is_the_plain_method():
+    X, _ = noisy_tucker((30, 25, 20), (4, 3, 5), 10.0, seed=21)
+    a = rbki_tucker(X, (4, 3, 5), 5, 2, 9)
+    b = rbki_tucker(X, (4, 3, 5), 5, 2, 9, sample_rate=1.0)
+    assert a[2] == b[2]
+    for u, v in zip(a[1], b[1]):
+        assert np.array_equal(u, v)
+
+
+def test_partial_columns_recover_an_exact_rank_tensor():
+    # the sampled columns of an exactly rank-R unfolding span its column space
+    Xc, _ = synth.orthonormal_tucker((40, 36, 30), (4, 3, 5), seed=22)
+    G, Us, err = rbki_tucker(Xc, (4, 3, 5), 5, 2, 10, sample_rate=0.2)
+    assert err <= 1e-12
+
+
+def test_partial_columns_factor_is_the_rayleigh_ritz_of_the_whole_unfolding():
+    # Z uses the whole unfolding (Alg. 2, step 3): of all R-dimensional
+    # subspaces of the sampled Krylov space, the factor leaves the least
+    # residual of X_(n); the subspace chosen from the sampled columns alone
+    # (Z from Y) and random subspaces of the basis do no better
+    X, _ = noisy_tucker((60, 50, 40), (6, 5, 4), 0.0, seed=23)
+    n, R = 0, 6
+    U, info = mode_factor(X, n, R, 3, 1, 11, return_info=True, sample_rate=0.15)
+    Q = info["Q"]
+    Xn = unfold(X, n)
+    e = per_mode_error(X, n, U)
+    Y = Xn[:, info["columns"]]
+    Uy, _ = ritz_factor(Y, Q, R)
+    assert e <= per_mode_error(X, n, Uy) * (1 + 1e-12)
+    assert per_mode_error(X, n, Uy) > e * (1 + 1e-6)
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        V, _ = np.linalg.qr(Q @ rng.standard_normal((Q.shape[1], R)))
+        assert e <= per_mode_error(X, n, V) * (1 + 1e-12)
+    # and the basis is the Krylov space of the sampled columns with an
+    # m-row sketch
+    Om = philox.omega(11, n, Y.shape[1], info["S"])
+    Qy, _ = rbki_basis(Y, Om, 1)
+    assert projector_distance(Q, Qy) <= 1e-12

@@ -3,6 +3,8 @@
 truncation error, and the Tucker + ring error split."""
 import itertools
 
+import pytest
+
 import numpy as np
 
 import synth
@@ -116,3 +118,18 @@ def test_ring_sweep_depends_on_first_step_signs_and_the_rule_fixes_them():
         out.append(C.reshape(r[3], S[3], r[0]))
         errs.append(fro(G - tr_to_full(out)))
     assert abs(errs[0] - errs[1]) > 1e-6 * fro(G)
+
+
+@pytest.mark.parametrize("dims,tk,tr", [((14, 12, 13, 11), (6, 5, 6, 5), (3, 3, 3, 3)),
+                                        ((10, 9, 11), (6, 6, 6), (4, 3, 5))])
+def test_core_level_error_equals_the_full_ring_error(dims, tk, tr):
+    # ||X - TR(X_n)||^2 = ||X - [[G; U]]||^2 + ||G - TR(G_n)||^2 for orthonormal
+    # Tucker factors: the large-tensor form of the HTR error, checked against
+    # the full ring contracted elementwise (with zero-padded ranks in the
+    # second case: r_0 r_1 = 20 > 6)
+    X, _ = synth.tensor_ring_data(dims, 3, seed=7, var=1.0 / 3)
+    X = synth.add_noise(X, 15.0, np.random.default_rng(8))
+    _, e_full, _ = rbki_htr(X, tk, 3, 2, 9, tr, explicit_error=True)
+    _, e_core, info = rbki_htr(X, tk, 3, 2, 9, tr, explicit_error="core")
+    assert abs(e_full - e_core) <= 1e-12 * e_full
+    assert info["core_gap2"] >= 0.0
