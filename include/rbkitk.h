@@ -75,7 +75,17 @@ typedef enum { RBKI_KRYLOV = 0, RBKI_POWER = 1 } rbki_variant;
  * oversample = 5), and the number of Krylov steps q ("power"; Alg. 1 gives it
  * only as Theta(log d / sqrt(eps)), Sec. 3.1 uses 2).  The Krylov basis of
  * mode n has width S'_n = min(S_n (q+1), I_n); the power variant's has width
- * S_n. */
+ * S_n.
+ *
+ * Partial columns (Sec. 3.1): with sample_rate omega < 1 the Krylov basis of
+ * mode n is built from the m_n = max(1, round(omega J_n)) sampled columns Y of
+ * X_(n) instead of all J_n: W = Y Omega (Omega of m_n rows, the sketch stream
+ * with J_n replaced by m_n), the Krylov steps with Y Y^T, and S_n =
+ * min(R_n + oversample, I_n, m_n).  Z = Q^T X_(n) X_(n)^T Q still uses the whole
+ * unfolding (Alg. 2, step 3), as do the core and the error.  The sample is
+ * stratified uniform: stratum k = [floor(k J_n / m_n), floor((k+1) J_n / m_n))
+ * gives the column at offset floor(w width / 2^32), w the first word of the
+ * Philox block at counter (lo32(k), hi32(k), n, 1) under the sketch key. */
 typedef struct {
   int order;              /* N >= 2 (N = 2 is the matrix rBKI-SVD case) */
   const int64_t *dims;    /* host[N], I_n >= 1 */
@@ -85,6 +95,8 @@ typedef struct {
   uint64_t seed;          /* key of the Philox sketch stream */
   int precision;          /* rbki_precision */
   int variant;            /* rbki_variant (0, the Krylov space, when zero-initialised) */
+  double sample_rate;     /* omega in (0, 1]: build each mode's basis from m_n = round(omega J_n)
+                             columns of the unfolding (Sec. 3.1); 0 (zero-initialised) means 1 */
 } rbki_params;
 
 /* Library version string (static storage). */

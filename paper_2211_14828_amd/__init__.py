@@ -49,7 +49,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("dims", ctypes.POINTER(ctypes.c_int64)),
                 ("ranks", ctypes.POINTER(ctypes.c_int64)), ("oversample", ctypes.c_int),
                 ("power", ctypes.c_int), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int),
-                ("variant", ctypes.c_int)]
+                ("variant", ctypes.c_int), ("sample_rate", ctypes.c_double)]
 
 
 _lib = None
@@ -139,7 +139,7 @@ def _dtype_code(torch, dt):
 _VARIANTS = {"krylov": 0, "power": 1}
 
 
-def _params(dims, ranks, p, q, seed, precision, variant="krylov"):
+def _params(dims, ranks, p, q, seed, precision, variant="krylov", sample_rate=1.0):
     n = len(dims)
     if len(ranks) != n:
         raise ValueError("ranks must have one entry per mode")
@@ -148,7 +148,7 @@ def _params(dims, ranks, p, q, seed, precision, variant="krylov"):
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     prm = _Params(n, ctypes.cast(d, ctypes.POINTER(ctypes.c_int64)), ctypes.cast(r, ctypes.POINTER(ctypes.c_int64)),
                   int(p), int(q), int(seed) & 0xFFFFFFFFFFFFFFFF, prec,
-                  _VARIANTS[variant] if isinstance(variant, str) else int(variant))
+                  _VARIANTS[variant] if isinstance(variant, str) else int(variant), float(sample_rate))
     prm._keep = (d, r)
     return prm
 
@@ -180,10 +180,10 @@ def _as_input(torch, X):
 
 # ------------------------------------------------------------------ public API
 
-def workspace_bytes(dims, ranks, p, q, dtype, precision="plain", tr_ranks=None):
+def workspace_bytes(dims, ranks, p, q, dtype, precision="plain", tr_ranks=None, variant="krylov", sample_rate=1.0):
     lib = load_library()
     import torch
-    prm = _params(dims, ranks, p, q, 0, precision)
+    prm = _params(dims, ranks, p, q, 0, precision, variant, sample_rate)
     code = _dtype_code(torch, dtype)
     if tr_ranks is not None:
         tr = (ctypes.c_int64 * len(tr_ranks))(*tr_ranks)
@@ -192,10 +192,12 @@ def workspace_bytes(dims, ranks, p, q, dtype, precision="plain", tr_ranks=None):
 
 
 def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_err=True, stream=None,
-           workspace=None, variant="krylov"):
+           workspace=None, variant="krylov", sample_rate=1.0):
     """rBKI-TK (Alg. 2).  Returns (core, [U^(1), ..., U^(N)], rel_err or None).
     variant "power": each factor from the power iterate (XX^T)^q W alone
-    (the power-iteration comparison of Sec. 3.1)."""
+    (the power-iteration comparison of Sec. 3.1).  sample_rate < 1: each
+    mode's Krylov basis from that fraction of the unfolding's columns
+    (Sec. 3.1)."""
     torch = _torch()
     lib = load_library()
     X = _as_input(torch, X)
@@ -203,7 +205,7 @@ def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_er
     if out_dtype is None:
         out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
     ocode = _dtype_code(torch, out_dtype)
-    prm = _params(X.shape, ranks, p, q, seed, precision, variant)
+    prm = _params(X.shape, ranks, p, q, seed, precision, variant, sample_rate)
     need = lib.rbki_tucker_workspace(ctypes.byref(prm), code)
     if need == 0:
         _check(lib.rbki_tucker(None, code, ctypes.byref(prm), None, None, ocode, None, 0, None, None))
@@ -219,7 +221,7 @@ def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_er
 
 
 def htr(X, tucker_ranks, tr_ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_err=True,
-        stream=None):
+        stream=None, variant="krylov", sample_rate=1.0):
     """rBKI-TK-TR (Alg. 3, TR-SVD branch).  Returns ([X_1, ..., X_N], rel_err or None)."""
     torch = _torch()
     lib = load_library()
@@ -229,7 +231,7 @@ def htr(X, tucker_ranks, tr_ranks, p=5, q=2, seed=0, precision="plain", out_dtyp
         out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
     ocode = _dtype_code(torch, out_dtype)
     N = X.dim()
-    prm = _params(X.shape, tucker_ranks, p, q, seed, precision)
+    prm = _params(X.shape, tucker_ranks, p, q, seed, precision, variant, sample_rate)
     tr = (ctypes.c_int64 * N)(*[int(v) for v in tr_ranks])
     need = lib.rbki_htr_workspace(ctypes.byref(prm), code, tr)
     if need == 0:
@@ -245,14 +247,14 @@ def htr(X, tucker_ranks, tr_ranks, p=5, q=2, seed=0, precision="plain", out_dtyp
     return cores, (err.value if rel_err else None)
 
 
-def basis(X, mode, ranks, p=5, q=2, seed=0, precision="plain", stream=None):
+def basis(X, mode, ranks, p=5, q=2, seed=0, precision="plain", stream=None, variant="krylov", sample_rate=1.0):
     """Alg. 1 for one mode.  Returns (Qt as a float64 (S' x I_n) tensor whose
     first `width` rows are the orthonormal basis, width)."""
     torch = _torch()
     lib = load_library()
     X = _as_input(torch, X)
     code = _dtype_code(torch, X.dtype)
-    prm = _params(X.shape, ranks, p, q, seed, precision)
+    prm = _params(X.shape, ranks, p, q, seed, precision, variant, sample_rate)
     need = lib.rbki_basis_workspace(ctypes.byref(prm), code, int(mode))
     if need == 0:
         _check(lib.rbki_basis(None, code, ctypes.byref(prm), int(mode), None, None, None, 0, None))
@@ -372,7 +374,8 @@ class Server:
         prm = _params(dims, ranks, p, q, 0, precision)
         return self._lib.rbki_server_request_bytes(ctypes.byref(prm), _dtype_code(self._torch, dtype))
 
-    def submit(self, X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, variant="krylov"):
+    def submit(self, X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, variant="krylov",
+               sample_rate=1.0):
         torch = self._torch
         if self._h is None:
             raise RuntimeError("server is closed")
@@ -381,7 +384,7 @@ class Server:
         if out_dtype is None:
             out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
         ocode = _dtype_code(torch, out_dtype)
-        prm = _params(X.shape, ranks, p, q, seed, precision, variant)
+        prm = _params(X.shape, ranks, p, q, seed, precision, variant, sample_rate)
         core = torch.empty(tuple(int(r) for r in ranks), dtype=out_dtype, device=X.device)
         factors = [torch.empty((int(I), int(R)), dtype=out_dtype, device=X.device) for I, R in zip(X.shape, ranks)]
         fptr = (ctypes.c_void_p * len(factors))(*[f.data_ptr() for f in factors])

@@ -110,6 +110,9 @@ int cu_count() {
 // ------------------------------------------------------------------ planning
 struct ModeGeom {
   int64_t A, I, B, J, R, S, Sp;   // Sp = S * (q + 1): rows of the Krylov basis buffer
+  int64_t m = 0;                  // columns the Krylov basis is built from (J, or the sample)
+  bool sampled = false;           // m < J: partial columns (Sec. 3.1)
+  int yelem = 0;                  // element type of the gathered sample
   bool pipe = false;              // mixed forms: the pipelined Gram kernel on a blocked copy
   int pelem = 0;                  // its element type (E_BF16 or E_FP8)
   int64_t nkt = 0;                // its K tiles
@@ -133,6 +136,10 @@ struct Plan {
   bool need_xpad = false;    // some reader of Xpad remains (a Gram fallback or the first product)
   bool concurrent = false;   // runs beside other solves on the device (request server)
   bool power = false;        // power iteration: only the last block spans the factor's space
+  double rate = 1.0;         // column sampling rate omega (Sec. 3.1)
+  bool any_sampled = false;
+  int64_t maxM = 0;          // largest column sample
+  size_t ybytes = 0;         // largest gathered sample
   int64_t oblk_bytes = 0;                   // one mode's blocked bf16 sketch (the largest)
   int64_t in_pad = 0;        // last dimension padded to a multiple of 64
   int64_t rows_pad = 0;      // T / I_N padded to a multiple of 64 (row length of Xt)
@@ -189,6 +196,12 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
   if (prm->variant != RBKI_KRYLOV && prm->variant != RBKI_POWER)
     return fail(RBKI_E_INVALID, "unknown variant %d", prm->variant);
   P.power = prm->variant == RBKI_POWER;
+  {
+    const double rate = prm->sample_rate == 0.0 ? 1.0 : prm->sample_rate;
+    if (!(rate > 0.0 && rate <= 1.0))
+      return fail(RBKI_E_INVALID, "sample_rate %g outside (0, 1]", prm->sample_rate);
+    P.rate = rate;
+  }
   P.N = prm->order;
   P.p = prm->oversample;
   P.q = prm->power;
@@ -224,7 +237,9 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     g.R = P.ranks[n];
     if (g.R < 1 || g.R > g.I || g.R > g.J)
       return fail(RBKI_E_INVALID, "ranks[%d] = %lld outside [1, min(I_n, J_n)]", n, (long long)g.R);
-    g.S = std::min<int64_t>(std::min<int64_t>(g.R + P.p, g.I), g.J);   // Sec. 2.3, Sec. 4.1
+    g.m = sample_count(g.J, P.rate);
+    g.sampled = g.m < g.J;
+    g.S = std::min<int64_t>(std::min<int64_t>(g.R + P.p, g.I), g.m);   // Sec. 2.3, Sec. 4.1
     g.Sp = P.power ? g.S : g.S * (P.q + 1);
     if (g.Sp > 1200) return fail(RBKI_E_UNSUPPORTED, "Krylov width %lld > 1200 (mode %d)", (long long)g.Sp, n);
     const double ratio = (double)g.I / (double)g.R;
@@ -233,6 +248,16 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     P.maxS = std::max(P.maxS, g.S);
     P.maxSp = std::max(P.maxSp, g.Sp);
     P.maxRI = std::max(P.maxRI, g.R * g.I);
+    if (g.sampled) {
+      // the Krylov products read the gathered sample (bf16 in the mixed forms)
+      g.yelem = P.need_pad ? E_BF16 : P.xelem;
+      P.any_sampled = true;
+      P.maxM = std::max(P.maxM, g.m);
+      P.ybytes = std::max(P.ybytes, (size_t)g.I * g.m * elem_size(g.yelem));
+      P.maxSJ = std::max(P.maxSJ, g.S * g.m);
+      GramArgs gy = gram_plan(g.yelem, 1, g.I, g.m, (int)g.S, cu_count());
+      P.partial_bytes = std::max(P.partial_bytes, gram_partial_bytes(gy, g.yelem));
+    }
     if (P.need_pad) {
       int64_t A, Bp;
       g.pipe = gram_pipe_ok(g.I, (int)g.S);
@@ -314,6 +339,9 @@ struct Lane {
   double* L = nullptr;
   int* flags = nullptr;
   double* ref2 = nullptr;
+  double* CY = nullptr;     // partial columns: Y Y^T of the sample
+  void* ysmp = nullptr;     //   the gathered sample Y (I x m)
+  int64_t* cols = nullptr;  //   its column indices
 };
 constexpr int kMaxLanes = 3;
 
@@ -388,6 +416,11 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
     L.L = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
     L.flags = (int*)ar.take((size_t)P.maxSp * 4);
     L.ref2 = (double*)ar.take((size_t)P.maxS * 8);
+    if (P.any_sampled) {
+      L.CY = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
+      L.ysmp = ar.take(P.ybytes);
+      L.cols = (int64_t*)ar.take((size_t)P.maxM * 8);
+    }
   }
   for (int n = 0; n < P.N; ++n) b.Qt[n] = (double*)ar.take((size_t)P.m[n].Sp * P.m[n].I * 8);
   for (int n = 0; n < P.N; ++n) {
@@ -508,11 +541,13 @@ rbki_status run_mode_heavy(const Plan& P, const Buffers& b, int lane, const void
       HIPCHK(launch_gram_reduce(E_BF16, ga, L.C, L.Yt, st));
     }
   } else {
-    {
+    // a sampled mode needs only C from the whole unfolding (for Z): no sketch
+    const int Sf = g.sampled ? 0 : (int)S;
+    if (Sf) {
       ProfScope ps("omega", st);
       HIPCHK(launch_omega(P.gelem, P.seed, n, S * g.J, L.omegaT, st));
     }
-    GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, (int)S, cu_count());
+    GramArgs ga = gram_plan(P.gelem, g.A, g.I, g.B, Sf, cu_count());
     ga.X = xsrc;
     ga.omegaT = L.omegaT;
     ga.partial = L.partial;
@@ -521,6 +556,27 @@ rbki_status run_mode_heavy(const Plan& P, const Buffers& b, int lane, const void
       HIPCHK(launch_gram_main(P.gelem, ga, st));
     }
     HIPCHK(launch_gram_reduce(P.gelem, ga, L.C, L.Yt, st));
+  }
+
+  if (g.sampled) {
+    // Sec. 3.1, partial columns: the Krylov basis comes from the sampled
+    // columns Y of the unfolding; C_Y = Y Y^T and W = Y Omega (Omega of m
+    // rows) from the gathered sample
+    HIPCHK(launch_sample_columns(P.seed, n, g.J, g.m, L.cols, st));
+    HIPCHK(launch_gather_columns(P.xelem, xsrc, I, g.B, L.cols, g.m, g.yelem, L.ysmp, st));
+    {
+      ProfScope ps("omega", st);
+      HIPCHK(launch_omega(g.yelem, P.seed, n, S * g.m, L.omegaT, st));
+    }
+    GramArgs gy = gram_plan(g.yelem, 1, I, g.m, (int)S, cu_count());
+    gy.X = L.ysmp;
+    gy.omegaT = L.omegaT;
+    gy.partial = L.partial;
+    {
+      ProfScope ps("gram_sample", st);
+      HIPCHK(launch_gram_main(g.yelem, gy, st));
+    }
+    HIPCHK(launch_gram_reduce(g.yelem, gy, L.CY, L.Yt, st));
   }
 
   if (heavy_done) HIPCHK(hipEventRecord(heavy_done, st));
@@ -535,6 +591,8 @@ rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, boo
   const ModeGeom& g = P.m[n];
   const int64_t I = g.I, S = g.S, Sp = g.Sp;
   double* Qt = b.Qt[n];
+  // the Krylov products: with the sample's Y Y^T for a sampled mode
+  const double* Ck = g.sampled ? L.CY : L.C;
   // block 0: Q_0 = orth(W).  The first pass of every block's CholeskyQR2
   // also keeps the basis at most I_n wide: once it spans the whole space the
   // later blocks are rounding noise and are dropped whatever their norm.
@@ -547,7 +605,7 @@ rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, boo
     // replacing the last, with the same drop rule relative to the step's
     // largest squared row norm
     for (int j = 1; j <= P.q; ++j) {
-      HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt, I, L.C, I, 0.0, L.Yt, I, st));
+      HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt, I, Ck, I, 0.0, L.Yt, I, st));
       HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
       HIPCHK(chol_orth(L.Yt, L.Ytmp, S, I, L.G, L.L, L.flags, L.ref2, TAU_REL, TAU_ABS, st));
       HIPCHK(chol_orth(L.Ytmp, Qt, S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
@@ -561,7 +619,7 @@ rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, boo
     const int64_t m = S * j;                     // rows of the basis so far
     const double* Qlast = Qt + (m - S) * I;
     // Y_j^T = Q_{j-1}^T C  (C symmetric)
-    HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qlast, I, L.C, I, 0.0, L.Yt, I, st));
+    HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qlast, I, Ck, I, 0.0, L.Yt, I, st));
     HIPCHK(copy_rows_f64(L.CQt + (m - S) * I, I, L.Yt, I, S, I, st));
     HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
     for (int pass = 0; pass < 2; ++pass) {       // remove earlier blocks, twice
@@ -573,8 +631,13 @@ rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, boo
     HIPCHK(chol_orth(L.Ytmp, Qt + m * I, S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
   }
   if (!with_factor) return RBKI_OK;
-  // C Q_q, then Z = Q^T (C Q) (Alg. 2, step 3)
-  HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt + (Sp - S) * I, I, L.C, I, 0.0, L.CQt + (Sp - S) * I, I, st));
+  // C Q_q, then Z = Q^T (C Q) (Alg. 2, step 3); a sampled mode's earlier
+  // products were with Y Y^T, so C Q is formed for the whole basis
+  if (g.sampled) {
+    HIPCHK(dgemm(0, 0, Sp, I, I, 1.0, Qt, I, L.C, I, 0.0, L.CQt, I, st));
+  } else {
+    HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qt + (Sp - S) * I, I, L.C, I, 0.0, L.CQt + (Sp - S) * I, I, st));
+  }
   HIPCHK(dgemm(0, 1, Sp, Sp, I, 1.0, Qt, I, L.CQt, I, 0.0, b.Z[n], Sp, st));
   return RBKI_OK;
 }

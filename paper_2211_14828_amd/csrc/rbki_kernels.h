@@ -72,6 +72,17 @@ hipError_t launch_omega_block(uint64_t seed, int mode, int64_t S, int64_t J, int
                               int KT, void* out, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint64_t seed, uint32_t* out, hipStream_t s);
 
+// ------------------------------------------------------------ sample.hip
+// Partial-column sampling (Sec. 3.1): m = round(rate J) columns of a J-column
+// unfolding (all of them for rate >= 1), one per stratum
+// [floor(k J / m), floor((k+1) J / m)) at a Philox-drawn offset (tag 1).
+int64_t sample_count(int64_t J, double rate);
+hipError_t launch_sample_columns(uint64_t seed, int mode, int64_t J, int64_t m, int64_t* cols, hipStream_t s);
+// Y (I x m row-major, y_elem: x_elem, or E_BF16 rounded to nearest even)
+// = the columns cols[0..m) of the view [A, I, B] of X (column j = a B + b).
+hipError_t launch_gather_columns(int x_elem, const void* X, int64_t I, int64_t B, const int64_t* cols, int64_t m,
+                                 int y_elem, void* Y, hipStream_t s);
+
 // ------------------------------------------------------------ linalg.hip (float64)
 // C[m x n] = alpha * op(A) op(B) + beta * C, all row-major with leading dims.
 // opA: 0 -> A is m x k (lda), 1 -> A is k x m (A^T used).

@@ -146,3 +146,22 @@ def test_unknown_variant_is_rejected_and_the_power_basis_is_one_block_wide():
     st = lib.rbki_tucker(ctypes.c_void_p(16), 1, ctypes.byref(prm), None, None, 1, None, 0, None, None)
     assert st == 1 and "variant" in lib.rbki_last_error().decode()
     assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) == 0
+
+
+def test_sample_rate_is_validated_and_sizes_the_basis():
+    lib = rb.load_library()
+    prm = _params((40, 50, 30), (6, 6, 6), 5, 2, 0)
+    full = lib.rbki_tucker_workspace(ctypes.byref(prm), 1)
+    assert lib.rbki_basis_rows(ctypes.byref(prm), 1, 0) == 33      # S (q + 1) = 11 * 3 <= I
+    prm.sample_rate = 1.0
+    assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) == full
+    prm.sample_rate = 0.01                                          # m = 15 columns of mode 0
+    assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) > full
+    assert lib.rbki_basis_rows(ctypes.byref(prm), 1, 0) == 33
+    prm.sample_rate = 0.002                                         # m = 3 < R + p: S = 3
+    assert lib.rbki_basis_rows(ctypes.byref(prm), 1, 0) == 9
+    for bad in (-0.5, 1.5, float("nan")):
+        prm.sample_rate = bad
+        st = lib.rbki_tucker(ctypes.c_void_p(16), 1, ctypes.byref(prm), None, None, 1, None, 0, None, None)
+        assert st == 1 and "sample_rate" in lib.rbki_last_error().decode()
+        assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) == 0

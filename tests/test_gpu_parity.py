@@ -432,3 +432,62 @@ def test_failed_eigen_solve_is_reported_without_rel_err(env, monkeypatch):
     lam, _ = rb.sym_eig_top(Z, 10)
     ref = np.sort(np.linalg.eigvalsh(Z.cpu().numpy()))[::-1][:10]
     assert np.max(np.abs(lam.cpu().numpy() - ref)) <= 1e-12 * ref[0]
+
+
+# ------------------------------------------------------------------ partial columns (Sec. 3.1)
+
+SAMPLED = [
+    # dims, ranks, p, q, dtype, precision, sampling rate
+    ((64, 64, 64), (8, 8, 8), 5, 2, "float64", "plain", 0.1),
+    ((12, 10, 14, 9), (3, 4, 2, 3), 4, 2, "float64", "plain", 0.5),
+    ((37, 45, 29), (4, 5, 3), 5, 2, "float64", "plain", 0.03),
+    ((130, 70, 150), (10, 8, 12), 5, 2, "float32", "plain", 0.3),
+    ((130, 70, 150), (10, 8, 12), 5, 2, "float32", "mixed_bf16", 0.3),
+    ((300, 40, 270), (12, 6, 10), 5, 2, "float32", "mixed_fp8", 0.25),
+    ((600, 40, 530), (20, 6, 15), 10, 2, "float32", "mixed_fp8", 0.1),
+    ((64, 50, 40), (6, 6, 6), 5, 1, "bfloat16", "plain", 0.2),
+]
+
+
+@pytest.mark.parametrize("dims,ranks,p,q,dtype,prec,rate", SAMPLED)
+def test_partial_columns_match_oracle(env, dims, ranks, p, q, dtype, prec, rate):
+    torch, rb = env
+    seed = 2000 + len(dims) * 7 + sum(dims)
+    X = make_case(dims, ranks, dtype, "sampled", seed)
+    Xg = to_device(torch, X, dtype)
+    Xh = host_values(torch, Xg)
+    core, facs, e_g = rb.tucker(Xg, ranks, p=p, q=q, seed=seed + 1, precision=prec, out_dtype=torch.float64,
+                                sample_rate=rate)
+    _, Us, e_o, infos = rbki_tucker(Xh, ranks, p, q, seed + 1, return_info=True, sample_rate=rate)
+    assert abs(e_g - e_o) / e_o <= TOL[(dtype, prec)], (e_g, e_o)
+    Ug = [f.cpu().numpy() for f in facs]
+    for n in range(len(dims)):
+        assert orthonormality_defect(Ug[n]) <= 1e-11
+        if gap_ok(infos[n]["eigenvalues"], ranks[n]):
+            key = dtype if prec == "plain" else ("fp8" if prec == "mixed_fp8" else "bfloat16")
+            assert projector_distance(Ug[n], Us[n]) <= PROJ_TOL[key]
+
+
+@pytest.mark.parametrize("mode,rate,variant", [(0, 0.2, "krylov"), (2, 0.05, "krylov"), (1, 0.3, "power")])
+def test_partial_column_basis_spans_the_oracle_space(env, mode, rate, variant):
+    torch, rb = env
+    w = synth.WORKLOADS["tucker64_f64"]
+    X, _ = synth.make_host(w)
+    Xg = torch.from_numpy(X).cuda()
+    Qt, width = rb.basis(Xg, mode, w["ranks"], p=w["p"], q=w["q"], seed=w["seeds"][1], variant=variant,
+                         sample_rate=rate)
+    _, info = mode_factor(X, mode, w["ranks"][mode], w["p"], w["q"], w["seeds"][1], return_info=True,
+                          variant=variant, sample_rate=rate)
+    Q = Qt[:width].cpu().numpy().T
+    assert width == info["Q"].shape[1]
+    assert orthonormality_defect(Q) <= 1e-12
+    assert projector_distance(Q, info["Q"]) <= 1e-10
+
+
+def test_partial_columns_with_the_power_variant(env):
+    torch, rb = env
+    X = make_case((70, 60, 50), (7, 6, 5), "float64", "sampled", 77)
+    Xg = torch.from_numpy(X).cuda()
+    _, facs, e_g = rb.tucker(Xg, (7, 6, 5), p=4, q=2, seed=78, variant="power", sample_rate=0.15)
+    _, Us, e_o = rbki_tucker(X, (7, 6, 5), 4, 2, 78, variant="power", sample_rate=0.15)
+    assert abs(e_g - e_o) / e_o <= 1e-10
