@@ -204,3 +204,51 @@ def per_mode_error(X, n, U):
     """||X_(n) - U U^T X_(n)||_F, the per-mode error of Lemma 4 (eq. (8))."""
     Xn = unfold(np.asarray(X, dtype=np.float64), n)
     return fro(Xn - U @ (U.T @ Xn))
+
+
+def rbki_tucker_sequential(X, ranks, p, q, seed, tau=TAU, return_info=False, variant="krylov", sample_rate=1.0):
+    """Alg. 2 with step 6 taken as sequential truncation (the ST-HOSVD form,
+    the other reading of "G <- X x_n U^(n)T" inside the loop): Y_0 = X, the
+    factor of mode n is computed from Y_{n-1} (whose modes before n are
+    already the ranks R_1 .. R_{n-1}), Y_n = Y_{n-1} x_n U^(n)T, and G = Y_N.
+    The sketch of mode n has as many rows as Y_{n-1}'s mode-n unfolding has
+    columns (the same stream, with J_n replaced by that number)."""
+    X = np.asarray(X, dtype=np.float64)
+    from .tensor import mode_product
+    Y = X
+    factors, infos, stage_err2 = [], [], []
+    for n in range(X.ndim):
+        U, info = mode_factor(Y, n, ranks[n], p, q, seed, tau, return_info=True, variant=variant,
+                              sample_rate=sample_rate)
+        stage_err2.append(per_mode_error(Y, n, U) ** 2)
+        Y = mode_product(Y, U.T, n)
+        factors.append(U)
+        infos.append(info)
+    G = Y
+    err = fro(X - tucker_to_full(G, factors)) / fro(X)
+    if return_info:
+        return G, factors, err, infos, stage_err2
+    return G, factors, err
+
+
+def fit_fraction(rel_err):
+    """Fit of Sec. 4 as a fraction: 1 - ||X - Xhat|| / ||X||."""
+    return 1.0 - rel_err
+
+
+def rbki_tucker_adaptive(X, ranks, p, seed, fit_tol=1e-3, max_q=20, tau=TAU, sample_rate=1.0):
+    """rBKI-TK with the number of Krylov steps chosen by the stopping rule of
+    Sec. 4: t = 0, 1, ... Krylov steps (the same sketch each time, so the
+    Krylov spaces are nested) until |Fit_t - Fit_{t-1}| <= fit_tol, or
+    t = max_q; Fit_t is the fit of the rank-k approximation after t steps to
+    the input X (the only tensor the method sees), as a fraction.  Returns
+    (G, factors, err, q_used)."""
+    X = np.asarray(X, dtype=np.float64)
+    prev = None
+    for t in range(max_q + 1):
+        G, factors, err = rbki_tucker(X, ranks, p, t, seed, tau, sample_rate=sample_rate)
+        fit = fit_fraction(err)
+        if prev is not None and abs(fit - prev) <= fit_tol:
+            return G, factors, err, t
+        prev = fit
+    return G, factors, err, max_q

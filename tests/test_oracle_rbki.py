@@ -304,3 +304,82 @@ def test_partial_columns_factor_is_the_rayleigh_ritz_of_the_whole_unfolding():
     Om = philox.omega(11, n, Y.shape[1], info["S"])
     Qy, _ = rbki_basis(Y, Om, 1)
     assert projector_distance(Q, Qy) <= 1e-12
+
+
+# ------------------------------------------------- sequential truncation, adaptive q
+
+from oracle.rbki import rbki_tucker_sequential, rbki_tucker_adaptive  # noqa: E402
+
+
+def test_sequential_recovers_an_exact_rank_tensor():
+    Xc, _ = synth.orthonormal_tucker((20, 24, 18), (3, 4, 2), seed=5)
+    G, Us, err = rbki_tucker_sequential(Xc, (3, 4, 2), p=5, q=2, seed=11)
+    assert err <= 1e-12
+    assert G.shape == (3, 4, 2)
+
+
+def test_sequential_error_is_the_sum_of_its_stage_residuals():
+    # sequential truncation with orthonormal factors: the stage residuals
+    # are mutually orthogonal, so ||X - Xhat||^2 = sum_n ||Y_{n-1} - Y_{n-1} x_n U U^T||^2
+    X, _ = noisy_tucker((30, 26, 22, 12), (5, 4, 6, 3), 5.0, seed=31)
+    G, Us, err, infos, st2 = rbki_tucker_sequential(X, (5, 4, 6, 3), 3, 1, 12, return_info=True)
+    nx2 = fro(X) ** 2
+    assert abs(err ** 2 * nx2 - sum(st2)) <= 1e-10 * nx2
+    # and the core is the last partially projected tensor: X x_n U_n^T
+    assert fro(G - project_core(X, Us)) <= 1e-12 * fro(G)
+
+
+def test_sequential_with_a_full_krylov_space_is_st_hosvd():
+    # S (q + 1) >= I_n in every mode: each factor is the leading left singular
+    # subspace of the successive partially projected unfolding
+    X, _ = noisy_tucker((12, 14, 10), (3, 4, 2), 10.0, seed=32)
+    G, Us, err = rbki_tucker_sequential(X, (3, 4, 2), p=3, q=3, seed=13)
+    Y = X
+    from oracle.tensor import mode_product
+    for n, R in enumerate((3, 4, 2)):
+        Ut, s = leading_left_singular(unfold(Y, n), R)
+        assert (s[R - 1] - s[R]) / s[0] > 1e-6
+        assert projector_distance(Us[n], Ut) <= 1e-10
+        Y = mode_product(Y, Ut.T, n)
+
+
+def test_sequential_first_mode_is_the_independent_one_and_the_rest_differ():
+    X, _ = noisy_tucker((40, 30, 35), (5, 4, 6), 5.0, seed=33)
+    Gi, Ui, ei = rbki_tucker(X, (5, 4, 6), 4, 1, 14)
+    Gs, Us, es = rbki_tucker_sequential(X, (5, 4, 6), 4, 1, 14)
+    assert np.array_equal(Ui[0], Us[0])
+    assert projector_distance(Ui[1], Us[1]) > 1e-8
+
+
+def test_table4_rerr_is_the_independent_form_not_the_sequential_one():
+    # Table 4 prints RErr 1.10 for rBKI-TK on the power-functional 200^3 case;
+    # the independent-mode form reproduces it (test_oracle_paper), the
+    # sequential form does not (it lands below 1, better than T-HOSVD)
+    Xc = synth.power_functional((200, 200, 200))
+    X = synth.noisy(Xc, 5.0, seed=600)
+    G, U, _ = thosvd(X, (10,) * 3)
+    Xt = tucker_to_full(G, U)
+    Gs, Us, _ = rbki_tucker_sequential(X, (10,) * 3, 5, 2, 601)
+    rerr = np.linalg.norm((Xc - tucker_to_full(Gs, Us)).ravel()) / np.linalg.norm((Xc - Xt).ravel())
+    assert rerr < 1.0 and abs(rerr - 1.10) > 0.1
+
+
+def test_adaptive_q_stops_at_the_first_small_fit_change():
+    X, _ = noisy_tucker((40, 36, 30), (5, 4, 3), 0.0, seed=34)
+    G, Us, err, qu = rbki_tucker_adaptive(X, (5, 4, 3), 3, 15, fit_tol=1e-4, max_q=10)
+    fits = [1.0 - rbki_tucker(X, (5, 4, 3), 3, t, 15)[2] for t in range(qu + 1)]
+    assert abs(fits[qu] - fits[qu - 1]) <= 1e-4
+    assert all(abs(fits[t] - fits[t - 1]) > 1e-4 for t in range(1, qu))
+    assert err == rbki_tucker(X, (5, 4, 3), 3, qu, 15)[2]
+    # a tolerance no change can meet runs to max_q; a loose one stops at once
+    assert rbki_tucker_adaptive(X, (5, 4, 3), 3, 15, fit_tol=-1.0, max_q=3)[3] == 3
+    assert rbki_tucker_adaptive(X, (5, 4, 3), 3, 15, fit_tol=1.0, max_q=3)[3] == 1
+
+
+def test_adaptive_q_on_the_table3_case_is_small():
+    # Sec. 3.1: q = 2 is enough in practice; with the stopping rule of
+    # Sec. 4 the Gaussian Tucker case of Table 3 stops within 3 steps
+    Xc = synth.gaussian_tucker((200, 200, 200), (10, 10, 10), seed=301)
+    X = synth.noisy(Xc, -5.0, seed=401)
+    _, _, _, qu = rbki_tucker_adaptive(X, (10, 10, 10), 5, 501)
+    assert 1 <= qu <= 3
