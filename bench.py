@@ -174,7 +174,10 @@ def cpu_baseline(X, w, target_s=20.0):
             rbki_tucker(Xs, ranks, p, q, seed)
         return time.perf_counter() - t0, Xs.shape, ranks
 
-    probe = max(1, min(last, 60))
+    # the probe slab: at most about 3e7 entries (a 64^5 tensor gives one
+    # slice of its last mode)
+    rest = X.numel() // last
+    probe = max(1, min(last, 60, int(3e7 // rest)))
     dt, _, _ = run(probe)
     slab = int(min(last, max(probe, probe * target_s / max(dt, 1e-3))))
     dt, shape, ranks = run(slab)

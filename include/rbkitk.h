@@ -70,6 +70,16 @@ typedef enum { RBKI_PLAIN = 0, RBKI_MIXED_BF16 = 1, RBKI_MIXED_FP8 = 2 } rbki_pr
  * width S_n.  With q = 0 both are the single-sketch range finder (GR-SVD). */
 typedef enum { RBKI_KRYLOV = 0, RBKI_POWER = 1 } rbki_variant;
 
+/* How the modes follow each other (Alg. 2, step 6 inside the loop over n).
+ * RBKI_INDEPENDENT: every factor from the original X, then the core
+ * G = X x_1 U^(1)T ... x_N U^(N)T (the randomized-HOSVD form).
+ * RBKI_SEQUENTIAL: sequential truncation (the ST-HOSVD form): Y_0 = X, the
+ * factor of mode n from Y_{n-1}, Y_n = Y_{n-1} x_n U^(n)T, G = Y_N; mode n's
+ * sketch has as many rows as Y_{n-1}'s unfolding has columns.  Modes after
+ * the first read Y_{n-1} in float32 (float64 for a float64 X) in the plain
+ * form, whatever `precision` says for the first. */
+typedef enum { RBKI_INDEPENDENT = 0, RBKI_SEQUENTIAL = 1 } rbki_truncation;
+
 /* Problem statement of Alg. 2: tensor order N, sizes I_n, multilinear rank
  * R_n, sketch sizes S_n = min(R_n + oversample, I_n, J_n) (Sec. 4.1 uses
  * oversample = 5), and the number of Krylov steps q ("power"; Alg. 1 gives it
@@ -97,6 +107,7 @@ typedef struct {
   int variant;            /* rbki_variant (0, the Krylov space, when zero-initialised) */
   double sample_rate;     /* omega in (0, 1]: build each mode's basis from m_n = round(omega J_n)
                              columns of the unfolding (Sec. 3.1); 0 (zero-initialised) means 1 */
+  int truncation;         /* rbki_truncation (0, independent modes, when zero-initialised) */
 } rbki_params;
 
 /* Library version string (static storage). */
@@ -154,6 +165,26 @@ size_t rbki_tucker_workspace(const rbki_params *prm, int xtype);
 rbki_status rbki_tucker(const void *X, int xtype, const rbki_params *prm, void *core,
                         void *const *factors, int out_type, void *workspace, size_t ws_bytes,
                         double *rel_err, void *stream);
+
+/* rBKI-TK with the number of Krylov steps chosen by the stopping rule of
+ * Sec. 4: after t = 0, 1, ... steps (every mode; the same sketch, so the
+ * Krylov spaces are nested) the rank-k approximation X_t and its Fit
+ * 1 - ||X - X_t||_F / ||X||_F (a fraction, against the input X, the explicit
+ * residual) are formed, and the solve stops at the first t >= 1 with
+ * |Fit_t - Fit_{t-1}| <= fit_tol, or at t = prm->power (the paper's 20).
+ * Steps beyond ceil(I_n / S_n) cannot change a basis that spans its mode
+ * space, so at most max_n ceil(I_n / S_n) steps are taken.  The outputs are
+ * those of rbki_tucker with q = *q_used (bit for bit when no mode is
+ * sampled).  Krylov variant, independent modes only (RBKI_E_UNSUPPORTED
+ * otherwise).  Synchronises once per step.
+ *   fit_tol : the Fit change that stops the iteration (the paper's 1e-3).
+ *   rel_err : host, nullable: the error after the last step.
+ *   q_used  : host, nullable: the number of Krylov steps taken.
+ */
+size_t rbki_tucker_adaptive_workspace(const rbki_params *prm, int xtype);
+rbki_status rbki_tucker_adaptive(const void *X, int xtype, const rbki_params *prm, double fit_tol,
+                                 void *core, void *const *factors, int out_type, void *workspace,
+                                 size_t ws_bytes, double *rel_err, int *q_used, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Alg. 3 (rBKI-TK-TR) with the TR-SVD branch: rBKI-TK with the Tucker ranks

@@ -16,7 +16,7 @@ import ctypes
 import os
 import threading
 
-__all__ = ["tucker", "htr", "basis", "sym_eig", "sym_eig_top", "omega", "philox", "workspace_bytes", "profile_enable",
+__all__ = ["tucker", "tucker_adaptive", "htr", "basis", "sym_eig", "sym_eig_top", "omega", "philox", "workspace_bytes", "profile_enable",
            "profile_reset", "profile_read", "Server", "library_path", "load_library", "RbkiError",
            "PLAIN", "MIXED_BF16", "MIXED_FP8", "SYMBOLS"]
 
@@ -33,7 +33,7 @@ _STATUS = {0: "RBKI_OK", 1: "RBKI_E_INVALID", 2: "RBKI_E_NOMEM", 3: "RBKI_E_HIP"
 # Every symbol the header declares.
 SYMBOLS = ("rbki_version", "rbki_last_error", "rbki_omega", "rbki_philox", "rbki_basis_workspace",
            "rbki_basis", "rbki_tucker_workspace", "rbki_tucker", "rbki_htr_workspace", "rbki_htr",
-           "rbki_basis_rows", "rbki_release",
+           "rbki_basis_rows", "rbki_release", "rbki_tucker_adaptive_workspace", "rbki_tucker_adaptive",
            "rbki_sym_eig_workspace", "rbki_sym_eig", "rbki_sym_eig_top_workspace", "rbki_sym_eig_top",
            "rbki_profile_enable", "rbki_profile_reset", "rbki_profile_read", "rbki_server_request_bytes", "rbki_server_create", "rbki_server_submit",
            "rbki_server_poll", "rbki_server_wait", "rbki_server_destroy")
@@ -49,7 +49,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("dims", ctypes.POINTER(ctypes.c_int64)),
                 ("ranks", ctypes.POINTER(ctypes.c_int64)), ("oversample", ctypes.c_int),
                 ("power", ctypes.c_int), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int),
-                ("variant", ctypes.c_int), ("sample_rate", ctypes.c_double)]
+                ("variant", ctypes.c_int), ("sample_rate", ctypes.c_double), ("truncation", ctypes.c_int)]
 
 
 _lib = None
@@ -83,6 +83,8 @@ def load_library(build_if_missing=True):
             "rbki_basis": (ci, [vp, ci, P(_Params), ci, vp, P(i64), vp, sz, vp]),
             "rbki_basis_rows": (i64, [P(_Params), ci, ci]),
             "rbki_release": (None, []),
+            "rbki_tucker_adaptive_workspace": (sz, [P(_Params), ci]),
+            "rbki_tucker_adaptive": (ci, [vp, ci, P(_Params), dbl, vp, P(vp), ci, vp, sz, P(dbl), P(ci), vp]),
             "rbki_tucker_workspace": (sz, [P(_Params), ci]),
             "rbki_tucker": (ci, [vp, ci, P(_Params), vp, P(vp), ci, vp, sz, P(dbl), vp]),
             "rbki_htr_workspace": (sz, [P(_Params), ci, P(i64)]),
@@ -139,7 +141,10 @@ def _dtype_code(torch, dt):
 _VARIANTS = {"krylov": 0, "power": 1}
 
 
-def _params(dims, ranks, p, q, seed, precision, variant="krylov", sample_rate=1.0):
+_TRUNCATIONS = {"independent": 0, "sequential": 1}
+
+
+def _params(dims, ranks, p, q, seed, precision, variant="krylov", sample_rate=1.0, truncation="independent"):
     n = len(dims)
     if len(ranks) != n:
         raise ValueError("ranks must have one entry per mode")
@@ -148,7 +153,8 @@ def _params(dims, ranks, p, q, seed, precision, variant="krylov", sample_rate=1.
     prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     prm = _Params(n, ctypes.cast(d, ctypes.POINTER(ctypes.c_int64)), ctypes.cast(r, ctypes.POINTER(ctypes.c_int64)),
                   int(p), int(q), int(seed) & 0xFFFFFFFFFFFFFFFF, prec,
-                  _VARIANTS[variant] if isinstance(variant, str) else int(variant), float(sample_rate))
+                  _VARIANTS[variant] if isinstance(variant, str) else int(variant), float(sample_rate),
+                  _TRUNCATIONS[truncation] if isinstance(truncation, str) else int(truncation))
     prm._keep = (d, r)
     return prm
 
@@ -180,10 +186,11 @@ def _as_input(torch, X):
 
 # ------------------------------------------------------------------ public API
 
-def workspace_bytes(dims, ranks, p, q, dtype, precision="plain", tr_ranks=None, variant="krylov", sample_rate=1.0):
+def workspace_bytes(dims, ranks, p, q, dtype, precision="plain", tr_ranks=None, variant="krylov", sample_rate=1.0,
+                    truncation="independent"):
     lib = load_library()
     import torch
-    prm = _params(dims, ranks, p, q, 0, precision, variant, sample_rate)
+    prm = _params(dims, ranks, p, q, 0, precision, variant, sample_rate, truncation)
     code = _dtype_code(torch, dtype)
     if tr_ranks is not None:
         tr = (ctypes.c_int64 * len(tr_ranks))(*tr_ranks)
@@ -192,12 +199,13 @@ def workspace_bytes(dims, ranks, p, q, dtype, precision="plain", tr_ranks=None, 
 
 
 def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_err=True, stream=None,
-           workspace=None, variant="krylov", sample_rate=1.0):
+           workspace=None, variant="krylov", sample_rate=1.0, truncation="independent"):
     """rBKI-TK (Alg. 2).  Returns (core, [U^(1), ..., U^(N)], rel_err or None).
     variant "power": each factor from the power iterate (XX^T)^q W alone
     (the power-iteration comparison of Sec. 3.1).  sample_rate < 1: each
     mode's Krylov basis from that fraction of the unfolding's columns
-    (Sec. 3.1)."""
+    (Sec. 3.1).  truncation "sequential": each mode's factor from the tensor
+    already projected on the earlier modes (ST-HOSVD form)."""
     torch = _torch()
     lib = load_library()
     X = _as_input(torch, X)
@@ -205,7 +213,7 @@ def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_er
     if out_dtype is None:
         out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
     ocode = _dtype_code(torch, out_dtype)
-    prm = _params(X.shape, ranks, p, q, seed, precision, variant, sample_rate)
+    prm = _params(X.shape, ranks, p, q, seed, precision, variant, sample_rate, truncation)
     need = lib.rbki_tucker_workspace(ctypes.byref(prm), code)
     if need == 0:
         _check(lib.rbki_tucker(None, code, ctypes.byref(prm), None, None, ocode, None, 0, None, None))
@@ -220,8 +228,37 @@ def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_er
     return core, factors, (err.value if rel_err else None)
 
 
+def tucker_adaptive(X, ranks, p=5, max_q=20, fit_tol=1e-3, seed=0, precision="plain", out_dtype=None,
+                    stream=None, sample_rate=1.0):
+    """rBKI-TK with q chosen by the stopping rule of Sec. 4 (stop once the
+    Fit changes by at most fit_tol between Krylov steps).  Returns
+    (core, [U^(1), ..., U^(N)], rel_err, q_used)."""
+    torch = _torch()
+    lib = load_library()
+    X = _as_input(torch, X)
+    code = _dtype_code(torch, X.dtype)
+    if out_dtype is None:
+        out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
+    ocode = _dtype_code(torch, out_dtype)
+    prm = _params(X.shape, ranks, p, max_q, seed, precision, "krylov", sample_rate)
+    need = lib.rbki_tucker_adaptive_workspace(ctypes.byref(prm), code)
+    if need == 0:
+        _check(lib.rbki_tucker_adaptive(None, code, ctypes.byref(prm), float(fit_tol), None, None, ocode, None, 0,
+                                        None, None, None))
+    ws = _workspace(torch, X.device, need)
+    core = torch.empty(tuple(int(r) for r in ranks), dtype=out_dtype, device=X.device)
+    factors = [torch.empty((int(I), int(R)), dtype=out_dtype, device=X.device) for I, R in zip(X.shape, ranks)]
+    fptr = (ctypes.c_void_p * len(factors))(*[f.data_ptr() for f in factors])
+    err = ctypes.c_double(0.0)
+    qu = ctypes.c_int(0)
+    _check(lib.rbki_tucker_adaptive(ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm), float(fit_tol),
+                                    ctypes.c_void_p(core.data_ptr()), fptr, ocode, ctypes.c_void_p(ws.data_ptr()),
+                                    ws.numel(), ctypes.byref(err), ctypes.byref(qu), _stream(torch, stream)))
+    return core, factors, err.value, qu.value
+
+
 def htr(X, tucker_ranks, tr_ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_err=True,
-        stream=None, variant="krylov", sample_rate=1.0):
+        stream=None, variant="krylov", sample_rate=1.0, truncation="independent"):
     """rBKI-TK-TR (Alg. 3, TR-SVD branch).  Returns ([X_1, ..., X_N], rel_err or None)."""
     torch = _torch()
     lib = load_library()
@@ -231,7 +268,7 @@ def htr(X, tucker_ranks, tr_ranks, p=5, q=2, seed=0, precision="plain", out_dtyp
         out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
     ocode = _dtype_code(torch, out_dtype)
     N = X.dim()
-    prm = _params(X.shape, tucker_ranks, p, q, seed, precision, variant, sample_rate)
+    prm = _params(X.shape, tucker_ranks, p, q, seed, precision, variant, sample_rate, truncation)
     tr = (ctypes.c_int64 * N)(*[int(v) for v in tr_ranks])
     need = lib.rbki_htr_workspace(ctypes.byref(prm), code, tr)
     if need == 0:
@@ -375,7 +412,7 @@ class Server:
         return self._lib.rbki_server_request_bytes(ctypes.byref(prm), _dtype_code(self._torch, dtype))
 
     def submit(self, X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, variant="krylov",
-               sample_rate=1.0):
+               sample_rate=1.0, truncation="independent"):
         torch = self._torch
         if self._h is None:
             raise RuntimeError("server is closed")
@@ -384,7 +421,7 @@ class Server:
         if out_dtype is None:
             out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
         ocode = _dtype_code(torch, out_dtype)
-        prm = _params(X.shape, ranks, p, q, seed, precision, variant, sample_rate)
+        prm = _params(X.shape, ranks, p, q, seed, precision, variant, sample_rate, truncation)
         core = torch.empty(tuple(int(r) for r in ranks), dtype=out_dtype, device=X.device)
         factors = [torch.empty((int(I), int(R)), dtype=out_dtype, device=X.device) for I, R in zip(X.shape, ranks)]
         fptr = (ctypes.c_void_p * len(factors))(*[f.data_ptr() for f in factors])

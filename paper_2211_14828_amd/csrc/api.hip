@@ -137,6 +137,7 @@ struct Plan {
   bool concurrent = false;   // runs beside other solves on the device (request server)
   bool power = false;        // power iteration: only the last block spans the factor's space
   double rate = 1.0;         // column sampling rate omega (Sec. 3.1)
+  bool sequential = false;   // sequential truncation (ST-HOSVD form)
   bool any_sampled = false;
   int64_t maxM = 0;          // largest column sample
   size_t ybytes = 0;         // largest gathered sample
@@ -196,6 +197,9 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
   if (prm->variant != RBKI_KRYLOV && prm->variant != RBKI_POWER)
     return fail(RBKI_E_INVALID, "unknown variant %d", prm->variant);
   P.power = prm->variant == RBKI_POWER;
+  if (prm->truncation != RBKI_INDEPENDENT && prm->truncation != RBKI_SEQUENTIAL)
+    return fail(RBKI_E_INVALID, "unknown truncation %d", prm->truncation);
+  P.sequential = prm->truncation == RBKI_SEQUENTIAL;
   {
     const double rate = prm->sample_rate == 0.0 ? 1.0 : prm->sample_rate;
     if (!(rate > 0.0 && rate <= 1.0))
@@ -239,6 +243,9 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
       return fail(RBKI_E_INVALID, "ranks[%d] = %lld outside [1, min(I_n, J_n)]", n, (long long)g.R);
     g.m = sample_count(g.J, P.rate);
     g.sampled = g.m < g.J;
+    if (g.m < g.R)
+      return fail(RBKI_E_INVALID, "sample_rate %g leaves %lld columns in mode %d, fewer than its rank %lld",
+                  P.rate, (long long)g.m, n, (long long)g.R);
     g.S = std::min<int64_t>(std::min<int64_t>(g.R + P.p, g.I), g.m);   // Sec. 2.3, Sec. 4.1
     g.Sp = P.power ? g.S : g.S * (P.q + 1);
     if (g.Sp > 1200) return fail(RBKI_E_UNSUPPORTED, "Krylov width %lld > 1200 (mode %d)", (long long)g.Sp, n);
@@ -429,7 +436,10 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
     b.lam[n] = (double*)ar.take((size_t)Sp * 8);
     b.Vt[n] = (double*)ar.take((size_t)Sp * Sp * 8);
     const int64_t R = P.m[n].R;
-    b.jwork[n] = ar.take(std::max(jacobi_work_bytes(Sp), eig_top_ok(Sp, R) ? eig_top_work_bytes(Sp, R) : (size_t)0));
+    // the leading-eigenpair solver takes Z up to 512 wide (also the narrower
+    // Z of the first steps of an adaptive solve)
+    const int64_t et = std::min<int64_t>(Sp, 512);
+    b.jwork[n] = ar.take(std::max(jacobi_work_bytes(Sp), eig_top_ok(et, R) ? eig_top_work_bytes(et, R) : (size_t)0));
   }
   b.info = (int*)ar.take(counters_bytes(P));
   b.used = b.info + 64;
@@ -583,6 +593,51 @@ rbki_status run_mode_heavy(const Plan& P, const Buffers& b, int lane, const void
   return RBKI_OK;
 }
 
+// Alg. 1, block 0: Q_0 = orth(W) from W^T in the lane's Yt.  The first pass
+// of every block's CholeskyQR2 also keeps the basis at most I_n wide: once
+// it spans the whole space the later blocks are rounding noise and are
+// dropped whatever their norm.
+rbki_status krylov_block0(const Plan& P, const Buffers& b, const Lane& L, int n, hipStream_t st) {
+  const ModeGeom& g = P.m[n];
+  const int64_t I = g.I, S = g.S;
+  int* used = b.used + (size_t)n * (P.q + 2);
+  HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
+  HIPCHK(chol_orth(L.Yt, L.Ytmp, S, I, L.G, L.L, L.flags, L.ref2, TAU_REL, TAU_ABS, st, DimBudget{used, used + 1, I}));
+  HIPCHK(chol_orth(L.Ytmp, b.Qt[n], S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
+  return RBKI_OK;
+}
+
+// Alg. 1, Krylov step j >= 1: block j of the basis from (X X^T) Q_{j-1} (Ck
+// is X X^T, or Y Y^T of a sampled mode), projected off the earlier blocks
+// twice and orthonormalised.  The product C Q_{j-1} is formed into the
+// lane's Yt and, when CQ is given, kept as rows (j-1) S.. of CQ; with from_cq
+// it is taken from there instead (formed earlier with the same C).
+rbki_status krylov_step(const Plan& P, const Buffers& b, const Lane& L, int n, int j, const double* Ck, double* CQ,
+                        bool from_cq, hipStream_t st) {
+  const ModeGeom& g = P.m[n];
+  const int64_t I = g.I, S = g.S;
+  double* Qt = b.Qt[n];
+  int* used = b.used + (size_t)n * (P.q + 2);
+  const int64_t m = S * j;                     // rows of the basis so far
+  const double* Qlast = Qt + (m - S) * I;
+  if (from_cq) {
+    HIPCHK(copy_rows_f64(L.Yt, I, CQ + (m - S) * I, I, S, I, st));
+  } else {
+    // Y_j^T = Q_{j-1}^T C  (C symmetric)
+    HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qlast, I, Ck, I, 0.0, L.Yt, I, st));
+    if (CQ) HIPCHK(copy_rows_f64(CQ + (m - S) * I, I, L.Yt, I, S, I, st));
+  }
+  HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
+  for (int pass = 0; pass < 2; ++pass) {       // remove earlier blocks, twice
+    HIPCHK(dgemm(0, 1, S, m, I, 1.0, L.Yt, I, Qt, I, 0.0, L.Pm, m, st));
+    HIPCHK(dgemm(0, 0, S, I, m, -1.0, L.Pm, m, Qt, I, 1.0, L.Yt, I, st));
+  }
+  HIPCHK(chol_orth(L.Yt, L.Ytmp, S, I, L.G, L.L, L.flags, L.ref2, TAU_REL, TAU_ABS, st,
+                   DimBudget{used + j, used + j + 1, I}));
+  HIPCHK(chol_orth(L.Ytmp, Qt + m * I, S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
+  return RBKI_OK;
+}
+
 // Alg. 2, steps 2-3 of mode n after run_mode_heavy: the Krylov basis from C
 // and W in the scratch set, and Z.
 rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, bool with_factor, hipStream_t st) {
@@ -593,13 +648,8 @@ rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, boo
   double* Qt = b.Qt[n];
   // the Krylov products: with the sample's Y Y^T for a sampled mode
   const double* Ck = g.sampled ? L.CY : L.C;
-  // block 0: Q_0 = orth(W).  The first pass of every block's CholeskyQR2
-  // also keeps the basis at most I_n wide: once it spans the whole space the
-  // later blocks are rounding noise and are dropped whatever their norm.
-  int* used = b.used + (size_t)n * (P.q + 2);
-  HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
-  HIPCHK(chol_orth(L.Yt, L.Ytmp, S, I, L.G, L.L, L.flags, L.ref2, TAU_REL, TAU_ABS, st, DimBudget{used, used + 1, I}));
-  HIPCHK(chol_orth(L.Ytmp, Qt, S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
+  rbki_status s = krylov_block0(P, b, L, n, st);
+  if (s != RBKI_OK) return s;
   if (P.power) {
     // power iteration (Sec. 3.1): Q_j = orth(C Q_{j-1}), each step's block
     // replacing the last, with the same drop rule relative to the step's
@@ -616,19 +666,8 @@ rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, boo
     return RBKI_OK;
   }
   for (int j = 1; j <= P.q; ++j) {
-    const int64_t m = S * j;                     // rows of the basis so far
-    const double* Qlast = Qt + (m - S) * I;
-    // Y_j^T = Q_{j-1}^T C  (C symmetric)
-    HIPCHK(dgemm(0, 0, S, I, I, 1.0, Qlast, I, Ck, I, 0.0, L.Yt, I, st));
-    HIPCHK(copy_rows_f64(L.CQt + (m - S) * I, I, L.Yt, I, S, I, st));
-    HIPCHK(row_norms2(L.Yt, S, I, L.ref2, st));
-    for (int pass = 0; pass < 2; ++pass) {       // remove earlier blocks, twice
-      HIPCHK(dgemm(0, 1, S, m, I, 1.0, L.Yt, I, Qt, I, 0.0, L.Pm, m, st));
-      HIPCHK(dgemm(0, 0, S, I, m, -1.0, L.Pm, m, Qt, I, 1.0, L.Yt, I, st));
-    }
-    HIPCHK(chol_orth(L.Yt, L.Ytmp, S, I, L.G, L.L, L.flags, L.ref2, TAU_REL, TAU_ABS, st,
-                     DimBudget{used + j, used + j + 1, I}));
-    HIPCHK(chol_orth(L.Ytmp, Qt + m * I, S, I, L.G, L.L, L.flags, nullptr, TAU_REL, 0.0, st));
+    s = krylov_step(P, b, L, n, j, Ck, L.CQt, false, st);
+    if (s != RBKI_OK) return s;
   }
   if (!with_factor) return RBKI_OK;
   // C Q_q, then Z = Q^T (C Q) (Alg. 2, step 3); a sampled mode's earlier
@@ -667,6 +706,30 @@ rbki_status factor_one(const Plan& P, const Buffers& b, int n, hipStream_t st) {
     HIPCHK(eig_top_batched(1, &Z, &sn, &rn, &lam, &Vt, &w, &info, st, false));
   }
   HIPCHK(dgemm(0, 0, g.R, g.I, g.Sp, 1.0, b.Vt[n], g.Sp, b.Qt[n], g.I, 0.0, b.Ut64[n], g.I, st));
+  HIPCHK(canonical_sign_rows(b.Ut64[n], g.R, g.I, st));
+  return RBKI_OK;
+}
+
+// Alg. 2, steps 4-5 for mode n alone, on the caller's stream (the stages of
+// the sequential form): the R leading eigenpairs of Z (the Jacobi solver
+// beyond that solver's sizes), U^T = Vt(1:R, :) Q^T, sign rule.
+rbki_status factor_single(const Plan& P, const Buffers& b, int n, hipStream_t st, int64_t width = 0) {
+  const ModeGeom& g = P.m[n];
+  const double* Z = b.Z[n];
+  int64_t sn = width > 0 ? width : g.Sp, rn = g.R;
+  double* lam = b.lam[n];
+  double* Vt = b.Vt[n];
+  void* w = b.jwork[n];
+  int* info = b.info + 2 * n;
+  {
+    ProfScope ps("eig", st);
+    if (eig_top_ok(sn, rn)) {
+      HIPCHK(eig_top_batched(1, &Z, &sn, &rn, &lam, &Vt, &w, &info, st, !P.concurrent));
+    } else {
+      HIPCHK(jacobi_eig_batched(1, &Z, &sn, &lam, &Vt, &w, &info, 40, st, P.concurrent && sn <= 192));
+    }
+  }
+  HIPCHK(dgemm(0, 0, g.R, g.I, sn, 1.0, b.Vt[n], sn, b.Qt[n], g.I, 0.0, b.Ut64[n], g.I, st));
   HIPCHK(canonical_sign_rows(b.Ut64[n], g.R, g.I, st));
   return RBKI_OK;
 }
@@ -745,6 +808,44 @@ rbki_status first_product(const Plan& P, const Buffers& b, const void* xsrc, hip
   return RBKI_OK;
 }
 
+// The explicit error of a Tucker model whose core (R_1 x ... x R_N, chain
+// element type) is in chain buffer `which`: H = G x_2 U2 ... x_N UN through
+// the chain buffers, then sum (x - U^(1) H)^2 and sum x^2 over X_(0) into
+// sums (device, 2 doubles), copied to sums_host.
+rbki_status reconstruct_error(const Plan& P, const Buffers& b, const void* X, int which, double* sums,
+                              double* sums_host, hipStream_t st) {
+  void* bufs[2] = {b.chainA, b.chainB};
+  int64_t cur[8];
+  for (int n = 0; n < P.N; ++n) cur[n] = P.ranks[n];
+  void* src = bufs[which];
+  int wsrc = which;
+  for (int n = 1; n < P.N; ++n) {
+    // expanding mode n: Y[a, i, b] = sum_r U[i, r] G[a, r, b]; launch_ttm
+    // contracts the middle index (here of length R) against the rows of an
+    // "Ut" whose rows are the output index, so U itself (I x R) is passed
+    int64_t A = 1, B = 1;
+    for (int k = 0; k < n; ++k) A *= cur[k];
+    for (int k = n + 1; k < P.N; ++k) B *= cur[k];
+    const int64_t R = P.m[n].R, I = P.m[n].I;
+    HIPCHK(store_factor(b.Ut64[n], R, I, b.Uop, P.celem == E_F64 ? E_F64 : E_F32, st));
+    void* dst = bufs[wsrc ^ 1];
+    HIPCHK(launch_ttm(P.celem, src, A, R, B, b.Uop, I, dst, nullptr, 0, st));
+    src = dst;
+    wsrc ^= 1;
+    cur[n] = I;
+  }
+  // residual over X_(0) with U^(1)
+  {
+    const int64_t I0 = P.dims[0], J0 = P.T / P.dims[0], R0 = P.m[0].R;
+    HIPCHK(convert_tensor(E_F64, b.Ut64[0], P.celem, b.Uop, R0 * I0, st));
+    ProfScope ps("error", st);
+    // precision forms: U H from split bfloat16 operands, x and the sums exact
+    HIPCHK(launch_residual(P.xelem, X, P.celem, b.Uop, src, I0, J0, R0, sums, b.rpartial, 0, st, P.need_pad));
+  }
+  HIPCHK(hipMemcpyAsync(sums_host, sums, 16, hipMemcpyDeviceToHost, st));
+  return RBKI_OK;
+}
+
 // first_done: first_product has already been enqueued (on a stream that st
 // has joined).
 rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, const void* xsrc, void* core,
@@ -787,41 +888,15 @@ rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, c
     *core_out = b.gkeep;
   }
   if (!want_err) return RBKI_OK;
-  // reconstruction chain H = G x_2 U2 ... x_N UN into the other buffer(s)
-  void* src = G;
-  int wsrc = which;
-  for (int n = 1; n < P.N; ++n) {
-    // expanding mode n: Y[a, i, b] = sum_r U[i, r] G[a, r, b] -> product with U^T^T: use Ut = U (I x R)
-    int64_t A = 1, B = 1;
-    for (int k = 0; k < n; ++k) A *= cur[k];
-    for (int k = n + 1; k < P.N; ++k) B *= cur[k];
-    const int64_t R = P.m[n].R, I = P.m[n].I;
-    // launch_ttm contracts the middle index of length "I" against Ut rows: here
-    // the middle index is R and the output length I, so pass U as an I x R
-    // "Ut" (rows = output index, k = r).
-    HIPCHK(store_factor(b.Ut64[n], R, I, b.Uop, P.celem == E_F64 ? E_F64 : E_F32, st));
-    void* dst = bufs[wsrc ^ 1];
-    HIPCHK(launch_ttm(P.celem, src, A, R, B, b.Uop, I, dst, nullptr, 0, st));
-    src = dst;
-    wsrc ^= 1;
-    cur[n] = I;
-  }
-  // residual over X_(0) with U^(1)
-  {
-    const int64_t I0 = P.dims[0], J0 = P.T / P.dims[0], R0 = P.m[0].R;
-    HIPCHK(convert_tensor(E_F64, b.Ut64[0], P.celem, b.Uop, R0 * I0, st));
-    ProfScope ps("error", st);
-    // precision forms: U H from split bfloat16 operands, x and the sums exact
-    HIPCHK(launch_residual(P.xelem, X, P.celem, b.Uop, src, I0, J0, R0, b.sums, b.rpartial, 0, st, P.need_pad));
-  }
-  HIPCHK(hipMemcpyAsync(sums_host, b.sums, 16, hipMemcpyDeviceToHost, st));
   (void)ce;
-  return RBKI_OK;
+  return reconstruct_error(P, b, X, which, b.sums, sums_host, st);
 }
 
 }  // namespace
 
 // ====================================================================== ABI
+
+size_t tucker_bytes(const rbki_params* prm, int xtype, const Plan& P);
 
 extern "C" {
 
@@ -987,7 +1062,7 @@ int64_t rbki_basis_rows(const rbki_params* prm, int xtype, int mode) {
 size_t rbki_tucker_workspace(const rbki_params* prm, int xtype) {
   Plan P;
   if (make_plan(prm, xtype, P) != RBKI_OK) return 0;
-  return plan_bytes(P);
+  return tucker_bytes(prm, xtype, P);
 }
 
 }  // extern "C"
@@ -1084,6 +1159,264 @@ static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, 
   return s;
 }
 
+// ------------------------------------------------------------ sequential truncation
+// Stage n of the sequential form runs mode n of Y_{n-1} (Y_0 = X) with the
+// same kernels as an independent-mode solve of that tensor, then forms
+// Y_n = Y_{n-1} x_n U^(n)T.  Workspace: the factors, the core, the error sums
+// and the stage status kept for the whole solve; two buffers for the
+// successive Y; one region reused by every stage's scratch (and, at the end,
+// by the reconstruction of the error).
+struct SeqLayout {
+  Plan st[8];
+  int64_t sdims[8][8];       // dims of each stage's tensor
+  rbki_params sp[8];         // each stage's problem statement
+  int yelem = E_F32;         // element type of the intermediates
+  size_t fac[8] = {}, gkeep = 0, sums = 0, info = 0, ya = 0, yb = 0, stage = 0, stage_bytes = 0, total = 0;
+};
+
+rbki_status seq_layout(const rbki_params* prm, int xtype, const Plan& P0, SeqLayout& L) {
+  L.yelem = P0.xelem == E_F64 ? E_F64 : E_F32;
+  const int yt = L.yelem == E_F64 ? RBKI_F64 : RBKI_F32;
+  int64_t cur[8];
+  for (int n = 0; n < P0.N; ++n) cur[n] = P0.dims[n];
+  int64_t ymax = 1;
+  for (int n = 0; n < P0.N; ++n) {
+    for (int k = 0; k < P0.N; ++k) L.sdims[n][k] = cur[k];
+    L.sp[n] = *prm;
+    L.sp[n].dims = L.sdims[n];
+    L.sp[n].truncation = RBKI_INDEPENDENT;
+    if (n > 0) L.sp[n].precision = RBKI_PLAIN;
+    rbki_status s = make_plan(&L.sp[n], n == 0 ? xtype : yt, L.st[n]);
+    if (s != RBKI_OK) return s;
+    L.st[n].concurrent = P0.concurrent;
+    L.stage_bytes = std::max(L.stage_bytes, plan_bytes(L.st[n]));
+    cur[n] = P0.ranks[n];
+    int64_t t = 1;
+    for (int k = 0; k < P0.N; ++k) t *= cur[k];
+    ymax = std::max(ymax, t);
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) { off = (off + 255) & ~(size_t)255; size_t o = off; off += bytes; return o; };
+  for (int n = 0; n < P0.N; ++n) L.fac[n] = take((size_t)P0.m[n].R * P0.m[n].I * 8);
+  int64_t nc = 1;
+  for (int n = 0; n < P0.N; ++n) nc *= P0.ranks[n];
+  L.gkeep = take((size_t)nc * 8);
+  L.sums = take(64);
+  L.info = take(256);
+  L.ya = take((size_t)ymax * elem_size(L.yelem));
+  L.yb = take((size_t)ymax * elem_size(L.yelem));
+  L.stage = take(L.stage_bytes);
+  L.total = off + 256;
+  return RBKI_OK;
+}
+
+// The whole sequential solve on `st`.  On return b holds the factors (Ut64)
+// and the error sums, *core_chain the core in the chain element type of P0
+// (for Alg. 3), hr the sums and the solver status (copied when st reaches
+// them).
+rbki_status sequential_enqueue(const void* X, const rbki_params* prm, int xtype, const Plan& P0, void* core,
+                               void* const* factors, int out_type, char* ws, bool want_err, Buffers& b,
+                               void** core_chain, HostResult* hr, hipStream_t st) {
+  SeqLayout L;
+  rbki_status s = seq_layout(prm, xtype, P0, L);
+  if (s != RBKI_OK) return s;
+  double* fac[8];
+  for (int n = 0; n < P0.N; ++n) fac[n] = (double*)(ws + L.fac[n]);
+  int* info = (int*)(ws + L.info);
+  HIPCHK(fill_zero(info, 256, st));
+  void* ybuf[2] = {ws + L.ya, ws + L.yb};
+  const void* src = X;
+  int src_elem = P0.xelem;
+  for (int n = 0; n < P0.N; ++n) {
+    const Plan& Pn = L.st[n];
+    Arena ar(ws + L.stage, L.stage_bytes);
+    Buffers bn;
+    carve(Pn, ar, bn);
+    dgemm_set_scratch(bn.ln[0].dscratch, kDgemmScratch);
+    if (Pn.need_pad) {
+      ProfScope ps("convert", st);
+      s = convert_input(Pn, bn, src, st);
+      if (s != RBKI_OK) return s;
+    }
+    HIPCHK(fill_zero(bn.info, counters_bytes(Pn), st));
+    s = run_mode(Pn, bn, 0, src, n, true, st);
+    if (s != RBKI_OK) return s;
+    s = factor_single(Pn, bn, n, st);
+    if (s != RBKI_OK) return s;
+    const ModeGeom& g = Pn.m[n];
+    HIPCHK(copy_rows_f64(fac[n], g.I, bn.Ut64[n], g.I, g.R, g.I, st));
+    HIPCHK(hipMemcpyAsync(info + 2 * n, bn.info + 2 * n, 2 * sizeof(int), hipMemcpyDeviceToDevice, st));
+    // Y_n = Y_{n-1} x_n U^(n)T, in float32 (float64 for a float64 X)
+    HIPCHK(convert_tensor(E_F64, fac[n], src_elem, bn.Uop, g.R * g.I, st));
+    void* dst = ybuf[n & 1];
+    {
+      ProfScope ps("ttm", st);
+      HIPCHK(launch_ttm(src_elem, src, g.A, g.I, g.B, bn.Uop, g.R, dst, nullptr, 0, st));
+    }
+    src = dst;
+    src_elem = L.yelem;
+  }
+  // the core is Y_N; its copy in the chain element type for Alg. 3
+  int64_t nc = 1;
+  for (int n = 0; n < P0.N; ++n) nc *= P0.ranks[n];
+  if (core) HIPCHK(convert_tensor(L.yelem, src, dtype_elem(out_type), core, nc, st));
+  for (int n = 0; n < P0.N; ++n)
+    if (factors && factors[n])
+      HIPCHK(store_factor(fac[n], P0.m[n].R, P0.m[n].I, factors[n], dtype_elem(out_type), st));
+  void* gk = ws + L.gkeep;
+  HIPCHK(convert_tensor(L.yelem, src, P0.celem, gk, nc, st));
+  if (core_chain) *core_chain = gk;
+  // the error of the returned model, with the first stage's buffers
+  Arena ar(ws + L.stage, L.stage_bytes);
+  carve(P0, ar, b);
+  for (int n = 0; n < P0.N; ++n) b.Ut64[n] = fac[n];
+  b.sums = (double*)(ws + L.sums);
+  b.info = info;
+  if (want_err) {
+    HIPCHK(convert_tensor(P0.celem, gk, P0.celem, b.chainA, nc, st));
+    s = reconstruct_error(P0, b, X, 0, b.sums, hr->sums, st);
+    if (s != RBKI_OK) return s;
+  }
+  HIPCHK(hipMemcpyAsync(hr->info, info, 2 * P0.N * sizeof(int), hipMemcpyDeviceToHost, st));
+  hr->nmodes = P0.N;
+  return RBKI_OK;
+}
+
+// Workspace of a decomposition: the independent form's plan, or the
+// sequential form's layout.
+size_t tucker_bytes(const rbki_params* prm, int xtype, const Plan& P) {
+  if (!P.sequential) return plan_bytes(P);
+  SeqLayout L;
+  if (seq_layout(prm, xtype, P, L) != RBKI_OK) return 0;
+  return L.total;
+}
+
+// ------------------------------------------------------------ adaptive q
+// rBKI-TK with q chosen by the stopping rule of Sec. 4: after every Krylov
+// step t (all modes), the rank-k approximation and its Fit to X; stop once
+// two consecutive Fits differ by at most fit_tol.  Each mode's Gram matrix
+// (and a sampled mode's Y Y^T) and the products C Q of its basis blocks are
+// kept across the steps, so X is read by the sketch / Gram pass once, and by
+// the core and the error once per step.
+struct AdaptiveLayout {
+  size_t C[8] = {}, CY[8] = {}, CQ[8] = {};
+  size_t total = 0;
+};
+
+int adaptive_q(const rbki_params* prm, const Plan& P) {
+  // beyond ceil(I_n / S_n) steps every basis spans its mode space, and the
+  // Fit stops changing: the rule stops there at the latest
+  int64_t qmax = 0;
+  for (int n = 0; n < P.N; ++n) qmax = std::max<int64_t>(qmax, ceil_div(P.m[n].I, P.m[n].S));
+  int64_t q = std::min<int64_t>(prm->power, qmax);
+  for (int n = 0; n < P.N; ++n) q = std::min<int64_t>(q, 1200 / P.m[n].S - 1);
+  return (int)std::max<int64_t>(q, 0);
+}
+
+rbki_status adaptive_plan(const rbki_params* prm, int xtype, Plan& P, rbki_params& pa, AdaptiveLayout& L) {
+  Plan P0;
+  rbki_status s = make_plan(prm, xtype, P0);
+  if (s != RBKI_OK) return s;
+  if (P0.power || P0.sequential)
+    return fail(RBKI_E_UNSUPPORTED, "the stopping rule is built for the Krylov variant with independent modes");
+  pa = *prm;
+  pa.power = adaptive_q(prm, P0);
+  s = make_plan(&pa, xtype, P);
+  if (s != RBKI_OK) return s;
+  size_t off = plan_bytes(P);
+  auto take = [&](size_t bytes) { off = (off + 255) & ~(size_t)255; size_t o = off; off += bytes; return o; };
+  for (int n = 0; n < P.N; ++n) {
+    const ModeGeom& g = P.m[n];
+    L.C[n] = take((size_t)g.I * g.I * 8);
+    if (g.sampled) L.CY[n] = take((size_t)g.I * g.I * 8);
+    L.CQ[n] = take((size_t)g.Sp * g.I * 8);
+  }
+  L.total = off + 256;
+  return RBKI_OK;
+}
+
+rbki_status adaptive_impl(const void* X, int xtype, const rbki_params* prm, double fit_tol, void* core,
+                          void* const* factors, int out_type, void* workspace, size_t ws_bytes, double* rel_err,
+                          int* q_used, hipStream_t st) {
+  Plan P;
+  rbki_params pa;
+  AdaptiveLayout AL;
+  rbki_status s = adaptive_plan(prm, xtype, P, pa, AL);
+  if (s != RBKI_OK) return s;
+  if (!X) return fail(RBKI_E_INVALID, "X is NULL");
+  if (out_type != RBKI_F64 && out_type != RBKI_F32) return fail(RBKI_E_INVALID, "out_type must be F64 or F32");
+  if (!(fit_tol == fit_tol)) return fail(RBKI_E_INVALID, "fit_tol is NaN");
+  if (!workspace || ws_bytes < AL.total)
+    return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, AL.total);
+  char* ws = (char*)workspace;
+  Arena ar(workspace, ws_bytes);
+  Buffers b;
+  carve(P, ar, b);
+  const Lane& L0 = b.ln[0];
+  if (P.need_pad) {
+    ProfScope ps("convert", st);
+    s = convert_input(P, b, X, st);
+    if (s != RBKI_OK) return s;
+  }
+  HIPCHK(fill_zero(b.info, counters_bytes(P), st));
+  double *Cm[8], *CYm[8], *CQm[8];
+  for (int n = 0; n < P.N; ++n) {
+    const ModeGeom& g = P.m[n];
+    Cm[n] = (double*)(ws + AL.C[n]);
+    CYm[n] = g.sampled ? (double*)(ws + AL.CY[n]) : nullptr;
+    CQm[n] = (double*)(ws + AL.CQ[n]);
+    // the Gram pass (and the sample's), kept for every step; block 0
+    s = run_mode_heavy(P, b, 0, X, n, st);
+    if (s != RBKI_OK) return s;
+    HIPCHK(copy_rows_f64(Cm[n], g.I, L0.C, g.I, g.I, g.I, st));
+    if (g.sampled) HIPCHK(copy_rows_f64(CYm[n], g.I, L0.CY, g.I, g.I, g.I, st));
+    s = krylov_block0(P, b, L0, n, st);
+    if (s != RBKI_OK) return s;
+  }
+  dgemm_set_scratch(L0.dscratch, kDgemmScratch);
+  HostResult hr;
+  double fit_prev = 0.0, err = 0.0;
+  int t = 0;
+  for (;; ++t) {
+    for (int n = 0; n < P.N; ++n) {
+      const ModeGeom& g = P.m[n];
+      const int64_t I = g.I, S = g.S, m = S * (t + 1);
+      if (t > 0) {
+        // Krylov step t (Alg. 1); a mode that is not sampled takes C Q_{t-1}
+        // from the products kept for Z
+        s = krylov_step(P, b, L0, n, t, g.sampled ? CYm[n] : Cm[n], g.sampled ? nullptr : CQm[n], !g.sampled, st);
+        if (s != RBKI_OK) return s;
+      }
+      // C Q_t, then Z_t = Q^T C Q over the t + 1 blocks (Alg. 2, step 3)
+      HIPCHK(dgemm(0, 0, S, I, I, 1.0, b.Qt[n] + (m - S) * I, I, Cm[n], I, 0.0, CQm[n] + (m - S) * I, I, st));
+      HIPCHK(dgemm(0, 1, m, m, I, 1.0, b.Qt[n], I, CQm[n], I, 0.0, b.Z[n], m, st));
+      s = factor_single(P, b, n, st, m);
+      if (s != RBKI_OK) return s;
+    }
+    void* gk = nullptr;
+    s = run_core_and_error(P, b, X, X, nullptr, dtype_elem(out_type), true, hr.sums, &gk, st);
+    if (s != RBKI_OK) return s;
+    HIPCHK(hipMemcpyAsync(hr.info, b.info, 2 * P.N * sizeof(int), hipMemcpyDeviceToHost, st));
+    hr.nmodes = P.N;
+    HIPCHK(hipStreamSynchronize(st));
+    s = finish_result(hr, &err);
+    if (s != RBKI_OK) return s;
+    const double fit = 1.0 - err;     // Fit of Sec. 4, as a fraction, against X
+    if ((t > 0 && fabs(fit - fit_prev) <= fit_tol) || t >= P.q) break;
+    fit_prev = fit;
+  }
+  int64_t nc = 1;
+  for (int n = 0; n < P.N; ++n) nc *= P.ranks[n];
+  if (core) HIPCHK(convert_tensor(P.celem, b.gkeep, dtype_elem(out_type), core, nc, st));
+  for (int n = 0; n < P.N; ++n)
+    if (factors && factors[n])
+      HIPCHK(store_factor(b.Ut64[n], P.m[n].R, P.m[n].I, factors[n], dtype_elem(out_type), st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (rel_err) *rel_err = err;
+  if (q_used) *q_used = t;
+  return RBKI_OK;
+}
+
 static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
                         int out_type, void* workspace, size_t ws_bytes, double* rel_err, hipStream_t st, Plan& P,
                         Buffers& b, void** core_chain, HostResult* async_res) {
@@ -1092,9 +1425,19 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   P.concurrent = async_res != nullptr;        // enqueued by the request server
   if (!X) return fail(RBKI_E_INVALID, "X is NULL");
   if (out_type != RBKI_F64 && out_type != RBKI_F32) return fail(RBKI_E_INVALID, "out_type must be F64 or F32");
-  const size_t need = plan_bytes(P);
+  const size_t need = tucker_bytes(prm, xtype, P);
+  if (need == 0) return fail(RBKI_E_INVALID, "%s", g_err.c_str());
   if (!workspace || ws_bytes < need)
     return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
+  if (P.sequential) {
+    HostResult local;
+    HostResult* hr = async_res ? async_res : &local;
+    s = sequential_enqueue(X, prm, xtype, P, core, factors, out_type, (char*)workspace, rel_err || async_res, b,
+                           core_chain, hr, st);
+    if (s != RBKI_OK || async_res) return s;
+    HIPCHK(hipStreamSynchronize(st));
+    return finish_result(*hr, rel_err);
+  }
   Arena ar(workspace, ws_bytes);
   carve(P, ar, b);
   dgemm_set_scratch(b.ln[0].dscratch, kDgemmScratch);
@@ -1174,6 +1517,21 @@ rbki_status rbki_tucker(const void* X, int xtype, const rbki_params* prm, void* 
                      b, nullptr, nullptr);
 }
 
+size_t rbki_tucker_adaptive_workspace(const rbki_params* prm, int xtype) {
+  Plan P;
+  rbki_params pa;
+  AdaptiveLayout L;
+  if (adaptive_plan(prm, xtype, P, pa, L) != RBKI_OK) return 0;
+  return L.total;
+}
+
+rbki_status rbki_tucker_adaptive(const void* X, int xtype, const rbki_params* prm, double fit_tol, void* core,
+                                 void* const* factors, int out_type, void* workspace, size_t ws_bytes,
+                                 double* rel_err, int* q_used, void* stream) {
+  return adaptive_impl(X, xtype, prm, fit_tol, core, factors, out_type, workspace, ws_bytes, rel_err, q_used,
+                       (hipStream_t)stream);
+}
+
 // ---------------------------------------------------------------- Alg. 3
 static bool htr_sizes(const Plan& P, const int64_t* tr, int64_t* r) {
   // r[0..N]: r[0] = r_N closing rank, r[k] = tr[k-1]
@@ -1191,10 +1549,12 @@ size_t rbki_htr_workspace(const rbki_params* prm, int xtype, const int64_t* tr_r
   if (!htr_sizes(P, tr_ranks, r)) return 0;
   int64_t S[8];
   for (int n = 0; n < P.N; ++n) S[n] = P.ranks[n];
+  const size_t base = tucker_bytes(prm, xtype, P);
+  if (base == 0) return 0;
   size_t extra = 0;
   for (int n = 0; n < P.N; ++n) extra += ((size_t)r[n] * S[n] * r[n + 1] * 8 + 255) & ~(size_t)255;
   extra += tr_svd_work_bytes(P.N, S, r) + tr_gap2_work_bytes(P.N, S, r) + 1024;
-  return plan_bytes(P) + extra;
+  return base + extra;
 }
 
 rbki_status rbki_htr(const void* X, int xtype, const rbki_params* prm, const int64_t* tr_ranks,
@@ -1218,7 +1578,7 @@ rbki_status rbki_htr(const void* X, int xtype, const rbki_params* prm, const int
                   &Gchain, nullptr);
   if (s != RBKI_OK && s != RBKI_E_NOCONV) return s;
   // the remaining workspace after the Tucker plan
-  size_t off = (plan_bytes(P) + 255) & ~(size_t)255;
+  size_t off = (tucker_bytes(prm, xtype, P) + 255) & ~(size_t)255;
   char* base = (char*)workspace + off;
   int64_t S[8];
   for (int n = 0; n < P.N; ++n) S[n] = P.ranks[n];

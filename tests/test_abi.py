@@ -158,10 +158,29 @@ def test_sample_rate_is_validated_and_sizes_the_basis():
     prm.sample_rate = 0.01                                          # m = 15 columns of mode 0
     assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) > full
     assert lib.rbki_basis_rows(ctypes.byref(prm), 1, 0) == 33
-    prm.sample_rate = 0.002                                         # m = 3 < R + p: S = 3
-    assert lib.rbki_basis_rows(ctypes.byref(prm), 1, 0) == 9
+    prm.sample_rate = 0.005                                         # m = 8 < R + p in mode 0: S = 8
+    assert lib.rbki_basis_rows(ctypes.byref(prm), 1, 0) == 24
+    prm.sample_rate = 0.002                                         # m = 3 < R in mode 0: rejected
+    assert lib.rbki_basis_rows(ctypes.byref(prm), 1, 0) == 0
+    st = lib.rbki_tucker(ctypes.c_void_p(16), 1, ctypes.byref(prm), None, None, 1, None, 0, None, None)
+    assert st == 1 and "fewer than its rank" in lib.rbki_last_error().decode()
     for bad in (-0.5, 1.5, float("nan")):
         prm.sample_rate = bad
         st = lib.rbki_tucker(ctypes.c_void_p(16), 1, ctypes.byref(prm), None, None, 1, None, 0, None, None)
         assert st == 1 and "sample_rate" in lib.rbki_last_error().decode()
         assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) == 0
+
+
+def test_truncation_is_validated_and_sizes_its_workspace():
+    lib = rb.load_library()
+    prm = _params((40, 50, 30), (6, 6, 6), 5, 2, 0)
+    indep = lib.rbki_tucker_workspace(ctypes.byref(prm), 1)
+    prm.truncation = 1
+    seq = lib.rbki_tucker_workspace(ctypes.byref(prm), 1)
+    assert seq > indep > 0
+    tr = (ctypes.c_int64 * 3)(2, 2, 2)
+    assert lib.rbki_htr_workspace(ctypes.byref(prm), 1, tr) > seq
+    prm.truncation = 5
+    st = lib.rbki_tucker(ctypes.c_void_p(16), 1, ctypes.byref(prm), None, None, 1, None, 0, None, None)
+    assert st == 1 and "truncation" in lib.rbki_last_error().decode()
+    assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) == 0

@@ -491,3 +491,129 @@ def test_partial_columns_with_the_power_variant(env):
     _, facs, e_g = rb.tucker(Xg, (7, 6, 5), p=4, q=2, seed=78, variant="power", sample_rate=0.15)
     _, Us, e_o = rbki_tucker(X, (7, 6, 5), 4, 2, 78, variant="power", sample_rate=0.15)
     assert abs(e_g - e_o) / e_o <= 1e-10
+
+
+# ------------------------------------------------------------------ sequential truncation
+
+from oracle.rbki import rbki_tucker_sequential  # noqa: E402
+
+SEQUENTIAL = [
+    # dims, ranks, p, q, dtype, precision, variant, sampling rate
+    ((64, 64, 64), (8, 8, 8), 5, 2, "float64", "plain", "krylov", 1.0),
+    ((37, 45, 29), (4, 5, 3), 5, 2, "float64", "plain", "krylov", 1.0),
+    ((12, 10, 14, 9), (3, 4, 2, 3), 4, 2, "float64", "plain", "power", 1.0),
+    ((130, 70, 150), (10, 8, 12), 5, 2, "float32", "plain", "krylov", 1.0),
+    ((300, 40, 270), (12, 6, 10), 5, 2, "float32", "mixed_bf16", "krylov", 1.0),
+    ((600, 40, 530), (20, 6, 15), 10, 2, "float32", "mixed_fp8", "krylov", 1.0),
+    ((80, 60, 70), (8, 6, 7), 5, 2, "float64", "plain", "krylov", 0.2),
+    ((64, 50, 40), (6, 6, 6), 5, 1, "bfloat16", "plain", "krylov", 1.0),
+]
+
+
+@pytest.mark.parametrize("dims,ranks,p,q,dtype,prec,variant,rate", SEQUENTIAL)
+def test_sequential_truncation_matches_oracle(env, dims, ranks, p, q, dtype, prec, variant, rate):
+    torch, rb = env
+    seed = 3000 + len(dims) * 7 + sum(dims)
+    X = make_case(dims, ranks, dtype, "sequential", seed)
+    Xg = to_device(torch, X, dtype)
+    Xh = host_values(torch, Xg)
+    core, facs, e_g = rb.tucker(Xg, ranks, p=p, q=q, seed=seed + 1, precision=prec, out_dtype=torch.float64,
+                                variant=variant, sample_rate=rate, truncation="sequential")
+    G, Us, e_o, infos, _ = rbki_tucker_sequential(Xh, ranks, p, q, seed + 1, return_info=True, variant=variant,
+                                                  sample_rate=rate)
+    assert abs(e_g - e_o) / e_o <= TOL[(dtype, prec)], (e_g, e_o)
+    Ug = [f.cpu().numpy() for f in facs]
+    for n in range(len(dims)):
+        assert orthonormality_defect(Ug[n]) <= 1e-11
+    # the first stage is the independent form's first mode; where the gaps
+    # allow, every factor spans the oracle's space
+    for n in range(len(dims)):
+        if gap_ok(infos[n]["eigenvalues"], ranks[n]):
+            key = dtype if prec == "plain" else ("fp8" if prec == "mixed_fp8" else "bfloat16")
+            assert projector_distance(Ug[n], Us[n]) <= PROJ_TOL[key]
+    # the core is X x_n U^(n)T for the returned factors, and the reported
+    # error is the explicit residual of the returned model
+    Gref = project_core(Xh, Ug)
+    ctol = 1e-12 if dtype == "float64" else (2e-6 if prec == "plain" and dtype == "float32" else 5e-3)
+    assert fro(core.cpu().numpy() - Gref) <= ctol * fro(Gref)
+    e_explicit = fro(Xh - tucker_to_full(core.cpu().numpy(), Ug)) / fro(Xh)
+    assert abs(e_explicit - e_g) <= (1e-12 if dtype == "float64" else 1e-5) * e_explicit + 1e-14
+
+
+def test_sequential_htr_matches_oracle(env):
+    # Alg. 3 on top of the sequential form: the TR-SVD of its core
+    torch, rb = env
+    dims, tk, tr = (20, 18, 22, 16), (6, 6, 6, 6), (3, 3, 3, 3)
+    X, _ = synth.tensor_ring_data(dims, 3, seed=15, var=1.0 / 3)
+    X = synth.add_noise(X, 15.0, np.random.default_rng(16))
+    Xg = torch.from_numpy(X).cuda()
+    cores, e_g = rb.htr(Xg, tk, tr, p=4, q=2, seed=17, truncation="sequential", out_dtype=torch.float64)
+    from oracle.trsvd import tr_svd, attach_factors
+    G, Us, e_tk = rbki_tucker_sequential(X, tk, 4, 2, 17)
+    cc, _ = tr_svd(G, tr)
+    e_o = fro(X - tr_to_full(attach_factors(cc, Us))) / fro(X)
+    assert abs(e_g - e_o) / e_o <= 1e-10
+
+
+# ------------------------------------------------------------------ adaptive q (Sec. 4 stopping rule)
+
+from oracle.rbki import rbki_tucker_adaptive  # noqa: E402
+
+ADAPTIVE = [
+    # dims, ranks, p, dtype, precision, fit_tol, sampling rate
+    ((80, 70, 60), (6, 5, 4), 3, "float64", "plain", 1e-4, 1.0),
+    ((80, 70, 60), (6, 5, 4), 3, "float64", "plain", 1e-3, 1.0),
+    ((12, 10, 14, 9), (3, 4, 2, 3), 2, "float64", "plain", 1e-6, 1.0),
+    ((130, 70, 150), (10, 8, 12), 5, "float32", "plain", 1e-4, 1.0),
+    ((64, 64, 64), (8, 8, 8), 5, "float64", "plain", 1e-4, 0.2),
+]
+
+
+@pytest.mark.parametrize("dims,ranks,p,dtype,prec,tol,rate", ADAPTIVE)
+def test_adaptive_q_matches_oracle(env, dims, ranks, p, dtype, prec, tol, rate):
+    torch, rb = env
+    seed = 4000 + sum(dims)
+    Xc, rng = synth.orthonormal_tucker(dims, ranks, seed, factor_decay="inverse")
+    X = synth.add_noise(Xc, -3.0, rng).astype(np.float64 if dtype == "float64" else np.float32)
+    Xg = to_device(torch, X, dtype)
+    Xh = host_values(torch, Xg)
+    core, facs, e_g, q_g = rb.tucker_adaptive(Xg, ranks, p=p, max_q=20, fit_tol=tol, seed=seed + 1, precision=prec,
+                                              out_dtype=torch.float64, sample_rate=rate)
+    _, Us, e_o, q_o = rbki_tucker_adaptive(Xh, ranks, p, seed + 1, fit_tol=tol, max_q=20, sample_rate=rate)
+    assert q_g == q_o
+    assert abs(e_g - e_o) / e_o <= TOL[(dtype, prec)], (e_g, e_o)
+    if rate == 1.0:
+        # the same as the fixed-q solve with q = q_used, bit for bit
+        c2, f2, e2 = rb.tucker(Xg, ranks, p=p, q=q_g, seed=seed + 1, precision=prec, out_dtype=torch.float64)
+        assert e2 == e_g and torch.equal(c2, core)
+        for u, v in zip(f2, facs):
+            assert torch.equal(u, v)
+
+
+def test_adaptive_q_mixed_form(env):
+    # the fp8 form takes the stopping decision on its own Fits; its result is
+    # the fixed-q solve at the q it chose, and within the mixed forms' gate of
+    # the oracle at that q
+    torch, rb = env
+    dims, ranks = (600, 40, 530), (20, 6, 15)
+    Xc, rng = synth.orthonormal_tucker(dims, ranks, 77, factor_decay="inverse")
+    X = synth.add_noise(Xc, 0.0, rng).astype(np.float32)
+    Xg = torch.from_numpy(X).cuda()
+    core, facs, e_g, q_g = rb.tucker_adaptive(Xg, ranks, p=10, fit_tol=1e-3, seed=78, precision="mixed_fp8",
+                                              out_dtype=torch.float64)
+    assert 1 <= q_g <= 20
+    _, _, e_o = rbki_tucker(X.astype(np.float64), ranks, 10, q_g, 78)
+    assert abs(e_g - e_o) / e_o <= TOL[("float32", "mixed_fp8")]
+    c2, f2, e2 = rb.tucker(Xg, ranks, p=10, q=q_g, seed=78, precision="mixed_fp8", out_dtype=torch.float64)
+    assert e2 == e_g
+
+
+def test_adaptive_q_rejects_the_power_variant(env):
+    torch, rb = env
+    import ctypes
+    lib = rb.load_library()
+    prm = rb._params((20, 20, 20), (3, 3, 3), 5, 4, 0, "plain", "power")
+    assert lib.rbki_tucker_adaptive_workspace(ctypes.byref(prm), 1) == 0
+    st = lib.rbki_tucker_adaptive(ctypes.c_void_p(16), 1, ctypes.byref(prm), 1e-3, None, None, 1, None, 0, None,
+                                  None, None)
+    assert st == 5
