@@ -133,3 +133,89 @@ def test_core_level_error_equals_the_full_ring_error(dims, tk, tr):
     _, e_core, info = rbki_htr(X, tk, 3, 2, 9, tr, explicit_error="core")
     assert abs(e_full - e_core) <= 1e-12 * e_full
     assert info["core_gap2"] >= 0.0
+
+
+# ------------------------------------------------------------------ TR-ALS
+
+from oracle.trsvd import tr_als, als_design, als_update, cyclic_unfolding, rbki_htr_als  # noqa: E402
+
+
+def _ring(dims, r, snr, seed):
+    X, _ = synth.tensor_ring_data(dims, r, seed=seed, var=1.0 / r)
+    return synth.add_noise(X, snr, np.random.default_rng(seed + 1))
+
+
+def test_als_design_matrix_is_the_ring_with_an_indicator_core():
+    # column (a, b) of the design matrix of core k is the ring whose k-th core
+    # is the indicator of (a, b), read along any row of its cyclic unfolding
+    X = _ring((5, 4, 6, 3), 2, 10.0, 40)
+    cores, _ = tr_svd(X, (2, 3, 2, 2))
+    for k in range(4):
+        D = als_design(cores, k)
+        ra, S, rb = cores[k].shape
+        for a in range(ra):
+            for b in range(rb):
+                E = [c.copy() for c in cores]
+                E[k] = np.zeros((ra, S, rb))
+                E[k][a, :, b] = 1.0
+                col = cyclic_unfolding(tr_to_full(E), k)
+                assert np.allclose(col, col[0][None, :], atol=1e-14)
+                assert np.allclose(col[0], D[:, a * rb + b], atol=1e-12)
+
+
+def test_als_update_solves_its_least_squares_problem():
+    # normal equations hold after the update, and no perturbation of the
+    # updated core lowers the error
+    X = _ring((6, 5, 7, 4), 3, 5.0, 41)
+    cores, _ = tr_svd(X, (3, 2, 3, 2))
+    k = 2
+    cores[k] = als_update(X, cores, k)
+    D = als_design(cores, k)
+    Gk = cyclic_unfolding(X, k)
+    ra, S, rb = cores[k].shape
+    Zm = cores[k].transpose(1, 0, 2).reshape(S, ra * rb)
+    grad = D.T @ (D @ Zm.T - Gk.T)
+    assert np.abs(grad).max() <= 1e-10 * np.linalg.norm(D) ** 2 * np.linalg.norm(Gk)
+    e0 = fro(X - tr_to_full(cores))
+    rng = np.random.default_rng(0)
+    for _ in range(5):
+        P = [c.copy() for c in cores]
+        P[k] = P[k] + 1e-4 * rng.standard_normal(P[k].shape)
+        assert fro(X - tr_to_full(P)) >= e0 * (1 - 1e-12)
+
+
+def test_als_error_never_increases_and_starts_from_tr_svd():
+    X = _ring((10, 9, 11, 8), 3, 10.0, 42)
+    cores0, _ = tr_svd(X, (2, 2, 2, 2))
+    e_svd = fro(X - tr_to_full(cores0)) / fro(X)
+    cores, sweeps, errs = tr_als(X, (2, 2, 2, 2), fit_tol=1e-6, history=True)
+    assert errs[0] == e_svd
+    assert np.all(np.diff(errs) <= 1e-12 * errs[0])
+    assert errs[-1] < e_svd
+
+
+def test_als_stops_by_the_fit_rule():
+    X = _ring((8, 7, 9, 6), 3, 10.0, 43)
+    cores, sweeps, errs = tr_als(X, (2, 3, 2, 2), fit_tol=1e-4, history=True)
+    N = 4
+    fits = [1 - errs[0]] + [1 - errs[s * N] for s in range(1, sweeps + 1)]
+    assert abs(fits[sweeps] - fits[sweeps - 1]) <= 1e-4
+    assert all(abs(fits[s] - fits[s - 1]) > 1e-4 for s in range(1, sweeps))
+    assert tr_als(X, (2, 3, 2, 2), max_sweeps=3, fit_tol=-1.0)[1] == 3
+
+
+def test_als_recovers_an_exact_train():
+    # r_0 = 1 (a tensor train): TR-SVD already recovers it, and ALS keeps it
+    rng = np.random.default_rng(44)
+    cores = [rng.standard_normal((1, 5, 3)), rng.standard_normal((3, 6, 2)), rng.standard_normal((2, 4, 1))]
+    X = tr_to_full(cores)
+    out, sweeps = tr_als(X, (3, 2, 1))
+    assert fro(X - tr_to_full(out)) <= 1e-12 * fro(X)
+
+
+def test_htr_als_error_splits_and_beats_tr_svd():
+    X = _ring((14, 12, 13, 11), 3, 15.0, 45)
+    cores, err, info = rbki_htr_als(X, (6, 5, 6, 5), 3, 2, 9, (3, 3, 3, 3))
+    assert abs(err - fro(X - tr_to_full(cores)) / fro(X)) <= 1e-12 * err
+    _, e_svd, _ = rbki_htr(X, (6, 5, 6, 5), 3, 2, 9, (3, 3, 3, 3))
+    assert err <= e_svd * (1 + 1e-12)
