@@ -203,6 +203,26 @@ rbki_status rbki_htr(const void *X, int xtype, const rbki_params *prm, const int
                      void *const *tr_cores, int out_type, void *workspace, size_t ws_bytes,
                      double *rel_err, void *stream);
 
+/* Alg. 3 with the TR-ALS branch named in its step 3: as rbki_htr, with TR-ALS
+ * sweeps on the core instead of TR-SVD.  The cores start from the Gaussian
+ * sketch stream of prm->seed with tag 2: core k's entry at linear index
+ * (a S_k + i) r_k + b is z of stream (seed, k, 2) at that index, divided by
+ * sqrt(S_k r_{k-1} r_k) (a zero-padded TR-SVD start would make the updates
+ * rank-deficient).  Each sweep updates the
+ * cores in order; core k is the least-squares fit of the core's cyclic
+ * mode-k unfolding by the ring of the other cores (normal equations, minimum-
+ * norm solution: eigenvalues of the Gram matrix of the design below 1e-13 of
+ * the largest count as zero, so zero-padded directions stay zero).  The
+ * sweeps stop when the Fit 1 - ||G - TR|| / ||G|| changes by at most fit_tol
+ * (the rule of Sec. 4, 1e-3 there), or after max_sweeps (20 there).  The
+ * core and the TR ranks are small: TR ranks <= 64, float64 throughout.
+ *   sweeps : host, nullable: sweeps taken (synchronises once per sweep).
+ */
+size_t rbki_htr_als_workspace(const rbki_params *prm, int xtype, const int64_t *tr_ranks);
+rbki_status rbki_htr_als(const void *X, int xtype, const rbki_params *prm, const int64_t *tr_ranks,
+                         int max_sweeps, double fit_tol, void *const *tr_cores, int out_type,
+                         void *workspace, size_t ws_bytes, double *rel_err, int *sweeps, void *stream);
+
 /* ---------------------------------------------------------------------------
  * The small symmetric eigenproblem of Alg. 2, steps 3-4 (Z = Q^T X X^T Q,
  * "svd(Z)"; Remark 1): eigenvalues in descending order and unit eigenvectors

@@ -143,12 +143,16 @@ def rbki_htr(X, tucker_ranks, p, q, seed, tr_ranks, explicit_error=True):
 # unfolding G_<k> in that column order by this linear model; a sweep updates
 # k = 1, ..., N in turn.
 #
-# Readings: the cores start from the TR-SVD of G (deterministic, so no second
-# random stream is needed); the iteration follows the rule of Sec. 4 for all
-# methods: at most 20 sweeps, stopping when the Fit 1 - ||G - TR||/||G|| (a
-# fraction) changes by at most 1e-3 between sweeps; each least-squares
-# problem takes its minimum-norm solution (the zero-padded directions of the
-# TR-SVD start stay exactly zero unless the data asks for them).
+# Readings: the cores start from Gaussian values of the sketch stream
+# (philox, tag 2: core k's entry at linear index (a S_k + i) r_k + b of
+# stream (seed, k)), scaled by 1/sqrt(S_k r_{k-1} r_k).  (A TR-SVD start is
+# zero-padded whenever r_{k-1} r_k exceeds the rank of a core's unfolding,
+# which makes the least-squares updates rank-deficient and their solution a
+# matter of thresholds; a random start gives full-rank updates.)  The
+# iteration follows the rule of Sec. 4 for all methods: at most 20 sweeps,
+# stopping when the Fit 1 - ||G - TR||/||G|| (a fraction) changes by at most
+# 1e-3 between sweeps (the start counts as sweep 0); each least-squares
+# problem takes its minimum-norm solution.
 
 
 def subchain(cores, k):
@@ -187,12 +191,29 @@ def als_update(G, cores, k):
     return Zt.reshape(rk1, rk, Sk).transpose(0, 2, 1).copy()
 
 
-def tr_als(G, tr_ranks, max_sweeps=20, fit_tol=1e-3, history=False):
-    """TR-ALS of G with TR ranks (r_1..r_N), r_0 = r_N, from the TR-SVD start.
-    Returns the cores, the number of sweeps taken and (history=True) the
-    relative error after every single-core update."""
+TAG_TR_START = 2
+
+
+def tr_als_start(shape, tr_ranks, seed):
+    """The TR-ALS start: core k (r_{k-1} x S_k x r_k) holds the Gaussian values
+    of stream (seed, k, tag 2) at linear indices 0 .. r_{k-1} S_k r_k - 1,
+    divided by sqrt(S_k r_{k-1} r_k)."""
+    from . import philox
+    r = [int(tr_ranks[-1])] + [int(v) for v in tr_ranks]
+    cores = []
+    for k, S in enumerate(shape):
+        n = r[k] * S * r[k + 1]
+        z = philox.gaussian_at(seed, k, np.arange(n, dtype=np.uint64), tag=TAG_TR_START)
+        cores.append(z.reshape(r[k], S, r[k + 1]) / np.sqrt(S * r[k] * r[k + 1]))
+    return cores
+
+
+def tr_als(G, tr_ranks, max_sweeps=20, fit_tol=1e-3, history=False, seed=0, start=None):
+    """TR-ALS of G with TR ranks (r_1..r_N), r_0 = r_N, from tr_als_start
+    (or the given cores).  Returns the cores, the number of sweeps taken and
+    (history=True) the relative error after every single-core update."""
     G = np.asarray(G, np.float64)
-    cores, _ = tr_svd(G, tr_ranks)
+    cores = [np.array(c, np.float64) for c in start] if start is not None else tr_als_start(G.shape, tr_ranks, seed)
     ng = fro(G)
     errs = [fro(G - tr_to_full(cores)) / ng]
     prev = 1.0 - errs[0]
@@ -212,12 +233,12 @@ def tr_als(G, tr_ranks, max_sweeps=20, fit_tol=1e-3, history=False):
 
 
 def rbki_htr_als(X, tucker_ranks, p, q, seed, tr_ranks, max_sweeps=20, fit_tol=1e-3):
-    """Alg. 3 with the TR-ALS branch: rBKI-TK, TR-ALS of the core, X_n =
-    G_n x_2 U^(n).  The error is sqrt(||X - [[G; U]]||^2 + ||G - TR(G_n)||^2)
+    """Alg. 3 with the TR-ALS branch: rBKI-TK, TR-ALS of the core (its start
+    from the same seed), X_n = G_n x_2 U^(n).  The error is sqrt(||X - [[G; U]]||^2 + ||G - TR(G_n)||^2)
     / ||X|| (orthonormal Tucker factors; both terms explicit)."""
     X = np.asarray(X, np.float64)
     G, factors, e_tk = rbki_tucker(X, tucker_ranks, p, q, seed)
-    core_cores, sweeps = tr_als(G, tr_ranks, max_sweeps, fit_tol)
+    core_cores, sweeps = tr_als(G, tr_ranks, max_sweeps, fit_tol, seed=seed)
     cores = attach_factors(core_cores, factors)
     nx = fro(X)
     gap2 = fro(G - tr_to_full(core_cores)) ** 2

@@ -34,6 +34,7 @@ _STATUS = {0: "RBKI_OK", 1: "RBKI_E_INVALID", 2: "RBKI_E_NOMEM", 3: "RBKI_E_HIP"
 SYMBOLS = ("rbki_version", "rbki_last_error", "rbki_omega", "rbki_philox", "rbki_basis_workspace",
            "rbki_basis", "rbki_tucker_workspace", "rbki_tucker", "rbki_htr_workspace", "rbki_htr",
            "rbki_basis_rows", "rbki_release", "rbki_tucker_adaptive_workspace", "rbki_tucker_adaptive",
+           "rbki_htr_als_workspace", "rbki_htr_als",
            "rbki_sym_eig_workspace", "rbki_sym_eig", "rbki_sym_eig_top_workspace", "rbki_sym_eig_top",
            "rbki_profile_enable", "rbki_profile_reset", "rbki_profile_read", "rbki_server_request_bytes", "rbki_server_create", "rbki_server_submit",
            "rbki_server_poll", "rbki_server_wait", "rbki_server_destroy")
@@ -89,6 +90,8 @@ def load_library(build_if_missing=True):
             "rbki_tucker": (ci, [vp, ci, P(_Params), vp, P(vp), ci, vp, sz, P(dbl), vp]),
             "rbki_htr_workspace": (sz, [P(_Params), ci, P(i64)]),
             "rbki_htr": (ci, [vp, ci, P(_Params), P(i64), P(vp), ci, vp, sz, P(dbl), vp]),
+            "rbki_htr_als_workspace": (sz, [P(_Params), ci, P(i64)]),
+            "rbki_htr_als": (ci, [vp, ci, P(_Params), P(i64), ci, dbl, P(vp), ci, vp, sz, P(dbl), P(ci), vp]),
             "rbki_sym_eig_workspace": (sz, [i64]),
             "rbki_sym_eig": (ci, [vp, i64, vp, vp, vp, sz, P(ci), vp]),
             "rbki_sym_eig_top_workspace": (sz, [i64, i64]),
@@ -258,8 +261,12 @@ def tucker_adaptive(X, ranks, p=5, max_q=20, fit_tol=1e-3, seed=0, precision="pl
 
 
 def htr(X, tucker_ranks, tr_ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_err=True,
-        stream=None, variant="krylov", sample_rate=1.0, truncation="independent"):
-    """rBKI-TK-TR (Alg. 3, TR-SVD branch).  Returns ([X_1, ..., X_N], rel_err or None)."""
+        stream=None, variant="krylov", sample_rate=1.0, truncation="independent", method="svd", max_sweeps=20,
+        fit_tol=1e-3, return_sweeps=False):
+    """rBKI-TK-TR (Alg. 3).  method "svd": TR-SVD of the core; "als": TR-ALS
+    sweeps from the TR-SVD cores (stopping rule of Sec. 4).  Returns
+    ([X_1, ..., X_N], rel_err or None) (and the sweeps taken with
+    return_sweeps)."""
     torch = _torch()
     lib = load_library()
     X = _as_input(torch, X)
@@ -270,17 +277,31 @@ def htr(X, tucker_ranks, tr_ranks, p=5, q=2, seed=0, precision="plain", out_dtyp
     N = X.dim()
     prm = _params(X.shape, tucker_ranks, p, q, seed, precision, variant, sample_rate, truncation)
     tr = (ctypes.c_int64 * N)(*[int(v) for v in tr_ranks])
-    need = lib.rbki_htr_workspace(ctypes.byref(prm), code, tr)
+    als = method == "als"
+    if method not in ("svd", "als"):
+        raise ValueError("method must be 'svd' or 'als'")
+    need = (lib.rbki_htr_als_workspace if als else lib.rbki_htr_workspace)(ctypes.byref(prm), code, tr)
     if need == 0:
+        if als:
+            _check(lib.rbki_htr_als(None, code, ctypes.byref(prm), tr, int(max_sweeps), float(fit_tol), None, ocode,
+                                    None, 0, None, None, None))
         _check(lib.rbki_htr(None, code, ctypes.byref(prm), tr, None, ocode, None, 0, None, None))
     ws = _workspace(torch, X.device, need)
     r = [int(tr_ranks[-1])] + [int(v) for v in tr_ranks]
     cores = [torch.empty((r[n], int(X.shape[n]), r[n + 1]), dtype=out_dtype, device=X.device) for n in range(N)]
     cptr = (ctypes.c_void_p * N)(*[c.data_ptr() for c in cores])
     err = ctypes.c_double(0.0)
-    _check(lib.rbki_htr(ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm), tr, cptr, ocode,
-                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(err) if rel_err else None,
-                        _stream(torch, stream)))
+    sweeps = ctypes.c_int(0)
+    if als:
+        _check(lib.rbki_htr_als(ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm), tr, int(max_sweeps),
+                                float(fit_tol), cptr, ocode, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                ctypes.byref(err) if rel_err else None, ctypes.byref(sweeps), _stream(torch, stream)))
+    else:
+        _check(lib.rbki_htr(ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm), tr, cptr, ocode,
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(err) if rel_err else None,
+                            _stream(torch, stream)))
+    if return_sweeps:
+        return cores, (err.value if rel_err else None), sweeps.value
     return cores, (err.value if rel_err else None)
 
 

@@ -26,6 +26,10 @@ hipError_t tr_attach(const double* core, const double* Ut, int64_t ra, int64_t S
 hipError_t tr_gap2(const void* Gcore, int core_elem, int N, const int64_t* S, const int64_t* r,
                    double* const* cores, double* work, double* out, hipStream_t st);
 size_t tr_gap2_work_bytes(int N, const int64_t* S, const int64_t* r);
+size_t tr_als_work_bytes(int N, const int64_t* S, const int64_t* r);
+hipError_t tr_als_device(const double* Gd, int N, const int64_t* S, const int64_t* r, double* const* cores,
+                         uint64_t seed, int max_sweeps, double fit_tol, void* work, int* info, int* sweeps_out,
+                         double* err2_out, hipStream_t st);
 }  // namespace rbki
 
 using namespace rbki;
@@ -1542,7 +1546,7 @@ static bool htr_sizes(const Plan& P, const int64_t* tr, int64_t* r) {
   return true;
 }
 
-size_t rbki_htr_workspace(const rbki_params* prm, int xtype, const int64_t* tr_ranks) {
+static size_t htr_bytes(const rbki_params* prm, int xtype, const int64_t* tr_ranks, bool als) {
   Plan P;
   if (make_plan(prm, xtype, P) != RBKI_OK || !tr_ranks) return 0;
   int64_t r[9];
@@ -1554,23 +1558,37 @@ size_t rbki_htr_workspace(const rbki_params* prm, int xtype, const int64_t* tr_r
   size_t extra = 0;
   for (int n = 0; n < P.N; ++n) extra += ((size_t)r[n] * S[n] * r[n + 1] * 8 + 255) & ~(size_t)255;
   extra += tr_svd_work_bytes(P.N, S, r) + tr_gap2_work_bytes(P.N, S, r) + 1024;
+  if (als) extra += tr_als_work_bytes(P.N, S, r) + 256;
   return base + extra;
 }
 
-rbki_status rbki_htr(const void* X, int xtype, const rbki_params* prm, const int64_t* tr_ranks,
-                     void* const* tr_cores, int out_type, void* workspace, size_t ws_bytes, double* rel_err,
-                     void* stream) {
+size_t rbki_htr_workspace(const rbki_params* prm, int xtype, const int64_t* tr_ranks) {
+  return htr_bytes(prm, xtype, tr_ranks, false);
+}
+
+size_t rbki_htr_als_workspace(const rbki_params* prm, int xtype, const int64_t* tr_ranks) {
+  return htr_bytes(prm, xtype, tr_ranks, true);
+}
+
+// Alg. 3: the Tucker step, then TR-SVD of the core (or, with als, TR-ALS
+// sweeps from a start of the sketch stream), then X_n = G_n x_2 U^(n).
+static rbki_status htr_impl(const void* X, int xtype, const rbki_params* prm, const int64_t* tr_ranks,
+                            void* const* tr_cores, int out_type, void* workspace, size_t ws_bytes, double* rel_err,
+                            bool als, int max_sweeps, double fit_tol, int* sweeps, hipStream_t st) {
   Plan P;
   rbki_status s = make_plan(prm, xtype, P);
   if (s != RBKI_OK) return s;
   if (!tr_ranks || !tr_cores) return fail(RBKI_E_INVALID, "NULL tr_ranks or tr_cores");
   int64_t r[9];
   if (!htr_sizes(P, tr_ranks, r)) return fail(RBKI_E_INVALID, "TR ranks must be >= 1");
+  for (int k = 0; k <= P.N; ++k)
+    if (r[k] > 64) return fail(RBKI_E_UNSUPPORTED, "TR rank %lld > 64", (long long)r[k]);
   for (int n = 0; n < P.N; ++n)
     if (!tr_cores[n]) return fail(RBKI_E_INVALID, "tr_cores[%d] is NULL", n);
-  const size_t need = rbki_htr_workspace(prm, xtype, tr_ranks);
+  if (als && (max_sweeps < 0 || max_sweeps > 1000 || !(fit_tol == fit_tol)))
+    return fail(RBKI_E_INVALID, "max_sweeps %d outside [0, 1000] or fit_tol NaN", max_sweeps);
+  const size_t need = htr_bytes(prm, xtype, tr_ranks, als);
   if (!workspace || ws_bytes < need) return fail(RBKI_E_INVALID, "workspace %zu bytes < required %zu", ws_bytes, need);
-  hipStream_t st = (hipStream_t)stream;
   Buffers b;
   void* Gchain = nullptr;
   double e_tk = 0.0;
@@ -1593,7 +1611,17 @@ rbki_status rbki_htr(const void* X, int xtype, const rbki_params* prm, const int
   double* gwork = (double*)base;
   base += (tr_gap2_work_bytes(P.N, S, r) + 255) & ~(size_t)255;
   double* small = (double*)base;   // [0..1]: gap2, discarded; int info at +64
+  base += 1024;
   HIPCHK(tr_svd_device(Gchain, P.celem, P.N, S, r, cores, twork, tw, (int*)(small + 8), small + 1, st));
+  int sw = 0;
+  if (als) {
+    // TR-ALS from its own start (the sketch stream, tag 2); tr_svd_device
+    // left the core in float64 at the start of its work area
+    double err2 = 0.0;
+    HIPCHK(tr_als_device(twork, P.N, S, r, cores, P.seed, max_sweeps, fit_tol, base, (int*)(small + 10), &sw, &err2,
+                         st));
+  }
+  if (sweeps) *sweeps = sw;
   for (int n = 0; n < P.N; ++n)
     HIPCHK(tr_attach(cores[n], b.Ut64[n], r[n], S[n], r[n + 1], P.dims[n], tr_cores[n], dtype_elem(out_type), st));
   if (rel_err) {
@@ -1606,6 +1634,20 @@ rbki_status rbki_htr(const void* X, int xtype, const rbki_params* prm, const int
     *rel_err = sums[1] > 0 ? std::sqrt((sums[0] + gap2) / sums[1]) : 0.0;
   }
   return s;
+}
+
+rbki_status rbki_htr(const void* X, int xtype, const rbki_params* prm, const int64_t* tr_ranks,
+                     void* const* tr_cores, int out_type, void* workspace, size_t ws_bytes, double* rel_err,
+                     void* stream) {
+  return htr_impl(X, xtype, prm, tr_ranks, tr_cores, out_type, workspace, ws_bytes, rel_err, false, 0, 0.0, nullptr,
+                  (hipStream_t)stream);
+}
+
+rbki_status rbki_htr_als(const void* X, int xtype, const rbki_params* prm, const int64_t* tr_ranks, int max_sweeps,
+                         double fit_tol, void* const* tr_cores, int out_type, void* workspace, size_t ws_bytes,
+                         double* rel_err, int* sweeps, void* stream) {
+  return htr_impl(X, xtype, prm, tr_ranks, tr_cores, out_type, workspace, ws_bytes, rel_err, true, max_sweeps,
+                  fit_tol, sweeps, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -13,7 +13,10 @@ For each workload the file holds
                 U_n U_n^T (independent of factor signs);
   htr         : (64^5 only) the error of rBKI-TK-TR (Alg. 3, TR-SVD branch),
                 from the explicit Tucker residual and the explicit residual
-                of the TR-SVD of the core.
+                of the TR-SVD of the core;
+  htr_als     : (64^5 only) the same with the TR-ALS branch (Gaussian start
+                from the sketch stream, Sec. 4 stopping rule), and its sweep
+                count.
 
 Run from the repository root:  python tests/golden/make_full_size.py [names]
 (about 25 minutes and 45 GB of host memory for all three on 8 cores).
@@ -30,7 +33,8 @@ sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
 from oracle.rbki import rbki_tucker  # noqa: E402
-from oracle.trsvd import rbki_htr  # noqa: E402
+from oracle.tensor import fro  # noqa: E402
+from oracle.trsvd import rbki_htr, tr_als, tr_to_full  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_size.json")
 NAMES = ("tucker400_f32", "ring64x5_f32", "tucker1000_f32")
@@ -76,6 +80,13 @@ def run(name):
         rec["htr"] = {"tr_ranks": list(w["tr_ranks"]), "rel_err": err,
                       "core_gap2_rel": info["core_gap2"] / nx2, "discarded_rel": info["discarded"] / nx2}
         e_tk, factors, infos = info["tucker_error"], info["factors"], info["tucker_infos"]
+        # the TR-ALS branch of Alg. 3 on the same core, from its start of the
+        # sketch stream
+        als_cores, sweeps = tr_als(info["G"], w["tr_ranks"], seed=w["seeds"][1])
+        gap2 = fro(info["G"] - tr_to_full(als_cores)) ** 2
+        rec["htr_als"] = {"tr_ranks": list(w["tr_ranks"]), "sweeps": int(sweeps), "max_sweeps": 20,
+                          "fit_tol": 1e-3, "core_gap2_rel": gap2 / nx2,
+                          "rel_err": float(np.sqrt((e_tk ** 2) + gap2 / nx2))}
     else:
         _, factors, e_tk, infos = rbki_tucker(X, w["ranks"], w["p"], w["q"], w["seeds"][1], return_info=True)
     rec["oracle"] = {"rel_err": e_tk, **oracle_record(infos, factors, w["ranks"])}

@@ -184,3 +184,21 @@ def test_truncation_is_validated_and_sizes_its_workspace():
     st = lib.rbki_tucker(ctypes.c_void_p(16), 1, ctypes.byref(prm), None, None, 1, None, 0, None, None)
     assert st == 1 and "truncation" in lib.rbki_last_error().decode()
     assert lib.rbki_tucker_workspace(ctypes.byref(prm), 1) == 0
+
+
+def test_htr_als_arguments_are_checked():
+    lib = rb.load_library()
+    prm = _params((20, 20, 20), (6, 6, 6))
+    tr = (ctypes.c_int64 * 3)(2, 2, 2)
+    svd = lib.rbki_htr_workspace(ctypes.byref(prm), 1, tr)
+    als = lib.rbki_htr_als_workspace(ctypes.byref(prm), 1, tr)
+    assert als > svd > 0
+    cores = (ctypes.c_void_p * 3)(16, 16, 16)
+    for ms, tol in ((-1, 1e-3), (5000, 1e-3), (20, float("nan"))):
+        st = lib.rbki_htr_als(ctypes.c_void_p(16), 1, ctypes.byref(prm), tr, ms, tol, cores, 1, ctypes.c_void_p(256),
+                              als, None, None, None)
+        assert st == 1
+    big = (ctypes.c_int64 * 3)(65, 2, 2)
+    st = lib.rbki_htr(ctypes.c_void_p(16), 1, ctypes.byref(prm), big, cores, 1, ctypes.c_void_p(256), 1 << 40, None,
+                      None)
+    assert st == 5

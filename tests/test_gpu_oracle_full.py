@@ -138,3 +138,23 @@ def test_htr_ring64x5_matches_oracle(env):
     gap2 = g["htr"]["core_gap2_rel"]
     assert abs(e * e - (e_tk * e_tk + gap2)) <= 1e-5 * e * e
     assert math.isfinite(e)
+
+
+def test_htr_als_ring64x5_matches_oracle(env):
+    # the TR-ALS branch of Alg. 3 at 64^5: sweeps on the 16^5 core from the
+    # Gaussian start of the sketch stream, TR ranks 8, Sec. 4 stopping rule
+    torch, rb = env
+    name = "ring64x5_f32"
+    w = synth.WORKLOADS[name]
+    g = golden(name)
+    if "htr_als" not in g:
+        pytest.fail("no stored TR-ALS result; run tests/golden/make_full_size.py ring64x5_f32")
+    X = device_tensor(torch, name)
+    cores, e, sweeps = rb.htr(X, w["ranks"], w["tr_ranks"], p=w["p"], q=w["q"], seed=w["seeds"][1], method="als",
+                              max_sweeps=g["htr_als"]["max_sweeps"], fit_tol=g["htr_als"]["fit_tol"],
+                              return_sweeps=True, out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    print(f"htr als: gpu {e:.12f} ({sweeps} sweeps) oracle {g['htr_als']['rel_err']:.12f} "
+          f"({g['htr_als']['sweeps']} sweeps)", flush=True)
+    assert sweeps == g["htr_als"]["sweeps"]
+    assert abs(e - g["htr_als"]["rel_err"]) <= 1e-5 * g["htr_als"]["rel_err"]

@@ -617,3 +617,31 @@ def test_adaptive_q_rejects_the_power_variant(env):
     st = lib.rbki_tucker_adaptive(ctypes.c_void_p(16), 1, ctypes.byref(prm), 1e-3, None, None, 1, None, 0, None,
                                   None, None)
     assert st == 5
+
+
+# ------------------------------------------------------------------ TR-ALS (Alg. 3, step 3)
+
+from oracle.trsvd import rbki_htr_als  # noqa: E402
+
+
+@pytest.mark.parametrize("dims,tk,tr,dtype,tol", [((20, 18, 22, 16), (6, 6, 6, 6), (3, 3, 3, 3), "float64", 1e-4),
+                                                  ((24, 20, 26), (10, 9, 12), (4, 3, 5), "float64", 1e-6),
+                                                  ((16, 14, 15), (6, 5, 6), (4, 4, 4), "float64", 1e-3),
+                                                  ((30, 28, 26, 24), (8, 8, 8, 8), (3, 3, 3, 3), "float32", 1e-3)])
+def test_htr_als_matches_oracle(env, dims, tk, tr, dtype, tol):
+    # TR-ALS sweeps from the Gaussian start of the sketch stream (tag 2); the
+    # third case has r_0 r_1 = 16 > S_1 = 6; the data are rings of rank 5
+    torch, rb = env
+    X, _ = synth.tensor_ring_data(dims, 5, seed=25, var=1.0 / 5)
+    X = synth.add_noise(X, 15.0, np.random.default_rng(26)).astype(dtype)
+    Xg = torch.from_numpy(X).cuda()
+    cores, e_g, sw_g = rb.htr(Xg, tk, tr, p=4, q=2, seed=27, method="als", fit_tol=tol, return_sweeps=True,
+                              out_dtype=torch.float64)
+    ocores, e_o, info = rbki_htr_als(X.astype(np.float64), tk, 4, 2, 27, tr, fit_tol=tol)
+    assert sw_g == info["sweeps"]
+    assert abs(e_g - e_o) / e_o <= (1e-8 if dtype == "float64" else 1e-5)
+    # the returned cores reproduce the reported error (the float32 form's
+    # factors and core carry float32 rounding)
+    Xr = tr_to_full([c.cpu().numpy() for c in cores])
+    e_explicit = fro(X.astype(np.float64) - Xr) / fro(X.astype(np.float64))
+    assert abs(e_explicit - e_g) <= (1e-9 if dtype == "float64" else 1e-5) * e_g

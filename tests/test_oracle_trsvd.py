@@ -184,14 +184,30 @@ def test_als_update_solves_its_least_squares_problem():
         assert fro(X - tr_to_full(P)) >= e0 * (1 - 1e-12)
 
 
-def test_als_error_never_increases_and_starts_from_tr_svd():
+def test_als_error_never_increases_from_its_start():
     X = _ring((10, 9, 11, 8), 3, 10.0, 42)
+    from oracle.trsvd import tr_als_start
+    start = tr_als_start(X.shape, (2, 2, 2, 2), 5)
+    cores, sweeps, errs = tr_als(X, (2, 2, 2, 2), fit_tol=1e-6, history=True, seed=5)
+    assert errs[0] == fro(X - tr_to_full(start)) / fro(X)
+    assert np.all(np.diff(errs) <= 1e-12 * errs[1])
+    # and from the TR-SVD cores it improves on them
     cores0, _ = tr_svd(X, (2, 2, 2, 2))
     e_svd = fro(X - tr_to_full(cores0)) / fro(X)
-    cores, sweeps, errs = tr_als(X, (2, 2, 2, 2), fit_tol=1e-6, history=True)
-    assert errs[0] == e_svd
-    assert np.all(np.diff(errs) <= 1e-12 * errs[0])
-    assert errs[-1] < e_svd
+    _, _, errs2 = tr_als(X, (2, 2, 2, 2), fit_tol=1e-6, history=True, start=cores0)
+    assert errs2[0] == e_svd and errs2[-1] < e_svd and np.all(np.diff(errs2) <= 1e-12 * e_svd)
+
+
+def test_als_start_is_the_tagged_gaussian_stream():
+    from oracle import philox
+    from oracle.trsvd import tr_als_start
+    cores = tr_als_start((5, 4, 6), (2, 3, 4), 77)
+    assert [c.shape for c in cores] == [(4, 5, 2), (2, 4, 3), (3, 6, 4)]
+    for k, c in enumerate(cores):
+        z = philox.gaussian_at(77, k, np.arange(c.size, dtype=np.uint64), tag=2)
+        assert np.array_equal(c.ravel(), z / np.sqrt(c.shape[1] * c.shape[0] * c.shape[2]))
+    # a stream of its own: not the sketch's (tag 0)
+    assert not np.allclose(cores[0].ravel() * np.sqrt(40), philox.gaussian_at(77, 0, np.arange(40, dtype=np.uint64)))
 
 
 def test_als_stops_by_the_fit_rule():
@@ -204,18 +220,18 @@ def test_als_stops_by_the_fit_rule():
     assert tr_als(X, (2, 3, 2, 2), max_sweeps=3, fit_tol=-1.0)[1] == 3
 
 
-def test_als_recovers_an_exact_train():
-    # r_0 = 1 (a tensor train): TR-SVD already recovers it, and ALS keeps it
+def test_als_keeps_an_exact_train():
+    # r_0 = 1 (a tensor train): TR-SVD recovers it, and ALS started there
+    # stays exact (its error cannot increase from zero)
     rng = np.random.default_rng(44)
     cores = [rng.standard_normal((1, 5, 3)), rng.standard_normal((3, 6, 2)), rng.standard_normal((2, 4, 1))]
     X = tr_to_full(cores)
-    out, sweeps = tr_als(X, (3, 2, 1))
+    start, _ = tr_svd(X, (3, 2, 1))
+    out, sweeps = tr_als(X, (3, 2, 1), start=start)
     assert fro(X - tr_to_full(out)) <= 1e-12 * fro(X)
 
 
-def test_htr_als_error_splits_and_beats_tr_svd():
+def test_htr_als_error_splits():
     X = _ring((14, 12, 13, 11), 3, 15.0, 45)
     cores, err, info = rbki_htr_als(X, (6, 5, 6, 5), 3, 2, 9, (3, 3, 3, 3))
     assert abs(err - fro(X - tr_to_full(cores)) / fro(X)) <= 1e-12 * err
-    _, e_svd, _ = rbki_htr(X, (6, 5, 6, 5), 3, 2, 9, (3, 3, 3, 3))
-    assert err <= e_svd * (1 + 1e-12)
