@@ -186,6 +186,23 @@ rbki_status rbki_tucker_adaptive(const void *X, int xtype, const rbki_params *pr
                                  void *core, void *const *factors, int out_type, void *workspace,
                                  size_t ws_bytes, double *rel_err, int *q_used, void *stream);
 
+/* rbki_tucker for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * workspace is a fixed array of the library's own device memory instead of a
+ * caller buffer.  Each device the library runs on holds one such array of
+ * rbki_tucker_noalloc_limit() bytes (128 MiB) from the first load of the
+ * library until the process ends; the call allocates nothing, creates no
+ * stream, and runs every mode on `stream`.
+ * Arguments, outputs and errors are those of rbki_tucker; a problem whose
+ * workspace (rbki_tucker_workspace) exceeds the limit returns
+ * RBKI_E_INVALID before anything is launched.  All calls on one device share
+ * that device's array, which keeps the last call's contents: calls that
+ * overlap on one device (different streams or threads) race and must not be
+ * issued.  Synchronises `stream` (as rbki_tucker does). */
+size_t rbki_tucker_noalloc_limit(void);
+rbki_status rbki_tucker_noalloc(const void *X, int xtype, const rbki_params *prm, void *core,
+                                void *const *factors, int out_type, double *rel_err, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Alg. 3 (rBKI-TK-TR) with the TR-SVD branch: rBKI-TK with the Tucker ranks
  * of prm (the compress sizes), TR-SVD of the core with TR ranks

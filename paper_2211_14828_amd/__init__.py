@@ -34,7 +34,7 @@ _STATUS = {0: "RBKI_OK", 1: "RBKI_E_INVALID", 2: "RBKI_E_NOMEM", 3: "RBKI_E_HIP"
 SYMBOLS = ("rbki_version", "rbki_last_error", "rbki_omega", "rbki_philox", "rbki_basis_workspace",
            "rbki_basis", "rbki_tucker_workspace", "rbki_tucker", "rbki_htr_workspace", "rbki_htr",
            "rbki_basis_rows", "rbki_release", "rbki_tucker_adaptive_workspace", "rbki_tucker_adaptive",
-           "rbki_htr_als_workspace", "rbki_htr_als",
+           "rbki_htr_als_workspace", "rbki_htr_als", "rbki_tucker_noalloc_limit", "rbki_tucker_noalloc",
            "rbki_sym_eig_workspace", "rbki_sym_eig", "rbki_sym_eig_top_workspace", "rbki_sym_eig_top",
            "rbki_profile_enable", "rbki_profile_reset", "rbki_profile_read", "rbki_server_request_bytes", "rbki_server_create", "rbki_server_submit",
            "rbki_server_poll", "rbki_server_wait", "rbki_server_destroy")
@@ -91,6 +91,8 @@ def load_library(build_if_missing=True):
             "rbki_htr_workspace": (sz, [P(_Params), ci, P(i64)]),
             "rbki_htr": (ci, [vp, ci, P(_Params), P(i64), P(vp), ci, vp, sz, P(dbl), vp]),
             "rbki_htr_als_workspace": (sz, [P(_Params), ci, P(i64)]),
+            "rbki_tucker_noalloc_limit": (sz, []),
+            "rbki_tucker_noalloc": (ci, [vp, ci, P(_Params), vp, P(vp), ci, P(dbl), vp]),
             "rbki_htr_als": (ci, [vp, ci, P(_Params), P(i64), ci, dbl, P(vp), ci, vp, sz, P(dbl), P(ci), vp]),
             "rbki_sym_eig_workspace": (sz, [i64]),
             "rbki_sym_eig": (ci, [vp, i64, vp, vp, vp, sz, P(ci), vp]),

@@ -142,6 +142,7 @@ struct Plan {
   bool power = false;        // power iteration: only the last block spans the factor's space
   double rate = 1.0;         // column sampling rate omega (Sec. 3.1)
   bool sequential = false;   // sequential truncation (ST-HOSVD form)
+  bool one_stream = false;   // every mode on the caller's stream (no helper streams)
   bool any_sampled = false;
   int64_t maxM = 0;          // largest column sample
   size_t ybytes = 0;         // largest gathered sample
@@ -1114,7 +1115,7 @@ static hipStream_t lane_stream(int lane) {
 // that it runs beside the later modes' work.
 static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, hipStream_t st,
                              bool inline_factors = false) {
-  const int lanes = P.concurrent ? 1 : b.lanes;
+  const int lanes = (P.concurrent || P.one_stream) ? 1 : b.lanes;
   hipStream_t ls[kMaxLanes] = {st, st, st};
   hipEvent_t ev[kMaxLanes] = {};
   for (int l = 1; l < lanes; ++l) {
@@ -1423,10 +1424,11 @@ rbki_status adaptive_impl(const void* X, int xtype, const rbki_params* prm, doub
 
 static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
                         int out_type, void* workspace, size_t ws_bytes, double* rel_err, hipStream_t st, Plan& P,
-                        Buffers& b, void** core_chain, HostResult* async_res) {
+                        Buffers& b, void** core_chain, HostResult* async_res, bool one_stream = false) {
   rbki_status s = make_plan(prm, xtype, P);
   if (s != RBKI_OK) return s;
   P.concurrent = async_res != nullptr;        // enqueued by the request server
+  P.one_stream = one_stream;
   if (!X) return fail(RBKI_E_INVALID, "X is NULL");
   if (out_type != RBKI_F64 && out_type != RBKI_F32) return fail(RBKI_E_INVALID, "out_type must be F64 or F32");
   const size_t need = tucker_bytes(prm, xtype, P);
@@ -1455,7 +1457,7 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   // with concurrent modes, each mode's eigenproblem and factor (and the first
   // product of the core chain) run on its stream as soon as its Krylov basis
   // is done
-  bool inline_factors = !P.concurrent && b.lanes > 1;
+  bool inline_factors = !P.concurrent && !P.one_stream && b.lanes > 1;
   for (int n = 0; n < P.N; ++n) inline_factors = inline_factors && eig_top_ok(P.m[n].Sp, P.m[n].R);
   s = run_modes(P, b, xsrc, st, inline_factors);
   if (s != RBKI_OK) return s;
@@ -1519,6 +1521,56 @@ rbki_status rbki_tucker(const void* X, int xtype, const rbki_params* prm, void* 
   Buffers b;
   return tucker_impl(X, xtype, prm, core, factors, out_type, workspace, ws_bytes, rel_err, (hipStream_t)stream, P,
                      b, nullptr, nullptr);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ fixed device scratch
+// For callers that cannot allocate: rbki_tucker with its workspace in this
+// array.  Each device that loads the library holds its own copy for the
+// life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+static rbki_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(RBKI_E_UNSUPPORTED, "device %d: at most 64 devices", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(RBKI_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RBKI_OK;
+}
+
+extern "C" {
+
+size_t rbki_tucker_noalloc_limit(void) { return kScratchBytes; }
+
+rbki_status rbki_tucker_noalloc(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
+                                int out_type, double* rel_err, void* stream) {
+  Plan P;
+  rbki_status s = make_plan(prm, xtype, P);
+  if (s != RBKI_OK) return s;
+  const size_t need = tucker_bytes(prm, xtype, P);
+  if (need == 0) return fail(RBKI_E_INVALID, "%s", g_err.c_str());
+  if (need > kScratchBytes)
+    return fail(RBKI_E_INVALID, "this problem needs %zu bytes of scratch; the fixed device scratch holds %zu", need,
+                kScratchBytes);
+  void* ws = nullptr;
+  s = scratch_address(&ws);
+  if (s != RBKI_OK) return s;
+  Buffers b;
+  return tucker_impl(X, xtype, prm, core, factors, out_type, ws, kScratchBytes, rel_err, (hipStream_t)stream, P, b,
+                     nullptr, nullptr, true);
 }
 
 size_t rbki_tucker_adaptive_workspace(const rbki_params* prm, int xtype) {
