@@ -276,6 +276,166 @@ __device__ inline float x_to_f(XT v);
 template <> __device__ inline float x_to_f<float>(float v) { return v; }
 template <> __device__ inline float x_to_f<bf16_t>(bf16_t v) { return bf16_to_f32(v); }
 
+// The split-bfloat16 form with fewer registers, so that two workgroups share
+// a compute unit: each workgroup owns 64 columns j0.. of X_(0), their H
+// block split into bfloat16 hi + lo parts in LDS as [j][k]; wave w walks the
+// 32-row tiles w, w + 4, ... (measured: 1.03 ms at 1000^3 against 2.7 ms when
+// the four waves took adjacent column blocks of the same rows, and 1.42 ms
+// for the former form at one workgroup per compute unit).  Xhat (32 x 64) of a wave is formed
+// as two 32 x 32 blocks, K = 64 with lane half h taking k in [32 h, 32 h + 32),
+// 8 per MFMA, three products (Ul Hh + Uh Hl + Uh Hh).  The U fragments and X
+// values of the next row tile are requested before the current one is formed
+// (the load counter retires in order, so those requests stay in flight).
+constexpr int RS_COLS = 64;
+constexpr int RS_LDS_ROW = 72;       // bf16 per LDS row: 64 k + 16 bytes of padding
+struct ResSplitArgs {
+  const bf16_t* Uh;     // I x 64 (columns >= R zero), hi parts
+  const bf16_t* Ul;     // lo parts
+  const float* H;       // R x J row-major
+  const void* X;        // I x J row-major
+  int64_t I, J;
+  int R;
+  double* partial;      // [gridDim.x] x 2
+};
+
+template <class XT>
+__global__ void __launch_bounds__(256, 2) residual_split_kernel(ResSplitArgs a) {
+  __shared__ __attribute__((aligned(16))) bf16_t hh[RS_COLS * RS_LDS_ROW];
+  __shared__ __attribute__((aligned(16))) bf16_t hl[RS_COLS * RS_LDS_ROW];
+  __shared__ double red[2][4];
+  // the wave index is uniform across the wave: readfirstlane lets the
+  // compiler keep row pointers and loop counters in scalar registers
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int half = lane >> 5, lr = lane & 31;
+  const int64_t jb = (int64_t)blockIdx.x * RS_COLS;
+  const int64_t j0 = jb;
+
+  // H block -> LDS as [j][k]: thread takes 4 consecutive j at one k
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = tid + 256 * q;
+    const int kk = c >> 4, jj = (c & 15) * 4;
+    const bool ok = kk < a.R && jb + jj < a.J;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ok) v = *(const float4*)(a.H + (int64_t)kk * a.J + jb + jj);
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bf16_t hi = f32_to_bf16(vv[e]);
+      hh[(jj + e) * RS_LDS_ROW + kk] = hi;
+      hl[(jj + e) * RS_LDS_ROW + kk] = f32_to_bf16(vv[e] - bf16_to_f32(hi));
+    }
+  }
+  __syncthreads();
+
+  const XT* X = (const XT*)a.X;
+  const int64_t NT = ceil_div(a.I, 32);
+  const int64_t ns = NT > wave ? (NT - wave + 3) / 4 : 0;     // this wave's row tiles wave + 4 s
+  const bf16_t* hhw = hh;
+  const bf16_t* hlw = hl;
+  // a row tile of X in the accumulator layout: value v of block n at row
+  // 8 (v / 4) + 4 half + v % 4, column 32 n + lr.  Whole tiles address each
+  // row from a uniform pointer plus a 32-bit lane offset (few registers);
+  // the last row tile and column block clamp rows and columns instead.
+  const bool whole_cols = j0 + 64 <= a.J && (4 * a.J + 64) * (int64_t)sizeof(XT) < ((int64_t)1 << 31);
+  const int32_t lane_off = 4 * half * (int32_t)a.J + lr;
+  auto load_x = [&](int64_t t, XT (&xv)[32]) {
+    const int64_t i0 = t * 32;
+    if (whole_cols && i0 + 32 <= a.I) {
+      const XT* base = X + i0 * a.J + j0;
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        const int n = j >> 4, v = j & 15;
+        const XT* rp = base + (int64_t)(8 * (v >> 2) + (v & 3)) * a.J + 32 * n;
+        xv[j] = rp[lane_off];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 32; ++j) {
+        const int n = j >> 4, v = j & 15;
+        int64_t i = i0 + 8 * (v >> 2) + 4 * half + (v & 3);
+        int64_t jj = j0 + 32 * n + lr;
+        i = i < a.I ? i : a.I - 1;
+        jj = jj < a.J ? jj : a.J - 1;
+        xv[j] = X[i * a.J + jj];
+      }
+    }
+  };
+  // a tile's U fragments: its 32 rows, lane half h taking k in [32 h, 32 h + 32)
+  auto load_u = [&](int64_t t, bf16x8_t (&ah)[4], bf16x8_t (&al)[4]) {
+    int64_t iu = t * 32 + lr;
+    iu = iu < a.I ? iu : a.I - 1;
+    const bf16x8_t* ph = (const bf16x8_t*)(a.Uh + iu * 64 + half * 32);
+    const bf16x8_t* pl = (const bf16x8_t*)(a.Ul + iu * 64 + half * 32);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ah[q] = ph[q];
+      al[q] = pl[q];
+    }
+  };
+  double res = 0.0, nrm = 0.0;
+  auto tile = [&](int64_t t, const bf16x8_t (&ah)[4], const bf16x8_t (&al)[4], const XT (&xv)[32]) {
+    const int64_t i0 = t * 32;
+    f32x16_t acc[2];
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[n][v] = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const int row = (32 * n + lr) * RS_LDS_ROW + half * 32 + q * 8;
+        const bf16x8_t bh = *(const bf16x8_t*)(hhw + row);
+        const bf16x8_t bl = *(const bf16x8_t*)(hlw + row);
+        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[q], bh, acc[n], 0, 0, 0);
+        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[q], bl, acc[n], 0, 0, 0);
+        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[q], bh, acc[n], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const int n = j >> 4, v = j & 15;
+      const bool ok = i0 + 8 * (v >> 2) + 4 * half + (v & 3) < a.I && j0 + 32 * n + lr < a.J;
+      const double x = ok ? (double)x_to_f<XT>(xv[j]) : 0.0;
+      const double d = ok ? x - (double)acc[n][v] : 0.0;
+      res = fma(d, d, res);
+      nrm = fma(x, x, nrm);
+    }
+  };
+  bf16x8_t uha[4], ula[4], uhb[4], ulb[4];
+  XT xa[32], xb[32];
+  if (ns > 0) {
+    load_u(wave, uha, ula);
+    load_x(wave, xa);
+  }
+  for (int64_t s = 0; s < ns; s += 2) {
+    if (s + 1 < ns) {
+      load_u(wave + 4 * (s + 1), uhb, ulb);
+      load_x(wave + 4 * (s + 1), xb);
+    }
+    tile(wave + 4 * s, uha, ula, xa);
+    if (s + 1 < ns) {
+      if (s + 2 < ns) {
+        load_u(wave + 4 * (s + 2), uha, ula);
+        load_x(wave + 4 * (s + 2), xa);
+      }
+      tile(wave + 4 * (s + 1), uhb, ulb, xb);
+    }
+  }
+  res = warp_sum(res);
+  nrm = warp_sum(nrm);
+  if (lane == 0) {
+    red[0][wave] = res;
+    red[1][wave] = nrm;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.partial[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    a.partial[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
 template <class XT, int PE>
 __global__ void __launch_bounds__(256, PE == E_F32 ? 2 : 1) residual_kernel(ResArgs a) {
   __shared__ __attribute__((aligned(16))) char ldsB[2][TILE * LDS_ROW];
@@ -768,13 +928,13 @@ hipError_t launch_ttm_first_blocked(int elem, const void* xb, const void* scales
 }
 
 size_t residual_work_bytes(int64_t I, int64_t J) {
-  const int64_t tiles = std::max<int64_t>(ceil_div(I, TILE) * ceil_div(J, TILE), ceil_div(J, TILE));
+  const int64_t tiles = std::max<int64_t>(ceil_div(I, TILE) * ceil_div(J, TILE), ceil_div(J, RS_COLS));
   return (size_t)tiles * 16 + 256 + (size_t)I * 64 * 4 + 64;
 }
 
 hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* Ut, const void* H, int64_t I,
                            int64_t J, int64_t R, double* out, void* work, size_t, hipStream_t s, bool bf16_products) {
-  const int64_t tiles = std::max<int64_t>(ceil_div(I, TILE) * ceil_div(J, TILE), ceil_div(J, TILE));
+  const int64_t tiles = std::max<int64_t>(ceil_div(I, TILE) * ceil_div(J, TILE), ceil_div(J, RS_COLS));
   double* partial = (double*)work;
   if (op_elem == E_F32 && R <= 64 && (x_elem == E_F32 || x_elem == E_BF16) && J % 4 == 0 && aligned16(H) &&
       ceil_div(J, TILE) <= 0x7fffffff) {
@@ -792,10 +952,20 @@ hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* U
     ra.R = (int)R;
     ra.nkt = (int)ceil_div(R, 32);
     ra.partial = partial;
-    const dim3 grid((unsigned)ceil_div(J, TILE));
+    dim3 grid((unsigned)ceil_div(J, TILE));
     if (bf16_products) {
-      if (x_elem == E_F32) hipLaunchKernelGGL((residual_kernel<float, E_BF16>), grid, dim3(256), 0, s, ra);
-      else hipLaunchKernelGGL((residual_kernel<bf16_t, E_BF16>), grid, dim3(256), 0, s, ra);
+      ResSplitArgs rs;
+      rs.Uh = (const bf16_t*)Up;
+      rs.Ul = (const bf16_t*)Up + I * 64;
+      rs.H = (const float*)H;
+      rs.X = X;
+      rs.I = I;
+      rs.J = J;
+      rs.R = (int)R;
+      rs.partial = partial;
+      grid = dim3((unsigned)ceil_div(J, RS_COLS));
+      if (x_elem == E_F32) hipLaunchKernelGGL((residual_split_kernel<float>), grid, dim3(256), 0, s, rs);
+      else hipLaunchKernelGGL((residual_split_kernel<bf16_t>), grid, dim3(256), 0, s, rs);
     } else {
       if (x_elem == E_F32) hipLaunchKernelGGL((residual_kernel<float, E_F32>), grid, dim3(256), 0, s, ra);
       else hipLaunchKernelGGL((residual_kernel<bf16_t, E_F32>), grid, dim3(256), 0, s, ra);
