@@ -218,12 +218,17 @@ def serving_leg(torch, rb, synth, count, slots, budget_gib, load, precision):
     dB, bf16 storage, p = 5, q U{1,2,3}), all resident in HBM before timing.
 
     1. one-at-a-time: each request solved alone by the plain form on its
-       float32 copy, in arrival order, one after the other;
+       float32 copy, in arrival order, one after the other; and the same on
+       the bf16 tensors in the served precision (the same arithmetic as the
+       server, so the two capacities separate batching from arithmetic);
     2. saturated: every request submitted to the request server at once
        (capacity in solves/s);
-    3. Poisson: arrivals at `load` x the saturated rate with the recipe's
-       exponential gaps; latency is from the scheduled arrival to completion.
-    The served results' relative errors are compared with the plain ones."""
+    3. the same Poisson arrivals (the recipe's exponential gaps) at one
+       offered rate, `load` x the one-at-a-time float32 capacity, for the
+       one-at-a-time float32 solver (a FIFO queue) and for the server;
+    4. the server alone at `load` x its saturated rate.
+    Latency is from the scheduled arrival to completion.  The served results'
+    relative errors are compared with the plain ones."""
     import threading
     reqs = synth.served_requests(count=count)
     Xb, X32 = [], []
@@ -239,37 +244,34 @@ def serving_leg(torch, rb, synth, count, slots, budget_gib, load, precision):
     def args_of(w):
         return dict(p=w["p"], q=w["q"], seed=w["seeds"][1])
 
-    for w, x in list(zip(reqs, X32))[:8]:
-        rb.tucker(x, w["ranks"], precision="plain", **args_of(w))
-    torch.cuda.synchronize()
-    lat_plain, err_plain = [], []
-    t0 = time.perf_counter()
-    for w, x in zip(reqs, X32):
-        t = time.perf_counter()
-        _, _, e = rb.tucker(x, w["ranks"], precision="plain", **args_of(w))
-        lat_plain.append((time.perf_counter() - t) * 1e3)
-        err_plain.append(e)
-    t_plain = time.perf_counter() - t0
-    plain_rate = count / t_plain
-    print(f"[serve] one-at-a-time plain f32: {plain_rate:.1f} solves/s", file=sys.stderr, flush=True)
-    del X32
-    torch.cuda.empty_cache()
-
-    budget = int(budget_gib * (1 << 30))
-    out = {}
-    with rb.Server(budget, slots=slots) as sv:
-        for w, x in list(zip(reqs, Xb))[:2 * slots]:
-            sv.wait(sv.submit(x, w["ranks"], precision=precision, **args_of(w)))
+    def one_at_a_time(xs, prec):
+        for w, x in list(zip(reqs, xs))[:8]:
+            rb.tucker(x, w["ranks"], precision=prec, **args_of(w))
+        torch.cuda.synchronize()
+        lat, err = [], []
         t0 = time.perf_counter()
-        tickets = [sv.submit(x, w["ranks"], precision=precision, **args_of(w)) for w, x in zip(reqs, Xb)]
-        res = [sv.wait(t) for t in tickets]
-        t_sat = time.perf_counter() - t0
-        sat_rate = count / t_sat
-        err_served = [r[2] for r in res]
-        print(f"[serve] saturated: {sat_rate:.1f} solves/s", file=sys.stderr, flush=True)
-        del res
+        for w, x in zip(reqs, xs):
+            t = time.perf_counter()
+            _, _, e = rb.tucker(x, w["ranks"], precision=prec, **args_of(w))
+            lat.append((time.perf_counter() - t) * 1e3)
+            err.append(e)
+        return count / (time.perf_counter() - t0), lat, err
 
-        rate = load * sat_rate
+    def fifo(xs, prec, rate):
+        # one solver, requests taken in arrival order: a request waits for the
+        # ones before it
+        arrivals = [w["arrival"] / rate for w in reqs]
+        lat = []
+        t0 = time.perf_counter()
+        for w, x, a in zip(reqs, xs, arrivals):
+            d = t0 + a - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            rb.tucker(x, w["ranks"], precision=prec, **args_of(w))
+            lat.append((time.perf_counter() - t0 - a) * 1e3)
+        return lat
+
+    def served_poisson(sv, rate):
         arrivals = [w["arrival"] / rate for w in reqs]
         lat = [None] * count
         lag = [0.0] * count
@@ -295,7 +297,35 @@ def serving_leg(torch, rb, synth, count, slots, budget_gib, load, precision):
             tick[i] = sv.submit(x, w["ranks"], precision=precision, **args_of(w))
             ready.release()
         th.join()
-        achieved = count / (max(done_at) - t0)
+        return lat, count / (max(done_at) - t0)
+
+    plain_rate, lat_plain, err_plain = one_at_a_time(X32, "plain")
+    print(f"[serve] one-at-a-time plain f32: {plain_rate:.1f} solves/s", file=sys.stderr, flush=True)
+    same_rate = load * plain_rate
+    lat_fifo = fifo(X32, "plain", same_rate)
+    print(f"[serve] one-at-a-time plain f32 at {same_rate:.1f}/s offered: p50 {_pct(lat_fifo, 50):.3f} ms "
+          f"p99 {_pct(lat_fifo, 99):.3f} ms", file=sys.stderr, flush=True)
+    del X32
+    torch.cuda.empty_cache()
+    prec_rate, _, _ = one_at_a_time(Xb, precision)
+    print(f"[serve] one-at-a-time {precision} on bf16: {prec_rate:.1f} solves/s", file=sys.stderr, flush=True)
+
+    budget = int(budget_gib * (1 << 30))
+    with rb.Server(budget, slots=slots) as sv:
+        for w, x in list(zip(reqs, Xb))[:2 * slots]:
+            sv.wait(sv.submit(x, w["ranks"], precision=precision, **args_of(w)))
+        t0 = time.perf_counter()
+        tickets = [sv.submit(x, w["ranks"], precision=precision, **args_of(w)) for w, x in zip(reqs, Xb)]
+        res = [sv.wait(t) for t in tickets]
+        sat_rate = count / (time.perf_counter() - t0)
+        err_served = [r[2] for r in res]
+        print(f"[serve] saturated: {sat_rate:.1f} solves/s", file=sys.stderr, flush=True)
+        del res
+        lat_same, _ = served_poisson(sv, same_rate)
+        print(f"[serve] served at {same_rate:.1f}/s offered: p50 {_pct(lat_same, 50):.3f} ms "
+              f"p99 {_pct(lat_same, 99):.3f} ms", file=sys.stderr, flush=True)
+        rate = load * sat_rate
+        lat, achieved = served_poisson(sv, rate)
     ex = [(a - b) / b for a, b in zip(err_served, err_plain) if b > 0]
     out = {"requests": count, "mix": "3rd-order, dims U{32..256}, ranks U{4..32} capped at dim/2, bf16, p=5, "
                                       "q U{1,2,3}, SNR U[5,30] dB",
@@ -303,6 +333,13 @@ def serving_leg(torch, rb, synth, count, slots, budget_gib, load, precision):
            "solves_per_s": round(sat_rate, 2),
            "plain_one_at_a_time_solves_per_s": round(plain_rate, 2),
            "speedup_vs_plain": round(sat_rate / plain_rate, 3),
+           "same_precision_one_at_a_time_solves_per_s": round(prec_rate, 2),
+           "speedup_vs_same_precision": round(sat_rate / prec_rate, 3),
+           "same_offered_rate": {"offered_rate": round(same_rate, 2),
+                                 "served_p50_ms": round(_pct(lat_same, 50), 4),
+                                 "served_p99_ms": round(_pct(lat_same, 99), 4),
+                                 "plain_fifo_p50_ms": round(_pct(lat_fifo, 50), 4),
+                                 "plain_fifo_p99_ms": round(_pct(lat_fifo, 99), 4)},
            "offered_rate": round(rate, 2), "achieved_rate": round(achieved, 2),
            "p50_ms": round(_pct(lat, 50), 4), "p99_ms": round(_pct(lat, 99), 4),
            "plain_p50_ms": round(_pct(lat_plain, 50), 4), "plain_p99_ms": round(_pct(lat_plain, 99), 4),
@@ -343,7 +380,8 @@ def main():
                     help="hardware queues of the process (default: one per slot, at most 32)")
     ap.add_argument("--serve-budget-gib", type=float, default=16.0)
     ap.add_argument("--serve-load", type=float, default=0.7,
-                    help="Poisson arrival rate as a fraction of the saturated rate")
+                    help="Poisson arrival rate as a fraction of a capacity: of the one-at-a-time float32 rate for "
+                         "the same-rate comparison, and of the saturated rate for the served run")
     ap.add_argument("--serve-precision", default="plain")
     ap.add_argument("--serve-only", action="store_true")
     args = ap.parse_args()

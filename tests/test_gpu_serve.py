@@ -3,6 +3,9 @@ batch gives the same result when it is served in the mix as when it is
 solved alone by rbki_tucker; admission under a small HBM budget; rejection
 of oversize and invalid requests; latencies recorded.  One served request is
 also checked against the FP64 oracle."""
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -57,6 +60,37 @@ def test_each_request_is_the_same_alone_and_in_the_mix(env, precision):
         print(w["dims"], w["ranks"], w["q"], a[2], s[2], flush=True)
         assert identical(torch, a, s), (w["dims"], w["ranks"], w["q"])
         assert s[3] > 0.0
+
+
+def test_solves_overlap_at_the_default_queue_count(env):
+    # HIP's default of 4 hardware queues per process: a 4-slot server finishes
+    # a batch of small requests well before one slot does, so the slots'
+    # solves run together on the device rather than one after the other
+    torch, rb = env
+    assert int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) <= 4
+    reqs = mix(48, 48, 128, seed=31)
+    Xs = [make(torch, w) for w in reqs]
+    torch.cuda.synchronize()
+
+    def makespan(slots):
+        with rb.Server(1 << 30, slots=slots) as sv:
+            for X, w in list(zip(Xs, reqs))[:2 * slots]:
+                sv.wait(sv.submit(X, w["ranks"], p=w["p"], q=w["q"], seed=w["seeds"][1]))
+            best = None
+            for _ in range(2):
+                t0 = time.perf_counter()
+                tickets = [sv.submit(X, w["ranks"], p=w["p"], q=w["q"], seed=w["seeds"][1])
+                           for X, w in zip(Xs, reqs)]
+                for t in tickets:
+                    sv.wait(t)
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            return best
+
+    one, four = makespan(1), makespan(4)
+    print(f"48 requests: 1 slot {one * 1e3:.2f} ms, 4 slots {four * 1e3:.2f} ms, ratio {four / one:.3f}",
+          flush=True)
+    assert four <= 0.6 * one
 
 
 def test_admission_under_a_small_budget(env):
