@@ -143,6 +143,7 @@ struct Plan {
   double rate = 1.0;         // column sampling rate omega (Sec. 3.1)
   bool sequential = false;   // sequential truncation (ST-HOSVD form)
   bool one_stream = false;   // every mode on the caller's stream (no helper streams)
+  bool fused = false;        // every mode's Krylov chain in one persistent launch (small modes)
   bool any_sampled = false;
   int64_t maxM = 0;          // largest column sample
   size_t ybytes = 0;         // largest gathered sample
@@ -315,6 +316,10 @@ rbki_status make_plan(const rbki_params* prm, int xtype, Plan& P) {
     if (n != P.first_mode) { cur[n] = P.ranks[n]; mx = std::max(mx, prod(cur)); }
   for (int n = 1; n < P.N; ++n) { cur[n] = P.dims[n]; mx = std::max(mx, prod(cur)); }
   P.chain_elems = mx;
+  // small modes: the Krylov chains (Alg. 1 after the Gram pass, and Z) of
+  // all modes in one launch, one workgroup per mode
+  P.fused = !P.any_sampled;
+  for (int n = 0; n < P.N; ++n) P.fused = P.fused && krylov_chain_ok(P.m[n].I, P.m[n].S);
   return RBKI_OK;
 }
 
@@ -363,8 +368,9 @@ struct Buffers {
   void* xs[8] = {};
   void* xt = nullptr;      // bf16, I_N x rows_pad: the last mode, transposed and zero-padded
   void* u16 = nullptr;     // the first product's factor as bf16 [64][block rows]
-  Lane ln[kMaxLanes];
-  int lanes = 1;
+  Lane ln[8];
+  int lanes = 1;             // scratch sets of concurrently running modes
+  int chain_lanes = 1;       // scratch sets of the Krylov chains (one per mode in a fused plan)
   double* Qt[8] = {};      // per mode: S'_n x I_n basis rows
   double* Z[8] = {};       // per mode: S'_n x S'_n
   double* lam[8] = {};
@@ -407,8 +413,21 @@ void carve(const Plan& P, Arena& ar, Buffers& b) {
     }
   }
   b.lanes = mode_lanes(P);
-  for (int l = 0; l < b.lanes; ++l) {
+  b.chain_lanes = P.fused ? std::max(b.lanes, P.N) : b.lanes;
+  for (int l = 0; l < b.chain_lanes; ++l) {
     Lane& L = b.ln[l];
+    if (l >= b.lanes) {
+      // a fused plan's extra sets: chain buffers of their own; the sketch and
+      // Gram scratch of set 0 (those passes run one after the other)
+      L = b.ln[0];
+      L.C = (double*)ar.take((size_t)P.maxI * P.maxI * 8);
+      L.CQt = (double*)ar.take((size_t)P.maxSp * P.maxI * 8);
+      L.Yt = (double*)ar.take((size_t)P.maxS * P.maxI * 8);
+      L.Ytmp = (double*)ar.take((size_t)P.maxS * P.maxI * 8);
+      L.Pm = (double*)ar.take((size_t)P.maxS * P.maxSp * 8);
+      L.G = (double*)ar.take((size_t)P.maxS * P.maxS * 8);
+      continue;
+    }
     if (P.need_pad && P.oblk_bytes) {
       if (!P.need_fp8) L.oblk = ar.take((size_t)P.oblk_bytes);   // the fp8 sketch is made in one pass
       if (P.need_fp8) {
@@ -686,10 +705,48 @@ rbki_status run_mode_chain(const Plan& P, const Buffers& b, int lane, int n, boo
   return RBKI_OK;
 }
 
+// The persistent chain of mode n on scratch set `lane` (fused plans): blocks
+// j0..j1 of the basis, then Z over its first zr rows (zr = 0: no Z).
+ChainJob chain_job(const Plan& P, const Buffers& b, int lane, int n, int zr) {
+  const Lane& L = b.ln[lane];
+  const ModeGeom& g = P.m[n];
+  ChainJob j;
+  j.C = L.C;
+  j.Yt = L.Yt;
+  j.Ytmp = L.Ytmp;
+  j.Pm = L.Pm;
+  j.G = L.G;
+  j.CQ = L.CQt;
+  j.Qt = b.Qt[n];
+  j.Z = b.Z[n];
+  j.used = b.used + (size_t)n * (P.q + 2);
+  j.I = (int)g.I;
+  j.S = (int)g.S;
+  j.zr = zr;
+  return j;
+}
+
+rbki_status run_chains(const Plan& P, const ChainJob* jobs, int njobs, int j0, int j1, hipStream_t st) {
+  ChainArgs a = {};
+  a.power = P.power ? 1 : 0;
+  for (int i = 0; i < njobs; ++i) a.job[i] = jobs[i];
+  a.j0 = j0;
+  a.j1 = j1;
+  a.tau_rel = TAU_REL;
+  a.tau_abs = TAU_ABS;
+  ProfScope ps("chain", st);
+  HIPCHK(launch_krylov_chain(a, njobs, st));
+  return RBKI_OK;
+}
+
 rbki_status run_mode(const Plan& P, const Buffers& b, int lane, const void* xsrc, int n, bool with_factor,
                      hipStream_t st) {
   rbki_status s = run_mode_heavy(P, b, lane, xsrc, n, st);
   if (s != RBKI_OK) return s;
+  if (P.fused) {
+    const ChainJob j = chain_job(P, b, lane, n, with_factor ? (int)P.m[n].Sp : 0);
+    return run_chains(P, &j, 1, 0, P.q, st);
+  }
   return run_mode_chain(P, b, lane, n, with_factor, st);
 }
 
@@ -1115,6 +1172,17 @@ static hipStream_t lane_stream(int lane) {
 // that it runs beside the later modes' work.
 static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, hipStream_t st,
                              bool inline_factors = false) {
+  if (P.fused) {
+    // the sketch and Gram passes one after the other, each into its mode's
+    // set, then every mode's Krylov chain in one launch
+    ChainJob jobs[8];
+    for (int n = 0; n < P.N; ++n) {
+      rbki_status s = run_mode_heavy(P, b, n, xsrc, n, st);
+      if (s != RBKI_OK) return s;
+      jobs[n] = chain_job(P, b, n, n, (int)P.m[n].Sp);
+    }
+    return run_chains(P, jobs, P.N, 0, P.q, st);
+  }
   const int lanes = (P.concurrent || P.one_stream) ? 1 : b.lanes;
   hipStream_t ls[kMaxLanes] = {st, st, st};
   hipEvent_t ev[kMaxLanes] = {};
@@ -1370,6 +1438,13 @@ rbki_status adaptive_impl(const void* X, int xtype, const rbki_params* prm, doub
     Cm[n] = (double*)(ws + AL.C[n]);
     CYm[n] = g.sampled ? (double*)(ws + AL.CY[n]) : nullptr;
     CQm[n] = (double*)(ws + AL.CQ[n]);
+    if (P.fused) {
+      // each mode's Gram pass into its own chain set, which keeps C and the
+      // products C Q for every step
+      s = run_mode_heavy(P, b, n, X, n, st);
+      if (s != RBKI_OK) return s;
+      continue;
+    }
     // the Gram pass (and the sample's), kept for every step; block 0
     s = run_mode_heavy(P, b, 0, X, n, st);
     if (s != RBKI_OK) return s;
@@ -1383,9 +1458,22 @@ rbki_status adaptive_impl(const void* X, int xtype, const rbki_params* prm, doub
   double fit_prev = 0.0, err = 0.0;
   int t = 0;
   for (;; ++t) {
+    if (P.fused) {
+      // block t of every mode's basis and Z over the t + 1 blocks, in one
+      // launch: the same steps as the fixed-q launch, one block at a time
+      ChainJob jobs[8];
+      for (int n = 0; n < P.N; ++n) jobs[n] = chain_job(P, b, n, n, (int)(P.m[n].S * (t + 1)));
+      s = run_chains(P, jobs, P.N, t, t, st);
+      if (s != RBKI_OK) return s;
+    }
     for (int n = 0; n < P.N; ++n) {
       const ModeGeom& g = P.m[n];
       const int64_t I = g.I, S = g.S, m = S * (t + 1);
+      if (P.fused) {
+        s = factor_single(P, b, n, st, m);
+        if (s != RBKI_OK) return s;
+        continue;
+      }
       if (t > 0) {
         // Krylov step t (Alg. 1); a mode that is not sampled takes C Q_{t-1}
         // from the products kept for Z
@@ -1457,7 +1545,7 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   // with concurrent modes, each mode's eigenproblem and factor (and the first
   // product of the core chain) run on its stream as soon as its Krylov basis
   // is done
-  bool inline_factors = !P.concurrent && !P.one_stream && b.lanes > 1;
+  bool inline_factors = !P.concurrent && !P.one_stream && !P.fused && b.lanes > 1;
   for (int n = 0; n < P.N; ++n) inline_factors = inline_factors && eig_top_ok(P.m[n].Sp, P.m[n].R);
   s = run_modes(P, b, xsrc, st, inline_factors);
   if (s != RBKI_OK) return s;

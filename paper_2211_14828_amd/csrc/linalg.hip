@@ -198,77 +198,68 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
 
 // CholeskyQR step for s <= 64 in one launch: Yout = L^{-1} Y where G = L L^T
 // (same drop rule as above: a dropped vector gets a zero row of Yout).
-// Every workgroup factors G itself: wave 0, lane i owning row i in
-// registers, runs a right-looking Cholesky; the update of step k reads the
-// finished column k from the lanes that hold it (v_readlane into scalar
-// registers), so no barriers or LDS round trips are needed.  Then each thread solves L y = Y(:, c) for one column c by forward
-// substitution, with y in registers and L read by LDS broadcast.  flags is
-// written by workgroup 0.  All global loads are issued before their use.
+// Every workgroup factors G itself in LDS: wave 0, lane i owning row i, runs
+// a left-looking Cholesky whose step k forms the Schur-complement column k as
+// G(i, k) - sum_{j<k} L(i, j) L(k, j), subtracting in increasing j (the
+// order of a right-looking update), and takes the pivot from lane k.  The
+// loops over k and j run at run time, so the factor is a few hundred
+// instructions whatever s is.  Then each thread solves L y = Y(:, c) for one
+// column c by forward substitution, with y in registers (unrolled to the size
+// bound SMAX) and L read by LDS broadcast.  The thread's column of Y is
+// loaded before the factor starts.  flags is written by workgroup 0.
 constexpr int CS_MAX = 64;
 
+template <int SMAX>
 __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s, const double* Y, int64_t n,
                                                          double* Yout, int* flags, const double* ref2,
                                                          double tau_rel, double tau_abs, DimBudget bud) {
-  __shared__ double Ls[CS_MAX][CS_MAX + 1];
-  __shared__ double dinv[CS_MAX];
-  __shared__ int keep[CS_MAX];
+  __shared__ double Ls[SMAX][SMAX + 1];
+  __shared__ double dinv[SMAX];
+  __shared__ int keep[SMAX];
   const int tid = threadIdx.x;
-  {
-    double g[CS_MAX * CS_MAX / 256];
-#pragma unroll
-    for (int t = 0; t < CS_MAX * CS_MAX / 256; ++t) {
-      const int e = tid + t * 256;
-      g[t] = e < s * s ? G[e] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < CS_MAX * CS_MAX / 256; ++t) {
-      const int e = tid + t * 256;
-      if (e < s * s) {
-        const int i = e / s, j = e - i * s;
-        Ls[i][j] = g[t];
-      }
-    }
+  for (int e = tid; e < s * s; e += 256) {
+    const int i = e / s, j = e - i * s;
+    Ls[i][j] = G[e];
   }
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + tid;
+  double y[SMAX];
+#pragma unroll
+  for (int k = 0; k < SMAX; ++k) y[k] = (k < s && c < n) ? Y[(int64_t)k * n + c] : 0.0;
   __syncthreads();
   if (tid < 64) {
     const int i = tid;
-    double mx = (ref2 && i < s) ? ref2[i] : 0.0;
+    const bool row = i < s;
+    double mx = (ref2 && row) ? ref2[i] : 0.0;
     mx = warp_max(mx);
     const double abs_floor = tau_abs * tau_abs * mx;
-    const double d0 = i < s ? Ls[i][i] : 0.0;
-    double row[CS_MAX];
-#pragma unroll
-    for (int j = 0; j < CS_MAX; ++j) row[j] = (i < s && j < s) ? Ls[i][j] : 0.0;
+    const double d0 = row ? Ls[i][i] : 0.0;
     const int64_t allowed = bud.allowed();
     int64_t nkept = 0;
-#pragma unroll
-    for (int k = 0; k < CS_MAX; ++k) {
-      if (k < s) {
-        const double v = row[k];                 // G(i, k) minus the earlier columns' terms
-        const double d = __shfl(v, k, 64);
-        const double dk0 = __shfl(d0, k, 64);
-        const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor) && nkept < allowed;
-        nkept += kp;
-        const double piv = kp ? sqrt(d) : 0.0;
-        const double inv = kp ? 1.0 / piv : 0.0;
-        const double lik = (i > k && i < s) ? v * inv : (i == k ? piv : 0.0);
-        row[k] = lik;
-        if (i == k) {
-          keep[k] = kp;
-          dinv[k] = inv;
-        }
-        // L(j, k) is lane j's lik: read into scalar registers (no LDS trip)
-        const int lhi = __double2hiint(lik), llo = __double2loint(lik);
-#pragma unroll
-        for (int j = k + 1; j < CS_MAX; ++j) {
-          const double cj = __hiloint2double(__builtin_amdgcn_readlane(lhi, j), __builtin_amdgcn_readlane(llo, j));
-          row[j] -= lik * cj;
-        }
+    for (int k = 0; k < s; ++k) {
+      // column k of the Schur complement: lanes k..s-1 (the others discard it)
+      double v = (row && i >= k) ? Ls[i][k] : 0.0;
+      if (row && i >= k)
+        for (int j = 0; j < k; ++j) v -= Ls[i][j] * Ls[k][j];
+      const double d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), k),
+                                        __builtin_amdgcn_readlane(__double2loint(v), k));
+      const double dk0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(d0), k),
+                                          __builtin_amdgcn_readlane(__double2loint(d0), k));
+      const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor) && nkept < allowed;
+      nkept += kp;
+      const double piv = kp ? sqrt(d) : 0.0;
+      const double inv = kp ? 1.0 / piv : 0.0;
+      if (row && i > k) Ls[i][k] = v * inv;
+      if (i == k) {
+        Ls[k][k] = piv;
+        keep[k] = kp;
+        dinv[k] = inv;
       }
+      // the column is read by every lane at the next step: the wave's LDS
+      // writes complete before its later reads
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-#pragma unroll
-    for (int j = 0; j < CS_MAX; ++j)
-      if (i < s && j < s) Ls[i][j] = j <= i ? row[j] : 0.0;
     // every workgroup reads the count of earlier blocks and writes a
     // different slot, so they agree without synchronising
     if (blockIdx.x == 0 && i == 0) bud.record(nkept);
@@ -276,13 +267,9 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
   __syncthreads();
   if (blockIdx.x == 0)
     for (int i = tid; i < s; i += blockDim.x) flags[i] = keep[i];
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + tid;
   if (c >= n) return;
-  double y[CS_MAX];
 #pragma unroll
-  for (int k = 0; k < CS_MAX; ++k) y[k] = k < s ? Y[(int64_t)k * n + c] : 0.0;
-#pragma unroll
-  for (int k = 0; k < CS_MAX; ++k) {
+  for (int k = 0; k < SMAX; ++k) {
     if (k < s) {
       double a0 = y[k], a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
@@ -296,8 +283,6 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
       for (int j = k & ~3; j < k; ++j) a0 -= Ls[k][j] * y[j];
       y[k] = ((a0 + a1) + (a2 + a3)) * dinv[k];   // zero for a dropped vector
       Yout[(int64_t)k * n + c] = y[k];
-    } else {
-      y[k] = 0.0;
     }
   }
 }
@@ -854,8 +839,16 @@ hipError_t chol_orth(double* Y, double* Yout, int64_t s, int64_t n, double* G, d
   hipError_t e = dgemm(0, 1, s, s, n, 1.0, Y, n, Y, n, 0.0, G, s, st);
   if (e != hipSuccess) return e;
   if (s <= CS_MAX) {
-    hipLaunchKernelGGL(chol_solve_kernel, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, G, (int)s, Y, n, Yout,
-                       flags, ref2, tau_rel, tau_abs, bud);
+    const dim3 grid((unsigned)ceil_div(n, 256));
+    if (s <= 16)
+      hipLaunchKernelGGL(chol_solve_kernel<16>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
+                         tau_abs, bud);
+    else if (s <= 32)
+      hipLaunchKernelGGL(chol_solve_kernel<32>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
+                         tau_abs, bud);
+    else
+      hipLaunchKernelGGL(chol_solve_kernel<64>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
+                         tau_abs, bud);
     return hipGetLastError();
   }
   if (s <= CHOL_MAX) {

@@ -192,6 +192,36 @@ hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* U
                            size_t work_bytes, hipStream_t s, bool bf16_products = false);
 size_t residual_work_bytes(int64_t I, int64_t J);
 
+// ------------------------------------------------------------ chain.hip
+// The Krylov chain of one mode (blocks j0..j1 of Alg. 1 by the Gram route,
+// then Z over the first zr basis rows) run by one workgroup; one launch runs
+// up to kChainJobs such instances.  Every pointer is the instance's own
+// (float64, row-major): C (I x I) and, for block 0, W^T in Yt (S x I) as left
+// by the Gram pass; scratch Yt, Ytmp (S x I), Pm (S x Sp), G (S x S); outputs
+// Qt and CQ (rows j S .. (j+1) S - 1 of block j, I wide; CQ holds Q_j C) and
+// Z (zr x zr); used: the q + 2 direction counters.
+constexpr int kChainJobs = 8;
+struct ChainJob {
+  const double* C;
+  double* Yt;
+  double* Ytmp;
+  double* Pm;
+  double* G;
+  double* CQ;
+  double* Qt;
+  double* Z;
+  int* used;
+  int I, S, zr;
+};
+struct ChainArgs {
+  ChainJob job[kChainJobs];
+  int j0, j1;
+  int power;                 // power iteration: one block, replaced at every step
+  double tau_rel, tau_abs;
+};
+bool krylov_chain_ok(int64_t I, int64_t S);
+hipError_t launch_krylov_chain(const ChainArgs& a, int njobs, hipStream_t st);
+
 // Element conversions of the whole tensor.
 hipError_t convert_tensor(int src_elem, const void* src, int dst_elem, void* dst, int64_t n,
                           hipStream_t s);
