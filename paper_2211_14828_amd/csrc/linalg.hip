@@ -198,15 +198,15 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
 
 // CholeskyQR step for s <= 64 in one launch: Yout = L^{-1} Y where G = L L^T
 // (same drop rule as above: a dropped vector gets a zero row of Yout).
-// Every workgroup factors G itself in LDS: wave 0, lane i owning row i, runs
-// a left-looking Cholesky whose step k forms the Schur-complement column k as
-// G(i, k) - sum_{j<k} L(i, j) L(k, j), subtracting in increasing j (the
-// order of a right-looking update), and takes the pivot from lane k.  The
-// loops over k and j run at run time, so the factor is a few hundred
-// instructions whatever s is.  Then each thread solves L y = Y(:, c) for one
-// column c by forward substitution, with y in registers (unrolled to the size
-// bound SMAX) and L read by LDS broadcast.  The thread's column of Y is
-// loaded before the factor starts.  flags is written by workgroup 0.
+// Every workgroup factors G itself: wave 0, lane i owning row i in
+// registers, runs a right-looking Cholesky; the update of step k reads the
+// finished column k from the lanes that hold it (v_readlane into scalar
+// registers), so no barriers or LDS round trips are needed.  Then each thread
+// solves L y = Y(:, c) for one column c by forward substitution, with y in
+// registers and L read by LDS broadcast.  Both loops are unrolled to the size
+// bound SMAX (16, 32, 48 or 64, the smallest that holds s), which keeps the
+// code of the common sizes small.  flags is written by workgroup 0.  The
+// thread's column of Y is loaded before the factor starts.
 constexpr int CS_MAX = 64;
 
 template <int SMAX>
@@ -228,38 +228,43 @@ __global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s,
   __syncthreads();
   if (tid < 64) {
     const int i = tid;
-    const bool row = i < s;
-    double mx = (ref2 && row) ? ref2[i] : 0.0;
+    double mx = (ref2 && i < s) ? ref2[i] : 0.0;
     mx = warp_max(mx);
     const double abs_floor = tau_abs * tau_abs * mx;
-    const double d0 = row ? Ls[i][i] : 0.0;
+    const double d0 = i < s ? Ls[i][i] : 0.0;
+    double row[SMAX];
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j) row[j] = (i < s && j < s) ? Ls[i][j] : 0.0;
     const int64_t allowed = bud.allowed();
     int64_t nkept = 0;
-    for (int k = 0; k < s; ++k) {
-      // column k of the Schur complement: lanes k..s-1 (the others discard it)
-      double v = (row && i >= k) ? Ls[i][k] : 0.0;
-      if (row && i >= k)
-        for (int j = 0; j < k; ++j) v -= Ls[i][j] * Ls[k][j];
-      const double d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), k),
-                                        __builtin_amdgcn_readlane(__double2loint(v), k));
-      const double dk0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(d0), k),
-                                          __builtin_amdgcn_readlane(__double2loint(d0), k));
-      const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor) && nkept < allowed;
-      nkept += kp;
-      const double piv = kp ? sqrt(d) : 0.0;
-      const double inv = kp ? 1.0 / piv : 0.0;
-      if (row && i > k) Ls[i][k] = v * inv;
-      if (i == k) {
-        Ls[k][k] = piv;
-        keep[k] = kp;
-        dinv[k] = inv;
+#pragma unroll
+    for (int k = 0; k < SMAX; ++k) {
+      if (k < s) {
+        const double v = row[k];                 // G(i, k) minus the earlier columns' terms
+        const double d = __shfl(v, k, 64);
+        const double dk0 = __shfl(d0, k, 64);
+        const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor) && nkept < allowed;
+        nkept += kp;
+        const double piv = kp ? sqrt(d) : 0.0;
+        const double inv = kp ? 1.0 / piv : 0.0;
+        const double lik = (i > k && i < s) ? v * inv : (i == k ? piv : 0.0);
+        row[k] = lik;
+        if (i == k) {
+          keep[k] = kp;
+          dinv[k] = inv;
+        }
+        // L(j, k) is lane j's lik: read into scalar registers (no LDS trip)
+        const int lhi = __double2hiint(lik), llo = __double2loint(lik);
+#pragma unroll
+        for (int j = k + 1; j < SMAX; ++j) {
+          const double cj = __hiloint2double(__builtin_amdgcn_readlane(lhi, j), __builtin_amdgcn_readlane(llo, j));
+          row[j] -= lik * cj;
+        }
       }
-      // the column is read by every lane at the next step: the wave's LDS
-      // writes complete before its later reads
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+#pragma unroll
+    for (int j = 0; j < SMAX; ++j)
+      if (i < s && j < s) Ls[i][j] = j <= i ? row[j] : 0.0;
     // every workgroup reads the count of earlier blocks and writes a
     // different slot, so they agree without synchronising
     if (blockIdx.x == 0 && i == 0) bud.record(nkept);
@@ -845,6 +850,9 @@ hipError_t chol_orth(double* Y, double* Yout, int64_t s, int64_t n, double* G, d
                          tau_abs, bud);
     else if (s <= 32)
       hipLaunchKernelGGL(chol_solve_kernel<32>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
+                         tau_abs, bud);
+    else if (s <= 48)
+      hipLaunchKernelGGL(chol_solve_kernel<48>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
                          tau_abs, bud);
     else
       hipLaunchKernelGGL(chol_solve_kernel<64>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
