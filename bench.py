@@ -473,7 +473,7 @@ def main():
     kernel = "gram_pipe_kernel" if gram_dtype in ("bf16", "fp8") else "gram_sketch_kernel"
     peak = PEAK_TFLOPS[gram_dtype]
     stages = {}
-    for k in ("omega", "gram", "eig", "ttm", "error", "convert"):
+    for k in ("omega", "gram", "chain", "eig", "ttm", "error", "convert"):
         n, t = rb.profile_read(k)
         if n:
             stages[k] = round(t / args.steps, 4)
