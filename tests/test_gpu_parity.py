@@ -151,6 +151,12 @@ CASES = [
     ((72, 52, 228), (23, 15, 19), 5, 3, "float32", "plain", "capped"),
     ((172, 237, 112), (8, 32, 24), 5, 3, "bfloat16", "mixed_bf16", "capped"),
     ((5, 300, 7), (2, 3, 2), 5, 2, "float64", "plain", "thin"),
+    # the persistent chain at its limits (I = 256, sketches of 50..60, the
+    # widest register bound), and one mode past I = 256 (every mode then takes
+    # the separate launches)
+    ((256, 200, 180), (50, 45, 40), 10, 2, "float64", "plain", "chain64"),
+    ((256, 200, 180), (50, 45, 40), 10, 2, "float32", "plain", "chain64"),
+    ((257, 60, 50), (10, 8, 6), 5, 2, "float64", "plain", "chain_edge"),
 ]
 
 

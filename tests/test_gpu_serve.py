@@ -93,6 +93,29 @@ def test_solves_overlap_at_the_default_queue_count(env):
     assert four <= 0.6 * one
 
 
+def test_served_requests_with_a_multi_workgroup_eigen_reduction(env):
+    # Z wider than about 165 (here 180, 165 and 150) is tridiagonalised by
+    # several workgroups that meet at a bounded barrier; beside other solves
+    # that reduction takes an ordinary launch.  Each request equals its solve
+    # alone, and meets the oracle.
+    torch, rb = env
+    reqs = []
+    for i in range(4):
+        w = dict(dims=(256, 200, 180), ranks=(50, 45, 40), p=10, q=2, snr=12.0, dtype="bfloat16", kind="tucker",
+                 seeds=(3 * 10 ** 6 + i, 4 * 10 ** 6 + i), arrival=0.0)
+        reqs.append(w)
+    Xs = [make(torch, w) for w in reqs]
+    alone = [solve_alone(rb, X, w, "plain") for X, w in zip(Xs, reqs)]
+    with rb.Server(1 << 30, slots=4) as sv:
+        tickets = [sv.submit(X, w["ranks"], p=w["p"], q=w["q"], seed=w["seeds"][1]) for X, w in zip(Xs, reqs)]
+        served = [sv.wait(t) for t in tickets]
+    for w, a, s_ in zip(reqs, alone, served):
+        assert identical(torch, a, s_), w["seeds"]
+    Xh = Xs[0].to(torch.float64).cpu().numpy()
+    _, _, e_o = rbki_tucker(Xh, reqs[0]["ranks"], reqs[0]["p"], reqs[0]["q"], reqs[0]["seeds"][1])
+    assert abs(served[0][2] - e_o) <= 1e-3 * e_o
+
+
 def test_admission_under_a_small_budget(env):
     torch, rb = env
     reqs = mix(10, 64, 200, seed=12)
