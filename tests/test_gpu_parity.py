@@ -314,7 +314,8 @@ def _top_case(kind, n, rng):
 
 
 TOP_CASES = ([("gauss", n, k) for n, k in [(1, 1), (2, 2), (3, 1), (5, 5), (7, 3), (63, 20), (64, 64), (65, 10),
-                                            (128, 40), (130, 65), (300, 50), (448, 60), (449, 30), (512, 100)]]
+                                            (128, 40), (130, 65), (180, 20), (256, 64), (300, 50), (305, 60),
+                                            (306, 30), (448, 60), (449, 30), (512, 100)]]
              + [(kind, n, k) for kind in ("decay", "repeated", "lowrank", "diagonal", "zero")
                 for n, k in [(40, 12), (300, 50)]])
 
