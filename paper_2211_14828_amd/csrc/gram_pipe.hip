@@ -865,6 +865,11 @@ __device__ inline int64_t lead_rowid(const CopyModes& cm, int m, IT r, IT col, I
   return (int64_t)kt * cm.ipad[m] + i;
 }
 
+constexpr int COPY_HG = 64;      // h blocks (of 4) per 256 rows of mode N-3
+
+// Workgroup ids of the copy: whole runs of 8 (one per XCD) x COPY_HG slots.
+__host__ __device__ inline int64_t copy_ids(int64_t ngroups) { return (ngroups + 7) / 8 * 8 * COPY_HG; }
+
 template <class T, int E, class IT>
 __global__ void __launch_bounds__(256) block_copy_kernel(const T* X, int64_t H_, int64_t L_, int64_t IN_,
                                                          int64_t INp_, bool vec, CopyModes cm, bf16_t* xpad) {
@@ -880,12 +885,21 @@ __global__ void __launch_bounds__(256) block_copy_kernel(const T* X, int64_t H_,
   const IT nlb = Lp / 64, nlead = INp / 64;
   const IT ncb = (IT)((cm.last ? cm.last_ipad : INp_) / 64);
   const IT nhb = (H + HB - 1) / HB;
-  const int64_t ntile = (int64_t)nhb * nlb * ncb;
   const int t = threadIdx.x, rr = t >> 2, q = t & 3;
-  for (int64_t id = blockIdx.x; id < ntile; id += gridDim.x) {
-    const IT tk = (IT)id;
-    const IT cb = tk % ncb, rest = tk / ncb;
-    const IT lb = rest % nlb, hb = rest / nlb;
+  // Tile order.  Workgroups go to the chip's XCDs in turn by id (8 of them).
+  // A line of mode N-3's e4m3 scales holds bytes of the 64 h blocks of one
+  // 256-row tile (at one K tile); those 64 tiles take consecutive slots on
+  // one XCD, so that the line is completed in one L2 and written back whole.
+  // Ids past the tiles (a short last group of h blocks) do nothing.
+  const int64_t nhg = ((int64_t)nhb + COPY_HG - 1) / COPY_HG;
+  const int64_t ngroups = nhg * nlb * ncb;
+  const int64_t nids = copy_ids(ngroups);
+  for (int64_t id = blockIdx.x; id < nids; id += gridDim.x) {
+    const int64_t slot = id >> 3, grp = (slot / COPY_HG) * 8 + (id & 7);
+    if (grp >= ngroups) continue;                // the same for the whole workgroup
+    const IT cb = (IT)(grp % ncb), rest = (IT)(grp / ncb);
+    const IT lb = rest % nlb, hb = (rest / nlb) * (IT)COPY_HG + (IT)(slot % COPY_HG);
+    if (hb >= nhb) continue;
     const IT l = lb * 64 + (IT)rr, c = cb * 64 + (IT)q * 16;
     const bool ok = l < L;
     const bool lead = cb < nlead;              // the tile holds leading-mode columns
@@ -1160,7 +1174,7 @@ hipError_t launch_block_copies(int src_elem, int elem, const void* X, int order,
   }
   if (cm.n == 0 && !cm.last && !xpad) return hipSuccess;
   const int64_t ncols = cm.last ? cm.last_ipad : INp;
-  const int64_t ntile = ceil_div(H, 4) * (Lp / 64) * (ncols / 64);
+  const int64_t ntile = copy_ids(ceil_div(ceil_div(H, 4), COPY_HG) * (Lp / 64) * (ncols / 64));
   if (ntile <= 0) return hipSuccess;
   const int es = src_elem == E_F64 ? 8 : src_elem == E_F32 ? 4 : 2;
   const bool vec = vec_ok(X, IN, es);
