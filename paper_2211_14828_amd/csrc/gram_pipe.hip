@@ -999,8 +999,8 @@ __global__ void zero_pad_rows_kernel(char* out, unsigned char* scales, int64_t n
 // The e4m3 sketch in one pass.  Row r = (K tile kt, sketch row sv) of the
 // blocked Omega^T holds the values at padded columns jp = kt KT + kk, drawn
 // from the sketch stream at L = sv J + j (j the unpadded column; zero in
-// padded columns and rows past S), rounded to bf16 and then to e4m3 (the
-// scale of each run of 32 in the layout the Gram kernel reads).  A wave takes two rows,
+// padded columns and rows past S; gauss_pair_e4m3), rounded to bf16 and then
+// to e4m3 (the scale of each run of 32 in the layout the Gram kernel reads).  A wave takes two rows,
 // a lane two neighbouring columns (one draw of a Gaussian pair when L is even).
 template <class IT>
 __global__ void omega_fp8_kernel(uint64_t seed, uint32_t mode, int64_t S_, int64_t J_, int64_t B_, int64_t IN_,
@@ -1025,14 +1025,14 @@ __global__ void omega_fp8_kernel(uint64_t seed, uint32_t mode, int64_t S_, int64
     if (rowok && cols_left > 0) {
       const int64_t L = (int64_t)sv * J_ + (int64_t)j;
       float z0, z1;
-      gauss_pair_f32((uint64_t)(L >> 1), mode, 0u, seed, z0, z1);
+      gauss_pair_e4m3((uint64_t)(L >> 1), mode, 0u, seed, z0, z1);
       if ((L & 1) == 0) {
         v[0] = z0;
         v[1] = z1;
       } else {
         v[0] = z1;
         float w0, w1;
-        gauss_pair_f32((uint64_t)((L + 1) >> 1), mode, 0u, seed, w0, w1);
+        gauss_pair_e4m3((uint64_t)((L + 1) >> 1), mode, 0u, seed, w0, w1);
         v[1] = w0;
       }
       if (cols_left < 2) v[1] = 0.f;

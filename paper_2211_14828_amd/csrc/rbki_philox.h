@@ -92,4 +92,21 @@ __device__ inline void gauss_pair_f32(uint64_t m, uint32_t mode, uint32_t tag, u
   z_odd = r * s;
 }
 
+// The same pair for the block-scaled e4m3 sketch, whose values are rounded to
+// bfloat16 and then to 3-bit mantissas under a shared power-of-two scale:
+// uniforms from the first word of each half (u = (w + 1/2) 2^-32, in float),
+// the hardware base-2 logarithm, square root, and sine and cosine of an
+// argument in turns (sin(2 pi a)).  The values follow the stream above to
+// about 1e-6, far below the bfloat16 step of 2^-8.
+__device__ inline void gauss_pair_e4m3(uint64_t m, uint32_t mode, uint32_t tag, uint64_t seed,
+                                       float& z_even, float& z_odd) {
+  PhiloxOut o = philox4x32_10((uint32_t)m, (uint32_t)(m >> 32), mode, tag, (uint32_t)seed,
+                              (uint32_t)(seed >> 32));
+  const float u1 = fmaf((float)o.w0, 0x1p-32f, 0x1p-33f);
+  const float a = fmaf((float)o.w2, 0x1p-32f, 0x1p-33f);
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));   // -2 ln 2 log2 u1
+  z_even = r * __builtin_amdgcn_cosf(a);
+  z_odd = r * __builtin_amdgcn_sinf(a);
+}
+
 }  // namespace rbki
