@@ -18,6 +18,13 @@
 // Workgroups are dispatched round-robin over the 8 XCDs.  When the split count
 // is a multiple of 8, all tiles of one split are mapped to the same XCD so the
 // slab of X that they share is fetched from HBM once into that XCD's L2.
+//
+// Thin modes (float32, I <= 64 and S <= 64, e.g. the 64-row modes of a 64^5
+// tensor) use one 128 x 64 output tile instead of two 128 x 128 ones: the
+// staged operand holds the mode's rows (0..63) and the sketch rows (64..127),
+// the other operand is its first 64 rows, so the tile is [C; W^T] and a wave
+// computes 64 x 32 of it.  Two thirds of its products are wanted, against a
+// sixth for the square tiles.
 #include "rbki_kernels.h"
 #include "rbki_mma.h"
 #include "rbki_philox.h"
@@ -154,6 +161,166 @@ __device__ inline void decode_tile(const GramArgs& g, int tile, int& ti, int& tj
   }
 }
 
+// Thin tile staging (float32): chunk j < 2 of a thread is one of 512 chunks
+// of the mode's 64 rows, j >= 2 one of the sketch's 64 rows.
+struct ThinStage {
+  uint4 chunk[4];
+  unsigned valid;
+};
+
+template <bool VEC>
+__device__ inline void load_thin(ThinStage& st, const GramArgs& g, int64_t a, int64_t b0, int64_t kvalid) {
+  const float* X = (const float*)g.X;
+  const float* O = (const float*)g.omegaT;
+  const int tid = threadIdx.x;
+  st.valid = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = tid + 256 * (j & 1);
+    if (j < 2 && g.B == 1) {
+      // the last mode: rows of X_(n) are the contiguous index; chunk c covers
+      // 4 consecutive rows at one k
+      const int kk = c >> 4, row = (c & 15) * 4;
+      const bool ok = kk < kvalid && row < g.I;
+      if (VEC) {
+        const int64_t rc = row < g.I ? row : g.I - 4;
+        const int kc = kk < kvalid ? kk : 0;
+        st.chunk[j] = *(const uint4*)(X + (b0 + kc) * g.I + rc);
+      } else {
+        union { uint4 v; float e[4]; } u;
+        u.v = make_uint4(0, 0, 0, 0);
+        if (kk < kvalid) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (row + e < g.I) u.e[e] = X[(b0 + kk) * g.I + row + e];
+        }
+        st.chunk[j] = u.v;
+      }
+      st.valid |= ok ? 1u << j : 0u;
+    } else {
+      // row c / 8, k offset (c % 8) * 4; the mode's rows or the sketch's
+      const int row = c >> 3, kk = (c & 7) * 4;
+      const bool om = j >= 2;
+      const int64_t nrows = om ? g.S : g.I;
+      const bool ok = row < nrows && kk < kvalid;
+      const int64_t kbase = g.B > 1 ? a * g.B + b0 : b0;
+      if (VEC) {
+        const int64_t rc = row < nrows ? row : nrows - 1;
+        const int kc = kk < kvalid ? kk : 0;
+        st.chunk[j] = om ? *(const uint4*)(O + rc * g.J + kbase + kc)
+                         : *(const uint4*)(X + (a * g.I + rc) * g.B + b0 + kc);
+      } else {
+        union { uint4 v; float e[4]; } u;
+        u.v = make_uint4(0, 0, 0, 0);
+        if (row < nrows) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (kk + e < kvalid)
+              u.e[e] = om ? O[(int64_t)row * g.J + kbase + kk + e] : X[(a * g.I + row) * g.B + b0 + kk + e];
+        }
+        st.chunk[j] = u.v;
+      }
+      st.valid |= ok ? 1u << j : 0u;
+    }
+  }
+}
+
+__device__ inline void store_thin(const ThinStage& st, const GramArgs& g, char* lds) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = tid + 256 * (j & 1);
+    const uint4 v = ((st.valid >> j) & 1u) ? st.chunk[j] : make_uint4(0, 0, 0, 0);
+    if (j < 2 && g.B == 1) {
+      const int kk = c >> 4, row = (c & 15) * 4;
+      union { uint4 v; float e[4]; } u;
+      u.v = v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) *(float*)(lds + (row + e) * LDS_ROW + kk * 4) = u.e[e];
+    } else {
+      const int row = (c >> 3) + (j >= 2 ? 64 : 0), kk = (c & 7) * 4;
+      *(uint4*)(lds + row * LDS_ROW + kk * 4) = v;
+    }
+  }
+}
+
+// One K tile of the thin product for a wave's 64 x 32 block: rows wr + 32 m
+// + (lane % 32) of the staged operand, columns wc + (lane % 32) of its first
+// 64 rows (the 32x32 layout of rbki_mma.h, blocks m = 0, 1).
+__device__ inline void thin_step(f32x16_t (&c)[2], const char* lds, int lane, int wr, int wc) {
+  const int half = lane >> 5, r = lane & 31;
+  float a[2][16], b[16];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const float4* pa = (const float4*)(lds + (wr + m * 32 + r) * LDS_ROW + half * 64);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 v = pa[q];
+      a[m][4 * q] = v.x; a[m][4 * q + 1] = v.y; a[m][4 * q + 2] = v.z; a[m][4 * q + 3] = v.w;
+    }
+  }
+  const float4* pb = (const float4*)(lds + (wc + r) * LDS_ROW + half * 64);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float4 v = pb[q];
+    b[4 * q] = v.x; b[4 * q + 1] = v.y; b[4 * q + 2] = v.z; b[4 * q + 3] = v.w;
+  }
+#pragma unroll
+  for (int t = 0; t < 16; ++t)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) c[m] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[m][t], b[t], c[m], 0, 0, 0);
+}
+
+template <bool VEC>
+__device__ inline void thin_tile(const GramArgs& g, int split, char (&lds)[2][2][TILE * LDS_ROW]) {
+  constexpr int BK = Mma<E_F32>::BK;
+  const int64_t kt0 = (int64_t)split * g.nkt / g.splits;
+  const int64_t kt1 = (int64_t)(split + 1) * g.nkt / g.splits;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 32;
+  f32x16_t acc[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[m][v] = 0.f;
+  ThinStage st;
+  auto load = [&](int64_t kt) {
+    int64_t a, b0, kv;
+    if (g.B > 1) {
+      a = kt / g.nbt;
+      b0 = (kt - a * g.nbt) * BK;
+      kv = g.B - b0 < BK ? g.B - b0 : BK;
+    } else {
+      a = 0;
+      b0 = kt * BK;
+      kv = g.A - b0 < BK ? g.A - b0 : BK;
+    }
+    load_thin<VEC>(st, g, a, b0, kv);
+  };
+  if (kt0 < kt1) {
+    load(kt0);
+    store_thin(st, g, lds[0][0]);
+    __syncthreads();
+    for (int64_t kt = kt0; kt < kt1; ++kt) {
+      const int buf = (int)((kt - kt0) & 1);
+      const bool more = kt + 1 < kt1;
+      if (more) load(kt + 1);
+      thin_step(acc, lds[buf][0], lane, wr, wc);
+      if (more) store_thin(st, g, lds[buf ^ 1][0]);
+      __syncthreads();
+    }
+  }
+  // rows 0..63: C (row i, column j); rows 64..127: W^T (row 64 + s, column i)
+  float* out = (float*)g.partial + (int64_t)split * (TILE * TILE);
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = wr + m * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      out[row * TILE + wc + (lane & 31)] = acc[m][v];
+    }
+}
+
 template <int E, bool VEC>
 __global__ void __launch_bounds__(256, E == E_F64 ? 1 : 2) gram_sketch_kernel(GramArgs g) {
   typedef Mma<E> M;
@@ -161,6 +328,13 @@ __global__ void __launch_bounds__(256, E == E_F64 ? 1 : 2) gram_sketch_kernel(Gr
   constexpr int BK = M::BK;
   __shared__ __attribute__((aligned(16))) char lds[2][2][TILE * LDS_ROW];
 
+  if constexpr (E == E_F32) {
+    if (g.thin) {
+      // one tile: the split is the workgroup (the XCD map gives the same)
+      thin_tile<VEC>(g, (int)blockIdx.x, lds);
+      return;
+    }
+  }
   // workgroup -> (split, tile)
   const int w = blockIdx.x;
   int split, tile;
@@ -256,6 +430,11 @@ __global__ void gram_reduce_kernel(GramArgs g, double* C, double* Wt) {
         tile = tj * (tj + 1) / 2 + ti;
         idx = (j - tj * TILE) * TILE + (i - ti * TILE);
       }
+    } else if (g.thin) {
+      int64_t f = e - nC;
+      int64_t s = f / g.I, i = f - s * g.I;
+      tile = 0;
+      idx = (64 + s) * TILE + i;
     } else {
       int64_t f = e - nC;
       int64_t s = f / g.I, i = f - s * g.I;
@@ -345,6 +524,11 @@ GramArgs gram_plan(int elem, int64_t A, int64_t I, int64_t B, int S, int cu_coun
   g.ntri = g.nt * (g.nt + 1) / 2;
   g.nw = S > 0 ? (int)ceil_div(S, TILE) : 0;
   g.ntiles = g.ntri + g.nt * g.nw;
+  g.thin = (elem == E_F32 && I <= 64 && S >= 1 && S <= 64) ? 1 : 0;
+  if (g.thin) {
+    g.nw = 0;
+    g.ntiles = 1;
+  }
   const int bk = gram_bk(elem);
   if (B > 1) {
     g.nbt = ceil_div(B, bk);
