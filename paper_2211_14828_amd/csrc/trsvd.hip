@@ -10,8 +10,10 @@
 //      gives core k from its leading r_k left singular vectors (reshaped to
 //      (r_{k-1}, S_k, r_k)) and the next remainder U^T M;
 //   3. the last remainder is core N, (r_{N-1}, S_N, r_0).
-// Left singular vectors come from the eigenvectors of the Gram matrix M M^T
-// (one-sided Jacobi), all in float64, each signed so that its largest-
+// Left singular vectors come from the eigenvectors of the Gram matrix M M^T,
+// only the leading ones each step keeps (the leading-eigenpair solver:
+// tridiagonal reduction, bisection, inverse iteration; one-sided Jacobi for
+// Gram matrices beyond its sizes), all in float64, each signed so that its largest-
 // magnitude entry is positive: with r_0 > 1 the first step files vector c
 // under the pair (a0, a1), and a sign change there is not an orthogonal change
 // of the next unfolding, so the sweep is only a function of G once signs are
@@ -170,7 +172,7 @@ size_t tr_svd_work_bytes(int N, const int64_t* S, const int64_t* r) {
   add((size_t)maxm * maxm * 8);
   add((size_t)maxm * 8);
   add((size_t)maxm * maxm * 8);
-  add(jacobi_work_bytes(maxm));
+  add(std::max(jacobi_work_bytes(maxm), eig_top_ok(maxm, maxm) ? eig_top_work_bytes(maxm, maxm) : (size_t)0));
   return b + 256;
 }
 
@@ -189,8 +191,27 @@ hipError_t tr_svd_device(const void* Gcore, int core_elem, int N, const int64_t*
   double* Gram = (double*)take((size_t)maxm * maxm * 8);
   double* lam = (double*)take((size_t)maxm * 8);
   double* Vt = (double*)take((size_t)maxm * maxm * 8);
-  void* jw = take(jacobi_work_bytes(maxm));
+  void* jw = take(std::max(jacobi_work_bytes(maxm), eig_top_ok(maxm, maxm) ? eig_top_work_bytes(maxm, maxm)
+                                                                            : (size_t)0));
   hipError_t e;
+  // the R leading eigenpairs of the m x m Gram matrix into lam (descending)
+  // and the first R rows of Vt (row stride m), signed
+  auto leading = [&](int64_t m, int64_t R) -> hipError_t {
+    hipError_t r;
+    if (eig_top_ok(m, R)) {
+      const double* zs[1] = {Gram};
+      const int64_t ns[1] = {m}, rs[1] = {R};
+      double* ls[1] = {lam};
+      double* vs[1] = {Vt};
+      void* ws[1] = {jw};
+      int* is[1] = {info};
+      r = eig_top_batched(1, zs, ns, rs, ls, vs, ws, is, st);
+    } else {
+      r = jacobi_eig(Gram, m, lam, Vt, jw, info, 40, st);
+    }
+    if (r != hipSuccess) return r;
+    return canonical_sign_rows(Vt, R, m, st);
+  };
   if (core_elem == E_F64) hipLaunchKernelGGL(to_double_kernel<double>, dim3(gridn(total)), dim3(256), 0, st, (const double*)Gcore, Gd, total);
   else hipLaunchKernelGGL(to_double_kernel<float>, dim3(gridn(total)), dim3(256), 0, st, (const float*)Gcore, Gd, total);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -199,13 +220,12 @@ hipError_t tr_svd_device(const void* Gcore, int core_elem, int N, const int64_t*
   // step 1
   const int64_t S1 = S[0], rest1 = total / S1, r0r1 = r[0] * r[1];
   if ((e = dgemm(0, 1, S1, S1, rest1, 1.0, Gd, rest1, Gd, rest1, 0.0, Gram, S1, st)) != hipSuccess) return e;
-  if ((e = jacobi_eig(Gram, S1, lam, Vt, jw, info, 40, st)) != hipSuccess) return e;
-  if ((e = canonical_sign_rows(Vt, S1, S1, st)) != hipSuccess) return e;
+  const int64_t kept1 = std::min<int64_t>(r0r1, S1);
+  if ((e = leading(S1, kept1)) != hipSuccess) return e;
   hipLaunchKernelGGL(trace_minus_kernel, dim3(1), dim3(64), 0, st, Gram, S1, lam, r0r1, discarded);
   hipLaunchKernelGGL(first_core_kernel, dim3(gridn(r[0] * S1 * r[1])), dim3(256), 0, st, Vt, S1, r[0], r[1], cores[0]);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // remainder C = U_k^T M (r0 r1 x rest1), rows beyond S1 zero
-  const int64_t kept1 = std::min<int64_t>(r0r1, S1);
   if ((e = fill_zero(C1, (size_t)r0r1 * rest1 * 8, st)) != hipSuccess) return e;
   if ((e = dgemm(0, 0, kept1, rest1, S1, 1.0, Vt, S1, Gd, rest1, 0.0, C1, rest1, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(move_first_last_kernel, dim3(gridn(r0r1 * rest1)), dim3(256), 0, st, C1, r[0], r[1], rest1, C2);
@@ -218,10 +238,9 @@ hipError_t tr_svd_device(const void* Gcore, int core_elem, int N, const int64_t*
     const int64_t m = r[k] * S[k];
     const int64_t ncols = (r[k] * rest) / m;   // = prod_{j>k} S_j * r0
     if ((e = dgemm(0, 1, m, m, ncols, 1.0, cur, ncols, cur, ncols, 0.0, Gram, m, st)) != hipSuccess) return e;
-    if ((e = jacobi_eig(Gram, m, lam, Vt, jw, info, 40, st)) != hipSuccess) return e;
-    if ((e = canonical_sign_rows(Vt, m, m, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(trace_minus_kernel, dim3(1), dim3(64), 0, st, Gram, m, lam, r[k + 1], discarded);
     const int64_t keep = std::min<int64_t>(r[k + 1], m);
+    if ((e = leading(m, keep)) != hipSuccess) return e;
+    hipLaunchKernelGGL(trace_minus_kernel, dim3(1), dim3(64), 0, st, Gram, m, lam, r[k + 1], discarded);
     hipLaunchKernelGGL(mid_core_kernel, dim3(gridn(r[k] * S[k] * r[k + 1])), dim3(256), 0, st, Vt, r[k], S[k],
                        r[k + 1], keep, cores[k]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
