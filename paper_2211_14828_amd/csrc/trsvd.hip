@@ -93,10 +93,14 @@ struct TRDesc {
   int N;
 };
 
-template <class T>
+// ||G - TR(G_n)||^2, one entry per thread: the ring's trace for the entry's
+// indices, product of the cores' slices from the left, kept in registers
+// (RM: the bound on the TR ranks, loops unrolled to it).
+template <class T, int RM>
 __global__ void gap2_kernel(const T* G, TRDesc d, int64_t total, double* partial) {
   __shared__ double red[16];
   double acc = 0.0;
+  const int64_t r0 = d.r[0], r1 = d.r[1];
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t idx[8];
     int64_t t = e;
@@ -105,21 +109,30 @@ __global__ void gap2_kernel(const T* G, TRDesc d, int64_t total, double* partial
       t /= d.S[k];
     }
     double val = 0.0;
-    for (int64_t a0 = 0; a0 < d.r[0]; ++a0) {
-      double v[MAXR], w[MAXR];
-      const int64_t r1 = d.r[1];
-      for (int64_t b = 0; b < r1; ++b) v[b] = d.cores[0][(a0 * d.S[0] + idx[0]) * r1 + b];
+    for (int64_t a0 = 0; a0 < r0; ++a0) {
+      double v[RM], w[RM];
+      const double* c0 = d.cores[0] + (a0 * d.S[0] + idx[0]) * r1;
+#pragma unroll
+      for (int b = 0; b < RM; ++b) v[b] = b < r1 ? c0[b] : 0.0;
       for (int k = 1; k < d.N; ++k) {
-        const int64_t ra = d.r[k], rb = d.r[k + 1];
+        const int64_t ra = d.r[k], rb = d.r[k + 1], step = d.S[k] * rb;
         const double* c = d.cores[k] + idx[k] * rb;
-        for (int64_t b = 0; b < rb; ++b) {
+#pragma unroll
+        for (int b = 0; b < RM; ++b) {
           double s = 0.0;
-          for (int64_t a = 0; a < ra; ++a) s = fma(v[a], c[a * d.S[k] * rb + b], s);
+          if (b < rb) {
+#pragma unroll
+            for (int a = 0; a < RM; ++a)
+              if (a < ra) s = fma(v[a], c[a * step + b], s);
+          }
           w[b] = s;
         }
-        for (int64_t b = 0; b < rb; ++b) v[b] = w[b];
+#pragma unroll
+        for (int b = 0; b < RM; ++b) v[b] = w[b];
       }
-      val += v[a0];
+#pragma unroll
+      for (int b = 0; b < RM; ++b)
+        if (b == a0) val += v[b];
     }
     const double diff = (double)G[e] - val;
     acc = fma(diff, diff, acc);
@@ -281,8 +294,18 @@ hipError_t tr_gap2(const void* Gcore, int core_elem, int N, const int64_t* S, co
     if (r[k] > MAXR) return hipErrorInvalidValue;
   }
   const unsigned g = (unsigned)std::min<int64_t>(4096, ceil_div(total, 256));
-  if (core_elem == E_F64) hipLaunchKernelGGL(gap2_kernel<double>, dim3(g), dim3(256), 0, st, (const double*)Gcore, d, total, work);
-  else hipLaunchKernelGGL(gap2_kernel<float>, dim3(g), dim3(256), 0, st, (const float*)Gcore, d, total, work);
+  int64_t rmax = 1;
+  for (int k = 0; k <= N; ++k) rmax = std::max(rmax, r[k]);
+#define GAP2(RM)                                                                                                 \
+  if (core_elem == E_F64)                                                                                       \
+    hipLaunchKernelGGL((gap2_kernel<double, RM>), dim3(g), dim3(256), 0, st, (const double*)Gcore, d, total, work); \
+  else                                                                                                          \
+    hipLaunchKernelGGL((gap2_kernel<float, RM>), dim3(g), dim3(256), 0, st, (const float*)Gcore, d, total, work)
+  if (rmax <= 8) GAP2(8);
+  else if (rmax <= 16) GAP2(16);
+  else if (rmax <= 32) GAP2(32);
+  else GAP2(64);
+#undef GAP2
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, st, work, (int64_t)g, out);
