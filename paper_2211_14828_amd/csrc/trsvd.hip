@@ -147,11 +147,20 @@ __global__ void gap2_kernel(const T* G, TRDesc d, int64_t total, double* partial
   }
 }
 
+// The partials' sum in a fixed order: one workgroup, strided per thread,
+// then across lanes and waves.
 __global__ void sum_kernel(const double* partial, int64_t n, double* out) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int64_t i = 0; i < n; ++i) s += partial[i];
-  *out = s;
+  __shared__ double red[16];
+  double r = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) r += partial[i];
+  r = warp_sum(r);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+    *out = s;
+  }
 }
 
 // Largest remainder of the sweep: r0 r1 x prod_{k>1} S_k after step 1, then
@@ -308,7 +317,7 @@ hipError_t tr_gap2(const void* Gcore, int core_elem, int N, const int64_t* S, co
 #undef GAP2
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(64), 0, st, work, (int64_t)g, out);
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(1024), 0, st, work, (int64_t)g, out);
   return hipGetLastError();
 }
 
