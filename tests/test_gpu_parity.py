@@ -149,6 +149,12 @@ CASES = [
     ((63, 120, 146), (28, 14, 28), 5, 3, "float64", "plain", "capped"),
     ((63, 120, 146), (28, 14, 28), 5, 3, "bfloat16", "plain", "capped"),
     ((72, 52, 228), (23, 15, 19), 5, 3, "float32", "plain", "capped"),
+    # the thin float32 Gram tile [C; W^T] (I <= 64, S <= 64): I = 64 with a
+    # 64-wide sketch, a middle mode (A > 1 and B > 1), a last mode whose
+    # size is not a multiple of 4 (element-wise staging), and order 4 with a
+    # thin mode inside
+    ((64, 33, 61), (59, 20, 7), 5, 1, "float32", "plain", "thin"),
+    ((20, 64, 9, 16), (5, 40, 4, 6), 5, 2, "float32", "plain", "thin4"),
     ((172, 237, 112), (8, 32, 24), 5, 3, "bfloat16", "mixed_bf16", "capped"),
     ((5, 300, 7), (2, 3, 2), 5, 2, "float64", "plain", "thin"),
     # the persistent chain at its limits (I = 256, sketches of 50..60, the
