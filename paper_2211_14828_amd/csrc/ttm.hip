@@ -641,10 +641,14 @@ __global__ void convert_kernel(const S* src, D* dst, int64_t n) {
 // padded columns (one e4m3 K tile or two bfloat16 ones) and all R rows of Y.
 // The contraction over the ipad rows runs in chunks of 256: each chunk is
 // decoded to bfloat16 and transposed into LDS as [column][row] (a thread
-// decodes 8 rows x 8 columns and writes 8 16-byte column pieces), the next
-// chunk's loads in flight meanwhile.  Wave w forms the 32 x 32 block rows
-// 32 (w >> 1).., columns 32 (w & 1).. on 32x32x16 bfloat16 MFMA, U rows read
-// from L2 ([64][ipad] bfloat16, zero past R and I).
+// decodes 8 rows x 8 columns and writes 8 16-byte column pieces).  Wave w
+// takes positions 64 w .. 64 w + 63 of every chunk for the whole 64 x 64
+// block (2 x 2 32x32x16 bfloat16 MFMA tiles, one row tile when R <= 32); the
+// four partial blocks are added through LDS at the end.  The loads are
+// ordered for the in-order retirement of vector loads: the chunk two ahead is
+// in flight while a chunk is multiplied, and a wave's U pieces ([64][ipad]
+// bfloat16 in L2, zero past R and I) for the next chunk are loaded one chunk
+// ahead into registers, so no MFMA waits on a load issued after an X load.
 struct FirstArgs {
   const unsigned char* X;    // blocked copy
   const unsigned char* sc;   // e4m3 scales (the Gram operand's layout), or null
@@ -656,13 +660,25 @@ struct FirstArgs {
 
 constexpr int F_CH = 256;                    // rows per chunk
 constexpr int F_ROW = F_CH * 2 + 16;         // LDS bytes per column row (padded)
+constexpr int F_PART = 65;                   // floats per row of a partial block in LDS
+static_assert(4 * 64 * F_PART * 4 <= 2 * 64 * F_ROW, "the partial blocks reuse the chunk buffers");
 
-__device__ inline int64_t first_scale_pos(int64_t rowid, int h) {
-  const int rr = (int)(rowid & 255);
-  return ((rowid >> 8) * 2 + h) * 256 + (rr & 31) * 8 + (rr >> 5);
+// two floats -> packed bfloat16 (a in the low half), rounded to nearest even
+__device__ inline uint32_t pack_bf16x2(float a, float b) {
+  typedef __attribute__((ext_vector_type(2))) float f2v;
+  typedef __attribute__((ext_vector_type(2))) __bf16 b2v;
+  const b2v h = __builtin_convertvector((f2v){a, b}, b2v);
+  return __builtin_bit_cast(uint32_t, h);
 }
 
-template <int E>
+// one thread's share of a chunk: 8 rows x 16 bytes (bfloat16) or 8 bytes
+// (e4m3, in .x .y) and, for e4m3, the 8 rows' scale bytes
+struct FirstRaw {
+  uint4 v[8];
+  uint2 scl;
+};
+
+template <int E, bool TWO>
 __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
   __shared__ __attribute__((aligned(16))) char lds[2][64 * F_ROW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -670,70 +686,75 @@ __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
   // columns 8 cg .. 8 cg + 7.  Row rl + 32 e goes to chunk position 8 rl + e
   // (the contraction order inside a chunk is free; U is stored in the same
   // order), so a thread writes 8 consecutive positions of every column, and
-  // its 8 e4m3 scales are 8 consecutive bytes of the scale layout.
-  const int rl = tid >> 3, cg = tid & 7;
+  // its 8 e4m3 scales are 8 consecutive bytes of the scale layout.  rl runs
+  // fastest over the lanes: the 8 lanes of a group write 8 consecutive 16-byte
+  // pieces of one column row (distinct LDS banks), and a wave still loads 8
+  // whole 64-byte rows.
+  const int rl = (wave << 3) | (lane & 7), cg = lane >> 3;
   const int half = lane >> 5, lr = lane & 31;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  const int kw = wave * 64 + half * 8;             // this lane's first position in a chunk
   const int64_t blk = blockIdx.x;                  // 64 padded columns
   const int nch = (int)(a.ipad / F_CH);
 
-  uint4 raw[8];
-  uint2 scl = make_uint2(0u, 0u);
-  auto load = [&](int ch) {
+  auto load_x = [&](int ch, FirstRaw& x) {
     const int64_t row0 = (int64_t)ch * F_CH;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int64_t i = row0 + rl + 32 * e;
       if (E == E_FP8) {
         const uint2 v = *(const uint2*)(a.X + (blk * a.ipad + i) * 64 + cg * 8);
-        raw[e] = make_uint4(v.x, v.y, 0u, 0u);
+        x.v[e] = make_uint4(v.x, v.y, 0u, 0u);
       } else {
         const int64_t kt = blk * 2 + (cg >> 2);
-        raw[e] = *(const uint4*)(a.X + (kt * a.ipad + i) * 64 + (cg & 3) * 16);
+        x.v[e] = *(const uint4*)(a.X + (kt * a.ipad + i) * 64 + (cg & 3) * 16);
       }
     }
     if (E == E_FP8) {
       // scale byte e of row rl + 32 e: [K tile][256-row tile][half][row % 32][row / 32]
       const int64_t tile = (blk * a.ipad + row0) >> 8;
-      scl = *(const uint2*)(a.sc + (tile * 2 + (cg >> 2)) * 256 + rl * 8);
+      x.scl = *(const uint2*)(a.sc + (tile * 2 + (cg >> 2)) * 256 + rl * 8);
+    }
+  };
+  // U pieces of a chunk: [k step][row tile], rows lr and 32 + lr
+  auto load_u = [&](int ch, bf16x8_t (&u)[4][2]) {
+    const bf16_t* p = a.U + (int64_t)lr * a.ipad + (int64_t)ch * F_CH + kw;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      u[s][0] = *(const bf16x8_t*)(p + 16 * s);
+      if (TWO) u[s][1] = *(const bf16x8_t*)(p + 32 * a.ipad + 16 * s);
     }
   };
   // decode and write the transposed pieces: column 8 cg + c, positions 8 rl .. 8 rl + 7
-  auto store = [&](char* buf) {
+  // (dword j of a piece: positions 2 j and 2 j + 1, the even one in the low half)
+  auto store = [&](char* buf, const FirstRaw& x) {
     uint32_t o[8][4];                              // [column][position pair]
-    if (E == E_FP8) {
-      // e4m3 values with 8-bit-exponent scales are exact in bf16: the bf16
-      // bits are the upper half of the float's
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t sb = ((e < 4 ? scl.x : scl.y) >> (8 * (e & 3))) & 0xFFu;
-        const float mul = __uint_as_float((sb > 0 ? sb : 1u) << 23) * (sb > 0 ? 1.f : 0.5f);
-        const uint32_t w[2] = {raw[e].x, raw[e].y};
+    for (int j = 0; j < 4; ++j) {
+      const int e0 = 2 * j, e1 = 2 * j + 1;
+      if (E == E_FP8) {
+        // the scaled conversion gives code * 2^(byte - 127) exactly (a zero
+        // byte is 2^-127); the products are e4m3 values times powers of two,
+        // exact in bf16 except below bf16's subnormal range (runs of scale
+        // byte 0, which hold zeros), so the packing rounds nothing else
+        const uint32_t sw = j < 2 ? x.scl.x : x.scl.y;
+        const float s0 = __uint_as_float(((sw >> (16 * (j & 1))) & 0xFFu) << 23);
+        const float s1 = __uint_as_float(((sw >> (16 * (j & 1) + 8)) & 0xFFu) << 23);
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-          // bytes 2p, 2p + 1 (columns 2p, 2p + 1): the hardware conversion of
-          // OCP e4m3 to float is exact, and so is the power-of-two scaling
-          const f32x2_t f = (p & 1) ? __builtin_amdgcn_cvt_pk_f32_fp8((int)w[p >> 1], true)
-                                    : __builtin_amdgcn_cvt_pk_f32_fp8((int)w[p >> 1], false);
-          const uint32_t h0 = __float_as_uint(f.x * mul) >> 16, h1 = __float_as_uint(f.y * mul) >> 16;
-          if (e & 1) {
-            o[2 * p][e >> 1] |= h0 << 16;
-            o[2 * p + 1][e >> 1] |= h1 << 16;
-          } else {
-            o[2 * p][e >> 1] = h0;
-            o[2 * p + 1][e >> 1] = h1;
-          }
+          const f32x2_t f0 = (p & 1) ? __builtin_amdgcn_cvt_scalef32_pk_f32_fp8((int)(p < 2 ? x.v[e0].x : x.v[e0].y), s0, true)
+                                     : __builtin_amdgcn_cvt_scalef32_pk_f32_fp8((int)(p < 2 ? x.v[e0].x : x.v[e0].y), s0, false);
+          const f32x2_t f1 = (p & 1) ? __builtin_amdgcn_cvt_scalef32_pk_f32_fp8((int)(p < 2 ? x.v[e1].x : x.v[e1].y), s1, true)
+                                     : __builtin_amdgcn_cvt_scalef32_pk_f32_fp8((int)(p < 2 ? x.v[e1].x : x.v[e1].y), s1, false);
+          o[2 * p][j] = pack_bf16x2(f0.x, f1.x);
+          o[2 * p + 1][j] = pack_bf16x2(f0.y, f1.y);
         }
-      }
-    } else {
+      } else {
+        const uint32_t wa[4] = {x.v[e0].x, x.v[e0].y, x.v[e0].z, x.v[e0].w};
+        const uint32_t wb[4] = {x.v[e1].x, x.v[e1].y, x.v[e1].z, x.v[e1].w};
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const uint32_t w[4] = {raw[e].x, raw[e].y, raw[e].z, raw[e].w};
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const uint32_t h = (w[c >> 1] >> (16 * (c & 1))) & 0xFFFFu;
-          if (e & 1) o[c][e >> 1] |= h << 16;
-          else o[c][e >> 1] = h;
+        for (int q = 0; q < 4; ++q) {
+          o[2 * q][j] = (wa[q] & 0xFFFFu) | (wb[q] << 16);
+          o[2 * q + 1][j] = (wa[q] >> 16) | (wb[q] & 0xFFFF0000u);
         }
       }
     }
@@ -742,40 +763,86 @@ __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
       *(uint4*)(buf + (cg * 8 + c) * F_ROW + rl * 16) = make_uint4(o[c][0], o[c][1], o[c][2], o[c][3]);
   };
 
-  f32x16_t acc;
+  f32x16_t acc[2][2];                              // [row tile][column tile]
 #pragma unroll
-  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-  const bf16_t* Urow = a.U + (int64_t)(wr + lr) * a.ipad;
-  load(0);
-  store(lds[0]);
-  __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const bool more = ch + 1 < nch;
-    if (more) load(ch + 1);
-    const char* buf = lds[ch & 1];
-    // K steps of 16 positions: lane half h takes positions 16 s + 8 h .. + 7
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int st = 0; st < F_CH / 16; ++st) {
-      const int k = st * 16 + half * 8;
-      const bf16x8_t av = *(const bf16x8_t*)(Urow + (int64_t)ch * F_CH + k);
-      const bf16x8_t bv = *(const bf16x8_t*)(buf + (wc + lr) * F_ROW + k * 2);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[t][c][v] = 0.f;
+  auto mma = [&](const char* buf, const bf16x8_t (&u)[4][2]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = kw + 16 * s;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const bf16x8_t bv = *(const bf16x8_t*)(buf + (c * 32 + lr) * F_ROW + k * 2);
+        acc[0][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(u[s][0], bv, acc[0][c], 0, 0, 0);
+        if (TWO) acc[1][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(u[s][1], bv, acc[1][c], 0, 0, 0);
+      }
     }
-    if (more) store(lds[(ch + 1) & 1]);
+  };
+  // one chunk: issue U(ch + 1) then X(ch + 2), multiply chunk ch, then write
+  // X(ch + 1) (loaded one step earlier) to the other LDS buffer.  The loads
+  // are unconditional (indices clamped to the last chunk, a repeat of which
+  // is an L2 hit) so that the wait before each MFMA counts only the loads
+  // issued after its operand's.
+  auto step = [&](int ch, const bf16x8_t (&ucur)[4][2], bf16x8_t (&unext)[4][2], const FirstRaw& have,
+                  FirstRaw& next) {
+    load_u(min(ch + 1, nch - 1), unext);
+    load_x(min(ch + 2, nch - 1), next);
+    mma(lds[ch & 1], ucur);
+    if (ch + 1 < nch) store(lds[(ch + 1) & 1], have);
+    __syncthreads();
+  };
+
+  FirstRaw x0, x1;
+  bf16x8_t u0[4][2], u1[4][2];
+  load_u(0, u0);
+  load_x(0, x0);
+  load_x(min(1, nch - 1), x1);
+  store(lds[0], x0);
+  __syncthreads();
+  int ch = 0;
+  for (; ch + 1 < nch; ch += 2) {
+    step(ch, u0, u1, x1, x0);
+    step(ch + 1, u1, u0, x0, x1);
+  }
+  if (ch < nch) {                                  // odd count: the last chunk, its U in u0
+    mma(lds[ch & 1], u0);
     __syncthreads();
   }
 
-  // value v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+  // partial blocks [wave][row][column] (the chunk buffers are free after the
+  // last barrier); value v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4 of
+  // the tile, column l % 32
+  float* part = (float*)&lds[0][0];
+#pragma unroll
+  for (int t = 0; t < (TWO ? 2 : 1); ++t)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = t * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        part[(wave * 64 + r) * F_PART + c * 32 + lr] = acc[t][c][v];
+      }
+  __syncthreads();
+  const int col = tid & 63;
   const int64_t g0 = blk * 64;                     // first padded column (over all a)
   const int64_t av_ = g0 / a.Bp, bp0 = g0 - av_ * a.Bp;
-  const int64_t bp = bp0 + wc + lr;
+  const int64_t bp = bp0 + col;
   const int64_t hi = bp / a.INp, lo = bp - hi * a.INp;
   if (lo < a.IN) {
     float* out = a.Y + av_ * a.R * a.B + hi * a.IN + lo;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int r = wr + 8 * (v >> 2) + 4 * half + (v & 3);
-      if (r < a.R) out[(int64_t)r * a.B] = acc[v];
+    for (int j = 0; j < (TWO ? 16 : 8); ++j) {
+      const int r = (tid >> 6) + 4 * j;
+      if (r < a.R) {
+        float s = 0.f;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) s += part[(w * 64 + r) * F_PART + col];
+        out[(int64_t)r * a.B] = s;
+      }
     }
   }
 }
@@ -922,8 +989,14 @@ hipError_t launch_ttm_first_blocked(int elem, const void* xb, const void* scales
   fa.R = (int)R;
   const int64_t blocks = A * Bp / 64;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  if (elem == E_FP8) hipLaunchKernelGGL(ttm_first_kernel<E_FP8>, dim3((unsigned)blocks), dim3(256), 0, s, fa);
-  else hipLaunchKernelGGL(ttm_first_kernel<E_BF16>, dim3((unsigned)blocks), dim3(256), 0, s, fa);
+  const dim3 grid((unsigned)blocks), block(256);
+  if (elem == E_FP8) {
+    if (R > 32) hipLaunchKernelGGL((ttm_first_kernel<E_FP8, true>), grid, block, 0, s, fa);
+    else hipLaunchKernelGGL((ttm_first_kernel<E_FP8, false>), grid, block, 0, s, fa);
+  } else {
+    if (R > 32) hipLaunchKernelGGL((ttm_first_kernel<E_BF16, true>), grid, block, 0, s, fa);
+    else hipLaunchKernelGGL((ttm_first_kernel<E_BF16, false>), grid, block, 0, s, fa);
+  }
   return hipGetLastError();
 }
 
