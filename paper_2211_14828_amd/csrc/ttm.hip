@@ -644,23 +644,31 @@ __global__ void convert_kernel(const S* src, D* dst, int64_t n) {
 // decodes 8 rows x 8 columns and writes 8 16-byte column pieces).  Wave w
 // takes positions 64 w .. 64 w + 63 of every chunk for the whole 64 x 64
 // block (2 x 2 32x32x16 bfloat16 MFMA tiles, one row tile when R <= 32); the
-// four partial blocks are added through LDS at the end.  The loads are
-// ordered for the in-order retirement of vector loads: the chunk two ahead is
-// in flight while a chunk is multiplied, and a wave's U pieces ([64][ipad]
-// bfloat16 in L2, zero past R and I) for the next chunk are loaded one chunk
+// four partial blocks are added through LDS at the end of the block.  A
+// workgroup takes a run of consecutive blocks and walks their chunks as one
+// stream, so the loads run ahead across block ends and the next block's first
+// chunks arrive while a block's partials are added.  The loads are ordered for the in-order retirement of
+// vector loads: the chunk two steps ahead is in flight while a chunk is
+// multiplied, and a wave's U pieces for the next step are loaded one step
 // ahead into registers, so no MFMA waits on a load issued after an X load.
+// U (bfloat16, zero past R and I) is stored in the order the waves read it:
+// for chunk ch, wave w, k step s and row tile t, the 64 lanes' 8-value pieces
+// are 1 KB contiguous, so a U load reads whole cache lines.
 struct FirstArgs {
   const unsigned char* X;    // blocked copy
   const unsigned char* sc;   // e4m3 scales (the Gram operand's layout), or null
-  const bf16_t* U;           // [64][ipad]
+  const bf16_t* U;           // fragment order, 64 x ipad values
   float* Y;                  // [A][R][B]
   int64_t ipad, Bp, B, IN, INp;
+  int64_t nblk;              // 64-column blocks
+  int bpw;                   // consecutive blocks per workgroup
   int R;
 };
 
 constexpr int F_CH = 256;                    // rows per chunk
 constexpr int F_ROW = F_CH * 2 + 16;         // LDS bytes per column row (padded)
 constexpr int F_PART = 65;                   // floats per row of a partial block in LDS
+constexpr int FIRST_RUN = 4;                 // 64-column blocks per workgroup
 static_assert(4 * 64 * F_PART * 4 <= 2 * 64 * F_ROW, "the partial blocks reuse the chunk buffers");
 
 // two floats -> packed bfloat16 (a in the low half), rounded to nearest even
@@ -693,10 +701,17 @@ __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
   const int rl = (wave << 3) | (lane & 7), cg = lane >> 3;
   const int half = lane >> 5, lr = lane & 31;
   const int kw = wave * 64 + half * 8;             // this lane's first position in a chunk
-  const int64_t blk = blockIdx.x;                  // 64 padded columns
   const int nch = (int)(a.ipad / F_CH);
+  // this workgroup's stream: step s is chunk s % nch of block first + s / nch
+  const int64_t first = (int64_t)blockIdx.x * a.bpw;
+  const int nmine = (int)std::min<int64_t>(a.bpw, a.nblk - first);
+  const int S = nmine * nch;
+  if (S <= 0) return;
+  auto block_of = [&](int s) { return first + s / nch; };
 
-  auto load_x = [&](int ch, FirstRaw& x) {
+  auto load_x = [&](int s, FirstRaw& x) {
+    const int64_t blk = block_of(s);
+    const int ch = s % nch;
     const int64_t row0 = (int64_t)ch * F_CH;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -715,13 +730,14 @@ __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
       x.scl = *(const uint2*)(a.sc + (tile * 2 + (cg >> 2)) * 256 + rl * 8);
     }
   };
-  // U pieces of a chunk: [k step][row tile], rows lr and 32 + lr
+  // U pieces of a chunk: [k step][row tile] (rows lr and 32 + lr, positions
+  // kw + 16 s .. + 7)
   auto load_u = [&](int ch, bf16x8_t (&u)[4][2]) {
-    const bf16_t* p = a.U + (int64_t)lr * a.ipad + (int64_t)ch * F_CH + kw;
+    const bf16_t* p = a.U + ((int64_t)ch * 4 + wave) * 4096 + lane * 8;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      u[s][0] = *(const bf16x8_t*)(p + 16 * s);
-      if (TWO) u[s][1] = *(const bf16x8_t*)(p + 32 * a.ipad + 16 * s);
+      u[s][0] = *(const bf16x8_t*)(p + s * 1024);
+      if (TWO) u[s][1] = *(const bf16x8_t*)(p + s * 1024 + 512);
     }
   };
   // decode and write the transposed pieces: column 8 cg + c, positions 8 rl .. 8 rl + 7
@@ -782,17 +798,61 @@ __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
       }
     }
   };
-  // one chunk: issue U(ch + 1) then X(ch + 2), multiply chunk ch, then write
-  // X(ch + 1) (loaded one step earlier) to the other LDS buffer.  The loads
-  // are unconditional (indices clamped to the last chunk, a repeat of which
-  // is an L2 hit) so that the wait before each MFMA counts only the loads
+  // the sum of the four waves' partial blocks of block blk -> Y (the chunk
+  // buffers are free when it starts; it ends with the block's partials read)
+  auto finish = [&](int64_t blk) {
+    // partial blocks [wave][row][column]; value v of lane l: row
+    // 8 (v / 4) + 4 (l / 32) + v % 4 of the tile, column l % 32
+    float* part = (float*)&lds[0][0];
+#pragma unroll
+    for (int t = 0; t < (TWO ? 2 : 1); ++t)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int r = t * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+          part[(wave * 64 + r) * F_PART + c * 32 + lr] = acc[t][c][v];
+          acc[t][c][v] = 0.f;
+        }
+    __syncthreads();
+    const int col = tid & 63;
+    const int64_t g0 = blk * 64;                   // first padded column (over all a)
+    const int64_t av_ = g0 / a.Bp, bp0 = g0 - av_ * a.Bp;
+    const int64_t bp = bp0 + col;
+    const int64_t hi = bp / a.INp, lo = bp - hi * a.INp;
+    if (lo < a.IN) {
+      float* out = a.Y + av_ * a.R * a.B + hi * a.IN + lo;
+#pragma unroll
+      for (int j = 0; j < (TWO ? 16 : 8); ++j) {
+        const int r = (tid >> 6) + 4 * j;
+        if (r < a.R) {
+          float sum = 0.f;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) sum += part[(w * 64 + r) * F_PART + col];
+          out[(int64_t)r * a.B] = sum;
+        }
+      }
+    }
+    __syncthreads();
+  };
+  // stream step s: issue U of step s + 1 then X of step s + 2, multiply step
+  // s's chunk, then write step s + 1's chunk (loaded one step earlier) to the
+  // other LDS buffer; at a block's last chunk its partials are added first.
+  // The loads are unconditional (a step past the end is clamped to the last
+  // one, an L2 hit) so that the wait before each MFMA counts only the loads
   // issued after its operand's.
-  auto step = [&](int ch, const bf16x8_t (&ucur)[4][2], bf16x8_t (&unext)[4][2], const FirstRaw& have,
+  auto step = [&](int s, const bf16x8_t (&ucur)[4][2], bf16x8_t (&unext)[4][2], const FirstRaw& have,
                   FirstRaw& next) {
-    load_u(min(ch + 1, nch - 1), unext);
-    load_x(min(ch + 2, nch - 1), next);
-    mma(lds[ch & 1], ucur);
-    if (ch + 1 < nch) store(lds[(ch + 1) & 1], have);
+    const int ch = s % nch;
+    const bool last = ch + 1 == nch;
+    load_u(last ? 0 : ch + 1, unext);
+    load_x(min(s + 2, S - 1), next);
+    mma(lds[s & 1], ucur);
+    if (last) {
+      __syncthreads();
+      finish(block_of(s));
+    }
+    if (s + 1 < S) store(lds[(s + 1) & 1], have);
     __syncthreads();
   };
 
@@ -800,63 +860,31 @@ __global__ void __launch_bounds__(256, 2) ttm_first_kernel(FirstArgs a) {
   bf16x8_t u0[4][2], u1[4][2];
   load_u(0, u0);
   load_x(0, x0);
-  load_x(min(1, nch - 1), x1);
+  load_x(min(1, S - 1), x1);
   store(lds[0], x0);
   __syncthreads();
-  int ch = 0;
-  for (; ch + 1 < nch; ch += 2) {
-    step(ch, u0, u1, x1, x0);
-    step(ch + 1, u1, u0, x0, x1);
+  int s = 0;
+  for (; s + 1 < S; s += 2) {
+    step(s, u0, u1, x1, x0);
+    step(s + 1, u1, u0, x0, x1);
   }
-  if (ch < nch) {                                  // odd count: the last chunk, its U in u0
-    mma(lds[ch & 1], u0);
-    __syncthreads();
-  }
-
-  // partial blocks [wave][row][column] (the chunk buffers are free after the
-  // last barrier); value v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4 of
-  // the tile, column l % 32
-  float* part = (float*)&lds[0][0];
-#pragma unroll
-  for (int t = 0; t < (TWO ? 2 : 1); ++t)
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int r = t * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-        part[(wave * 64 + r) * F_PART + c * 32 + lr] = acc[t][c][v];
-      }
-  __syncthreads();
-  const int col = tid & 63;
-  const int64_t g0 = blk * 64;                     // first padded column (over all a)
-  const int64_t av_ = g0 / a.Bp, bp0 = g0 - av_ * a.Bp;
-  const int64_t bp = bp0 + col;
-  const int64_t hi = bp / a.INp, lo = bp - hi * a.INp;
-  if (lo < a.IN) {
-    float* out = a.Y + av_ * a.R * a.B + hi * a.IN + lo;
-#pragma unroll
-    for (int j = 0; j < (TWO ? 16 : 8); ++j) {
-      const int r = (tid >> 6) + 4 * j;
-      if (r < a.R) {
-        float s = 0.f;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) s += part[(w * 64 + r) * F_PART + col];
-        out[(int64_t)r * a.B] = s;
-      }
-    }
-  }
+  if (s < S) step(s, u0, u1, x1, x0);             // odd length: the last step
 }
 
-// U (given as Ut, R x I float64) -> [64][ipad] bfloat16 in the chunk order of
-// ttm_first_kernel (position 8 q + e of a 256-row chunk holds row q + 32 e),
-// zero past R and I
+// U (given as Ut, R x I float64) -> bfloat16 in ttm_first_kernel's read
+// order: element 8 (64 (2 (4 (4 ch + w) + s) + t) + l) + e is row
+// 32 t + l % 32 at chunk position 64 w + 16 s + 8 (l / 32) + e, and position
+// 8 q + e' of a 256-row chunk holds row q + 32 e' of U; zero past R and I
 __global__ void u_first_kernel(const double* Ut, int64_t R, int64_t I, int64_t ipad, bf16_t* U) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 64 * ipad;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / ipad, p = e - r * ipad;
-    const int64_t pc = p & (F_CH - 1);
-    const int64_t i = (p - pc) + (pc >> 3) + 32 * (pc & 7);
-    U[e] = (r < R && i < I) ? f32_to_bf16((float)Ut[r * I + i]) : (bf16_t)0;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < 64 * ipad;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(idx & 7), l = (int)((idx >> 3) & 63), t = (int)((idx >> 9) & 1);
+    const int s = (int)((idx >> 10) & 3), w = (int)((idx >> 12) & 3);
+    const int64_t ch = idx >> 14;
+    const int64_t r = 32 * t + (l & 31);
+    const int pc = 64 * w + 16 * s + 8 * (l >> 5) + e;     // position in the chunk
+    const int64_t i = ch * F_CH + (pc >> 3) + 32 * (pc & 7);
+    U[idx] = (r < R && i < I) ? f32_to_bf16((float)Ut[r * I + i]) : (bf16_t)0;
   }
 }
 
@@ -988,8 +1016,15 @@ hipError_t launch_ttm_first_blocked(int elem, const void* xb, const void* scales
   fa.INp = INp;
   fa.R = (int)R;
   const int64_t blocks = A * Bp / 64;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)blocks), block(256);
+  fa.nblk = blocks;
+  if (blocks < 1) return hipSuccess;
+  // runs of FIRST_RUN blocks: long enough to amortise a workgroup's start
+  // (its first loads and LDS fill), short enough that the dispatcher balances
+  // the grid against kernels running beside it
+  fa.bpw = FIRST_RUN;
+  const int64_t wgs = ceil_div(blocks, (int64_t)FIRST_RUN);
+  if (wgs > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)wgs), block(256);
   if (elem == E_FP8) {
     if (R > 32) hipLaunchKernelGGL((ttm_first_kernel<E_FP8, true>), grid, block, 0, s, fa);
     else hipLaunchKernelGGL((ttm_first_kernel<E_FP8, false>), grid, block, 0, s, fa);
