@@ -908,37 +908,59 @@ rbki_status reconstruct_error(const Plan& P, const Buffers& b, const void* X, in
   return RBKI_OK;
 }
 
-// first_done: first_product has already been enqueued (on a stream that st
-// has joined).
-rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, const void* xsrc, void* core,
-                               int out_elem, bool want_err, double* sums_host, void** core_out, hipStream_t st,
-                               bool first_done = false) {
-  const size_t ce = P.celem == E_F64 ? 8 : 4;
+// Alg. 2, step 6, a later product of the core chain: G <- G x_n U^(n)T from
+// chain buffer `which` into the other one; cur holds G's dimensions.
+rbki_status chain_product(const Plan& P, const Buffers& b, int n, int64_t* cur, int& which, hipStream_t st) {
+  int64_t A = 1, B = 1;
+  for (int k = 0; k < n; ++k) A *= cur[k];
+  for (int k = n + 1; k < P.N; ++k) B *= cur[k];
+  const int64_t I = cur[n];
+  void* bufs[2] = {b.chainA, b.chainB};
+  HIPCHK(convert_tensor(E_F64, b.Ut64[n], P.celem, b.Uop, P.m[n].R * I, st));
+  HIPCHK(launch_ttm(P.celem, bufs[which], A, I, B, b.Uop, P.m[n].R, bufs[which ^ 1], nullptr, 0, st));
+  which ^= 1;
+  cur[n] = P.m[n].R;
+  return RBKI_OK;
+}
+
+// The core chain runs the first mode, then the others in increasing order;
+// the mode of its second product (-1 for one mode).
+int second_chain_mode(const Plan& P) { return P.N < 2 ? -1 : (P.first_mode == 0 ? 1 : 0); }
+
+// The second product of the core chain, on G_1 in chain buffer A (into B).
+rbki_status second_product(const Plan& P, const Buffers& b, hipStream_t st) {
   int64_t cur[8];
   for (int n = 0; n < P.N; ++n) cur[n] = P.dims[n];
-  auto view = [&](int n, int64_t& A, int64_t& I, int64_t& B) {
-    A = 1;
-    for (int k = 0; k < n; ++k) A *= cur[k];
-    I = cur[n];
-    B = 1;
-    for (int k = n + 1; k < P.N; ++k) B *= cur[k];
-  };
+  cur[P.first_mode] = P.m[P.first_mode].R;
+  int which = 0;
+  return chain_product(P, b, second_chain_mode(P), cur, which, st);
+}
+
+// done: the number of the core chain's products already enqueued (0, 1 or 2,
+// on streams that st has joined).
+rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, const void* xsrc, void* core,
+                               int out_elem, bool want_err, double* sums_host, void** core_out, hipStream_t st,
+                               int done = 0) {
+  int64_t cur[8];
+  for (int n = 0; n < P.N; ++n) cur[n] = P.dims[n];
   void* bufs[2] = {b.chainA, b.chainB};
   int which = 0;
   // first product reads X
-  if (!first_done) {
+  if (done < 1) {
     rbki_status s = first_product(P, b, xsrc, st);
     if (s != RBKI_OK) return s;
   }
   cur[P.first_mode] = P.m[P.first_mode].R;
+  int k = 1;                                       // products so far
   for (int n = 0; n < P.N; ++n) {
     if (n == P.first_mode) continue;
-    int64_t A, I, B;
-    view(n, A, I, B);
-    HIPCHK(convert_tensor(E_F64, b.Ut64[n], P.celem, b.Uop, P.m[n].R * I, st));
-    HIPCHK(launch_ttm(P.celem, bufs[which], A, I, B, b.Uop, P.m[n].R, bufs[which ^ 1], nullptr, 0, st));
-    which ^= 1;
-    cur[n] = P.m[n].R;
+    if (k++ < done) {                              // enqueued beside the modes' work
+      which ^= 1;
+      cur[n] = P.m[n].R;
+      continue;
+    }
+    rbki_status s = chain_product(P, b, n, cur, which, st);
+    if (s != RBKI_OK) return s;
   }
   void* G = bufs[which];
   int64_t nc = 1;
@@ -950,7 +972,6 @@ rbki_status run_core_and_error(const Plan& P, const Buffers& b, const void* X, c
     *core_out = b.gkeep;
   }
   if (!want_err) return RBKI_OK;
-  (void)ce;
   return reconstruct_error(P, b, X, which, b.sums, sums_host, st);
 }
 
@@ -1169,9 +1190,13 @@ static hipStream_t lane_stream(int lane) {
 // request).  Each mode does the same work either way.
 // inline_factors: each mode's factor step (and, for the first mode of the
 // core chain, the first product) follows its Krylov chain on its stream, so
-// that it runs beside the later modes' work.
+// that it runs beside the later modes' work; the chain's second product
+// follows as soon as both its inputs are enqueued, on the stream of the later
+// one after an event of the other.  *chain_done receives the number of the
+// core chain's products enqueued.
 static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, hipStream_t st,
-                             bool inline_factors = false) {
+                             bool inline_factors = false, int* chain_done = nullptr) {
+  if (chain_done) *chain_done = 0;
   if (P.fused) {
     // the sketch and Gram passes one after the other, each into its mode's
     // set, then every mode's Krylov chain in one launch
@@ -1200,6 +1225,16 @@ static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, 
   hipEvent_t heavy[8] = {};
   if (lanes > 1)
     for (int n = 0; n < P.N; ++n) HIPCHK(hipEventCreateWithFlags(&heavy[n], hipEventDisableTiming));
+  // the second product of the core chain: its factor's mode and the first
+  // product, each with an event for the other's stream
+  const int n2 = inline_factors && lanes > 1 ? second_chain_mode(P) : -1;
+  hipEvent_t ev_first = nullptr, ev_fac2 = nullptr;
+  bool first_enq = false, fac2_enq = false;
+  int products = 0;
+  if (n2 >= 0) {
+    HIPCHK(hipEventCreateWithFlags(&ev_first, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev_fac2, hipEventDisableTiming));
+  }
   // With several scratch sets, the modes of a round (one per set) are enqueued
   // heavy phases first, so that the next mode's sketch and Gram kernels are
   // queued before the long chain of small Krylov kernels of the previous one.
@@ -1214,9 +1249,25 @@ static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, 
       for (int n = n0; n < n1 && s == RBKI_OK; ++n)
         s = run_mode_heavy(P, b, n % lanes, xsrc, n, ls[n % lanes], n > 0 ? heavy[n - 1] : nullptr, heavy[n]);
       for (int n = n0; n < n1 && s == RBKI_OK; ++n) {
-        s = run_mode_chain(P, b, n % lanes, n, true, ls[n % lanes]);
-        if (s == RBKI_OK && inline_factors) s = factor_one(P, b, n, ls[n % lanes]);
-        if (s == RBKI_OK && inline_factors && n == P.first_mode) s = first_product(P, b, xsrc, ls[n % lanes]);
+        hipStream_t ln = ls[n % lanes];
+        s = run_mode_chain(P, b, n % lanes, n, true, ln);
+        if (s == RBKI_OK && inline_factors) s = factor_one(P, b, n, ln);
+        if (s == RBKI_OK && inline_factors && n == P.first_mode) {
+          s = first_product(P, b, xsrc, ln);
+          products = 1;
+          first_enq = true;
+          if (s == RBKI_OK && n2 >= 0) HIPCHK(hipEventRecord(ev_first, ln));
+        }
+        if (s == RBKI_OK && n == n2) {
+          fac2_enq = true;
+          HIPCHK(hipEventRecord(ev_fac2, ln));
+        }
+        if (s == RBKI_OK && n2 >= 0 && products == 1 && first_enq && fac2_enq) {
+          // this stream has just enqueued the later of the two inputs
+          HIPCHK(hipStreamWaitEvent(ln, n == n2 ? ev_first : ev_fac2, 0));
+          s = second_product(P, b, ln);
+          products = 2;
+        }
       }
     }
   }
@@ -1227,7 +1278,10 @@ static rbki_status run_modes(const Plan& P, const Buffers& b, const void* xsrc, 
     }
     for (int l = 0; l < lanes; ++l) HIPCHK(hipEventDestroy(ev[l]));
     for (int n = 0; n < P.N; ++n) HIPCHK(hipEventDestroy(heavy[n]));
+    if (ev_first) HIPCHK(hipEventDestroy(ev_first));
+    if (ev_fac2) HIPCHK(hipEventDestroy(ev_fac2));
   }
+  if (chain_done && inline_factors) *chain_done = products;
   dgemm_set_scratch(b.ln[0].dscratch, kDgemmScratch);
   return s;
 }
@@ -1547,7 +1601,8 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   // is done
   bool inline_factors = !P.concurrent && !P.one_stream && !P.fused && b.lanes > 1;
   for (int n = 0; n < P.N; ++n) inline_factors = inline_factors && eig_top_ok(P.m[n].Sp, P.m[n].R);
-  s = run_modes(P, b, xsrc, st, inline_factors);
+  int chain_done = 0;
+  s = run_modes(P, b, xsrc, st, inline_factors, &chain_done);
   if (s != RBKI_OK) return s;
   if (!inline_factors) {
     s = run_factors(P, b, st);
@@ -1560,7 +1615,7 @@ static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm,
   HostResult* hr = async_res ? async_res : &local;
   const bool want_err = rel_err || async_res;
   s = run_core_and_error(P, b, X, xsrc, core, dtype_elem(out_type), want_err, hr->sums, core_chain, st,
-                         inline_factors);
+                         chain_done);
   if (s != RBKI_OK) return s;
   // the eigen-solver's status comes back whether or not the error was asked
   // for, so a failed solve is never returned as RBKI_OK
