@@ -888,6 +888,92 @@ __global__ void u_first_kernel(const double* Ut, int64_t R, int64_t I, int64_t i
   }
 }
 
+// Last-mode product with a short output and a long contraction, float32:
+// Y (A x R) = X (A x I) U (I x R) for R <= 64, U given as Ut (R x I).  The
+// generic tile has one workgroup per 128 x 128 output block, so A = 2500,
+// R = 50, I = 1000 ran on 20 workgroups with a serial loop over I.  Here a
+// workgroup owns 32 rows of X, its four waves split the contraction into
+// four ranges, and each wave forms the 32 x 64 block of its range on
+// 32x32x2 float32 MFMA; the partial blocks are added through LDS in a fixed
+// order.  Within a run of 8 contraction indices kb.., lane half h supplies
+// the indices kb + 4 h + t at step t (t = 0..3), so each lane reads 4
+// consecutive values of its X row and of its Ut row (16 bytes when I is a
+// multiple of 4); both operands come straight from memory.
+constexpr int LM_ROWS = 32;
+struct LastArgs {
+  const float* X;       // A x I row-major
+  const float* Ut;      // R x I row-major
+  float* Y;             // A x R row-major
+  int64_t A, I;
+  int R;
+  int64_t krange;       // contraction indices per wave, a multiple of 8
+};
+
+template <bool VEC>
+__global__ void __launch_bounds__(256) lastmode_small_kernel(LastArgs a) {
+  __shared__ float part[4][LM_ROWS][65];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, lr = lane & 31;
+  const int64_t a0 = (int64_t)blockIdx.x * LM_ROWS;
+  const int64_t arow = a0 + lr < a.A ? a0 + lr : a.A - 1;       // clamped; rows past A are not stored
+  const float* xr = a.X + arow * a.I;
+  const float* ur[2];
+  bool uok[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int r = c * 32 + lr;
+    uok[c] = r < a.R;
+    ur[c] = a.Ut + (int64_t)(uok[c] ? r : 0) * a.I;
+  }
+  const int64_t k0 = (int64_t)wave * a.krange;
+  const int64_t k1 = std::min<int64_t>(k0 + a.krange, a.I);
+  f32x16_t acc[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[c][v] = 0.f;
+  auto load4 = [&](const float* row, int64_t k, bool ok) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (VEC) {
+      if (ok && k < k1) v = *(const float4*)(row + k);
+    } else if (ok) {
+      if (k < k1) v.x = row[k];
+      if (k + 1 < k1) v.y = row[k + 1];
+      if (k + 2 < k1) v.z = row[k + 2];
+      if (k + 3 < k1) v.w = row[k + 3];
+    }
+    return v;
+  };
+  for (int64_t kb = k0; kb < k1; kb += 8) {
+    const int64_t k = kb + 4 * half;
+    const float4 xv = load4(xr, k, true);
+    const float4 u0 = load4(ur[0], k, uok[0]);
+    const float4 u1 = load4(ur[1], k, uok[1]);
+    const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
+    const float us0[4] = {u0.x, u0.y, u0.z, u0.w}, us1[4] = {u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[t], us0[t], acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[t], us1[t], acc[1], 0, 0, 0);
+    }
+  }
+  // value v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32 of the tile
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) part[wave][8 * (v >> 2) + 4 * half + (v & 3)][c * 32 + lr] = acc[c][v];
+  __syncthreads();
+  const int col = tid & 63;
+  if (col < a.R) {
+#pragma unroll
+    for (int j = 0; j < LM_ROWS / 4; ++j) {
+      const int row = (tid >> 6) + 4 * j;
+      if (a0 + row < a.A)
+        a.Y[(a0 + row) * a.R + col] = (part[0][row][col] + part[1][row][col]) + (part[2][row][col] + part[3][row][col]);
+    }
+  }
+}
+
 template <int E, int EPI, class XT>
 hipError_t launch_prod(const ProdArgs& p, int64_t batches, hipStream_t s) {
   // the batch index runs on grid.y (at most 65535 per launch)
@@ -934,6 +1020,23 @@ hipError_t launch_ttm(int elem, const void* X, int64_t A, int64_t I, int64_t B, 
     p.vec_b = (B * es) % 16 == 0 && aligned16(X);
     batches = A;
   } else {
+    if (elem == E_F32 && R <= 64 && I >= 256) {
+      // long contraction, short output: waves split the contraction
+      LastArgs la;
+      la.X = (const float*)X;
+      la.Ut = (const float*)Ut;
+      la.Y = (float*)Y;
+      la.A = A;
+      la.I = I;
+      la.R = (int)R;
+      la.krange = ceil_div(ceil_div(I, 4), 8) * 8;
+      const int64_t wgs = ceil_div(A, LM_ROWS);
+      if (wgs > 0x7fffffff) return hipErrorInvalidValue;
+      const bool vec = I % 4 == 0 && aligned16(X) && aligned16(Ut);
+      if (vec) hipLaunchKernelGGL(lastmode_small_kernel<true>, dim3((unsigned)wgs), dim3(256), 0, s, la);
+      else hipLaunchKernelGGL(lastmode_small_kernel<false>, dim3((unsigned)wgs), dim3(256), 0, s, la);
+      return hipGetLastError();
+    }
     // Y (A x R) = X (A x I) . U (I x R): rows a, cols r
     p.a = {X, I, 1, 0, A};
     p.b = {Ut, I, 1, 0, R};
