@@ -974,6 +974,93 @@ __global__ void __launch_bounds__(256) lastmode_small_kernel(LastArgs a) {
   }
 }
 
+// Last-mode product with a short contraction and a wide output, float32:
+// Y (A x R) = X (A x I) U (I x R) for I <= 64, U given as Ut (R x I) (the
+// expansion G x_N U^(N) of the reconstruction, 50000 x 50 times 50 x 1000 at
+// 1000^3, which the generic tile ran at a fifth of the write rate).  A
+// workgroup owns 64 rows of X and 128 columns of Y: its X rows and Ut rows
+// are each one contiguous run of memory, copied to LDS with coalesced loads;
+// wave w forms the 32 x 64 block at rows 32 (w / 2), columns 64 (w % 2) on
+// 32x32x2 float32 MFMA over the whole contraction (lane half h supplies the
+// indices kb + 4 h + t at step t, as in lastmode_small_kernel).
+constexpr int EX_ROWS = 64;
+constexpr int EX_COLS = 128;
+struct ExpArgs {
+  const float* X;       // A x I row-major
+  const float* Ut;      // R x I row-major
+  float* Y;             // A x R row-major
+  int64_t A, R;
+  int I;                // <= 64
+};
+
+__global__ void __launch_bounds__(256) expand_small_kernel(ExpArgs a) {
+  __shared__ __attribute__((aligned(16))) float xs[EX_ROWS * 64];
+  __shared__ __attribute__((aligned(16))) float us[EX_COLS * 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5, lr = lane & 31;
+  // consecutive workgroups take the column blocks of the same rows, so they
+  // write whole output rows together
+  const int64_t c0 = (int64_t)blockIdx.x * EX_COLS, a0 = (int64_t)blockIdx.y * EX_ROWS;
+  const int I = a.I;
+  // the runs: rows a0.. of X and c0.. of Ut, I values each (packed in LDS
+  // with the same row length I)
+  auto copy = [&](const float* src, int64_t n, float* dst) {
+    if (((uintptr_t)src & 15) == 0) {
+      const int64_t n4 = n >> 2;
+      for (int64_t q = tid; q < n4; q += 256) *(float4*)(dst + 4 * q) = *(const float4*)(src + 4 * q);
+      for (int64_t q = 4 * n4 + tid; q < n; q += 256) dst[q] = src[q];
+    } else {
+      for (int64_t q = tid; q < n; q += 256) dst[q] = src[q];
+    }
+  };
+  copy(a.X + a0 * I, std::min<int64_t>(EX_ROWS, a.A - a0) * I, xs);
+  copy(a.Ut + c0 * I, std::min<int64_t>(EX_COLS, a.R - c0) * I, us);
+  __syncthreads();
+  // rows past A and columns past R read stale LDS values: their outputs are
+  // not stored, and the contraction past I is masked
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;
+  const float* xr = xs + (wr + lr) * I;
+  const float* u0r = us + (wc + lr) * I;
+  const float* u1r = us + (wc + 32 + lr) * I;
+  f32x16_t acc[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[c][v] = 0.f;
+  const int nk = (I + 7) / 8;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (j < nk) {
+      float xv[4], u0[4], u1[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = 8 * j + 4 * half + t;
+        const bool ok = k < I;
+        const int kc = ok ? k : 0;
+        xv[t] = ok ? xr[kc] : 0.f;
+        u0[t] = ok ? u0r[kc] : 0.f;
+        u1[t] = ok ? u1r[kc] : 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[t], u0[t], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[t], u1[t], acc[1], 0, 0, 0);
+      }
+    }
+  }
+  // value v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32 of the tile
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int64_t col = c0 + wc + c * 32 + lr;
+    if (col >= a.R) continue;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = a0 + wr + 8 * (v >> 2) + 4 * half + (v & 3);
+      if (row < a.A) a.Y[row * a.R + col] = acc[c][v];
+    }
+  }
+}
+
 template <int E, int EPI, class XT>
 hipError_t launch_prod(const ProdArgs& p, int64_t batches, hipStream_t s) {
   // the batch index runs on grid.y (at most 65535 per launch)
@@ -1035,6 +1122,20 @@ hipError_t launch_ttm(int elem, const void* X, int64_t A, int64_t I, int64_t B, 
       const bool vec = I % 4 == 0 && aligned16(X) && aligned16(Ut);
       if (vec) hipLaunchKernelGGL(lastmode_small_kernel<true>, dim3((unsigned)wgs), dim3(256), 0, s, la);
       else hipLaunchKernelGGL(lastmode_small_kernel<false>, dim3((unsigned)wgs), dim3(256), 0, s, la);
+      return hipGetLastError();
+    }
+    if (elem == E_F32 && I <= 64 && R > 64) {
+      // short contraction, wide output
+      ExpArgs ea;
+      ea.X = (const float*)X;
+      ea.Ut = (const float*)Ut;
+      ea.Y = (float*)Y;
+      ea.A = A;
+      ea.R = R;
+      ea.I = (int)I;
+      const int64_t gx = ceil_div(R, EX_COLS), gy = ceil_div(A, EX_ROWS);
+      if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(expand_small_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, ea);
       return hipGetLastError();
     }
     // Y (A x R) = X (A x I) . U (I x R): rows a, cols r
