@@ -17,6 +17,7 @@ typedef unsigned char fp8_t;     // OCP e4m3 bit pattern
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
 typedef __attribute__((ext_vector_type(16))) float f32x16_t;
 typedef __attribute__((ext_vector_type(2))) float f32x2_t;
+typedef __attribute__((ext_vector_type(4))) float f32x4_t;
 typedef __attribute__((ext_vector_type(4))) double f64x4_t;
 typedef __attribute__((ext_vector_type(8))) int i32x8_t;
 

@@ -276,18 +276,22 @@ __device__ inline float x_to_f(XT v);
 template <> __device__ inline float x_to_f<float>(float v) { return v; }
 template <> __device__ inline float x_to_f<bf16_t>(bf16_t v) { return bf16_to_f32(v); }
 
-// The split-bfloat16 form with fewer registers, so that two workgroups share
-// a compute unit: each workgroup owns 64 columns j0.. of X_(0), their H
-// block split into bfloat16 hi + lo parts in LDS as [j][k]; wave w walks the
-// 32-row tiles w, w + 4, ... (measured: 1.03 ms at 1000^3 against 2.7 ms when
-// the four waves took adjacent column blocks of the same rows, and 1.42 ms
-// for the former form at one workgroup per compute unit).  Xhat (32 x 64) of a wave is formed
-// as two 32 x 32 blocks, K = 64 with lane half h taking k in [32 h, 32 h + 32),
-// 8 per MFMA, three products (Ul Hh + Uh Hl + Uh Hh).  The U fragments and X
-// values of the next row tile are requested before the current one is formed
-// (the load counter retires in order, so those requests stay in flight).
+// The split-bfloat16 form: each workgroup owns 64 columns j0.. of X_(0),
+// their H block split into bfloat16 hi + lo parts in LDS; wave w walks the
+// 16-row tiles w, w + 4, ... and forms Xhat (16 x 64) of a tile as four
+// 16 x 16 blocks on 16x16x32 bfloat16 MFMA, K = 64 in two steps, three
+// products (Ul Hh + Uh Hl + Uh Hh).  Column c of block n is X column
+// j0 + 4 c + n (H is staged in that order), so a lane's four values of a row
+// are four consecutive X values, one 16-byte load.  The bound is the bytes in
+// flight: with small tiles each wave has X three tiles ahead and U one tile
+// ahead, two workgroups per compute unit (1.05 ms alone at 1000^3, against
+// 1.16 ms with 32-row tiles one tile ahead; three workgroups per compute unit
+// spill registers and took 1.55 ms).  The loads are unconditional (a tile past the
+// wave's last is clamped to it) so that the wait before each product counts
+// only the loads issued after its operands'.
 constexpr int RS_COLS = 64;
 constexpr int RS_LDS_ROW = 72;       // bf16 per LDS row: 64 k + 16 bytes of padding
+constexpr int RS_TR = 16;            // rows per tile
 struct ResSplitArgs {
   const bf16_t* Uh;     // I x 64 (columns >= R zero), hi parts
   const bf16_t* Ul;     // lo parts
@@ -298,7 +302,21 @@ struct ResSplitArgs {
   double* partial;      // [gridDim.x] x 2
 };
 
-template <class XT>
+// four consecutive values of X as floats (VEC: one 16-byte or 8-byte load)
+template <class XT, bool VEC>
+__device__ inline float4 load_x4(const XT* p);
+template <> __device__ inline float4 load_x4<float, true>(const float* p) { return *(const float4*)p; }
+template <> __device__ inline float4 load_x4<float, false>(const float* p) { return make_float4(p[0], p[1], p[2], p[3]); }
+template <> __device__ inline float4 load_x4<bf16_t, true>(const bf16_t* p) {
+  const uint2 v = *(const uint2*)p;
+  return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xFFFF0000u), __uint_as_float(v.y << 16),
+                     __uint_as_float(v.y & 0xFFFF0000u));
+}
+template <> __device__ inline float4 load_x4<bf16_t, false>(const bf16_t* p) {
+  return make_float4(bf16_to_f32(p[0]), bf16_to_f32(p[1]), bf16_to_f32(p[2]), bf16_to_f32(p[3]));
+}
+
+template <class XT, bool VEC>
 __global__ void __launch_bounds__(256, 2) residual_split_kernel(ResSplitArgs a) {
   __shared__ __attribute__((aligned(16))) bf16_t hh[RS_COLS * RS_LDS_ROW];
   __shared__ __attribute__((aligned(16))) bf16_t hl[RS_COLS * RS_LDS_ROW];
@@ -306,128 +324,131 @@ __global__ void __launch_bounds__(256, 2) residual_split_kernel(ResSplitArgs a) 
   // the wave index is uniform across the wave: readfirstlane lets the
   // compiler keep row pointers and loop counters in scalar registers
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int half = lane >> 5, lr = lane & 31;
-  const int64_t jb = (int64_t)blockIdx.x * RS_COLS;
-  const int64_t j0 = jb;
+  const int c16 = lane & 15, g = lane >> 4;
+  const int64_t j0 = (int64_t)blockIdx.x * RS_COLS;
 
-  // H block -> LDS as [j][k]: thread takes 4 consecutive j at one k
+  // H block -> LDS as [p][k], row p = 16 n + c holding column j0 + 4 c + n:
+  // a thread takes 4 consecutive columns at one k
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int c = tid + 256 * q;
     const int kk = c >> 4, jj = (c & 15) * 4;
-    const bool ok = kk < a.R && jb + jj < a.J;
+    const bool ok = kk < a.R && j0 + jj < a.J;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (ok) v = *(const float4*)(a.H + (int64_t)kk * a.J + jb + jj);
+    if (ok) v = *(const float4*)(a.H + (int64_t)kk * a.J + j0 + jj);
     const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
+      const int p = 16 * e + (jj >> 2);
       const bf16_t hi = f32_to_bf16(vv[e]);
-      hh[(jj + e) * RS_LDS_ROW + kk] = hi;
-      hl[(jj + e) * RS_LDS_ROW + kk] = f32_to_bf16(vv[e] - bf16_to_f32(hi));
+      hh[p * RS_LDS_ROW + kk] = hi;
+      hl[p * RS_LDS_ROW + kk] = f32_to_bf16(vv[e] - bf16_to_f32(hi));
     }
   }
   __syncthreads();
 
   const XT* X = (const XT*)a.X;
-  const int64_t NT = ceil_div(a.I, 32);
-  const int64_t ns = NT > wave ? (NT - wave + 3) / 4 : 0;     // this wave's row tiles wave + 4 s
-  const bf16_t* hhw = hh;
-  const bf16_t* hlw = hl;
-  // a row tile of X in the accumulator layout: value v of block n at row
-  // 8 (v / 4) + 4 half + v % 4, column 32 n + lr.  Whole tiles address each
-  // row from a uniform pointer plus a 32-bit lane offset (few registers);
-  // the last row tile and column block clamp rows and columns instead.
-  const bool whole_cols = j0 + 64 <= a.J && (4 * a.J + 64) * (int64_t)sizeof(XT) < ((int64_t)1 << 31);
-  const int32_t lane_off = 4 * half * (int32_t)a.J + lr;
-  auto load_x = [&](int64_t t, XT (&xv)[32]) {
-    const int64_t i0 = t * 32;
-    if (whole_cols && i0 + 32 <= a.I) {
-      const XT* base = X + i0 * a.J + j0;
-#pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        const int n = j >> 4, v = j & 15;
-        const XT* rp = base + (int64_t)(8 * (v >> 2) + (v & 3)) * a.J + 32 * n;
-        xv[j] = rp[lane_off];
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < 32; ++j) {
-        const int n = j >> 4, v = j & 15;
-        int64_t i = i0 + 8 * (v >> 2) + 4 * half + (v & 3);
-        int64_t jj = j0 + 32 * n + lr;
-        i = i < a.I ? i : a.I - 1;
-        jj = jj < a.J ? jj : a.J - 1;
-        xv[j] = X[i * a.J + jj];
-      }
-    }
-  };
-  // a tile's U fragments: its 32 rows, lane half h taking k in [32 h, 32 h + 32)
-  auto load_u = [&](int64_t t, bf16x8_t (&ah)[4], bf16x8_t (&al)[4]) {
-    int64_t iu = t * 32 + lr;
-    iu = iu < a.I ? iu : a.I - 1;
-    const bf16x8_t* ph = (const bf16x8_t*)(a.Uh + iu * 64 + half * 32);
-    const bf16x8_t* pl = (const bf16x8_t*)(a.Ul + iu * 64 + half * 32);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ah[q] = ph[q];
-      al[q] = pl[q];
-    }
-  };
-  double res = 0.0, nrm = 0.0;
-  auto tile = [&](int64_t t, const bf16x8_t (&ah)[4], const bf16x8_t (&al)[4], const XT (&xv)[32]) {
-    const int64_t i0 = t * 32;
-    f32x16_t acc[2];
-#pragma unroll
-    for (int n = 0; n < 2; ++n)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[n][v] = 0.f;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const int row = (32 * n + lr) * RS_LDS_ROW + half * 32 + q * 8;
-        const bf16x8_t bh = *(const bf16x8_t*)(hhw + row);
-        const bf16x8_t bl = *(const bf16x8_t*)(hlw + row);
-        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[q], bh, acc[n], 0, 0, 0);
-        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[q], bl, acc[n], 0, 0, 0);
-        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[q], bh, acc[n], 0, 0, 0);
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 32; ++j) {
-      const int n = j >> 4, v = j & 15;
-      const bool ok = i0 + 8 * (v >> 2) + 4 * half + (v & 3) < a.I && j0 + 32 * n + lr < a.J;
-      const double x = ok ? (double)x_to_f<XT>(xv[j]) : 0.0;
-      const double d = ok ? x - (double)acc[n][v] : 0.0;
-      res = fma(d, d, res);
-      nrm = fma(x, x, nrm);
-    }
-  };
-  bf16x8_t uha[4], ula[4], uhb[4], ulb[4];
-  XT xa[32], xb[32];
+  const int64_t NT = ceil_div(a.I, RS_TR);
+  const int ns = NT > wave ? (int)((NT - wave + 3) / 4) : 0;      // this wave's tiles wave + 4 s
   if (ns > 0) {
-    load_u(wave, uha, ula);
-    load_x(wave, xa);
-  }
-  for (int64_t s = 0; s < ns; s += 2) {
-    if (s + 1 < ns) {
-      load_u(wave + 4 * (s + 1), uhb, ulb);
-      load_x(wave + 4 * (s + 1), xb);
-    }
-    tile(wave + 4 * s, uha, ula, xa);
-    if (s + 1 < ns) {
-      if (s + 2 < ns) {
-        load_u(wave + 4 * (s + 2), uha, ula);
-        load_x(wave + 4 * (s + 2), xa);
+    const bool whole_cols = j0 + RS_COLS <= a.J;
+    // this lane's first column, clamped into the matrix (columns past J are masked)
+    const int64_t jl = std::min<int64_t>(j0 + 4 * c16, a.J - 4 > 0 ? a.J - 4 : 0);
+    auto tile_of = [&](int s) { return (int64_t)wave + 4 * (int64_t)std::min(s, ns - 1); };
+    // X: rows 16 t + 4 g + v (clamped), columns jl .. jl + 3
+    auto load_x = [&](int s, float4 (&xv)[4]) {
+      const int64_t i0 = tile_of(s) * RS_TR + 4 * g;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + v < a.I ? i0 + v : a.I - 1;
+        xv[v] = load_x4<XT, VEC>(X + i * a.J + jl);
       }
-      tile(wave + 4 * (s + 1), uhb, ulb, xb);
+    };
+    // U fragments: row 16 t + c16, k = 32 ks + 8 g .. + 7, hi then lo
+    auto load_u = [&](int s, bf16x8_t (&u)[4]) {
+      int64_t iu = tile_of(s) * RS_TR + c16;
+      iu = iu < a.I ? iu : a.I - 1;
+      const bf16_t* ph = a.Uh + iu * 64 + 8 * g;
+      const bf16_t* pl = a.Ul + iu * 64 + 8 * g;
+      u[0] = *(const bf16x8_t*)ph;
+      u[1] = *(const bf16x8_t*)(ph + 32);
+      u[2] = *(const bf16x8_t*)pl;
+      u[3] = *(const bf16x8_t*)(pl + 32);
+    };
+    double res = 0.0, nrm = 0.0;
+    auto tile = [&](int s, const bf16x8_t (&u)[4], const float4 (&xv)[4]) {
+      f32x4_t acc[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) acc[n] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          const int row = (16 * n + c16) * RS_LDS_ROW + 32 * ks + 8 * g;
+          const bf16x8_t bh = *(const bf16x8_t*)(hh + row);
+          const bf16x8_t bl = *(const bf16x8_t*)(hl + row);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u[2 + ks], bh, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u[ks], bl, acc[n], 0, 0, 0);
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u[ks], bh, acc[n], 0, 0, 0);
+        }
+      // item v of acc[n]: row 16 t + 4 g + v, column j0 + 4 c16 + n
+      const int64_t i0 = ((int64_t)wave + 4 * (int64_t)s) * RS_TR + 4 * g;
+      if (whole_cols && i0 - 4 * g + RS_TR <= a.I) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float xs[4] = {xv[v].x, xv[v].y, xv[v].z, xv[v].w};
+#pragma unroll
+          for (int n = 0; n < 4; ++n) {
+            const double x = (double)xs[n];
+            const double d = x - (double)acc[n][v];
+            res = fma(d, d, res);
+            nrm = fma(x, x, nrm);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float xs[4] = {xv[v].x, xv[v].y, xv[v].z, xv[v].w};
+#pragma unroll
+          for (int n = 0; n < 4; ++n) {
+            // the loaded column is jl + n; it is the tile's column only when unclamped
+            const bool ok = i0 + v < a.I && j0 + 4 * c16 + n < a.J && jl == j0 + 4 * c16;
+            const double x = ok ? (double)xs[n] : 0.0;
+            const double d = ok ? x - (double)acc[n][v] : 0.0;
+            res = fma(d, d, res);
+            nrm = fma(x, x, nrm);
+          }
+        }
+      }
+    };
+    // X three tiles ahead, U one tile ahead; the register sets rotate with s
+    float4 x0[4], x1[4], x2[4], x3[4];
+    bf16x8_t ua[4], ub[4];
+    load_x(0, x0);
+    load_u(0, ua);
+    load_x(1, x1);
+    load_x(2, x2);
+    auto step = [&](int s, const bf16x8_t (&ucur)[4], bf16x8_t (&unext)[4], const float4 (&xcur)[4],
+                    float4 (&xfar)[4]) {
+      load_u(s + 1, unext);
+      load_x(s + 3, xfar);
+      if (s < ns) tile(s, ucur, xcur);
+    };
+    for (int s = 0; s < ns; s += 4) {
+      step(s, ua, ub, x0, x3);
+      step(s + 1, ub, ua, x1, x0);
+      step(s + 2, ua, ub, x2, x1);
+      step(s + 3, ub, ua, x3, x2);
     }
-  }
-  res = warp_sum(res);
-  nrm = warp_sum(nrm);
-  if (lane == 0) {
-    red[0][wave] = res;
-    red[1][wave] = nrm;
+    res = warp_sum(res);
+    nrm = warp_sum(nrm);
+    if (lane == 0) {
+      red[0][wave] = res;
+      red[1][wave] = nrm;
+    }
+  } else if (lane == 0) {
+    red[0][wave] = 0.0;
+    red[1][wave] = 0.0;
   }
   __syncthreads();
   if (tid == 0) {
@@ -1276,8 +1297,15 @@ hipError_t launch_residual(int x_elem, const void* X, int op_elem, const void* U
       rs.R = (int)R;
       rs.partial = partial;
       grid = dim3((unsigned)ceil_div(J, RS_COLS));
-      if (x_elem == E_F32) hipLaunchKernelGGL((residual_split_kernel<float>), grid, dim3(256), 0, s, rs);
-      else hipLaunchKernelGGL((residual_split_kernel<bf16_t>), grid, dim3(256), 0, s, rs);
+      // VEC: every row starts on a 4-value boundary, so a lane's 4 values are one load
+      const bool vec = J % 4 == 0 && aligned16(X);
+      if (x_elem == E_F32) {
+        if (vec) hipLaunchKernelGGL((residual_split_kernel<float, true>), grid, dim3(256), 0, s, rs);
+        else hipLaunchKernelGGL((residual_split_kernel<float, false>), grid, dim3(256), 0, s, rs);
+      } else {
+        if (vec) hipLaunchKernelGGL((residual_split_kernel<bf16_t, true>), grid, dim3(256), 0, s, rs);
+        else hipLaunchKernelGGL((residual_split_kernel<bf16_t, false>), grid, dim3(256), 0, s, rs);
+      }
     } else {
       if (x_elem == E_F32) hipLaunchKernelGGL((residual_kernel<float, E_F32>), grid, dim3(256), 0, s, ra);
       else hipLaunchKernelGGL((residual_kernel<bf16_t, E_F32>), grid, dim3(256), 0, s, ra);
