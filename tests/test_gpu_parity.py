@@ -141,6 +141,9 @@ CASES = [
     ((300, 8, 7, 260), (12, 3, 3, 10), 6, 2, "float32", "mixed_fp8", "order4big"),
     ((300, 200, 90), (60, 50, 20), 10, 1, "float32", "mixed_fp8", "widesketch"),
     ((160, 160, 160), (20, 20, 20), 10, 3, "float32", "mixed_fp8", "c2small"),
+    # the split-bf16 residual's scalar loads: J_0 = I_1 I_2 not a multiple of 4
+    ((150, 33, 77), (12, 6, 10), 5, 2, "float32", "mixed_bf16", "oddJ"),
+    ((150, 33, 77), (12, 6, 10), 5, 2, "float32", "mixed_fp8", "oddJ"),
     ((8, 20, 20), (8, 5, 5), 2, 1, "float64", "plain", "full_rank_mode"),
     # the Krylov basis spans the whole mode space before its last block
     # (S (q+1) > I_n): the later blocks are rounding noise and must be dropped
