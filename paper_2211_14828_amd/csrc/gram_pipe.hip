@@ -23,7 +23,10 @@
 // upper-right 128 x 128 block is the transpose of the lower-left one, so that
 // wave computes the 256 x 64 sketch block W(rows, 0..63) instead (S <= 64).
 // All tiles cost the same, and the number of splits is chosen so that tiles x
-// splits fills whole rounds of the 256 compute units.
+// splits fills whole rounds of the 256 compute units.  The tiles of one split
+// share its K range, so they run on one XCD (one L2); when whole splits leave
+// spare compute units on every XCD (10 tiles: 3 splits, 30 of 32 units), the
+// spare units take further splits whose tiles are spread over several XCDs.
 //
 // Pipeline.  Stage s of the ring holds K tile kt (A rows and B rows, 64 bytes
 // each) in its own LDS array.  While tile kt is multiplied, tiles kt+1..kt+3
@@ -523,10 +526,18 @@ __global__ void __launch_bounds__(256, 1) gram_pipe_kernel(GramArgs g) {
   int split, tile;
   if (g.xcd_map) {
     // consecutive workgroups go to consecutive XCDs: keep the tiles of one
-    // split (which share its K range) on one XCD
+    // split (which share its K range) on one XCD; the spare slots of every
+    // XCD take the extra splits' tiles in turn (slots past them are idle)
     const int xcd = w & 7, slot = w >> 3;
-    split = xcd + 8 * (slot / g.ntiles);
-    tile = slot % g.ntiles;
+    if (g.xleft == 0 || slot < g.xbase * g.ntiles) {
+      split = xcd + 8 * (slot / g.ntiles);
+      tile = slot % g.ntiles;
+    } else {
+      const int e = xcd * g.xleft + (slot - g.xbase * g.ntiles);
+      if (e >= (g.splits - 8 * g.xbase) * g.ntiles) return;
+      split = 8 * g.xbase + e / g.ntiles;
+      tile = e % g.ntiles;
+    }
   } else {
     split = w / g.ntiles;
     tile = w % g.ntiles;
@@ -1084,6 +1095,24 @@ GramArgs gram_plan_pipe(int elem, int64_t A, int64_t I, int64_t Bp, int S, int c
   }
   g.splits = (int)best;
   g.xcd_map = (g.splits % 8 == 0) ? 1 : 0;
+  g.grid = (int)(g.ntiles * g.splits);
+  g.xbase = g.splits / 8;
+  g.xleft = 0;
+  if (g.xcd_map && g.ntiles * best <= cu) {
+    // one round, whole splits per XCD: the spare slots of the 8 XCDs take
+    // as many further splits as they hold whole (their tiles on several
+    // XCDs), when the cost above prefers it
+    const int64_t per_xcd = cu / 8;
+    const int64_t left = per_xcd - (int64_t)g.xbase * g.ntiles;
+    const int64_t extra = left > 0 ? 8 * left / g.ntiles : 0;
+    const int64_t s = best + extra;
+    if (extra > 0 && s <= g.nkt &&
+        (double)g.nkt / (double)s + 8.0 + 0.12 * (double)(g.ntiles * s) < best_cost) {
+      g.splits = (int)s;
+      g.xleft = (int)left;
+      g.grid = (int)(8 * per_xcd);
+    }
+  }
   g.wpart_off = (int64_t)g.ntri * PT * PT;
   g.part_stride = g.wpart_off + (int64_t)g.nt * PT * PW;
   return g;
@@ -1097,9 +1126,9 @@ hipError_t launch_gram_pipe(int elem, const GramArgs& g, hipStream_t s) {
   if (g.nkt < 1 || g.splits > g.nkt || g.S > PW || g.B % 64) return hipErrorInvalidValue;
   if (elem == E_FP8) {
     if (!g.xexp || !g.xexp_om) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(gram_pipe_kernel<E_FP8>, dim3((unsigned)(g.ntiles * g.splits)), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(gram_pipe_kernel<E_FP8>, dim3((unsigned)g.grid), dim3(256), 0, s, g);
   } else {
-    hipLaunchKernelGGL(gram_pipe_kernel<E_BF16>, dim3((unsigned)(g.ntiles * g.splits)), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(gram_pipe_kernel<E_BF16>, dim3((unsigned)g.grid), dim3(256), 0, s, g);
   }
   return hipGetLastError();
 }

@@ -16,6 +16,7 @@ struct GramArgs {
   int nt, ntri, nw, ntiles;
   int64_t nkt, nbt;
   int splits, xcd_map, vec_ok;
+  int xbase, xleft, grid;    // pipelined XCD map: whole splits per XCD, spare slots per XCD, workgroups
   int thin;                 // float32, I <= 64, S <= 64: one 128 x 64 tile [C; W^T] (gram.hip)
   void* partial;            // [splits][ntiles][128*128] float (double for fp64)
   int64_t part_stride;      // elements per split (pipelined bf16 form)

@@ -141,6 +141,9 @@ CASES = [
     ((300, 8, 7, 260), (12, 3, 3, 10), 6, 2, "float32", "mixed_fp8", "order4big"),
     ((300, 200, 90), (60, 50, 20), 10, 1, "float32", "mixed_fp8", "widesketch"),
     ((160, 160, 160), (20, 20, 20), 10, 3, "float32", "mixed_fp8", "c2small"),
+    # extra Gram splits on the XCDs' spare compute units (mode 0: 3 tiles,
+    # 80 + 5 splits)
+    ((300, 250, 400), (12, 10, 14), 5, 2, "float32", "mixed_bf16", "extrasplits"),
     # the split-bf16 residual's scalar loads: J_0 = I_1 I_2 not a multiple of 4
     ((150, 33, 77), (12, 6, 10), 5, 2, "float32", "mixed_bf16", "oddJ"),
     ((150, 33, 77), (12, 6, 10), 5, 2, "float32", "mixed_fp8", "oddJ"),
