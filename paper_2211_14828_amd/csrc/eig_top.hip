@@ -671,17 +671,20 @@ __global__ void __launch_bounds__(64) eig_back_kernel(EigArgs g) {
     const int i = 64 * t + lane;
     x[t] = i < n ? X[r * n + i] : 0.0;
   }
-  // row k of A from a clamped address; the reflector (1 at k+1, zero before)
-  // is formed from it at use, so that the loads stay in flight
-  auto load_v = [&](int k, double (&v)[NS]) {
+  // row k of A from a clamped address, and tau_k; the reflector (1 at k+1,
+  // zero before) is formed from the row at use, so that the loads stay in
+  // flight.  A zero tau gives a zero update, so no branch waits on it.
+  auto load_v = [&](int k, double (&v)[NS], double& tk) {
+    const int kc = k >= 0 ? k : 0;
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
       const int j = 64 * t + lane;
-      v[t] = A[(k >= 0 ? k : 0) * n + (j < n ? j : n - 1)];
+      v[t] = A[kc * n + (j < n ? j : n - 1)];
     }
+    tk = taus[kc];
   };
-  auto apply = [&](int k, const double (&a)[NS]) {
-    if (k < 0 || taus[k] == 0.0) return;
+  auto apply = [&](int k, const double (&a)[NS], double tk) {
+    if (k < 0) return;                             // uniform: past the last reflector
     double v[NS], dot = 0.0;
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -689,26 +692,24 @@ __global__ void __launch_bounds__(64) eig_back_kernel(EigArgs g) {
       v[t] = j == k + 1 ? 1.0 : (j >= k + 2 && j < n ? a[t] : 0.0);
       dot = fma(v[t], x[t], dot);
     }
-    const double f = taus[k] * wave_sum(dot);
+    const double f = tk * wave_sum(dot);
 #pragma unroll
     for (int t = 0; t < NS; ++t) x[t] = fma(-f, v[t], x[t]);
   };
-  // reflectors n-3 down to 0, four in flight
-  double v0[NS], v1[NS], v2[NS], v3[NS];
+  // reflectors n-3 down to 0, BD in flight: each waits on its row about a
+  // memory latency after the request, so the ring holds enough rows to
+  // cover it (one wave per workgroup, registers to spare)
+  constexpr int BD = 16;
+  double vr[BD][NS], tr[BD];
   int k = n - 3;
-  load_v(k, v0);
-  load_v(k - 1, v1);
-  load_v(k - 2, v2);
-  load_v(k - 3, v3);
-  for (; k >= 0; k -= 4) {
-    apply(k, v0);
-    load_v(k - 4, v0);
-    apply(k - 1, v1);
-    load_v(k - 5, v1);
-    apply(k - 2, v2);
-    load_v(k - 6, v2);
-    apply(k - 3, v3);
-    load_v(k - 7, v3);
+#pragma unroll
+  for (int u = 0; u < BD; ++u) load_v(k - u, vr[u], tr[u]);
+  for (; k >= 0; k -= BD) {
+#pragma unroll
+    for (int u = 0; u < BD; ++u) {
+      apply(k - u, vr[u], tr[u]);
+      load_v(k - u - BD, vr[u], tr[u]);
+    }
   }
   double* out = g.Vt[m] + (size_t)r * n;
 #pragma unroll
