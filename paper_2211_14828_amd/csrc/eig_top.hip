@@ -560,9 +560,11 @@ __global__ void __launch_bounds__(SOLVE_THREADS) eig_solve_kernel(EigArgs g) {
       const int r = tid;
       double* xr = X + r * n;
       double* yr = Y + r * n;
-      // blocks of 16 steps: all inputs of a block are loaded before any of
-      // its results is stored, so that the loads overlap
-      constexpr int B = 16;
+      // blocks of steps: all inputs of a block are loaded before any of its
+      // results is stored, so that the loads overlap; each block waits about
+      // one memory latency, so the blocks are as long as the registers allow
+      // (32 steps forward, 24 backward)
+      constexpr int B = 32;
       double yk = xr[0] * ptol;
       for (int k0 = 0; k0 + 1 < n; k0 += B) {
         double xv[B], mv[B];
@@ -587,10 +589,11 @@ __global__ void __launch_bounds__(SOLVE_THREADS) eig_solve_kernel(EigArgs g) {
       }
       yr[n - 1] = yk;
       double x1 = 0.0, x2 = 0.0;
-      for (int k0 = n - 1; k0 >= 0; k0 -= B) {
-        double yv[B], dv[B], bv[B], av[B];
+      constexpr int BB = 24;
+      for (int k0 = n - 1; k0 >= 0; k0 -= BB) {
+        double yv[BB], dv[BB], bv[BB], av[BB];
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
+        for (int u = 0; u < BB; ++u) {
           const int k = k0 - u >= 0 ? k0 - u : 0;
           yv[u] = yr[k];
           dv[u] = du[k * R + r];
@@ -598,7 +601,7 @@ __global__ void __launch_bounds__(SOLVE_THREADS) eig_solve_kernel(EigArgs g) {
           av[u] = ainv[k * R + r];
         }
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
+        for (int u = 0; u < BB; ++u) {
           if (k0 - u >= 0) {
             const double xk = fma(-dv[u], x2, fma(-bv[u], x1, yv[u])) * av[u];
             xr[k0 - u] = xk;
