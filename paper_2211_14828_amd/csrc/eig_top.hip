@@ -423,39 +423,48 @@ __device__ inline void spectrum_bounds(const double* d, const double* e, int n, 
 
 // Step 2: the R largest eigenvalues of T by multisection on Sturm counts
 // (the number of negative pivots of the LDL^T factorisation of T - x I is
-// the number of eigenvalues below x).  One wave per eigenvalue tests 128
-// points a round, so the interval shrinks 129-fold per round; BIS_WAVES
-// eigenvalues per workgroup, grid (ceil(R / BIS_WAVES), matrices).
+// the number of eigenvalues below x).  A workgroup of BIS_WAVES waves takes
+// one eigenvalue and tests 128 points per wave a round (P = 128 BIS_WAVES),
+// so the interval shrinks P + 1-fold per round: 6 rounds to float64 accuracy
+// with four waves, against 8 with one (each round is a sequential Sturm
+// count, the cost).  The waves add their counts in LDS; every wave then holds
+// the same interval, so all take the same exits.  Grid (R, matrices).
 constexpr int BIS_WAVES = 4;
 
 template <int NS>
 __global__ void __launch_bounds__(64 * BIS_WAVES) eig_bisect_kernel(EigArgs g) {
   constexpr int NM = 64 * NS;
   __shared__ double dl[NM], e2l[NM], bnd[4];
+  __shared__ int cnt[2][BIS_WAVES];
   const int m = blockIdx.y;
   const int n = g.n[m], R = g.R[m];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if ((int)blockIdx.x * BIS_WAVES >= R) return;    // the same for the whole workgroup
+  const int r = (int)blockIdx.x;
+  if (r >= R) return;                              // the same for the whole workgroup
   for (int i = tid; i < n; i += blockDim.x) dl[i] = g.d[m][i];
   if (wave == 0) spectrum_bounds<NS>(g.d[m], g.e[m], n, lane, e2l, bnd);
   __syncthreads();
-  const int r = (int)blockIdx.x * BIS_WAVES + wave;
-  if (r >= R) return;                              // no barrier follows
   const double tnorm = bnd[0], pivmin = bnd[1];
   const double margin = 2.0 * n * EPS * tnorm + 2.0 * pivmin;
   const double atol = EPS * tnorm;
-  constexpr int P = 128;                           // points a round
+  constexpr int P = 128 * BIS_WAVES;               // points a round
   const int kk = n - 1 - r;                        // ascending index of the eigenvalue
   double lo = bnd[2] - margin, hi = bnd[3] + margin;
-  // lo and hi are the same in every lane, so the loop is uniform in the wave
+  // lo and hi are the same in every thread, so the loop is uniform
   for (int it = 0; it < 96; ++it) {
     if (hi - lo <= fmax(atol, 2.0 * EPS * fmax(fabs(lo), fabs(hi)))) break;
     const double wd = hi - lo;
-    const double x0 = lo + wd * ((double)(lane + 1) / (double)(P + 1));
-    const double x1 = lo + wd * ((double)(lane + 65) / (double)(P + 1));
+    const int q = 128 * wave + lane;               // this lane's points q and q + 64
+    const double x0 = lo + wd * ((double)(q + 1) / (double)(P + 1));
+    const double x1 = lo + wd * ((double)(q + 65) / (double)(P + 1));
     int c0, c1;
     sturm2(dl, e2l, n, pivmin, x0, x1, c0, c1);
-    const int nb = __popcll(__ballot(c0 <= kk)) + __popcll(__ballot(c1 <= kk));
+    const int nw = __popcll(__ballot(c0 <= kk)) + __popcll(__ballot(c1 <= kk));
+    if (lane == 0) cnt[it & 1][wave] = nw;
+    __syncthreads();
+    int nb = 0;
+#pragma unroll
+    for (int w = 0; w < BIS_WAVES; ++w) nb += cnt[it & 1][w];
     const double nlo = nb > 0 ? lo + wd * ((double)nb / (double)(P + 1)) : lo;
     const double nhi = nb < P ? lo + wd * ((double)(nb + 1) / (double)(P + 1)) : hi;
     const bool progress = nhi - nlo < wd;          // false once float64 cannot split further
@@ -463,7 +472,7 @@ __global__ void __launch_bounds__(64 * BIS_WAVES) eig_bisect_kernel(EigArgs g) {
     hi = nhi;
     if (!progress) break;
   }
-  if (lane == 0) g.lam[m][r] = 0.5 * (lo + hi);
+  if (tid == 0) g.lam[m][r] = 0.5 * (lo + hi);
 }
 
 // Step 3 for one matrix per workgroup, from d and e of T and the eigenvalues.
@@ -803,8 +812,7 @@ hipError_t launch_ns(EigArgs& a, int nmat, int gmax, int64_t rows_cap, int rmax,
   if ((e = hipFuncSetAttribute((const void*)eig_solve_kernel<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)sshm)) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(eig_bisect_kernel<NS>, dim3((unsigned)ceil_div(rmax, BIS_WAVES), nmat), dim3(64 * BIS_WAVES), 0,
-                     st, a);
+  hipLaunchKernelGGL(eig_bisect_kernel<NS>, dim3((unsigned)rmax, nmat), dim3(64 * BIS_WAVES), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(eig_solve_kernel<NS>, dim3(nmat), dim3(SOLVE_THREADS), sshm, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
