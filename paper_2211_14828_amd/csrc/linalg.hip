@@ -198,96 +198,149 @@ __global__ void __launch_bounds__(1024) chol_inv_kernel(const double* G, int64_t
 
 // CholeskyQR step for s <= 64 in one launch: Yout = L^{-1} Y where G = L L^T
 // (same drop rule as above: a dropped vector gets a zero row of Yout).
-// Every workgroup factors G itself: wave 0, lane i owning row i in
-// registers, runs a right-looking Cholesky; the update of step k reads the
-// finished column k from the lanes that hold it (v_readlane into scalar
-// registers), so no barriers or LDS round trips are needed.  Then each thread
-// solves L y = Y(:, c) for one column c by forward substitution, with y in
-// registers and L read by LDS broadcast.  Both loops are unrolled to the size
-// bound SMAX (16, 32, 48 or 64, the smallest that holds s), which keeps the
-// code of the common sizes small.  flags is written by workgroup 0.  The
-// thread's column of Y is loaded before the factor starts.
+// One wave per workgroup, 64 columns of Y each; every workgroup factors G
+// itself, so no workgroup waits for another.  G is zero-padded to SMAX in LDS
+// (a padded pivot is dropped and changes nothing), and the factor runs in
+// panels of 16 columns: lane i holds row i of the panel in registers and
+// reads the finished column k from the lane that holds it (v_readlane), then
+// the wave applies the panel to the trailing rows and columns in 4 x 4 tiles.
+// Every entry receives its updates in column order, one FMA each, as in the
+// unblocked right-looking form.  The pivot is d * rsqrt(d) and its reciprocal
+// the Newton-refined rsqrt itself.  Then each lane solves L y = Y(:, c) for
+// its column c by forward substitution, with y in registers and L read by LDS
+// broadcast, four rows per branch.  Loads of G and Y are clamped into range
+// so they are all issued before the first wait.  flags is written by
+// workgroup 0.
 constexpr int CS_MAX = 64;
+constexpr int CS_NB = 16;
+
+__device__ inline double lane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
 
 template <int SMAX>
-__global__ void __launch_bounds__(256) chol_solve_kernel(const double* G, int s, const double* Y, int64_t n,
-                                                         double* Yout, int* flags, const double* ref2,
-                                                         double tau_rel, double tau_abs, DimBudget bud) {
+__global__ void __launch_bounds__(64) chol_solve_kernel(const double* G, int s, const double* Y, int64_t n,
+                                                        double* Yout, int* flags, const double* ref2,
+                                                        double tau_rel, double tau_abs, DimBudget bud) {
+  static_assert(SMAX % CS_NB == 0, "panels of 16 columns");
   __shared__ double Ls[SMAX][SMAX + 1];
   __shared__ double dinv[SMAX];
   __shared__ int keep[SMAX];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < s * s; e += 256) {
-    const int i = e / s, j = e - i * s;
-    Ls[i][j] = G[e];
+  const int lane = threadIdx.x;
+  {
+    double gv[SMAX * SMAX / 64];
+#pragma unroll
+    for (int q = 0; q < SMAX * SMAX / 64; ++q) {
+      const int e = lane + 64 * q, i = e / SMAX, j = e - i * SMAX;
+      gv[q] = G[(i < s ? i : s - 1) * s + (j < s ? j : s - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < SMAX * SMAX / 64; ++q) {
+      const int e = lane + 64 * q, i = e / SMAX, j = e - i * SMAX;
+      Ls[i][j] = (i < s && j < s) ? gv[q] : 0.0;
+    }
   }
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + tid;
+  const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t cc = c < n ? c : n - 1;
   double y[SMAX];
 #pragma unroll
-  for (int k = 0; k < SMAX; ++k) y[k] = (k < s && c < n) ? Y[(int64_t)k * n + c] : 0.0;
+  for (int k = 0; k < SMAX; ++k) y[k] = Y[(int64_t)(k < s ? k : s - 1) * n + cc];
+  const double mx = warp_max((ref2 && lane < s) ? ref2[lane] : 0.0);
+  const double abs_floor = tau_abs * tau_abs * mx;
+  const int64_t allowed = bud.allowed();
   __syncthreads();
-  if (tid < 64) {
-    const int i = tid;
-    double mx = (ref2 && i < s) ? ref2[i] : 0.0;
-    mx = warp_max(mx);
-    const double abs_floor = tau_abs * tau_abs * mx;
-    const double d0 = i < s ? Ls[i][i] : 0.0;
-    double row[SMAX];
+  const double d0 = lane < SMAX ? Ls[lane][lane] : 0.0;
+  int64_t nkept = 0;
+#pragma unroll 1
+  for (int c0 = 0; c0 < SMAX; c0 += CS_NB) {
+    {
+      const int i = lane;
+      double r[CS_NB];
 #pragma unroll
-    for (int j = 0; j < SMAX; ++j) row[j] = (i < s && j < s) ? Ls[i][j] : 0.0;
-    const int64_t allowed = bud.allowed();
-    int64_t nkept = 0;
+      for (int jj = 0; jj < CS_NB; ++jj) r[jj] = i < SMAX ? Ls[i][c0 + jj] : 0.0;
 #pragma unroll
-    for (int k = 0; k < SMAX; ++k) {
-      if (k < s) {
-        const double v = row[k];                 // G(i, k) minus the earlier columns' terms
-        const double d = __shfl(v, k, 64);
-        const double dk0 = __shfl(d0, k, 64);
+      for (int kk = 0; kk < CS_NB; ++kk) {
+        const int k = c0 + kk;
+        const double v = r[kk];           // G(i, k) minus the earlier columns' terms
+        const double d = lane_f64(v, k), dk0 = lane_f64(d0, k);
         const bool kp = (dk0 > 0.0) && (d > tau_rel * dk0) && (d > abs_floor) && nkept < allowed;
         nkept += kp;
-        const double piv = kp ? sqrt(d) : 0.0;
-        const double inv = kp ? 1.0 / piv : 0.0;
-        const double lik = (i > k && i < s) ? v * inv : (i == k ? piv : 0.0);
-        row[k] = lik;
+        const double rs = rsq_nr(kp ? d : 1.0);
+        const double inv = kp ? rs : 0.0;
+        const double lik = i > k ? v * inv : (i == k ? d * inv : 0.0);
+        r[kk] = lik;
         if (i == k) {
           keep[k] = kp;
           dinv[k] = inv;
         }
-        // L(j, k) is lane j's lik: read into scalar registers (no LDS trip)
-        const int lhi = __double2hiint(lik), llo = __double2loint(lik);
 #pragma unroll
-        for (int j = k + 1; j < SMAX; ++j) {
-          const double cj = __hiloint2double(__builtin_amdgcn_readlane(lhi, j), __builtin_amdgcn_readlane(llo, j));
-          row[j] -= lik * cj;
-        }
+        for (int jj = kk + 1; jj < CS_NB; ++jj) r[jj] -= lik * lane_f64(lik, c0 + jj);
+      }
+      if (i < SMAX) {
+#pragma unroll
+        for (int jj = 0; jj < CS_NB; ++jj) Ls[i][c0 + jj] = r[jj];
       }
     }
+    __syncthreads();
+    // trailing rows and columns t0.. of the lower triangle's square, 4 x 4
+    // tiles (the upper part is updated too and never read)
+    const int t0 = c0 + CS_NB, mt = (SMAX - t0) / 4;
+    for (int t = lane; t < mt * mt; t += 64) {
+      const int ti = t / mt, tj = t - ti * mt;
+      const int i0 = t0 + 4 * ti, j0 = t0 + 4 * tj;
+      double acc[4][4];
 #pragma unroll
-    for (int j = 0; j < SMAX; ++j)
-      if (i < s && j < s) Ls[i][j] = j <= i ? row[j] : 0.0;
-    // every workgroup reads the count of earlier blocks and writes a
-    // different slot, so they agree without synchronising
-    if (blockIdx.x == 0 && i == 0) bud.record(nkept);
-  }
-  __syncthreads();
-  if (blockIdx.x == 0)
-    for (int i = tid; i < s; i += blockDim.x) flags[i] = keep[i];
-  if (c >= n) return;
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-  for (int k = 0; k < SMAX; ++k) {
-    if (k < s) {
-      double a0 = y[k], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int q = 0; q < 4; ++q) acc[a][q] = Ls[i0 + a][j0 + q];
 #pragma unroll
-      for (int j = 0; j + 3 < k; j += 4) {
-        a0 -= Ls[k][j] * y[j];
-        a1 -= Ls[k][j + 1] * y[j + 1];
-        a2 -= Ls[k][j + 2] * y[j + 2];
-        a3 -= Ls[k][j + 3] * y[j + 3];
+      for (int kk = 0; kk < CS_NB; ++kk) {
+        double li[4], lj[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          li[a] = Ls[i0 + a][c0 + kk];
+          lj[a] = Ls[j0 + a][c0 + kk];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[a][q] -= li[a] * lj[q];
       }
 #pragma unroll
-      for (int j = k & ~3; j < k; ++j) a0 -= Ls[k][j] * y[j];
-      y[k] = ((a0 + a1) + (a2 + a3)) * dinv[k];   // zero for a dropped vector
-      Yout[(int64_t)k * n + c] = y[k];
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ls[i0 + a][j0 + q] = acc[a][q];
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    if (lane < s) flags[lane] = keep[lane];
+    // every workgroup reads the count of earlier blocks; one writes the total
+    if (lane == 0) bud.record(nkept);
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < SMAX; k0 += 4) {
+    if (k0 < s) {
+#pragma unroll
+      for (int k = k0; k < k0 + 4; ++k) {
+        double a0 = y[k], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int j = 0; j + 3 < k; j += 4) {
+          a0 -= Ls[k][j] * y[j];
+          a1 -= Ls[k][j + 1] * y[j + 1];
+          a2 -= Ls[k][j + 2] * y[j + 2];
+          a3 -= Ls[k][j + 3] * y[j + 3];
+        }
+#pragma unroll
+        for (int j = k & ~3; j < k; ++j) a0 -= Ls[k][j] * y[j];
+        y[k] = ((a0 + a1) + (a2 + a3)) * dinv[k];   // zero for a dropped or padded vector
+      }
+      if (c < n) {
+#pragma unroll
+        for (int k = k0; k < k0 + 4; ++k)
+          if (k < s) Yout[(int64_t)k * n + c] = y[k];
+      }
     }
   }
 }
@@ -844,18 +897,18 @@ hipError_t chol_orth(double* Y, double* Yout, int64_t s, int64_t n, double* G, d
   hipError_t e = dgemm(0, 1, s, s, n, 1.0, Y, n, Y, n, 0.0, G, s, st);
   if (e != hipSuccess) return e;
   if (s <= CS_MAX) {
-    const dim3 grid((unsigned)ceil_div(n, 256));
+    const dim3 grid((unsigned)ceil_div(n, 64));
     if (s <= 16)
-      hipLaunchKernelGGL(chol_solve_kernel<16>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
+      hipLaunchKernelGGL(chol_solve_kernel<16>, grid, dim3(64), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
                          tau_abs, bud);
     else if (s <= 32)
-      hipLaunchKernelGGL(chol_solve_kernel<32>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
+      hipLaunchKernelGGL(chol_solve_kernel<32>, grid, dim3(64), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
                          tau_abs, bud);
     else if (s <= 48)
-      hipLaunchKernelGGL(chol_solve_kernel<48>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
+      hipLaunchKernelGGL(chol_solve_kernel<48>, grid, dim3(64), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
                          tau_abs, bud);
     else
-      hipLaunchKernelGGL(chol_solve_kernel<64>, grid, dim3(256), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
+      hipLaunchKernelGGL(chol_solve_kernel<64>, grid, dim3(64), 0, st, G, (int)s, Y, n, Yout, flags, ref2, tau_rel,
                          tau_abs, bud);
     return hipGetLastError();
   }
