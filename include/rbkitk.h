@@ -166,6 +166,25 @@ rbki_status rbki_tucker(const void *X, int xtype, const rbki_params *prm, void *
                         void *const *factors, int out_type, void *workspace, size_t ws_bytes,
                         double *rel_err, void *stream);
 
+/* rbki_tucker without its final synchronisation, for callers that run
+ * decompositions back to back on one stream (Alg. 2, the same work and
+ * outputs as rbki_tucker, the explicit error included).  The error sums and
+ * the eigen-solvers' status are copied into `result` when the stream gets
+ * there; the call returns once everything is enqueued.
+ *   result : host memory of rbki_tucker_result_bytes() bytes, owned by the
+ *            caller.  Page-locked memory (hipHostMalloc) keeps the copy
+ *            asynchronous; it must be left alone until the stream has passed
+ *            this call's work.
+ * Calls that share a workspace must be issued on one stream.  After the
+ * stream has passed the call, rbki_tucker_result(result, &rel_err) returns
+ * rel_err as rbki_tucker would, and RBKI_E_NOCONV if an eigen-solve did not
+ * finish.  Invalid arguments are reported before anything is enqueued. */
+size_t rbki_tucker_result_bytes(void);
+rbki_status rbki_tucker_enqueue(const void *X, int xtype, const rbki_params *prm, void *core,
+                                void *const *factors, int out_type, void *workspace, size_t ws_bytes,
+                                void *result, void *stream);
+rbki_status rbki_tucker_result(const void *result, double *rel_err);
+
 /* rBKI-TK with the number of Krylov steps chosen by the stopping rule of
  * Sec. 4: after t = 0, 1, ... steps (every mode; the same sketch, so the
  * Krylov spaces are nested) the rank-k approximation X_t and its Fit

@@ -37,7 +37,8 @@ SYMBOLS = ("rbki_version", "rbki_last_error", "rbki_omega", "rbki_philox", "rbki
            "rbki_htr_als_workspace", "rbki_htr_als", "rbki_tucker_noalloc_limit", "rbki_tucker_noalloc",
            "rbki_sym_eig_workspace", "rbki_sym_eig", "rbki_sym_eig_top_workspace", "rbki_sym_eig_top",
            "rbki_profile_enable", "rbki_profile_reset", "rbki_profile_read", "rbki_server_request_bytes", "rbki_server_create", "rbki_server_submit",
-           "rbki_server_poll", "rbki_server_wait", "rbki_server_destroy")
+           "rbki_server_poll", "rbki_server_wait", "rbki_server_destroy", "rbki_tucker_result_bytes",
+           "rbki_tucker_enqueue", "rbki_tucker_result")
 
 
 class RbkiError(RuntimeError):
@@ -88,6 +89,9 @@ def load_library(build_if_missing=True):
             "rbki_tucker_adaptive": (ci, [vp, ci, P(_Params), dbl, vp, P(vp), ci, vp, sz, P(dbl), P(ci), vp]),
             "rbki_tucker_workspace": (sz, [P(_Params), ci]),
             "rbki_tucker": (ci, [vp, ci, P(_Params), vp, P(vp), ci, vp, sz, P(dbl), vp]),
+            "rbki_tucker_result_bytes": (sz, []),
+            "rbki_tucker_enqueue": (ci, [vp, ci, P(_Params), vp, P(vp), ci, vp, sz, vp, vp]),
+            "rbki_tucker_result": (ci, [vp, P(dbl)]),
             "rbki_htr_workspace": (sz, [P(_Params), ci, P(i64)]),
             "rbki_htr": (ci, [vp, ci, P(_Params), P(i64), P(vp), ci, vp, sz, P(dbl), vp]),
             "rbki_htr_als_workspace": (sz, [P(_Params), ci, P(i64)]),
@@ -231,6 +235,49 @@ def tucker(X, ranks, p=5, q=2, seed=0, precision="plain", out_dtype=None, rel_er
                            fptr, ocode, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                            ctypes.byref(err) if rel_err else None, _stream(torch, stream)))
     return core, factors, (err.value if rel_err else None)
+
+
+def tucker_result_buffer():
+    """Page-locked host memory for one tucker_enqueue result."""
+    torch = _torch()
+    return torch.empty(int(load_library().rbki_tucker_result_bytes()), dtype=torch.uint8, pin_memory=True)
+
+
+def tucker_enqueue(X, ranks, result, p=5, q=2, seed=0, precision="plain", out_dtype=None, stream=None,
+                   workspace=None, variant="krylov", sample_rate=1.0, truncation="independent"):
+    """tucker() without waiting for the stream: the same work, the explicit
+    error included.  `result` (tucker_result_buffer()) receives the error sums
+    when the stream gets there; tucker_result(result) then returns rel_err.
+    Calls that share a workspace must be issued on one stream.  Returns
+    (core, [U^(1), ..., U^(N)])."""
+    torch = _torch()
+    lib = load_library()
+    X = _as_input(torch, X)
+    code = _dtype_code(torch, X.dtype)
+    if out_dtype is None:
+        out_dtype = torch.float64 if X.dtype == torch.float64 else torch.float32
+    ocode = _dtype_code(torch, out_dtype)
+    prm = _params(X.shape, ranks, p, q, seed, precision, variant, sample_rate, truncation)
+    need = lib.rbki_tucker_workspace(ctypes.byref(prm), code)
+    if need == 0:
+        _check(lib.rbki_tucker(None, code, ctypes.byref(prm), None, None, ocode, None, 0, None, None))
+    if result.numel() < lib.rbki_tucker_result_bytes() or result.device.type != "cpu":
+        raise ValueError("result must be a tucker_result_buffer()")
+    ws = workspace if workspace is not None else _workspace(torch, X.device, need)
+    core = torch.empty(tuple(int(r) for r in ranks), dtype=out_dtype, device=X.device)
+    factors = [torch.empty((int(I), int(R)), dtype=out_dtype, device=X.device) for I, R in zip(X.shape, ranks)]
+    fptr = (ctypes.c_void_p * len(factors))(*[f.data_ptr() for f in factors])
+    _check(lib.rbki_tucker_enqueue(ctypes.c_void_p(X.data_ptr()), code, ctypes.byref(prm),
+                                   ctypes.c_void_p(core.data_ptr()), fptr, ocode, ctypes.c_void_p(ws.data_ptr()),
+                                   ws.numel(), ctypes.c_void_p(result.data_ptr()), _stream(torch, stream)))
+    return core, factors
+
+
+def tucker_result(result):
+    """rel_err of a tucker_enqueue call whose work the stream has passed."""
+    err = ctypes.c_double(0.0)
+    _check(load_library().rbki_tucker_result(ctypes.c_void_p(result.data_ptr()), ctypes.byref(err)))
+    return err.value
 
 
 def tucker_adaptive(X, ranks, p=5, max_q=20, fit_tol=1e-3, seed=0, precision="plain", out_dtype=None,

@@ -1566,10 +1566,11 @@ rbki_status adaptive_impl(const void* X, int xtype, const rbki_params* prm, doub
 
 static rbki_status tucker_impl(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
                         int out_type, void* workspace, size_t ws_bytes, double* rel_err, hipStream_t st, Plan& P,
-                        Buffers& b, void** core_chain, HostResult* async_res, bool one_stream = false) {
+                        Buffers& b, void** core_chain, HostResult* async_res, bool one_stream = false,
+                        bool served = false) {
   rbki_status s = make_plan(prm, xtype, P);
   if (s != RBKI_OK) return s;
-  P.concurrent = async_res != nullptr;        // enqueued by the request server
+  P.concurrent = served;                       // enqueued by the request server
   P.one_stream = one_stream;
   if (!X) return fail(RBKI_E_INVALID, "X is NULL");
   if (out_type != RBKI_F64 && out_type != RBKI_F32) return fail(RBKI_E_INVALID, "out_type must be F64 or F32");
@@ -1632,7 +1633,8 @@ rbki_status tucker_enqueue(const void* X, int xtype, const rbki_params* prm, voi
                            int out_type, void* workspace, size_t ws_bytes, hipStream_t st, HostResult* hr) {
   Plan P;
   Buffers b;
-  return tucker_impl(X, xtype, prm, core, factors, out_type, workspace, ws_bytes, nullptr, st, P, b, nullptr, hr);
+  return tucker_impl(X, xtype, prm, core, factors, out_type, workspace, ws_bytes, nullptr, st, P, b, nullptr, hr,
+                     false, true);
 }
 }  // namespace rbki
 
@@ -1656,6 +1658,26 @@ void rbki_release(void) {
   }
   if (have_cur) (void)hipSetDevice(cur);
   g_lane_pool.clear();
+}
+
+size_t rbki_tucker_result_bytes(void) { return sizeof(rbki::HostResult); }
+
+rbki_status rbki_tucker_enqueue(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
+                                int out_type, void* workspace, size_t ws_bytes, void* result, void* stream) {
+  if (!result) return fail(RBKI_E_INVALID, "result is required");
+  rbki::HostResult* hr = (rbki::HostResult*)result;
+  hr->nmodes = 0;
+  Plan P;
+  Buffers b;
+  // the solo configuration (the modes on helper streams beside the caller's),
+  // as rbki_tucker, without its final wait
+  return tucker_impl(X, xtype, prm, core, factors, out_type, workspace, ws_bytes, nullptr, (hipStream_t)stream, P,
+                     b, nullptr, hr);
+}
+
+rbki_status rbki_tucker_result(const void* result, double* rel_err) {
+  if (!result) return fail(RBKI_E_INVALID, "result is required");
+  return rbki::finish_result(*(const rbki::HostResult*)result, rel_err);
 }
 
 rbki_status rbki_tucker(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,

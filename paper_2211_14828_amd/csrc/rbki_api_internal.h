@@ -14,8 +14,10 @@ struct HostResult {
   int nmodes;
 };
 
-// Enqueue a whole rBKI-TK decomposition on `st` without synchronising; `hr`
-// receives the error sums and the solver status when the stream reaches it.
+// Enqueue a whole rBKI-TK decomposition on `st` without synchronising, in the
+// request server's form (every mode on `st`, beside other requests' solves);
+// `hr` receives the error sums and the solver status when the stream reaches
+// it.
 rbki_status tucker_enqueue(const void* X, int xtype, const rbki_params* prm, void* core, void* const* factors,
                            int out_type, void* workspace, size_t ws_bytes, hipStream_t st, HostResult* hr);
 

@@ -7,6 +7,8 @@ oracle cannot run, so the checks are properties that hold at any size:
 - the concurrent run gives bit for bit the factors, core and error of the
   same request solved with the modes in order (the request server runs a
   request on one stream), and of a second run;
+- decompositions enqueued back to back without waiting give those of the
+  synchronous calls, bit for bit;
 - the factors are orthonormal (Alg. 2 builds them from an orthonormal basis
   and unit eigenvectors);
 - the core is X x_1 U1^T x_2 U2^T x_3 U3^T (Alg. 2, step 6), up to the
@@ -97,3 +99,23 @@ def test_full_size_run_matches_the_modes_in_order(env, big, precision, variant):
     print(precision, "err", err, "projection err", err_proj, "core distance", dcore, flush=True)
     assert dcore <= CORE_TOL[precision]
     assert abs(err - err_proj) <= 1e-4 * err_proj
+
+
+def test_enqueued_decompositions_match_synchronous_ones(env, big):
+    # three decompositions enqueued back to back on one stream with no wait
+    # between them (two seeds, the first one twice) give, bit for bit, the
+    # factors, core and error of the synchronous calls
+    torch, rb = env
+    w, X = big
+    ranks, p, q = w["ranks"], w["p"], w["q"]
+    seeds = (w["seeds"][1], w["seeds"][1] + 7, w["seeds"][1])
+    args = dict(p=p, q=q, precision="mixed_fp8", out_dtype=torch.float64)
+    print("synchronous", flush=True)
+    ref = {s: rb.tucker(X, ranks, seed=s, **args) for s in set(seeds)}
+    print("enqueued", flush=True)
+    bufs = [rb.tucker_result_buffer() for _ in seeds]
+    outs = [rb.tucker_enqueue(X, ranks, r, seed=s, **args) for s, r in zip(seeds, bufs)]
+    torch.cuda.synchronize()
+    for s, (core, factors), r in zip(seeds, outs, bufs):
+        assert identical(torch, (core, factors, rb.tucker_result(r)), ref[s])
+    assert ref[seeds[0]][2] != ref[seeds[1]][2]
