@@ -155,6 +155,10 @@ CASES = [
     ((63, 120, 146), (28, 14, 28), 5, 3, "float64", "plain", "capped"),
     ((63, 120, 146), (28, 14, 28), 5, 3, "bfloat16", "plain", "capped"),
     ((72, 52, 228), (23, 15, 19), 5, 3, "float32", "plain", "capped"),
+    # the same on a mode past the persistent chain (I > 256): the CholeskyQR
+    # launches drop the last block's directions (S (q+1) = 300 > 280)
+    ((280, 40, 30), (50, 10, 8), 10, 4, "float64", "plain", "capped"),
+    ((280, 40, 30), (50, 10, 8), 10, 4, "float32", "mixed_bf16", "capped"),
     # the thin float32 Gram tile [C; W^T] (I <= 64, S <= 64): I = 64 with a
     # 64-wide sketch, a middle mode (A > 1 and B > 1), a last mode whose
     # size is not a multiple of 4 (element-wise staging), and order 4 with a
