@@ -159,6 +159,10 @@ CASES = [
     # launches drop the last block's directions (S (q+1) = 300 > 280)
     ((280, 40, 30), (50, 10, 8), 10, 4, "float64", "plain", "capped"),
     ((280, 40, 30), (50, 10, 8), 10, 4, "float32", "mixed_bf16", "capped"),
+    # a 45-wide sketch on a 300-row mode: the CholeskyQR kernel's 48-column
+    # bound (three panels of 16, the last zero-padded past column 45)
+    ((300, 30, 20), (40, 6, 5), 5, 2, "float64", "plain", "chol48"),
+    ((300, 30, 20), (40, 6, 5), 5, 2, "float32", "mixed_fp8", "chol48"),
     # the thin float32 Gram tile [C; W^T] (I <= 64, S <= 64): I = 64 with a
     # 64-wide sketch, a middle mode (A > 1 and B > 1), a last mode whose
     # size is not a multiple of 4 (element-wise staging), and order 4 with a
