@@ -202,3 +202,27 @@ def test_htr_als_arguments_are_checked():
     st = lib.rbki_htr(ctypes.c_void_p(16), 1, ctypes.byref(prm), big, cores, 1, ctypes.c_void_p(256), 1 << 40, None,
                       None)
     assert st == 5
+
+
+def test_enqueue_checks_its_result_buffer_and_arguments():
+    lib = rb.load_library()
+    prm = _params((20, 20, 20), (3, 3, 3))
+    need = lib.rbki_tucker_workspace(ctypes.byref(prm), 1)
+    nres = lib.rbki_tucker_result_bytes()
+    assert nres > 0
+    res = ctypes.create_string_buffer(nres)
+    resp = ctypes.cast(res, ctypes.c_void_p)
+    # no result buffer
+    st = lib.rbki_tucker_enqueue(ctypes.c_void_p(256), 1, ctypes.byref(prm), None, None, 1, ctypes.c_void_p(256),
+                                 need, None, None)
+    assert st == 1 and "result" in lib.rbki_last_error().decode()
+    # what rbki_tucker rejects (a workspace one byte short) is rejected before anything is enqueued
+    st = lib.rbki_tucker_enqueue(ctypes.c_void_p(256), 1, ctypes.byref(prm), None, None, 1, ctypes.c_void_p(256),
+                                 need - 1, resp, None)
+    assert st == 1 and "workspace" in lib.rbki_last_error().decode()
+    # a result with zero sums and no modes reads as error 0, status OK
+    err = ctypes.c_double(-1.0)
+    assert lib.rbki_tucker_result(ctypes.cast(ctypes.create_string_buffer(nres), ctypes.c_void_p),
+                                  ctypes.byref(err)) == 0
+    assert err.value == 0.0
+    assert lib.rbki_tucker_result(None, ctypes.byref(err)) == 1
