@@ -101,7 +101,10 @@ def test_full_size_run_matches_the_modes_in_order(env, big, precision, variant):
     assert abs(err - err_proj) <= 1e-4 * err_proj
 
 
-def test_enqueued_decompositions_match_synchronous_ones(env, big):
+@pytest.mark.parametrize("precision,variant,truncation", [("mixed_fp8", "krylov", "independent"),
+                                                          ("mixed_bf16", "power", "independent"),
+                                                          ("mixed_fp8", "krylov", "sequential")])
+def test_enqueued_decompositions_match_synchronous_ones(env, big, precision, variant, truncation):
     # three decompositions enqueued back to back on one stream with no wait
     # between them (two seeds, the first one twice) give, bit for bit, the
     # factors, core and error of the synchronous calls
@@ -109,7 +112,7 @@ def test_enqueued_decompositions_match_synchronous_ones(env, big):
     w, X = big
     ranks, p, q = w["ranks"], w["p"], w["q"]
     seeds = (w["seeds"][1], w["seeds"][1] + 7, w["seeds"][1])
-    args = dict(p=p, q=q, precision="mixed_fp8", out_dtype=torch.float64)
+    args = dict(p=p, q=q, precision=precision, variant=variant, truncation=truncation, out_dtype=torch.float64)
     print("synchronous", flush=True)
     ref = {s: rb.tucker(X, ranks, seed=s, **args) for s in set(seeds)}
     print("enqueued", flush=True)
